@@ -1,0 +1,208 @@
+/*
+ * mdp.h -- C ABI of the MI355X inexact-policy-iteration library.
+ *
+ * Problem (the paper's "Summary" and "Problem Setting and Solution Methods"
+ * sections): an infinite-horizon discounted MDP with finite state space
+ * {0..S-1}, finite action space {0..A-1}, stage costs g(s,a), discount
+ * gamma in [0,1) and transition probabilities P[(s,a), s'].  The solver
+ * minimises the expected discounted cumulative cost.  It uses inexact policy
+ * iteration: a greedy improvement step (one Bellman sweep) alternates with an
+ * approximate policy evaluation whose level of inexactness and inner solver
+ * (restarted GMRES or Richardson) the caller selects.
+ *
+ * Layout of an MDP handed to mdp_create ("Implementation" section: an MDP is
+ * created from offline data):
+ *   - rows r = s*A + a (state-major), S*A rows in total;
+ *   - row_ptr: int64[S*A+1], CSR row offsets, row_ptr[0] = 0, nondecreasing,
+ *     every row non-empty, row_ptr[S*A] = nnz;
+ *   - col: int32[nnz], column (successor state) indices in [0,S);
+ *   - val: double[nnz], probabilities, >= 0 and finite, each row summing to 1
+ *     within 1e-12*max(1, row length);
+ *   - cost: double[S*A], finite stage costs g(s,a), same row order.
+ *
+ * Pointers: every array argument may be host memory or device memory of the
+ * handle's GPU; the library tells them apart with hipPointerGetAttributes.
+ * Inputs are copied (the caller keeps ownership and may free them when the
+ * call returns); outputs are caller-allocated.
+ *
+ * Errors: every call returns an mdp_status.  No call aborts or throws.  A
+ * negative status leaves the outputs unspecified; mdp_last_error() returns a
+ * thread-local message describing the last failure on this thread.
+ *
+ * Threads: a handle serves one call at a time; a call made while another is
+ * running on the same handle returns MDP_E_STATE.
+ */
+#ifndef MDP_H
+#define MDP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mdp_handle* mdp_t;
+
+typedef enum {
+  MDP_OK = 0,
+  MDP_W_MAXITER = 1,   /* iteration cap reached; outputs hold the last iterate */
+  MDP_E_INVAL = -1,    /* invalid argument or invalid MDP data */
+  MDP_E_NOMEM = -2,    /* device or host allocation failed */
+  MDP_E_DEVICE = -3,   /* a HIP runtime call failed (also: no GPU present) */
+  MDP_E_NUMERIC = -4,  /* NaN or Inf met in a residual */
+  MDP_E_STATE = -5,    /* handle busy with another call */
+  MDP_E_NOTSUP = -6    /* valid request this build does not support */
+} mdp_status;
+
+/* Arithmetic of the sweeps and of the inner solver. */
+enum {
+  MDP_FP64 = 0,        /* everything in float64 */
+  MDP_MIXED_FP32 = 1,  /* P and vectors in float32 for inner sweeps/GMRES; float64 residuals and refinement */
+  MDP_MIXED_FP16 = 2   /* as MIXED_FP32 but P held in float16 with a float64 per-row sum correction */
+};
+
+/* Inner solver of the approximate policy evaluation. */
+enum { MDP_INNER_GMRES = 0, MDP_INNER_RICHARDSON = 1 };
+
+/* Bits of mdp_create_opts.low_precision: which reduced-precision copies of P to build. */
+enum { MDP_BUILD_FP32 = 1, MDP_BUILD_FP16 = 2 };
+
+typedef struct {
+  size_t struct_size;     /* sizeof(mdp_create_opts) */
+  void* stream;           /* hipStream_t to run on; NULL: the handle creates its own stream */
+  int32_t device;         /* HIP device ordinal; -1: the current device */
+  int32_t validate;       /* nonzero: check the MDP data (see the layout above) */
+  int32_t low_precision;  /* MDP_BUILD_* bits */
+  int32_t lanes_per_row;  /* 0: chosen from the mean row length; else 1,2,4,...,64 */
+} mdp_create_opts;
+
+typedef struct {
+  size_t struct_size;     /* sizeof(mdp_eval_opts) */
+  int32_t inner;          /* MDP_INNER_GMRES or MDP_INNER_RICHARDSON */
+  int32_t restart;        /* GMRES restart length m, 1..64 (default 30) */
+  int32_t precision;      /* MDP_FP64, MDP_MIXED_FP32 or MDP_MIXED_FP16 */
+  int32_t sync_every;     /* inner steps enqueued between host checks; 0: default */
+  double rtol;            /* stop when ||r|| <= rtol*||r0|| (GMRES: 2-norm of the residual;
+                             Richardson: max-norm of successive differences) */
+  int64_t max_iter;       /* cap on inner steps (default 10000) */
+} mdp_eval_opts;
+
+typedef struct {
+  size_t struct_size;     /* sizeof(mdp_solve_opts) */
+  int32_t inner;          /* inner solver, as in mdp_eval_opts */
+  int32_t restart;        /* GMRES restart length (default 30) */
+  int32_t precision;      /* MDP_FP64, MDP_MIXED_FP32 or MDP_MIXED_FP16 */
+  int32_t sync_every;     /* as in mdp_eval_opts */
+  double alpha;           /* inner forcing term: inner stop at alpha * ||r0|| (default 1e-4) */
+  double atol;            /* outer stop: ||T v - v||_inf <= atol (default 1e-8) */
+  double rtol_cert;       /* if > 0, also require ||T v - v||_inf <= rtol_cert*(1-gamma)*||T v||_inf */
+  int64_t max_outer;      /* cap on Bellman sweeps (default 1000) */
+  int64_t max_inner;      /* cap on inner steps per evaluation (default 10000) */
+} mdp_solve_opts;
+
+typedef struct {
+  size_t struct_size;     /* sizeof(mdp_stats) */
+  int64_t outer_iters;    /* policy improvement steps (Bellman sweeps minus one) */
+  int64_t inner_iters;    /* inner steps (Arnoldi or Richardson steps), summed */
+  int64_t bellman_sweeps; /* Bellman sweeps of any precision */
+  int64_t policy_applies; /* products with P_pi of any precision */
+  int64_t refinements;    /* float64 residual refinements (mixed precision only) */
+  double residual;        /* last ||T v - v||_inf (solve) or relative inner residual (eval) */
+  double time_ms;         /* wall time of the call */
+  double bytes;           /* algorithmic bytes moved by the call's kernels */
+  double* history;        /* optional caller array receiving ||T v_k - v_k||_inf per sweep */
+  int64_t history_cap;    /* its capacity */
+  int64_t history_len;    /* entries written */
+} mdp_stats;
+
+/* Fill option structs with defaults. */
+void mdp_default_create_opts(mdp_create_opts* o);
+void mdp_default_eval_opts(mdp_eval_opts* o);
+void mdp_default_solve_opts(mdp_solve_opts* o);
+
+/* Create a handle: copy the MDP (layout above) to the device, optionally
+ * validate it, and build the requested reduced-precision copies of P.
+ * opt may be NULL (defaults).  nnz must be below 2^31.  On success *out owns
+ * all device memory of the MDP. */
+mdp_status mdp_create(int64_t S, int32_t A, const int64_t* row_ptr, const int32_t* col,
+                      const double* val, const double* cost, double gamma,
+                      const mdp_create_opts* opt, mdp_t* out);
+
+/* One fused Bellman sweep in float64 (greedy step of policy iteration):
+ *   Tv[s] = min_a g(s,a) + gamma * sum_j P[(s,a),j] v[j],
+ *   policy[s] = the lowest action attaining the minimum,
+ *   *res_inf = max_s |Tv[s] - v[s]|.
+ * v: double[S].  Tv (double[S]), policy (int32[S]) and res_inf may be NULL. */
+mdp_status mdp_bellman(mdp_t h, const double* v, double* Tv, int32_t* policy, double* res_inf);
+
+/* Product with the transition matrix of a policy, gathering rows s*A+policy[s]
+ * of P without forming P_pi (policy evaluation operator):
+ *   mode 0: y = x - gamma * P_pi x         ((I - gamma P_pi) x)
+ *   mode 1: y = g_pi + gamma * P_pi x      (T_pi x)
+ * policy: int32[S] with entries in [0,A) (else MDP_E_INVAL); x, y: double[S]. */
+mdp_status mdp_policy_apply(mdp_t h, const int32_t* policy, const double* x, double* y,
+                            int32_t mode);
+
+/* Approximate policy evaluation: solve (I - gamma P_pi) v = g_pi starting from
+ * v0 (NULL: zero) with the inner solver and tolerance of opt (NULL: defaults).
+ * v: double[S] output.  stats may be NULL.  Returns MDP_W_MAXITER when the
+ * tolerance was not met within max_iter steps. */
+mdp_status mdp_policy_eval(mdp_t h, const int32_t* policy, const double* v0, double* v,
+                           const mdp_eval_opts* opt, mdp_stats* stats);
+
+/* Inexact policy iteration from v0 (NULL: zero).  Stops at the first sweep
+ * with ||T v_k - v_k||_inf <= atol (and the certified relative test if
+ * rtol_cert > 0); returns v = v_k and policy = the greedy policy of v_k.
+ * Returns MDP_W_MAXITER with the last iterate after max_outer sweeps. */
+mdp_status mdp_solve(mdp_t h, const double* v0, double* v, int32_t* policy,
+                     const mdp_solve_opts* opt, mdp_stats* stats);
+
+/* Sizes and placement of a handle (any pointer may be NULL). */
+mdp_status mdp_info(mdp_t h, int64_t* S, int32_t* A, int64_t* nnz, int32_t* lanes_per_row,
+                    int64_t* device_bytes);
+
+/* Choose lanes_per_row for this handle by timing candidate widths on the
+ * device (autotuner); writes the chosen width to *lanes (may be NULL). */
+mdp_status mdp_autotune(mdp_t h, int32_t* lanes);
+
+/* Kernel classes reported by the profiler. */
+enum {
+  MDP_K_BELLMAN = 0,         /* fused Bellman sweep */
+  MDP_K_ARNOLDI_APPLY = 1,   /* P_pi product fused with the Gram-Schmidt dot products */
+  MDP_K_ARNOLDI_UPDATE = 2,  /* Gram-Schmidt update and norm */
+  MDP_K_POLICY_APPLY = 3,    /* P_pi products: operator, T_pi (Richardson), residual */
+  MDP_K_GMRES_UPDATE_X = 4,  /* x += V y at the end of a GMRES cycle */
+  MDP_K_REDUCE = 5,          /* single-workgroup reductions, Givens rotations */
+  MDP_K_OTHER = 6,           /* casts, conversions, checks */
+  MDP_NUM_KERNEL_KINDS = 7
+};
+
+typedef struct {
+  size_t struct_size;                        /* sizeof(mdp_kernel_profile) */
+  int64_t launches[MDP_NUM_KERNEL_KINDS];    /* kernel launches per class */
+  double ms[MDP_NUM_KERNEL_KINDS];           /* summed kernel durations (HIP events on the handle's stream) */
+  double bytes[MDP_NUM_KERNEL_KINDS];        /* summed algorithmic bytes of those launches */
+} mdp_kernel_profile;
+
+/* Start (enable != 0, counters cleared) or stop recording a HIP event pair
+ * around every kernel launch of the handle. */
+mdp_status mdp_profile(mdp_t h, int32_t enable);
+
+/* Wait for the recorded launches and return the accumulated counters. */
+mdp_status mdp_profile_read(mdp_t h, mdp_kernel_profile* out);
+
+/* Release a handle and all of its device memory.  NULL is accepted. */
+mdp_status mdp_destroy(mdp_t h);
+
+/* Message for the last failure on the calling thread ("" if none). */
+const char* mdp_last_error(void);
+
+/* Library version string. */
+const char* mdp_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MDP_H */

@@ -1,0 +1,216 @@
+"""Python binding of the MI355X inexact-policy-iteration library.
+
+The functions mirror the C ABI of include/mdp.h (same names) and only marshal
+arguments: numpy arrays are passed as host pointers, torch tensors as host or
+device pointers.  Every step of the computation runs in libmdp.so.
+"""
+import ctypes as C
+
+import numpy as np
+
+from . import native
+from .native import (MDP_FP64, MDP_MIXED_FP32, MDP_MIXED_FP16, MDP_INNER_GMRES,  # noqa: F401
+                     MDP_INNER_RICHARDSON, MDP_BUILD_FP32, MDP_BUILD_FP16, MDP_OK,
+                     MDP_W_MAXITER, MDPError)
+
+__all__ = ["mdp_create", "mdp_bellman", "mdp_policy_apply", "mdp_policy_eval", "mdp_solve",
+           "mdp_destroy", "mdp_info", "mdp_autotune", "mdp_profile", "mdp_profile_read",
+           "mdp_last_error", "MDP", "MDPError"]
+
+
+def _ptr(a, dtype, n=None, name="array"):
+    """Pointer of a numpy array or torch tensor with the given dtype."""
+    if a is None:
+        return None
+    if isinstance(a, np.ndarray):
+        if a.dtype != dtype or not a.flags["C_CONTIGUOUS"]:
+            raise TypeError(f"{name}: need a C-contiguous {np.dtype(dtype)} array")
+        if n is not None and a.size < n:
+            raise ValueError(f"{name}: need {n} elements, got {a.size}")
+        return a.ctypes.data
+    import torch
+    if isinstance(a, torch.Tensor):
+        tdt = {np.float64: torch.float64, np.int32: torch.int32, np.int64: torch.int64}[dtype]
+        if a.dtype != tdt or not a.is_contiguous():
+            raise TypeError(f"{name}: need a contiguous {tdt} tensor")
+        if n is not None and a.numel() < n:
+            raise ValueError(f"{name}: need {n} elements, got {a.numel()}")
+        return a.data_ptr()
+    raise TypeError(f"{name}: numpy array or torch tensor expected")
+
+
+def mdp_last_error():
+    return native.load().mdp_last_error().decode()
+
+
+def mdp_create(S, A, row_ptr, col, val, cost, gamma, stream=None, device=-1, validate=True,
+               low_precision=0, lanes_per_row=0):
+    lib = native.load()
+    o = native.CreateOpts()
+    lib.mdp_default_create_opts(C.byref(o))
+    o.stream = stream
+    o.device = device
+    o.validate = 1 if validate else 0
+    o.low_precision = low_precision
+    o.lanes_per_row = lanes_per_row
+    h = C.c_void_p()
+    nnz = None
+    native.check(lib.mdp_create(int(S), int(A), _ptr(row_ptr, np.int64, S * A + 1, "row_ptr"),
+                                _ptr(col, np.int32, nnz, "col"), _ptr(val, np.float64, nnz, "val"),
+                                _ptr(cost, np.float64, S * A, "cost"), float(gamma), C.byref(o),
+                                C.byref(h)))
+    return h
+
+
+def mdp_destroy(h):
+    return native.check(native.load().mdp_destroy(h))
+
+
+def mdp_info(h):
+    S, A, nnz, L, b = C.c_int64(), C.c_int32(), C.c_int64(), C.c_int32(), C.c_int64()
+    native.check(native.load().mdp_info(h, C.byref(S), C.byref(A), C.byref(nnz), C.byref(L),
+                                        C.byref(b)))
+    return dict(S=S.value, A=A.value, nnz=nnz.value, lanes_per_row=L.value, device_bytes=b.value)
+
+
+def mdp_autotune(h):
+    L = C.c_int32()
+    native.check(native.load().mdp_autotune(h, C.byref(L)))
+    return L.value
+
+
+def mdp_profile(h, enable=True):
+    return native.check(native.load().mdp_profile(h, 1 if enable else 0))
+
+
+def mdp_profile_read(h):
+    """Per kernel class: launches, summed ms, summed algorithmic bytes."""
+    p = native.KernelProfile()
+    p.struct_size = C.sizeof(native.KernelProfile)
+    native.check(native.load().mdp_profile_read(h, C.byref(p)))
+    return {k: dict(launches=p.launches[i], ms=p.ms[i], bytes=p.bytes[i])
+            for i, k in enumerate(native.KERNEL_KINDS)}
+
+
+def mdp_bellman(h, v, Tv=None, policy=None):
+    res = C.c_double()
+    native.check(native.load().mdp_bellman(h, _ptr(v, np.float64, name="v"),
+                                            _ptr(Tv, np.float64, name="Tv"),
+                                            _ptr(policy, np.int32, name="policy"), C.byref(res)))
+    return res.value
+
+
+def mdp_policy_apply(h, policy, x, y, mode=0):
+    return native.check(native.load().mdp_policy_apply(h, _ptr(policy, np.int32, name="policy"),
+                                                        _ptr(x, np.float64, name="x"),
+                                                        _ptr(y, np.float64, name="y"), int(mode)))
+
+
+def _stats(history_cap=0):
+    st = native.Stats()
+    st.struct_size = C.sizeof(native.Stats)
+    hist = None
+    if history_cap:
+        hist = (C.c_double * history_cap)()
+        st.history = C.cast(hist, C.POINTER(C.c_double))
+        st.history_cap = history_cap
+    return st, hist
+
+
+def _stats_dict(st, hist):
+    d = {k: getattr(st, k) for k, _ in native.Stats._fields_ if k not in ("history", "struct_size")}
+    if hist is not None:
+        d["history"] = list(hist[:st.history_len])
+    return d
+
+
+def mdp_policy_eval(h, policy, v, v0=None, inner=MDP_INNER_GMRES, restart=30, precision=MDP_FP64,
+                    rtol=1e-10, max_iter=10000, sync_every=0):
+    lib = native.load()
+    o = native.EvalOpts()
+    lib.mdp_default_eval_opts(C.byref(o))
+    o.inner, o.restart, o.precision, o.rtol, o.max_iter = inner, restart, precision, rtol, max_iter
+    o.sync_every = sync_every
+    st, hist = _stats()
+    status = native.check(lib.mdp_policy_eval(h, _ptr(policy, np.int32, name="policy"),
+                                              _ptr(v0, np.float64, name="v0"),
+                                              _ptr(v, np.float64, name="v"), C.byref(o),
+                                              C.byref(st)))
+    d = _stats_dict(st, hist)
+    d["status"] = status
+    return d
+
+
+def mdp_solve(h, v, policy, v0=None, inner=MDP_INNER_GMRES, restart=30, precision=MDP_FP64,
+              alpha=1e-4, atol=1e-8, rtol_cert=0.0, max_outer=1000, max_inner=10000,
+              sync_every=0, history_cap=1024):
+    lib = native.load()
+    o = native.SolveOpts()
+    lib.mdp_default_solve_opts(C.byref(o))
+    o.inner, o.restart, o.precision, o.alpha, o.atol = inner, restart, precision, alpha, atol
+    o.rtol_cert, o.max_outer, o.max_inner, o.sync_every = rtol_cert, max_outer, max_inner, sync_every
+    st, hist = _stats(history_cap)
+    status = native.check(lib.mdp_solve(h, _ptr(v0, np.float64, name="v0"),
+                                        _ptr(v, np.float64, name="v"),
+                                        _ptr(policy, np.int32, name="policy"), C.byref(o),
+                                        C.byref(st)))
+    d = _stats_dict(st, hist)
+    d["status"] = status
+    return d
+
+
+class MDP:
+    """Owning wrapper of a handle (numpy in, numpy out)."""
+
+    def __init__(self, S, A, row_ptr, col, val, cost, gamma, **create_kw):
+        self.S, self.A, self.gamma = int(S), int(A), float(gamma)
+        self.h = mdp_create(S, A, row_ptr, col, val, cost, gamma, **create_kw)
+
+    @classmethod
+    def from_instance(cls, inst, **kw):
+        return cls(inst.S, inst.A, inst.row_ptr, inst.col, inst.val, inst.cost, inst.gamma, **kw)
+
+    def close(self):
+        if self.h is not None:
+            mdp_destroy(self.h)
+            self.h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def info(self):
+        return mdp_info(self.h)
+
+    def bellman(self, v):
+        Tv = np.empty(self.S)
+        pi = np.empty(self.S, np.int32)
+        res = mdp_bellman(self.h, np.ascontiguousarray(v, np.float64), Tv, pi)
+        return Tv, pi, res
+
+    def policy_apply(self, policy, x, mode=0):
+        y = np.empty(self.S)
+        mdp_policy_apply(self.h, np.ascontiguousarray(policy, np.int32),
+                         np.ascontiguousarray(x, np.float64), y, mode)
+        return y
+
+    def policy_eval(self, policy, v0=None, **kw):
+        v = np.empty(self.S)
+        st = mdp_policy_eval(self.h, np.ascontiguousarray(policy, np.int32), v,
+                             None if v0 is None else np.ascontiguousarray(v0, np.float64), **kw)
+        return v, st
+
+    def solve(self, v0=None, **kw):
+        v = np.empty(self.S)
+        pi = np.empty(self.S, np.int32)
+        st = mdp_solve(self.h, v, pi, None if v0 is None else np.ascontiguousarray(v0, np.float64),
+                       **kw)
+        return v, pi, st

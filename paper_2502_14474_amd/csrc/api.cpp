@@ -1,0 +1,862 @@
+// C-ABI entry points: validation, handle life cycle, and the host side of the
+// inexact policy iteration (outer loop, inner-solver control, precision
+// schedule).  The arithmetic itself runs in the kernels of kernels.hip.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <limits>
+#include <thread>
+#include <vector>
+
+#include "internal.h"
+
+namespace mdp {
+
+namespace {
+thread_local std::string g_err;
+
+struct BusyGuard {
+  mdp_handle* h;
+  bool ok;
+  explicit BusyGuard(mdp_handle* hh) : h(hh) {
+    int expect = 0;
+    ok = h->busy.compare_exchange_strong(expect, 1);
+  }
+  ~BusyGuard() {
+    if (ok) h->busy.store(0);
+  }
+};
+
+double now_ms() {
+  using namespace std::chrono;
+  return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
+}
+
+bool is_device_ptr(const void* p) {
+  if (!p) return false;
+  hipPointerAttribute_t a;
+  std::memset(&a, 0, sizeof(a));
+  if (hipPointerGetAttributes(&a, p) != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  return a.type == hipMemoryTypeDevice;
+}
+
+template <typename T>
+hipError_t dev_alloc(mdp_handle* h, T** p, size_t n) {
+  const size_t bytes = std::max<size_t>(1, n) * sizeof(T);
+  hipError_t e = hipMalloc(reinterpret_cast<void**>(p), bytes);
+  if (e == hipSuccess) h->device_bytes += static_cast<int64_t>(bytes);
+  return e;
+}
+
+template <typename T>
+void dev_free(T*& p) {
+  if (p) (void)hipFree(p);
+  p = nullptr;
+}
+
+// ---- validation on host arrays ----------------------------------------------
+mdp_status validate_host(int64_t S, int32_t A, const int64_t* rp, const int32_t* col,
+                         const double* val, const double* cost) {
+  const int64_t rows = S * A;
+  if (rp[0] != 0) return fail(MDP_E_INVAL, "row_ptr[0] must be 0");
+  for (int64_t r = 0; r < rows; ++r)
+    if (rp[r + 1] <= rp[r])
+      return fail(MDP_E_INVAL, "row_ptr must increase (row " + std::to_string(r) +
+                                   " of state " + std::to_string(r / A) + " is empty or decreasing)");
+  const int64_t nnz = rp[rows];
+  if (nnz >= (int64_t{1} << 31)) return fail(MDP_E_NOTSUP, "nnz must be below 2^31");
+  for (int64_t r = 0; r < rows; ++r)
+    if (!std::isfinite(cost[r])) return fail(MDP_E_INVAL, "non-finite cost at row " + std::to_string(r));
+  const unsigned nt = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+  std::vector<int64_t> bad(nt, -1);
+  std::vector<int> why(nt, 0);
+  std::vector<std::thread> th;
+  for (unsigned t = 0; t < nt; ++t) {
+    th.emplace_back([&, t]() {
+      const int64_t r0 = rows * t / nt, r1 = rows * (t + 1) / nt;
+      for (int64_t r = r0; r < r1; ++r) {
+        double sum = 0.0;
+        for (int64_t e = rp[r]; e < rp[r + 1]; ++e) {
+          if (col[e] < 0 || col[e] >= S) { bad[t] = r; why[t] = 1; return; }
+          if (!(val[e] >= 0.0) || !std::isfinite(val[e])) { bad[t] = r; why[t] = 2; return; }
+          sum += val[e];
+        }
+        const double len = static_cast<double>(rp[r + 1] - rp[r]);
+        if (std::fabs(sum - 1.0) > 1e-12 * std::max(1.0, len)) { bad[t] = r; why[t] = 3; return; }
+      }
+    });
+  }
+  for (auto& x : th) x.join();
+  for (unsigned t = 0; t < nt; ++t) {
+    if (bad[t] < 0) continue;
+    const char* w = why[t] == 1 ? "column index outside [0,S)"
+                    : why[t] == 2 ? "negative or non-finite probability"
+                                  : "row does not sum to 1";
+    return fail(MDP_E_INVAL, std::string(w) + " in row " + std::to_string(bad[t]));
+  }
+  return MDP_OK;
+}
+
+mdp_status sync_ctl(mdp_handle* h) {
+  MDP_HIP(hipMemcpyAsync(h->ctl_host, h->ctl, kCtlHeaderBytes, hipMemcpyDeviceToHost, h->stream));
+  MDP_HIP(hipStreamSynchronize(h->stream));
+  return MDP_OK;
+}
+
+mdp_status ensure_basis(mdp_handle* h, Prec prec, int m) {
+  if (prec == kF64) {
+    if (h->basis_m64 >= m) return MDP_OK;
+    dev_free(h->U64);
+    MDP_HIP(dev_alloc(h, &h->U64, static_cast<size_t>(m + 1) * h->ldu));
+    h->basis_m64 = m;
+  } else {
+    if (h->basis_m32 >= m) return MDP_OK;
+    dev_free(h->U32);
+    MDP_HIP(dev_alloc(h, &h->U32, static_cast<size_t>(m + 1) * h->ldu));
+    h->basis_m32 = m;
+  }
+  return MDP_OK;
+}
+
+mdp_status ensure_lowp(mdp_handle* h, Prec prec) {
+  if (prec == kF32 && !h->val32) {
+    MDP_HIP(dev_alloc(h, &h->val32, h->nnz));
+    MDP_HIP(launch_build_lowp(h, MDP_BUILD_FP32));
+  }
+  if (prec == kF16 && !h->val16) {
+    MDP_HIP(dev_alloc(h, &h->val16, h->nnz));
+    MDP_HIP(dev_alloc(h, &h->corr16, h->rows));
+    MDP_HIP(launch_build_lowp(h, MDP_BUILD_FP16));
+  }
+  if (prec != kF64 && !h->v32) MDP_HIP(dev_alloc(h, &h->v32, h->S));
+  return MDP_OK;
+}
+
+// Copy a caller policy to device memory and check its range.
+mdp_status load_policy(mdp_handle* h, const int32_t* policy, int32_t* dst) {
+  if (!policy) return fail(MDP_E_INVAL, "policy is NULL");
+  if (!is_device_ptr(policy)) {
+    for (int64_t s = 0; s < h->S; ++s)
+      if (policy[s] < 0 || policy[s] >= h->A)
+        return fail(MDP_E_INVAL, "policy entry outside [0,A) at state " + std::to_string(s));
+    MDP_HIP(hipMemcpyAsync(dst, policy, h->S * sizeof(int32_t), hipMemcpyHostToDevice, h->stream));
+    return MDP_OK;
+  }
+  MDP_HIP(hipMemcpyAsync(dst, policy, h->S * sizeof(int32_t), hipMemcpyDeviceToDevice, h->stream));
+  MDP_HIP(launch_ctl_reset(h, 0.0));
+  MDP_HIP(launch_check_policy(h, dst));
+  MDP_TRY(sync_ctl(h));
+  if (h->ctl_host->bad_policy)
+    return fail(MDP_E_INVAL, std::to_string(h->ctl_host->bad_policy) + " policy entries outside [0,A)");
+  return MDP_OK;
+}
+
+mdp_status load_vec(mdp_handle* h, const double* src, double* dst) {
+  if (src)
+    MDP_HIP(hipMemcpyAsync(dst, src, h->S * sizeof(double), hipMemcpyDefault, h->stream));
+  else
+    MDP_HIP(hipMemsetAsync(dst, 0, h->S * sizeof(double), h->stream));
+  return MDP_OK;
+}
+
+mdp_status store(mdp_handle* h, void* dst, const void* src, size_t bytes) {
+  if (dst && dst != src) MDP_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyDefault, h->stream));
+  return MDP_OK;
+}
+
+int default_lanes(double mean_row) {
+  int L = 2;
+  while (L < 64 && L < mean_row) L <<= 1;
+  return L;
+}
+
+Prec prec_of(int p) { return p == MDP_MIXED_FP16 ? kF16 : (p == MDP_MIXED_FP32 ? kF32 : kF64); }
+int bval_of(Prec p) { return p == kF64 ? 8 : (p == kF32 ? 4 : 2); }
+double floor_of(Prec p) { return p == kF64 ? 0.0 : (p == kF32 ? 1e-6 : 1e-3); }
+
+struct InnerResult {
+  int64_t steps = 0;
+  int64_t applies = 0;
+  int64_t refinements = 0;
+  double bytes = 0;
+  bool converged = false;
+};
+
+// GMRES(m) on (I - gamma P_pi) x = g_pi.  On entry basis slot 0 holds the
+// residual of x and ctl holds a started cycle (kRedGmresStart).  Arnoldi steps
+// run in `prec`; every restart recomputes the residual in float64 from the
+// float64 P, so the mixed-precision variants are iterative refinement.
+mdp_status gmres_inner(mdp_handle* h, Prec prec, const int32_t* pi, double* x, int m,
+                       int64_t max_iter, int sync_every, double alpha, InnerResult* out) {
+  const Prec bprec = prec == kF64 ? kF64 : kF32;
+  const int bb = bprec == kF64 ? 8 : 4;
+  for (;;) {
+    int j = 0;
+    MDP_TRY(sync_ctl(h));
+    while (!h->ctl_host->done && j < m) {
+      for (int b = 0; b < sync_every && j < m; ++b, ++j) {
+        MDP_HIP(launch_arnoldi_step(h, prec, pi, j, m));
+      }
+      MDP_TRY(sync_ctl(h));
+    }
+    const int done_j = h->ctl_host->j;
+    for (int jj = 0; jj < done_j; ++jj)
+      out->bytes += bytes_arnoldi_apply(h, bval_of(prec), bb, jj) + bytes_arnoldi_update(h, bb, jj);
+    out->applies += done_j;
+    if (done_j > 0) {
+      MDP_HIP(launch_gmres_update_x(h, bprec, x));
+      out->bytes += h->S * (16.0 + done_j * (double)bb);
+    }
+    out->steps = h->ctl_host->steps;
+    const double est = h->ctl_host->res_est;
+    if (!std::isfinite(est)) return fail(MDP_E_NUMERIC, "non-finite GMRES residual");
+    if (h->ctl_host->converged && prec == kF64) {
+      out->converged = true;
+      return MDP_OK;
+    }
+    if (out->steps >= max_iter) return MDP_OK;
+    // restart: true residual in float64 into basis slot 0, next cycle
+    void* slot0 = bprec == kF64 ? static_cast<void*>(h->U64) : static_cast<void*>(h->U32);
+    MDP_HIP(launch_apply(h, kApplyRes, pi, x, slot0, bprec != kF64, kRedGmresStart, 0, alpha,
+                         floor_of(prec)));
+    out->applies += 1;
+    out->refinements += prec == kF64 ? 0 : 1;
+    out->bytes += bytes_apply(h, 8, 8, bb);
+    MDP_TRY(sync_ctl(h));
+    if (!std::isfinite(h->ctl_host->beta)) return fail(MDP_E_NUMERIC, "non-finite residual");
+    if (h->ctl_host->converged) {
+      out->converged = true;
+      return MDP_OK;
+    }
+    if (done_j == 0 && h->ctl_host->done) {
+      // the residual cannot be reduced further in this arithmetic
+      return MDP_OK;
+    }
+  }
+}
+
+// Richardson x <- g_pi + gamma P_pi x on the pair (buf0, buf1), starting from
+// ctl->rich_cur; stops at ctl->tol or after max_iter total steps.  Returns the
+// buffer holding the last iterate.
+mdp_status richardson_inner(mdp_handle* h, const int32_t* pi, double* buf0, double* buf1,
+                            int64_t max_iter, int sync_every, InnerResult* out, double** last) {
+  MDP_TRY(sync_ctl(h));
+  while (!h->ctl_host->done && h->ctl_host->steps < max_iter) {
+    const int64_t left = max_iter - h->ctl_host->steps;
+    const int64_t n = std::min<int64_t>(sync_every, left);
+    for (int64_t i = 0; i < n; ++i) MDP_HIP(launch_richardson_step(h, pi, buf0, buf1));
+    MDP_TRY(sync_ctl(h));
+    if (!std::isfinite(h->ctl_host->res_est)) return fail(MDP_E_NUMERIC, "non-finite Richardson difference");
+  }
+  out->steps = h->ctl_host->steps;
+  out->applies = out->steps;
+  out->bytes += out->steps * bytes_apply(h, 8, 8, 8);
+  out->converged = h->ctl_host->converged != 0;
+  *last = h->ctl_host->rich_cur ? buf1 : buf0;
+  return MDP_OK;
+}
+
+void stats_begin(mdp_stats* st) {
+  if (!st) return;
+  double* hist = st->history;
+  int64_t cap = st->history_cap;
+  size_t sz = st->struct_size;
+  std::memset(st, 0, std::min(sz, sizeof(mdp_stats)));
+  st->struct_size = sz;
+  st->history = hist;
+  st->history_cap = cap;
+}
+
+bool stats_ok(const mdp_stats* st) { return !st || st->struct_size >= sizeof(mdp_stats); }
+
+}  // namespace
+
+double bytes_sweep(const mdp_handle* h, int bval, int bv, bool r0, int br) {
+  // CSR values + columns, row offsets, costs, v gathered (counted once), Tv and pi out
+  return static_cast<double>(h->nnz) * (bval + 4) + (h->rows + 1) * 4.0 + h->rows * 8.0 +
+         h->S * static_cast<double>(bv) + h->S * 12.0 + (r0 ? h->S * static_cast<double>(br) : 0.0);
+}
+double bytes_apply(const mdp_handle* h, int bval, int bx, int by) {
+  // selected rows (values + columns), pi, two row offsets, g_pi, x (once), y
+  const double nnz_pi = static_cast<double>(h->nnz) / h->rows * h->S;
+  return nnz_pi * (bval + 4) + h->S * (4.0 + 8.0 + 8.0 + bx + by);
+}
+double bytes_arnoldi_apply(const mdp_handle* h, int bval, int bb, int j) {
+  // product (x read once, w written) + one pass over U_0..U_j for the dots
+  const double nnz_pi = static_cast<double>(h->nnz) / h->rows * h->S;
+  return nnz_pi * (bval + 4) + h->S * (4.0 + 8.0 + 2.0 * bb) + h->S * static_cast<double>(bb) * (j + 1);
+}
+double bytes_arnoldi_update(const mdp_handle* h, int bb, int j) {
+  // U_0..U_j read, w read and written
+  return h->S * static_cast<double>(bb) * (j + 3);
+}
+
+void prof_begin(mdp_handle* h, hipEvent_t* a) {
+  *a = nullptr;
+  if (!h->prof_on) return;
+  if (h->prof_pool.empty()) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return;
+    h->prof_pool.push_back(e);
+  }
+  *a = h->prof_pool.back();
+  h->prof_pool.pop_back();
+  (void)hipEventRecord(*a, h->stream);
+}
+
+void prof_end(mdp_handle* h, int kind, hipEvent_t a, double bytes) {
+  if (!h->prof_on || !a) return;
+  hipEvent_t b;
+  if (h->prof_pool.empty()) {
+    if (hipEventCreate(&b) != hipSuccess) return;
+  } else {
+    b = h->prof_pool.back();
+    h->prof_pool.pop_back();
+  }
+  (void)hipEventRecord(b, h->stream);
+  h->prof_pending.push_back({kind, a, b, bytes});
+  if (h->prof_pending.size() >= 16384) prof_resolve(h);
+}
+
+void prof_resolve(mdp_handle* h) {
+  if (h->prof_pending.empty()) return;
+  (void)hipEventSynchronize(h->prof_pending.back().b);
+  for (auto& r : h->prof_pending) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
+      h->prof_ms[r.kind] += ms;
+      h->prof_launches[r.kind] += 1;
+      h->prof_bytes[r.kind] += r.bytes;
+    }
+    h->prof_pool.push_back(r.a);
+    h->prof_pool.push_back(r.b);
+  }
+  h->prof_pending.clear();
+}
+
+mdp_status fail(mdp_status st, const std::string& msg) {
+  g_err = msg;
+  return st;
+}
+void clear_error() { g_err.clear(); }
+
+}  // namespace mdp
+
+using namespace mdp;
+
+extern "C" {
+
+const char* mdp_last_error(void) { return g_err.c_str(); }
+const char* mdp_version(void) { return "mdp-mi355x 0.1 (gfx950)"; }
+
+void mdp_default_create_opts(mdp_create_opts* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->struct_size = sizeof(*o);
+  o->stream = nullptr;
+  o->device = -1;
+  o->validate = 1;
+  o->low_precision = 0;
+  o->lanes_per_row = 0;
+}
+
+void mdp_default_eval_opts(mdp_eval_opts* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->struct_size = sizeof(*o);
+  o->inner = MDP_INNER_GMRES;
+  o->restart = 30;
+  o->precision = MDP_FP64;
+  o->sync_every = 0;
+  o->rtol = 1e-10;
+  o->max_iter = 10000;
+}
+
+void mdp_default_solve_opts(mdp_solve_opts* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->struct_size = sizeof(*o);
+  o->inner = MDP_INNER_GMRES;
+  o->restart = 30;
+  o->precision = MDP_FP64;
+  o->sync_every = 0;
+  o->alpha = 1e-4;
+  o->atol = 1e-8;
+  o->rtol_cert = 0.0;
+  o->max_outer = 1000;
+  o->max_inner = 10000;
+}
+
+mdp_status mdp_destroy(mdp_t h) {
+  if (!h) return MDP_OK;
+  if (h->stream) (void)hipStreamSynchronize(h->stream);
+  dev_free(h->row_ptr);
+  dev_free(h->col);
+  dev_free(h->val);
+  dev_free(h->cost);
+  dev_free(h->val32);
+  dev_free(h->val16);
+  dev_free(h->corr16);
+  dev_free(h->cost32);
+  dev_free(h->v);
+  dev_free(h->Tv);
+  dev_free(h->x2);
+  dev_free(h->io);
+  dev_free(h->pi);
+  dev_free(h->pi_io);
+  dev_free(h->v32);
+  dev_free(h->x32a);
+  dev_free(h->x32b);
+  dev_free(h->U64);
+  dev_free(h->U32);
+  dev_free(h->part.buf);
+  dev_free(h->ctl);
+  if (h->ctl_host) (void)hipHostFree(h->ctl_host);
+  prof_resolve(h);
+  for (auto e : h->prof_pool) (void)hipEventDestroy(e);
+  if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
+  delete h;
+  return MDP_OK;
+}
+
+mdp_status mdp_create(int64_t S, int32_t A, const int64_t* row_ptr, const int32_t* col,
+                      const double* val, const double* cost, double gamma,
+                      const mdp_create_opts* opt, mdp_t* out) {
+  clear_error();
+  if (!out) return fail(MDP_E_INVAL, "out is NULL");
+  *out = nullptr;
+  mdp_create_opts o;
+  mdp_default_create_opts(&o);
+  if (opt) {
+    if (opt->struct_size < sizeof(mdp_create_opts)) return fail(MDP_E_INVAL, "mdp_create_opts.struct_size too small");
+    o = *opt;
+  }
+  if (S < 1 || A < 1) return fail(MDP_E_INVAL, "S and A must be at least 1");
+  if (A > 8192) return fail(MDP_E_NOTSUP, "A above 8192 is not supported");
+  if (S * static_cast<int64_t>(A) >= (int64_t{1} << 31) - 1)
+    return fail(MDP_E_NOTSUP, "S*A must be below 2^31");
+  if (!(gamma >= 0.0 && gamma < 1.0)) return fail(MDP_E_INVAL, "gamma must lie in [0,1)");
+  if (!row_ptr || !col || !val || !cost) return fail(MDP_E_INVAL, "NULL MDP array");
+  if (o.lanes_per_row != 0 &&
+      (o.lanes_per_row < 2 || o.lanes_per_row > 64 || (o.lanes_per_row & (o.lanes_per_row - 1))))
+    return fail(MDP_E_INVAL, "lanes_per_row must be 0 or a power of two in [2,64]");
+  if (o.low_precision & ~(MDP_BUILD_FP32 | MDP_BUILD_FP16))
+    return fail(MDP_E_INVAL, "unknown low_precision bits");
+  const int64_t rows = S * A;
+
+  const bool dev_in = is_device_ptr(row_ptr) || is_device_ptr(col) || is_device_ptr(val) ||
+                      is_device_ptr(cost);
+  std::vector<int64_t> h_rp;
+  const int64_t* rp_host = row_ptr;
+  int64_t nnz = 0;
+  if (dev_in) {
+    // stage through the host for validation
+    h_rp.resize(rows + 1);
+    MDP_HIP(hipMemcpy(h_rp.data(), row_ptr, (rows + 1) * sizeof(int64_t), hipMemcpyDefault));
+    rp_host = h_rp.data();
+  }
+  nnz = rp_host[rows];
+  if (nnz < rows) return fail(MDP_E_INVAL, "row_ptr[S*A] smaller than the number of rows");
+  if (nnz >= (int64_t{1} << 31)) return fail(MDP_E_NOTSUP, "nnz must be below 2^31");
+  if (o.validate) {
+    if (dev_in) {
+      std::vector<int32_t> c(nnz);
+      std::vector<double> v(nnz), g(rows);
+      MDP_HIP(hipMemcpy(c.data(), col, nnz * sizeof(int32_t), hipMemcpyDefault));
+      MDP_HIP(hipMemcpy(v.data(), val, nnz * sizeof(double), hipMemcpyDefault));
+      MDP_HIP(hipMemcpy(g.data(), cost, rows * sizeof(double), hipMemcpyDefault));
+      MDP_TRY(validate_host(S, A, rp_host, c.data(), v.data(), g.data()));
+    } else {
+      MDP_TRY(validate_host(S, A, rp_host, col, val, cost));
+    }
+  }
+
+  auto* h = new mdp_handle();
+  auto bail = [&](mdp_status st) {
+    std::string keep = g_err;
+    mdp_destroy(h);
+    g_err = keep;
+    return st;
+  };
+#define CHK(call)                                                                         \
+  do {                                                                                    \
+    hipError_t e_ = (call);                                                               \
+    if (e_ != hipSuccess)                                                                 \
+      return bail(fail(e_ == hipErrorOutOfMemory ? MDP_E_NOMEM : MDP_E_DEVICE,            \
+                       std::string(#call) + ": " + hipGetErrorString(e_)));               \
+  } while (0)
+  h->S = S;
+  h->A = A;
+  h->rows = rows;
+  h->nnz = nnz;
+  h->gamma = gamma;
+  h->lanes = o.lanes_per_row ? o.lanes_per_row : default_lanes(static_cast<double>(nnz) / rows);
+  if (o.device >= 0) CHK(hipSetDevice(o.device));
+  CHK(hipGetDevice(&h->device));
+  if (o.stream) {
+    h->stream = static_cast<hipStream_t>(o.stream);
+  } else {
+    CHK(hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking));
+    h->own_stream = true;
+  }
+  h->ldu = (S + 255) / 256 * 256;
+  CHK(dev_alloc(h, &h->row_ptr, rows + 1));
+  CHK(dev_alloc(h, &h->col, nnz));
+  CHK(dev_alloc(h, &h->val, nnz));
+  CHK(dev_alloc(h, &h->cost, rows));
+  if (dev_in) {
+    int64_t* tmp = nullptr;
+    CHK(hipMalloc(reinterpret_cast<void**>(&tmp), (rows + 1) * sizeof(int64_t)));
+    CHK(hipMemcpyAsync(tmp, row_ptr, (rows + 1) * sizeof(int64_t), hipMemcpyDefault, h->stream));
+    CHK(launch_i64_to_i32(h->stream, tmp, h->row_ptr, rows + 1));
+    CHK(hipStreamSynchronize(h->stream));
+    CHK(hipFree(tmp));
+  } else {
+    std::vector<int32_t> rp32(rows + 1);
+    for (int64_t r = 0; r <= rows; ++r) rp32[r] = static_cast<int32_t>(rp_host[r]);
+    CHK(hipMemcpy(h->row_ptr, rp32.data(), (rows + 1) * sizeof(int32_t), hipMemcpyHostToDevice));
+  }
+  CHK(hipMemcpyAsync(h->col, col, nnz * sizeof(int32_t), hipMemcpyDefault, h->stream));
+  CHK(hipMemcpyAsync(h->val, val, nnz * sizeof(double), hipMemcpyDefault, h->stream));
+  CHK(hipMemcpyAsync(h->cost, cost, rows * sizeof(double), hipMemcpyDefault, h->stream));
+  CHK(dev_alloc(h, &h->v, S));
+  CHK(dev_alloc(h, &h->Tv, S));
+  CHK(dev_alloc(h, &h->x2, S));
+  CHK(dev_alloc(h, &h->io, S));
+  CHK(dev_alloc(h, &h->pi, S));
+  CHK(dev_alloc(h, &h->pi_io, S));
+  h->part.cap = partials_doubles(S, A, kMaxRestart);
+  CHK(dev_alloc(h, &h->part.buf, h->part.cap));
+  CHK(dev_alloc(h, &h->ctl, 1));
+  CHK(hipHostMalloc(reinterpret_cast<void**>(&h->ctl_host), sizeof(Ctl), hipHostMallocDefault));
+  std::memset(h->ctl_host, 0, sizeof(Ctl));
+  CHK(hipMemsetAsync(h->ctl, 0, sizeof(Ctl), h->stream));
+  if (o.low_precision & MDP_BUILD_FP32) {
+    mdp_status st = ensure_lowp(h, kF32);
+    if (st < 0) return bail(st);
+  }
+  if (o.low_precision & MDP_BUILD_FP16) {
+    mdp_status st = ensure_lowp(h, kF16);
+    if (st < 0) return bail(st);
+  }
+  CHK(hipStreamSynchronize(h->stream));
+#undef CHK
+  *out = h;
+  return MDP_OK;
+}
+
+mdp_status mdp_info(mdp_t h, int64_t* S, int32_t* A, int64_t* nnz, int32_t* lanes,
+                    int64_t* device_bytes) {
+  clear_error();
+  if (!h) return fail(MDP_E_INVAL, "NULL handle");
+  if (S) *S = h->S;
+  if (A) *A = h->A;
+  if (nnz) *nnz = h->nnz;
+  if (lanes) *lanes = h->lanes;
+  if (device_bytes) *device_bytes = h->device_bytes;
+  return MDP_OK;
+}
+
+mdp_status mdp_bellman(mdp_t h, const double* v, double* Tv, int32_t* policy, double* res_inf) {
+  clear_error();
+  if (!h) return fail(MDP_E_INVAL, "NULL handle");
+  if (!v) return fail(MDP_E_INVAL, "v is NULL");
+  BusyGuard g(h);
+  if (!g.ok) return fail(MDP_E_STATE, "handle is busy");
+  const size_t vb = h->S * sizeof(double), pb = h->S * sizeof(int32_t);
+  const double* vin = v;
+  if (!is_device_ptr(v) || v == Tv) {
+    MDP_HIP(hipMemcpyAsync(h->io, v, vb, hipMemcpyDefault, h->stream));
+    vin = h->io;
+  }
+  double* tv_dev = (Tv && is_device_ptr(Tv)) ? Tv : h->Tv;
+  int32_t* pi_dev = (policy && is_device_ptr(policy)) ? policy : h->pi;
+  MDP_HIP(launch_bellman(h, kF64, vin, tv_dev, pi_dev, nullptr, false, kRedPlain, 0, 0.0, 0.0));
+  if (Tv) MDP_TRY(store(h, Tv, tv_dev, vb));
+  if (policy) MDP_TRY(store(h, policy, pi_dev, pb));
+  MDP_TRY(sync_ctl(h));
+  const double res = h->ctl_host->res_max;
+  if (res_inf) *res_inf = res;
+  if (!std::isfinite(res)) return fail(MDP_E_NUMERIC, "non-finite Bellman residual");
+  return MDP_OK;
+}
+
+mdp_status mdp_policy_apply(mdp_t h, const int32_t* policy, const double* x, double* y,
+                            int32_t mode) {
+  clear_error();
+  if (!h) return fail(MDP_E_INVAL, "NULL handle");
+  if (!x || !y) return fail(MDP_E_INVAL, "x and y must be non-NULL");
+  if (mode != 0 && mode != 1) return fail(MDP_E_INVAL, "mode must be 0 or 1");
+  BusyGuard g(h);
+  if (!g.ok) return fail(MDP_E_STATE, "handle is busy");
+  MDP_TRY(load_policy(h, policy, h->pi_io));
+  const size_t vb = h->S * sizeof(double);
+  const double* xin = x;
+  if (!is_device_ptr(x) || x == y) {
+    MDP_HIP(hipMemcpyAsync(h->io, x, vb, hipMemcpyDefault, h->stream));
+    xin = h->io;
+  }
+  double* ydev = is_device_ptr(y) ? y : h->Tv;
+  MDP_HIP(launch_apply(h, mode == 0 ? kApplyOp : kApplyT, h->pi_io, xin, ydev, false, kRedNone, 0,
+                       0.0, 0.0));
+  MDP_TRY(store(h, y, ydev, vb));
+  MDP_HIP(hipStreamSynchronize(h->stream));
+  return MDP_OK;
+}
+
+mdp_status mdp_policy_eval(mdp_t h, const int32_t* policy, const double* v0, double* v,
+                           const mdp_eval_opts* opt, mdp_stats* stats) {
+  clear_error();
+  const double t0 = now_ms();
+  if (!h) return fail(MDP_E_INVAL, "NULL handle");
+  if (!v) return fail(MDP_E_INVAL, "v is NULL");
+  if (!stats_ok(stats)) return fail(MDP_E_INVAL, "mdp_stats.struct_size too small");
+  mdp_eval_opts o;
+  mdp_default_eval_opts(&o);
+  if (opt) {
+    if (opt->struct_size < sizeof(mdp_eval_opts)) return fail(MDP_E_INVAL, "mdp_eval_opts.struct_size too small");
+    o = *opt;
+  }
+  if (o.inner != MDP_INNER_GMRES && o.inner != MDP_INNER_RICHARDSON) return fail(MDP_E_INVAL, "unknown inner solver");
+  if (o.restart < 1 || o.restart > kMaxRestart) return fail(MDP_E_INVAL, "restart must lie in [1,64]");
+  if (o.precision < MDP_FP64 || o.precision > MDP_MIXED_FP16) return fail(MDP_E_INVAL, "unknown precision");
+  if (o.inner == MDP_INNER_RICHARDSON && o.precision != MDP_FP64)
+    return fail(MDP_E_NOTSUP, "Richardson runs in float64 only");
+  if (!(o.rtol >= 0.0) || o.max_iter < 0) return fail(MDP_E_INVAL, "bad tolerance or iteration cap");
+  BusyGuard g(h);
+  if (!g.ok) return fail(MDP_E_STATE, "handle is busy");
+  stats_begin(stats);
+  const int sync_every = o.sync_every > 0 ? o.sync_every : 4;
+  MDP_TRY(load_policy(h, policy, h->pi));
+  MDP_TRY(load_vec(h, v0, h->v));
+  MDP_HIP(launch_ctl_reset(h, 0.0));
+  InnerResult ir;
+  double* result = h->v;
+  double rel = 0.0;
+  if (o.inner == MDP_INNER_GMRES) {
+    const Prec prec = prec_of(o.precision);
+    MDP_TRY(ensure_basis(h, prec == kF64 ? kF64 : kF32, o.restart));
+    if (prec != kF64) MDP_TRY(ensure_lowp(h, prec));
+    void* slot0 = prec == kF64 ? static_cast<void*>(h->U64) : static_cast<void*>(h->U32);
+    MDP_HIP(launch_apply(h, kApplyRes, h->pi, h->v, slot0, prec != kF64, kRedGmresStart, 1, o.rtol,
+                         floor_of(prec)));
+    ir.applies += 1;
+    MDP_TRY(gmres_inner(h, prec, h->pi, h->v, o.restart, o.max_iter, sync_every, o.rtol, &ir));
+    MDP_TRY(sync_ctl(h));
+    rel = h->ctl_host->beta0 > 0 ? h->ctl_host->res_est / h->ctl_host->beta0 : 0.0;
+    if (ir.converged && prec != kF64)
+      rel = h->ctl_host->beta0 > 0 ? h->ctl_host->beta / h->ctl_host->beta0 : 0.0;
+  } else {
+    // first step sets the tolerance rtol * max|x1 - x0|
+    MDP_HIP(launch_apply(h, kApplyT, h->pi, h->v, h->x2, false, kRedRichardson, 1, o.rtol, 0.0));
+    if (o.max_iter >= 1) {
+      MDP_TRY(richardson_inner(h, h->pi, h->v, h->x2, std::max<int64_t>(1, o.max_iter), sync_every,
+                               &ir, &result));
+    }
+    rel = ir.converged ? 0.0 : 1.0;
+  }
+  MDP_TRY(store(h, v, result, h->S * sizeof(double)));
+  MDP_HIP(hipStreamSynchronize(h->stream));
+  if (stats) {
+    stats->inner_iters = ir.steps;
+    stats->policy_applies = ir.applies;
+    stats->refinements = ir.refinements;
+    stats->residual = rel;
+    stats->bytes = ir.bytes;
+    stats->time_ms = now_ms() - t0;
+  }
+  return ir.converged ? MDP_OK : MDP_W_MAXITER;
+}
+
+mdp_status mdp_solve(mdp_t h, const double* v0, double* v, int32_t* policy,
+                     const mdp_solve_opts* opt, mdp_stats* stats) {
+  clear_error();
+  const double t0 = now_ms();
+  if (!h) return fail(MDP_E_INVAL, "NULL handle");
+  if (!v || !policy) return fail(MDP_E_INVAL, "v and policy must be non-NULL");
+  if (!stats_ok(stats)) return fail(MDP_E_INVAL, "mdp_stats.struct_size too small");
+  mdp_solve_opts o;
+  mdp_default_solve_opts(&o);
+  if (opt) {
+    if (opt->struct_size < sizeof(mdp_solve_opts)) return fail(MDP_E_INVAL, "mdp_solve_opts.struct_size too small");
+    o = *opt;
+  }
+  if (o.inner != MDP_INNER_GMRES && o.inner != MDP_INNER_RICHARDSON) return fail(MDP_E_INVAL, "unknown inner solver");
+  if (o.restart < 1 || o.restart > kMaxRestart) return fail(MDP_E_INVAL, "restart must lie in [1,64]");
+  if (o.precision < MDP_FP64 || o.precision > MDP_MIXED_FP16) return fail(MDP_E_INVAL, "unknown precision");
+  if (o.inner == MDP_INNER_RICHARDSON && o.precision != MDP_FP64)
+    return fail(MDP_E_NOTSUP, "Richardson runs in float64 only");
+  if (!(o.alpha > 0.0 && o.alpha < 1.0)) return fail(MDP_E_INVAL, "alpha must lie in (0,1)");
+  if (!(o.atol > 0.0) || o.max_outer < 0 || o.max_inner < 1) return fail(MDP_E_INVAL, "bad tolerance or caps");
+  BusyGuard g(h);
+  if (!g.ok) return fail(MDP_E_STATE, "handle is busy");
+  stats_begin(stats);
+  const int sync_every = o.sync_every > 0 ? o.sync_every : 4;
+  const Prec iprec = prec_of(o.precision);
+  const bool gm = o.inner == MDP_INNER_GMRES;
+  if (gm) MDP_TRY(ensure_basis(h, iprec == kF64 ? kF64 : kF32, o.restart));
+  if (iprec != kF64) MDP_TRY(ensure_lowp(h, iprec));
+  MDP_TRY(load_vec(h, v0, h->v));
+  MDP_HIP(launch_ctl_reset(h, 0.0));
+
+  double alpha = o.alpha;
+  double prev_res = std::numeric_limits<double>::infinity();
+  double res = prev_res, tv_max = 0.0;
+  int64_t k = 0, sweeps = 0, inner = 0, applies = 0, refinements = 0;
+  double bytes = 0.0;
+  bool converged = false;
+  // mixed precision: low-precision sweeps until the residual is small relative to |v|
+  bool lowp_sweep = iprec != kF64;
+  double prev_lowp_res = std::numeric_limits<double>::infinity();
+  for (;;) {
+    const Prec sp = lowp_sweep ? iprec : kF64;
+    const void* vin = h->v;
+    if (sp != kF64) {
+      MDP_HIP(launch_cast_f32(h->stream, h->v, h->v32, h->S));
+      vin = h->v32;
+    }
+    const bool r0f32 = iprec != kF64;
+    void* r0 = gm ? (iprec == kF64 ? static_cast<void*>(h->U64) : static_cast<void*>(h->U32)) : nullptr;
+    double* tv_out = gm ? nullptr : h->x2;
+    MDP_HIP(launch_bellman(h, sp, vin, tv_out, h->pi, r0, r0f32, gm ? kRedGmresStart : kRedPlain, 1,
+                           alpha, floor_of(iprec)));
+    ++sweeps;
+    bytes += bytes_sweep(h, bval_of(sp), sp == kF64 ? 8 : 4, gm, r0f32 ? 4 : 8);
+    MDP_TRY(sync_ctl(h));
+    res = h->ctl_host->res_max;
+    tv_max = h->ctl_host->aux_max;
+    if (!std::isfinite(res)) return fail(MDP_E_NUMERIC, "non-finite Bellman residual");
+    if (lowp_sweep) {
+      // The low-precision sweep stops being informative once its residual
+      // nears the rounding level of the reduced-precision P (unit roundoff u_P
+      // times |v|) or stops shrinking; from then on (and for the final stop
+      // test) sweeps run in float64.  The sweep is redone at once in float64.
+      const double uP = sp == kF16 ? 4.9e-4 : 6.0e-8;
+      if (res <= std::max(1e-5, 16.0 * uP) * tv_max || res <= 10.0 * o.atol ||
+          res > 0.5 * prev_lowp_res) {
+        lowp_sweep = false;
+        continue;
+      }
+      prev_lowp_res = res;
+    }
+    if (stats && stats->history && stats->history_len < stats->history_cap)
+      stats->history[stats->history_len++] = res;
+    const bool cert_ok = o.rtol_cert <= 0.0 || res <= o.rtol_cert * (1.0 - h->gamma) * tv_max;
+    if (!lowp_sweep && res <= o.atol && cert_ok) {
+      converged = true;
+      break;
+    }
+    if (k >= o.max_outer) break;
+    if (res > prev_res) alpha = std::max(alpha * 0.5, 1e-12);  // iPI is not globally monotone
+    prev_res = res;
+    InnerResult ir;
+    if (gm) {
+      MDP_TRY(gmres_inner(h, iprec, h->pi, h->v, o.restart, o.max_inner, sync_every, alpha, &ir));
+    } else {
+      // x1 = T v_k is already in x2; continue T_pi from there
+      double* last = h->x2;
+      ir.steps = 1;
+      ir.applies = 0;
+      if (o.max_inner > 1) {
+        // the iterate x1 = T v_k sits in buffer 1 (x2); one step is done
+        MDP_HIP(launch_rich_begin(h, alpha * res, 1, 1));
+        MDP_TRY(richardson_inner(h, h->pi, h->v, h->x2, o.max_inner, sync_every, &ir, &last));
+      }
+      if (last != h->v) std::swap(h->v, h->x2);
+    }
+    inner += ir.steps;
+    applies += ir.applies;
+    refinements += ir.refinements;
+    bytes += ir.bytes;
+    ++k;
+  }
+  MDP_TRY(store(h, v, h->v, h->S * sizeof(double)));
+  MDP_TRY(store(h, policy, h->pi, h->S * sizeof(int32_t)));
+  MDP_HIP(hipStreamSynchronize(h->stream));
+  if (stats) {
+    stats->outer_iters = k;
+    stats->inner_iters = inner;
+    stats->bellman_sweeps = sweeps;
+    stats->policy_applies = applies;
+    stats->refinements = refinements;
+    stats->residual = res;
+    stats->bytes = bytes;
+    stats->time_ms = now_ms() - t0;
+  }
+  return converged ? MDP_OK : MDP_W_MAXITER;
+}
+
+mdp_status mdp_profile(mdp_t h, int32_t enable) {
+  clear_error();
+  if (!h) return fail(MDP_E_INVAL, "NULL handle");
+  BusyGuard g(h);
+  if (!g.ok) return fail(MDP_E_STATE, "handle is busy");
+  prof_resolve(h);
+  if (enable) {
+    for (int k = 0; k < MDP_NUM_KERNEL_KINDS; ++k) {
+      h->prof_launches[k] = 0;
+      h->prof_ms[k] = 0.0;
+      h->prof_bytes[k] = 0.0;
+    }
+  }
+  h->prof_on = enable != 0;
+  return MDP_OK;
+}
+
+mdp_status mdp_profile_read(mdp_t h, mdp_kernel_profile* out) {
+  clear_error();
+  if (!h || !out) return fail(MDP_E_INVAL, "NULL argument");
+  if (out->struct_size < sizeof(mdp_kernel_profile)) return fail(MDP_E_INVAL, "mdp_kernel_profile.struct_size too small");
+  BusyGuard g(h);
+  if (!g.ok) return fail(MDP_E_STATE, "handle is busy");
+  prof_resolve(h);
+  for (int k = 0; k < MDP_NUM_KERNEL_KINDS; ++k) {
+    out->launches[k] = h->prof_launches[k];
+    out->ms[k] = h->prof_ms[k];
+    out->bytes[k] = h->prof_bytes[k];
+  }
+  return MDP_OK;
+}
+
+mdp_status mdp_autotune(mdp_t h, int32_t* lanes) {
+  clear_error();
+  if (!h) return fail(MDP_E_INVAL, "NULL handle");
+  BusyGuard g(h);
+  if (!g.ok) return fail(MDP_E_STATE, "handle is busy");
+  hipEvent_t e0, e1;
+  MDP_HIP(hipEventCreate(&e0));
+  MDP_HIP(hipEventCreate(&e1));
+  MDP_HIP(hipMemsetAsync(h->io, 0, h->S * sizeof(double), h->stream));
+  float best_ms = std::numeric_limits<float>::infinity();
+  int best = h->lanes;
+  const bool prof_was = h->prof_on;
+  h->prof_on = false;
+  for (int L = 2; L <= 64; L <<= 1) {
+    h->lanes = L;
+    for (int w = 0; w < 2; ++w)
+      MDP_HIP(launch_bellman(h, kF64, h->io, h->Tv, h->pi, nullptr, false, kRedNone, 0, 0, 0));
+    MDP_HIP(hipEventRecord(e0, h->stream));
+    for (int r = 0; r < 5; ++r)
+      MDP_HIP(launch_bellman(h, kF64, h->io, h->Tv, h->pi, nullptr, false, kRedNone, 0, 0, 0));
+    MDP_HIP(hipEventRecord(e1, h->stream));
+    MDP_HIP(hipEventSynchronize(e1));
+    float ms = 0;
+    MDP_HIP(hipEventElapsedTime(&ms, e0, e1));
+    if (ms < best_ms) {
+      best_ms = ms;
+      best = L;
+    }
+  }
+  h->lanes = best;
+  h->prof_on = prof_was;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (lanes) *lanes = best;
+  return MDP_OK;
+}
+
+}  // extern "C"

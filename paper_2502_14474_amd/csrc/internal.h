@@ -1,0 +1,194 @@
+// Internal declarations shared by the host driver and the HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_fp16.h>
+
+#include <atomic>
+#include <vector>
+#include <cstdint>
+#include <string>
+
+#include "mdp.h"
+
+namespace mdp {
+
+constexpr int kBlock = 256;       // threads per workgroup (4 wavefronts of 64)
+constexpr int kWave = 64;         // CDNA wavefront width
+constexpr int kNumXcd = 8;        // MI355X: 8 accelerator complex dies, one L2 each
+constexpr int kMaxRestart = 64;   // largest GMRES restart length
+constexpr int kApplyTile = 512;   // states per workgroup in the fused Arnoldi product
+constexpr int kUpdTile = 2048;    // states per workgroup in the Arnoldi update
+
+// Device-resident control block of the inner solvers.  Kernels read and
+// write it so that the host only synchronises once per batch of steps.
+struct Ctl {
+  // --- header: the part the host copies back --------------------------------
+  double res_max;      // last reduced max |d|
+  double sumsq;        // last reduced sum d^2
+  double beta;         // 2-norm of the residual that started the current cycle
+  double tol;          // absolute stop threshold of the inner solve
+  double res_est;      // GMRES residual estimate |g_{j+1}|
+  double beta0;        // 2-norm of the first residual of the inner solve
+  double tol_cycle;    // stop threshold of the current GMRES cycle (>= tol)
+  double aux_max;      // last reduced max |Tv| (Bellman sweeps)
+  int32_t j;           // Arnoldi columns completed in the current cycle
+  int32_t done;        // nonzero: kernels of the current batch exit at once
+  int32_t converged;   // 1: tolerance met
+  int32_t breakdown;   // 1: exact Krylov breakdown
+  int32_t bad_policy;  // count of policy entries outside [0, A)
+  int32_t steps;       // inner steps executed (device count)
+  int32_t rich_cur;    // Richardson: index (0/1) of the buffer holding the iterate
+  int32_t pad0;
+  // --- Krylov state (device only) -------------------------------------------
+  double scale[kMaxRestart + 1];               // 1/||w|| of each stored basis vector
+  double hc[kMaxRestart + 1];                  // h_i * scale_i for the update
+  double g[kMaxRestart + 1];                   // rotated right-hand side
+  double cs[kMaxRestart], sn[kMaxRestart];     // Givens rotations
+  double H[(kMaxRestart + 1) * kMaxRestart];   // Hessenberg / R, column-major
+  double y[kMaxRestart];                       // least-squares solution
+};
+constexpr size_t kCtlHeaderBytes = offsetof(Ctl, scale);
+
+struct Partials {
+  double* buf;       // device scratch for per-workgroup partial results
+  size_t cap;        // doubles
+};
+
+}  // namespace mdp
+
+struct mdp_handle {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  std::atomic<int> busy{0};
+
+  int64_t S = 0;
+  int32_t A = 0;
+  int64_t rows = 0, nnz = 0;
+  double gamma = 0;
+  int32_t lanes = 16;
+
+  // CSR on the device (int32 row offsets: nnz < 2^31)
+  int32_t* row_ptr = nullptr;
+  int32_t* col = nullptr;
+  double* val = nullptr;
+  double* cost = nullptr;
+  float* val32 = nullptr;       // float32 copy
+  __half* val16 = nullptr;      // float16 copy
+  double* corr16 = nullptr;     // per-row correction 1 - sum fp16(p)
+  float* cost32 = nullptr;      // float32 costs
+
+  // float64 vectors
+  double* v = nullptr;       // current value iterate
+  double* Tv = nullptr;      // Bellman sweep output
+  double* x2 = nullptr;      // spare (Richardson ping-pong, residual)
+  double* io = nullptr;      // staging for caller vectors
+  int32_t* pi = nullptr;     // current policy
+  int32_t* pi_io = nullptr;  // staging for caller policies
+  // float32 vectors for the mixed path
+  float* v32 = nullptr;
+  float* x32a = nullptr;
+  float* x32b = nullptr;
+
+  // GMRES basis, (m+1) x ldu, in float64 and float32
+  double* U64 = nullptr;
+  float* U32 = nullptr;
+  int32_t basis_m64 = 0, basis_m32 = 0;
+  int64_t ldu = 0;
+
+  mdp::Partials part{};
+  mdp::Ctl* ctl = nullptr;        // device
+  mdp::Ctl* ctl_host = nullptr;   // pinned host mirror of the header
+
+  int64_t device_bytes = 0;
+
+  // profiler: one event pair per launch while enabled
+  struct ProfRec {
+    int kind;
+    hipEvent_t a, b;
+    double bytes;
+  };
+  bool prof_on = false;
+  std::vector<ProfRec> prof_pending;
+  std::vector<hipEvent_t> prof_pool;
+  int64_t prof_launches[MDP_NUM_KERNEL_KINDS] = {};
+  double prof_ms[MDP_NUM_KERNEL_KINDS] = {};
+  double prof_bytes[MDP_NUM_KERNEL_KINDS] = {};
+};
+
+namespace mdp {
+
+// ---- error reporting (thread-local message) --------------------------------
+mdp_status fail(mdp_status st, const std::string& msg);
+void clear_error();
+
+#define MDP_HIP(call)                                                              \
+  do {                                                                             \
+    hipError_t e_ = (call);                                                        \
+    if (e_ != hipSuccess)                                                          \
+      return ::mdp::fail(e_ == hipErrorOutOfMemory ? MDP_E_NOMEM : MDP_E_DEVICE,   \
+                         std::string(#call) + ": " + hipGetErrorString(e_));       \
+  } while (0)
+
+#define MDP_TRY(expr)                     \
+  do {                                    \
+    mdp_status s_ = (expr);               \
+    if (s_ < 0) return s_;                \
+  } while (0)
+
+// ---- kernel launchers (kernels.hip) -----------------------------------------
+// All launchers enqueue on h->stream and return hipSuccess or the launch error.
+
+enum ApplyMode { kApplyOp = 0, kApplyT = 1, kApplyRes = 2 };
+enum Prec { kF64 = 0, kF32 = 1, kF16 = 2 };
+enum ReduceMode { kRedNone = -1, kRedPlain = 0, kRedGmresStart = 1, kRedRichardson = 2 };
+
+// Rows of the Bellman sweep handled by one workgroup (whole states).
+constexpr int kSweepRows = 1024;
+inline int sweep_tile_states(int A) { return A >= kSweepRows ? 1 : kSweepRows / A; }
+size_t partials_doubles(int64_t S, int A, int m);
+
+// Algorithmic bytes of one launch (P_pi row count estimated by the mean row length).
+double bytes_sweep(const mdp_handle* h, int bval, int bv, bool r0, int br);
+double bytes_apply(const mdp_handle* h, int bval, int bx, int by);
+double bytes_arnoldi_apply(const mdp_handle* h, int bval, int bb, int j);
+double bytes_arnoldi_update(const mdp_handle* h, int bb, int j);
+
+// Profiler hooks: bracket one launch with events when h->prof_on.
+void prof_begin(mdp_handle* h, hipEvent_t* a);
+void prof_end(mdp_handle* h, int kind, hipEvent_t a, double bytes);
+void prof_resolve(mdp_handle* h);
+
+// K1 fused Bellman sweep on v (double* for kF64, float* otherwise) with the P
+// copy of `prec`.  Writes Tv (may be null), pi (may be null) and r0 = Tv - v
+// (may be null; float when r0_f32).  Then reduces max|Tv-v|, sum (Tv-v)^2 and
+// max|Tv| into ctl with the given ReduceMode (kRedGmresStart starts a GMRES
+// cycle from r0; first_cycle fixes the inner tolerance alpha*||r0||_2).
+hipError_t launch_bellman(mdp_handle* h, Prec prec, const void* v, double* Tv, int32_t* pi,
+                          void* r0, bool r0_f32, int red_mode, int first_cycle, double alpha,
+                          double floor_rel);
+
+// K2/K3/K10 float64 policy products (see ApplyMode); y is float when y_f32.
+hipError_t launch_apply(mdp_handle* h, int mode, const int32_t* pi, const double* x, void* y,
+                        bool y_f32, int red_mode, int first_cycle, double alpha,
+                        double floor_rel);
+
+// Richardson step on the ping-pong pair, early-exiting on ctl->done.
+hipError_t launch_richardson_step(mdp_handle* h, const int32_t* pi, double* buf0, double* buf1);
+
+// One Arnoldi step j (product + Gram-Schmidt + norm + Givens), early-exiting.
+hipError_t launch_arnoldi_step(mdp_handle* h, Prec prec, const int32_t* pi, int j, int m);
+
+// x += V y over the completed columns of the current cycle.
+hipError_t launch_gmres_update_x(mdp_handle* h, Prec prec, double* x);
+
+hipError_t launch_check_policy(mdp_handle* h, const int32_t* pi);
+hipError_t launch_ctl_reset(mdp_handle* h, double tol);
+// Richardson start: tolerance, index of the buffer holding the iterate, steps done.
+hipError_t launch_rich_begin(mdp_handle* h, double tol, int cur, int steps);
+hipError_t launch_build_lowp(mdp_handle* h, int which);
+hipError_t launch_cast_f32(hipStream_t st, const double* src, float* dst, int64_t n);
+hipError_t launch_i64_to_i32(hipStream_t st, const int64_t* src, int32_t* dst, int64_t n);
+
+}  // namespace mdp

@@ -1,0 +1,983 @@
+// HIP kernels of the inexact-policy-iteration hot path (gfx950).
+//
+// The path is a memory-bound sparse contraction (about 2 flops per 12 bytes
+// of CSR data), so none of it uses MFMA.  What matters is streaming the CSR
+// value and column arrays once, coalesced, with enough loads in flight, while
+// the gathered vector stays in L2 / Infinity Cache:
+//   * L lanes of a 64-wide wavefront share one CSR row; lane l takes the row's
+//     entries l, l+L, l+2L, ... and the L partial sums meet in an xor
+//     butterfly.  The summation order of a row is therefore a fixed function of
+//     positions inside the row, so identical rows give bitwise identical
+//     results and the Bellman sweep and the policy products agree bit for bit.
+//   * every group keeps U rows in flight (their first entries are loaded
+//     before any gather is consumed);
+//   * the value and column streams use non-temporal loads so that they do not
+//     evict the gathered vector;
+//   * workgroups are remapped so that each of the 8 XCDs (one L2 each) works
+//     on a contiguous range of states, keeping banded gathers XCD-local;
+//   * every reduction is a fixed-order two-stage reduction (per-workgroup
+//     partials, then one small kernel), so results are deterministic.
+#include "internal.h"
+
+#include <cmath>
+
+namespace mdp {
+
+// ----------------------------------------------------------------------------
+// helpers
+// ----------------------------------------------------------------------------
+
+__device__ __forceinline__ int xcd_tile(int bid, int nb) {
+  // Workgroups are dispatched round-robin over the XCDs; give XCD x the
+  // contiguous tile range [x*base + min(x, rem), ...).
+  const int q = bid / kNumXcd, x = bid - q * kNumXcd;
+  const int base = nb / kNumXcd, rem = nb - base * kNumXcd;
+  return x * base + (x < rem ? x : rem) + q;
+}
+
+__device__ __forceinline__ double ld_val(const double* p) { return __builtin_nontemporal_load(p); }
+__device__ __forceinline__ float ld_val(const float* p) { return __builtin_nontemporal_load(p); }
+__device__ __forceinline__ float ld_val(const __half* p) {
+  const unsigned short b = __builtin_nontemporal_load(reinterpret_cast<const unsigned short*>(p));
+  return __half2float(__ushort_as_half(b));
+}
+__device__ __forceinline__ int ld_col(const int* p) { return __builtin_nontemporal_load(p); }
+
+__device__ __forceinline__ double max_nan(double a, double b) {
+  if (a != a) return a;
+  if (b != b) return b;
+  return a > b ? a : b;
+}
+
+template <int L, typename T>
+__device__ __forceinline__ T group_sum(T v) {
+#pragma unroll
+  for (int off = L / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+  return v;
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+  for (int off = kWave / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+  return v;
+}
+
+__device__ __forceinline__ double wave_max_nan(double v) {
+#pragma unroll
+  for (int off = kWave / 2; off > 0; off >>= 1) v = max_nan(v, __shfl_xor(v, off, kWave));
+  return v;
+}
+
+// (max, sum) over the workgroup; the result is valid in thread 0.
+__device__ __forceinline__ void block_max_sum(double& mx, double& sm) {
+  __shared__ double s_mx[kBlock / kWave], s_sm[kBlock / kWave];
+  mx = wave_max_nan(mx);
+  sm = wave_sum(sm);
+  const int w = threadIdx.x / kWave;
+  if ((threadIdx.x & (kWave - 1)) == 0) {
+    s_mx[w] = mx;
+    s_sm[w] = sm;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    mx = s_mx[0];
+    sm = s_sm[0];
+#pragma unroll
+    for (int i = 1; i < kBlock / kWave; ++i) {
+      mx = max_nan(mx, s_mx[i]);
+      sm += s_sm[i];
+    }
+  }
+  __syncthreads();
+}
+
+// Dot products of U rows held by one lane group (see the file comment).
+// st/en: entry range of each row (empty when st == en).  CORR additionally
+// sums the gathered x over the row (float16 row-sum correction).
+template <int L, int U, typename VT, typename XT, typename AT, bool CORR>
+__device__ __forceinline__ void rows_dot(const int (&st)[U], const int (&en)[U], int lane,
+                                         const int* __restrict__ col,
+                                         const VT* __restrict__ val,
+                                         const XT* __restrict__ x, AT (&acc)[U], AT (&xs)[U]) {
+  int c[U];
+  AT p[U];
+  bool ok[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int e = st[u] + lane;
+    ok[u] = e < en[u];
+    c[u] = ok[u] ? ld_col(col + e) : 0;
+    p[u] = ok[u] ? static_cast<AT>(ld_val(val + e)) : AT(0);
+  }
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const AT xv = ok[u] ? static_cast<AT>(x[c[u]]) : AT(0);
+    acc[u] = ok[u] ? fma(p[u], xv, AT(0)) : AT(0);
+    if (CORR) xs[u] = xv;
+  }
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    for (int e = st[u] + lane + L; e < en[u]; e += L) {
+      const AT xv = static_cast<AT>(x[ld_col(col + e)]);
+      acc[u] = fma(static_cast<AT>(ld_val(val + e)), xv, acc[u]);
+      if (CORR) xs[u] += xv;
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    acc[u] = group_sum<L>(acc[u]);
+    if (CORR) xs[u] = group_sum<L>(xs[u]);
+  }
+}
+
+// P[r,:] x for the row r, in the accumulation type; with the float16 copy the
+// row-sum correction c_r * mean_j x_j is added.
+template <bool CORR, typename AT>
+__device__ __forceinline__ AT row_value(AT acc, AT xs, const double* __restrict__ corr, int r,
+                                        int len) {
+  if (CORR) return acc + static_cast<AT>(corr[r]) * (xs / static_cast<AT>(len));
+  return acc;
+}
+
+template <typename T> struct Acc { using type = float; };
+template <> struct Acc<double> { using type = double; };
+
+// ----------------------------------------------------------------------------
+// K1: fused Bellman sweep
+// ----------------------------------------------------------------------------
+// Workgroup = tile of `tile_states` states (all A rows of each).  Phase 1: lane
+// groups compute Q(s,a) = g(s,a) + gamma * (P v)(s,a) into LDS.  Phase 2: one
+// thread per state takes the minimum over a = 0..A-1 with a strict '<' (lowest
+// action wins ties), writes Tv, pi and r0 = Tv - v, and accumulates
+// max|Tv - v| and sum (Tv - v)^2 into this workgroup's partials.
+template <int L, int U, typename VT, typename XT, bool CORR, typename RT>
+__global__ __launch_bounds__(kBlock) void k_bellman(
+    int64_t S, int A, int tile_states, const int* __restrict__ row_ptr,
+    const int* __restrict__ col, const VT* __restrict__ val, const double* __restrict__ corr,
+    const double* __restrict__ cost, const XT* __restrict__ v, double gamma,
+    double* __restrict__ Tv, int* __restrict__ pi, RT* __restrict__ r0,
+    double4* __restrict__ partials) {
+  using AT = typename Acc<XT>::type;
+  extern __shared__ unsigned char lds_raw[];
+  AT* q = reinterpret_cast<AT*>(lds_raw);
+  constexpr int G = kBlock / L;
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  const int64_t s0 = static_cast<int64_t>(tile) * tile_states;
+  const int ns = static_cast<int>(min<int64_t>(tile_states, S - s0));
+  const int nrows = ns * A;
+  const int64_t row0 = s0 * A;
+  const int g = threadIdx.x / L, lane = threadIdx.x % L;
+  const AT gam = static_cast<AT>(gamma);
+
+  for (int base = 0; base < nrows; base += G * U) {
+    int st[U], en[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int rr = base + g + u * G;
+      if (rr < nrows) {
+        st[u] = row_ptr[row0 + rr];
+        en[u] = row_ptr[row0 + rr + 1];
+      } else {
+        st[u] = en[u] = 0;
+      }
+    }
+    AT acc[U], xs[U];
+    rows_dot<L, U, VT, XT, AT, CORR>(st, en, lane, col, val, v, acc, xs);
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int rr = base + g + u * G;
+      if (rr < nrows && lane == 0) {
+        const AT pv = row_value<CORR, AT>(acc[u], xs[u], corr, static_cast<int>(row0 + rr),
+                                           en[u] - st[u]);
+        q[rr] = fma(gam, pv, static_cast<AT>(cost[row0 + rr]));
+      }
+    }
+  }
+  __syncthreads();
+
+  double dmax = 0.0, dsum = 0.0, tmax = 0.0;
+  for (int t = threadIdx.x; t < ns; t += kBlock) {
+    const int64_t s = s0 + t;
+    const AT* qs = q + t * A;
+    AT best = qs[0];
+    int arg = 0;
+    bool nan = best != best;
+    for (int a = 1; a < A; ++a) {
+      const AT qa = qs[a];
+      nan |= qa != qa;
+      if (qa < best) {
+        best = qa;
+        arg = a;
+      }
+    }
+    const double tv = nan ? NAN : static_cast<double>(best);
+    if (Tv) Tv[s] = tv;
+    if (pi) pi[s] = arg;
+    const double d = tv - static_cast<double>(v[s]);
+    if (r0) r0[s] = static_cast<RT>(d);
+    dmax = max_nan(dmax, fabs(d));
+    dsum = fma(d, d, dsum);
+    tmax = max_nan(tmax, fabs(tv));
+  }
+  block_max_sum(dmax, dsum);
+  double tm2 = 0.0;
+  block_max_sum(tmax, tm2);
+  if (threadIdx.x == 0) partials[tile] = make_double4(dmax, dsum, tmax, 0.0);
+}
+
+// ----------------------------------------------------------------------------
+// K2/K3/K10: products with P_pi, gathering rows s*A + pi(s)
+// ----------------------------------------------------------------------------
+// MODE kApplyOp : y = x - gamma P_pi x
+// MODE kApplyT  : y = g_pi + gamma P_pi x, partials (max|y - x|, sum (y-x)^2)
+// MODE kApplyRes: y = g_pi - (x - gamma P_pi x), partials (max|y|, sum y^2)
+// Each workgroup owns kApplyTile consecutive states.
+template <int L, int U, int MODE, typename VT, typename XT, typename YT, bool CORR>
+__global__ __launch_bounds__(kBlock) void k_policy_apply(
+    int64_t S, int A, const int* __restrict__ row_ptr, const int* __restrict__ col,
+    const VT* __restrict__ val, const double* __restrict__ corr,
+    const double* __restrict__ cost, const int* __restrict__ pi, const XT* __restrict__ x,
+    double gamma, YT* __restrict__ y, double4* __restrict__ partials,
+    const Ctl* __restrict__ ctl, const int* __restrict__ cur /* Richardson ping-pong or null */,
+    const XT* __restrict__ x_alt, YT* __restrict__ y_alt) {
+  using AT = typename Acc<XT>::type;
+  if (ctl && ctl->done) return;
+  if (cur && *cur) {  // Richardson: odd steps read the second buffer
+    const XT* t = x_alt;
+    x_alt = x;
+    x = t;
+    YT* u = y_alt;
+    y_alt = y;
+    y = u;
+  }
+  constexpr int G = kBlock / L;
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  const int64_t s0 = static_cast<int64_t>(tile) * kApplyTile;
+  const int ns = static_cast<int>(min<int64_t>(kApplyTile, S - s0));
+  const int g = threadIdx.x / L, lane = threadIdx.x % L;
+  const AT gam = static_cast<AT>(gamma);
+  double dmax = 0.0, dsum = 0.0;
+
+  for (int base = 0; base < ns; base += G * U) {
+    int st[U], en[U], rw[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int ss = base + g + u * G;
+      if (ss < ns) {
+        const int64_t s = s0 + ss;
+        rw[u] = static_cast<int>(s * A + pi[s]);
+        st[u] = row_ptr[rw[u]];
+        en[u] = row_ptr[rw[u] + 1];
+      } else {
+        rw[u] = 0;
+        st[u] = en[u] = 0;
+      }
+    }
+    AT acc[U], xs[U];
+    rows_dot<L, U, VT, XT, AT, CORR>(st, en, lane, col, val, x, acc, xs);
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int ss = base + g + u * G;
+      if (ss < ns && lane == 0) {
+        const int64_t s = s0 + ss;
+        const AT pv = row_value<CORR, AT>(acc[u], xs[u], corr, rw[u], en[u] - st[u]);
+        const AT xs_own = static_cast<AT>(x[s]);
+        if (MODE == kApplyOp) {
+          y[s] = static_cast<YT>(xs_own - gam * pv);
+        } else if (MODE == kApplyT) {
+          const AT yv = fma(gam, pv, static_cast<AT>(cost[rw[u]]));
+          y[s] = static_cast<YT>(yv);
+          const double d = static_cast<double>(yv) - static_cast<double>(xs_own);
+          dmax = max_nan(dmax, fabs(d));
+          dsum = fma(d, d, dsum);
+        } else {
+          const double r = cost[rw[u]] - (static_cast<double>(xs_own) -
+                                          static_cast<double>(gam) * static_cast<double>(pv));
+          y[s] = static_cast<YT>(r);
+          dmax = max_nan(dmax, fabs(r));
+          dsum = fma(r, r, dsum);
+        }
+      }
+    }
+  }
+  if (MODE != kApplyOp) {
+    block_max_sum(dmax, dsum);
+    if (threadIdx.x == 0) partials[tile] = make_double4(dmax, dsum, 0.0, 0.0);
+  }
+}
+
+// ----------------------------------------------------------------------------
+// GMRES kernels (K4-K7) on (I - gamma P_pi)
+// ----------------------------------------------------------------------------
+// Basis vectors are stored unnormalised: column i of the orthonormal basis is
+// ctl->scale[i] * U_i.  That lets the normalisation of a new vector ride on the
+// next pass instead of costing a pass of its own.
+
+// K2+K4: w = scale_j * (I - gamma P_pi) U_j stored into U_{j+1}, and the
+// workgroup's partial dot products sum_s U_i[s] w[s], i = 0..j (classical
+// Gram-Schmidt, one pass over the basis).  partials[i * nb + tile].
+template <int L, int U, typename VT, typename BT, bool CORR>
+__global__ __launch_bounds__(kBlock) void k_arnoldi_apply(
+    int64_t S, int A, const int* __restrict__ row_ptr, const int* __restrict__ col,
+    const VT* __restrict__ val, const double* __restrict__ corr, const int* __restrict__ pi,
+    BT* __restrict__ Ub, int64_t ldu, int j, double gamma, const Ctl* __restrict__ ctl,
+    double* __restrict__ partials) {
+  using AT = typename Acc<BT>::type;
+  if (ctl->done) return;
+  __shared__ double w_lds[kApplyTile];
+  __shared__ double red[kBlock / kWave][8];
+  constexpr int G = kBlock / L;
+  const int nb = gridDim.x;
+  const int tile = xcd_tile(blockIdx.x, nb);
+  const int64_t s0 = static_cast<int64_t>(tile) * kApplyTile;
+  const int ns = static_cast<int>(min<int64_t>(kApplyTile, S - s0));
+  const int g = threadIdx.x / L, lane = threadIdx.x % L;
+  const AT gam = static_cast<AT>(gamma);
+  const BT* __restrict__ xj = Ub + static_cast<int64_t>(j) * ldu;
+  BT* __restrict__ w = Ub + static_cast<int64_t>(j + 1) * ldu;
+  const double cj = ctl->scale[j];
+
+  for (int base = 0; base < ns; base += G * U) {
+    int st[U], en[U], rw[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int ss = base + g + u * G;
+      if (ss < ns) {
+        const int64_t s = s0 + ss;
+        rw[u] = static_cast<int>(s * A + pi[s]);
+        st[u] = row_ptr[rw[u]];
+        en[u] = row_ptr[rw[u] + 1];
+      } else {
+        rw[u] = 0;
+        st[u] = en[u] = 0;
+      }
+    }
+    AT acc[U], xs[U];
+    rows_dot<L, U, VT, BT, AT, CORR>(st, en, lane, col, val, xj, acc, xs);
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int ss = base + g + u * G;
+      if (ss < ns && lane == 0) {
+        const int64_t s = s0 + ss;
+        const AT pv = row_value<CORR, AT>(acc[u], xs[u], corr, rw[u], en[u] - st[u]);
+        const AT av = static_cast<AT>(xj[s]) - gam * pv;
+        const BT wv = static_cast<BT>(cj * static_cast<double>(av));
+        w[s] = wv;
+        w_lds[ss] = static_cast<double>(wv);
+      }
+    }
+  }
+  __syncthreads();
+
+  const int wv_id = threadIdx.x / kWave;
+  for (int i0 = 0; i0 <= j; i0 += 8) {
+    double a8[8];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) a8[c] = 0.0;
+    for (int t = threadIdx.x; t < ns; t += kBlock) {
+      const double wt = w_lds[t];
+      const int64_t s = s0 + t;
+#pragma unroll
+      for (int c = 0; c < 8; ++c)
+        if (i0 + c <= j)
+          a8[c] = fma(static_cast<double>(Ub[static_cast<int64_t>(i0 + c) * ldu + s]), wt, a8[c]);
+    }
+#pragma unroll
+    for (int c = 0; c < 8; ++c) a8[c] = wave_sum(a8[c]);
+    if ((threadIdx.x & (kWave - 1)) == 0) {
+#pragma unroll
+      for (int c = 0; c < 8; ++c) red[wv_id][c] = a8[c];
+    }
+    __syncthreads();
+    if (threadIdx.x < 8 && i0 + static_cast<int>(threadIdx.x) <= j) {
+      double sum = red[0][threadIdx.x];
+#pragma unroll
+      for (int k = 1; k < kBlock / kWave; ++k) sum += red[k][threadIdx.x];
+      partials[static_cast<int64_t>(i0 + threadIdx.x) * nb + tile] = sum;
+    }
+    __syncthreads();
+  }
+}
+
+// Reduce column i (= blockIdx.x) of the dot partials: H[i, j] = scale_i * sum.
+__global__ __launch_bounds__(kBlock) void k_reduce_dots(const double* __restrict__ partials,
+                                                        int nb, int j, Ctl* __restrict__ ctl) {
+  if (ctl->done) return;
+  const int i = blockIdx.x;
+  double s = 0.0;
+  for (int b = threadIdx.x; b < nb; b += kBlock) s += partials[static_cast<int64_t>(i) * nb + b];
+  double mx = 0.0;
+  block_max_sum(mx, s);
+  if (threadIdx.x == 0) {
+    const double h = ctl->scale[i] * s;
+    ctl->H[i + j * (kMaxRestart + 1)] = h;
+    ctl->hc[i] = h * ctl->scale[i];
+  }
+}
+
+// K5: w <- w - sum_{i<=j} hc_i U_i, with the workgroup's partial ||w||^2.
+template <typename BT>
+__global__ __launch_bounds__(kBlock) void k_arnoldi_update(int64_t S, BT* __restrict__ Ub,
+                                                           int64_t ldu, int j,
+                                                           const Ctl* __restrict__ ctl,
+                                                           double* __restrict__ partials) {
+  if (ctl->done) return;
+  __shared__ double hc[kMaxRestart + 1];
+  if (threadIdx.x <= j) hc[threadIdx.x] = ctl->hc[threadIdx.x];
+  __syncthreads();
+  constexpr int K = kUpdTile / kBlock;
+  const int64_t s0 = static_cast<int64_t>(blockIdx.x) * kUpdTile + threadIdx.x;
+  BT* __restrict__ w = Ub + static_cast<int64_t>(j + 1) * ldu;
+  double acc[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int64_t s = s0 + k * kBlock;
+    acc[k] = s < S ? static_cast<double>(w[s]) : 0.0;
+  }
+  for (int i = 0; i <= j; ++i) {
+    const double c = -hc[i];
+    const BT* __restrict__ ui = Ub + static_cast<int64_t>(i) * ldu;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const int64_t s = s0 + k * kBlock;
+      if (s < S) acc[k] = fma(c, static_cast<double>(ui[s]), acc[k]);
+    }
+  }
+  double sq = 0.0;
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int64_t s = s0 + k * kBlock;
+    if (s < S) {
+      const BT wv = static_cast<BT>(acc[k]);
+      w[s] = wv;
+      const double wd = static_cast<double>(wv);
+      sq = fma(wd, wd, sq);
+    }
+  }
+  double mx = 0.0;
+  block_max_sum(mx, sq);
+  if (threadIdx.x == 0) partials[blockIdx.x] = sq;
+}
+
+// Back substitution R y = g for the first n columns (single thread).
+__device__ void backsolve(Ctl* ctl, int n) {
+  for (int i = n - 1; i >= 0; --i) {
+    double t = ctl->g[i];
+    for (int k = i + 1; k < n; ++k) t -= ctl->H[i + k * (kMaxRestart + 1)] * ctl->y[k];
+    ctl->y[i] = t / ctl->H[i + i * (kMaxRestart + 1)];
+  }
+}
+
+// K6: ||w|| from the partials, then the Givens update of column j, the
+// residual estimate and the stop decision.  One workgroup.
+__global__ __launch_bounds__(kBlock) void k_norm_givens(const double* __restrict__ partials,
+                                                        int nb, int j, int m,
+                                                        Ctl* __restrict__ ctl) {
+  if (ctl->done) return;
+  double s = 0.0;
+  for (int b = threadIdx.x; b < nb; b += kBlock) s += partials[b];
+  double mx = 0.0;
+  block_max_sum(mx, s);
+  if (threadIdx.x != 0) return;
+  const int ld = kMaxRestart + 1;
+  double* h = ctl->H + j * ld;
+  const double hn = sqrt(s);
+  // size of the column before orthogonalisation, for the breakdown test
+  double colnorm2 = hn * hn;
+  for (int i = 0; i <= j; ++i) colnorm2 += h[i] * h[i];
+  for (int i = 0; i < j; ++i) {
+    const double t = ctl->cs[i] * h[i] + ctl->sn[i] * h[i + 1];
+    h[i + 1] = -ctl->sn[i] * h[i] + ctl->cs[i] * h[i + 1];
+    h[i] = t;
+  }
+  const double a = h[j], b = hn;
+  const double r = hypot(a, b);
+  double c = 1.0, sn = 0.0;
+  if (r > 0.0) {
+    c = a / r;
+    sn = b / r;
+  }
+  ctl->cs[j] = c;
+  ctl->sn[j] = sn;
+  h[j] = r;
+  h[j + 1] = 0.0;
+  const double gj = ctl->g[j];
+  ctl->g[j + 1] = -sn * gj;
+  ctl->g[j] = c * gj;
+  const double est = fabs(ctl->g[j + 1]);
+  ctl->res_est = est;
+  ctl->steps += 1;
+  const bool brk = !(hn > 1e-14 * sqrt(colnorm2));
+  ctl->scale[j + 1] = brk ? 0.0 : 1.0 / hn;
+  const int n = j + 1;
+  ctl->j = n;
+  int done = 0;
+  if (est <= ctl->tol_cycle) done = 1;
+  if (est <= ctl->tol) ctl->converged = 1;
+  if (brk) {
+    ctl->breakdown = 1;
+    done = 1;
+  }
+  if (n >= m) done = 1;
+  if (!(est == est)) done = 1;
+  if (done) {
+    backsolve(ctl, n);
+    ctl->done = 1;
+  }
+}
+
+// K7: x += sum_{i < n} y_i scale_i U_i for the n = ctl->j completed columns.
+template <typename BT, typename XT>
+__global__ __launch_bounds__(kBlock) void k_gmres_update_x(int64_t S, XT* __restrict__ x,
+                                                           const BT* __restrict__ Ub,
+                                                           int64_t ldu,
+                                                           const Ctl* __restrict__ ctl) {
+  const int n = ctl->j;
+  if (n == 0) return;
+  __shared__ double coef[kMaxRestart];
+  if (threadIdx.x < n) coef[threadIdx.x] = ctl->y[threadIdx.x] * ctl->scale[threadIdx.x];
+  __syncthreads();
+  constexpr int K = kUpdTile / kBlock;
+  const int64_t s0 = static_cast<int64_t>(blockIdx.x) * kUpdTile + threadIdx.x;
+  double d[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) d[k] = 0.0;
+  for (int i = 0; i < n; ++i) {
+    const double c = coef[i];
+    const BT* __restrict__ ui = Ub + static_cast<int64_t>(i) * ldu;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const int64_t s = s0 + k * kBlock;
+      if (s < S) d[k] = fma(c, static_cast<double>(ui[s]), d[k]);
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int64_t s = s0 + k * kBlock;
+    if (s < S) x[s] = static_cast<XT>(static_cast<double>(x[s]) + d[k]);
+  }
+}
+
+// ----------------------------------------------------------------------------
+// reductions of (max, sum) partials and the control-block transitions
+// ----------------------------------------------------------------------------
+
+
+__global__ __launch_bounds__(kBlock) void k_reduce_ms(const double4* __restrict__ partials,
+                                                      int nb, int mode, int first_cycle,
+                                                      double alpha, double floor_rel,
+                                                      Ctl* __restrict__ ctl) {
+  if (mode == kRedRichardson && ctl->done) return;
+  double mx = 0.0, sm = 0.0, am = 0.0, unused = 0.0;
+  for (int b = threadIdx.x; b < nb; b += kBlock) {
+    const double4 p = partials[b];
+    mx = max_nan(mx, p.x);
+    sm += p.y;
+    am = max_nan(am, p.z);
+  }
+  block_max_sum(mx, sm);
+  block_max_sum(am, unused);
+  if (threadIdx.x != 0) return;
+  ctl->res_max = mx;
+  ctl->sumsq = sm;
+  ctl->aux_max = am;
+  if (mode == kRedGmresStart) {
+    const double beta = sqrt(sm);
+    ctl->beta = beta;
+    if (first_cycle) {
+      ctl->beta0 = beta;
+      ctl->tol = alpha * beta;
+      ctl->steps = 0;
+      ctl->converged = 0;
+    }
+    // a cycle never asks for more relative reduction than its arithmetic can
+    // give (floor_rel > 0 for float32 Arnoldi steps); float64 restarts catch up
+    const double tol_cycle = fmax(ctl->tol, floor_rel * beta);
+    ctl->res_est = beta;
+    ctl->g[0] = beta;
+    ctl->scale[0] = beta > 0.0 ? 1.0 / beta : 0.0;
+    ctl->j = 0;
+    ctl->breakdown = 0;
+    ctl->done = 0;
+    if (!(beta > tol_cycle)) {
+      ctl->done = 1;
+      if (beta <= ctl->tol) ctl->converged = 1;
+    }
+    ctl->tol_cycle = tol_cycle;
+  } else if (mode == kRedRichardson) {
+    if (first_cycle) ctl->tol = alpha * mx;
+    ctl->steps += 1;
+    ctl->rich_cur ^= 1;
+    ctl->res_est = mx;
+    if (mx <= ctl->tol || !(mx == mx)) {
+      ctl->done = 1;
+      ctl->converged = mx <= ctl->tol ? 1 : 0;
+    }
+  }
+}
+
+__global__ void k_ctl_reset(Ctl* ctl, double tol) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    ctl->res_max = 0.0;
+    ctl->sumsq = 0.0;
+    ctl->beta = 0.0;
+    ctl->tol = tol;
+    ctl->res_est = 0.0;
+    ctl->beta0 = 0.0;
+    ctl->tol_cycle = tol;
+    ctl->aux_max = 0.0;
+    ctl->j = 0;
+    ctl->done = 0;
+    ctl->converged = 0;
+    ctl->breakdown = 0;
+    ctl->bad_policy = 0;
+    ctl->steps = 0;
+    ctl->rich_cur = 0;
+    ctl->pad0 = 0;
+  }
+}
+
+__global__ void k_rich_begin(Ctl* ctl, double tol, int cur, int steps) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    ctl->tol = tol;
+    ctl->rich_cur = cur;
+    ctl->steps = steps;
+    ctl->converged = 0;
+    ctl->done = 0;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_check_policy(int64_t S, int A,
+                                                         const int* __restrict__ pi,
+                                                         Ctl* __restrict__ ctl) {
+  const int64_t s = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+  int bad = 0;
+  if (s < S) bad = (pi[s] < 0 || pi[s] >= A) ? 1 : 0;
+  bad = wave_sum(bad);
+  if ((threadIdx.x & (kWave - 1)) == 0 && bad) atomicAdd(&ctl->bad_policy, bad);
+}
+
+// ----------------------------------------------------------------------------
+// K9: reduced-precision copies of P, and casts
+// ----------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_to_f32(const double* __restrict__ a,
+                                                   float* __restrict__ b, int64_t n) {
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * kBlock)
+    b[i] = static_cast<float>(a[i]);
+}
+
+// IEEE binary64 -> binary16 with round-to-nearest-even, taken directly from
+// the binary64 bits (no intermediate float32 rounding).
+__device__ __forceinline__ unsigned short f64_to_f16_bits(double x) {
+  unsigned long long b = static_cast<unsigned long long>(__double_as_longlong(x));
+  const unsigned short sign = static_cast<unsigned short>((b >> 48) & 0x8000u);
+  b &= 0x7FFFFFFFFFFFFFFFull;
+  const int e = static_cast<int>(b >> 52);
+  const unsigned long long frac = b & ((1ull << 52) - 1);
+  if (e == 0x7FF) return sign | 0x7C00u | (frac ? 0x200u : 0u);
+  if (e == 0) return sign;  // binary64 subnormals are far below the binary16 range
+  const int E = e - 1023;
+  if (E > 15) return sign | 0x7C00u;
+  const unsigned long long mant = frac | (1ull << 52);
+  const int shift = E >= -14 ? 42 : 28 - E;
+  if (shift >= 54) return sign;
+  unsigned long long q = mant >> shift;
+  const unsigned long long rem = mant & ((1ull << shift) - 1);
+  const unsigned long long half = 1ull << (shift - 1);
+  if (rem > half || (rem == half && (q & 1ull))) ++q;
+  if (E >= -14) {
+    int Eo = E;
+    if (q == (1ull << 11)) {
+      q >>= 1;
+      ++Eo;
+    }
+    if (Eo + 15 >= 31) return sign | 0x7C00u;
+    return sign | static_cast<unsigned short>(((Eo + 15) << 10) | (q & 0x3FFu));
+  }
+  return sign | static_cast<unsigned short>(q);  // q == 0x400 is the smallest normal
+}
+
+// One thread per row: float16 values (round to nearest even) and the row
+// correction c_r = 1 - sum_j double(fp16(p_rj)) summed in entry order.
+__global__ __launch_bounds__(kBlock) void k_to_f16_rows(int64_t rows,
+                                                        const int* __restrict__ row_ptr,
+                                                        const double* __restrict__ a,
+                                                        __half* __restrict__ h,
+                                                        double* __restrict__ corr) {
+  for (int64_t r = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; r < rows;
+       r += static_cast<int64_t>(gridDim.x) * kBlock) {
+    double sum = 0.0;
+    for (int e = row_ptr[r]; e < row_ptr[r + 1]; ++e) {
+      const __half hv = __ushort_as_half(f64_to_f16_bits(a[e]));
+      h[e] = hv;
+      sum += static_cast<double>(__half2float(hv));
+    }
+    corr[r] = 1.0 - sum;
+  }
+}
+
+}  // namespace mdp
+
+namespace mdp {
+
+__global__ __launch_bounds__(kBlock) void k_i64_to_i32(const int64_t* __restrict__ a,
+                                                       int32_t* __restrict__ b, int64_t n) {
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * kBlock)
+    b[i] = static_cast<int32_t>(a[i]);
+}
+
+// ----------------------------------------------------------------------------
+// launchers
+// ----------------------------------------------------------------------------
+namespace {
+
+// Event pair around one launch while the handle's profiler is on.
+struct Prof {
+  mdp_handle* h;
+  int kind;
+  double bytes;
+  hipEvent_t a;
+  Prof(mdp_handle* hh, int k, double b) : h(hh), kind(k), bytes(b) { prof_begin(h, &a); }
+  ~Prof() { prof_end(h, kind, a, bytes); }
+};
+
+template <int L> constexpr int rows_in_flight() { return L >= 32 ? 2 : 4; }
+
+template <typename F>
+hipError_t with_lanes(int L, F&& f) {
+  switch (L) {
+    case 2: return f(std::integral_constant<int, 2>{});
+    case 4: return f(std::integral_constant<int, 4>{});
+    case 8: return f(std::integral_constant<int, 8>{});
+    case 16: return f(std::integral_constant<int, 16>{});
+    case 32: return f(std::integral_constant<int, 32>{});
+    case 64: return f(std::integral_constant<int, 64>{});
+    default: return hipErrorInvalidValue;
+  }
+}
+
+inline int grid_for(int64_t n, int per) { return static_cast<int>((n + per - 1) / per); }
+inline int grid_stride(int64_t n) {
+  const int64_t g = (n + kBlock - 1) / kBlock;
+  return static_cast<int>(g < 8192 ? (g > 0 ? g : 1) : 8192);
+}
+
+hipError_t reduce_into_ctl(mdp_handle* h, int nb, int red_mode, int first_cycle, double alpha,
+                           double floor_rel) {
+  if (red_mode == kRedNone) return hipSuccess;
+  Prof pf(h, MDP_K_REDUCE, 0.0);
+  k_reduce_ms<<<1, kBlock, 0, h->stream>>>(reinterpret_cast<const double4*>(h->part.buf), nb,
+                                            red_mode, first_cycle, alpha, floor_rel, h->ctl);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+size_t partials_doubles(int64_t S, int A, int m) {
+  const int64_t nb_sweep = (S + sweep_tile_states(A) - 1) / sweep_tile_states(A);
+  const int64_t nb_apply = (S + kApplyTile - 1) / kApplyTile;
+  const int64_t nb_upd = (S + kUpdTile - 1) / kUpdTile;
+  int64_t need = 4 * nb_sweep;
+  need = need > 4 * nb_apply ? need : 4 * nb_apply;
+  need = need > (m + 1) * nb_apply ? need : (m + 1) * nb_apply;
+  need = need > nb_upd ? need : nb_upd;
+  return static_cast<size_t>(need);
+}
+
+hipError_t launch_bellman(mdp_handle* h, Prec prec, const void* v, double* Tv, int32_t* pi,
+                          void* r0, bool r0_f32, int red_mode, int first_cycle, double alpha,
+                          double floor_rel) {
+  const int ts = sweep_tile_states(h->A);
+  const int nb = grid_for(h->S, ts);
+  auto* part = reinterpret_cast<double4*>(h->part.buf);
+  hipError_t e;
+  {
+    Prof pf(h, MDP_K_BELLMAN, bytes_sweep(h, prec == kF64 ? 8 : (prec == kF32 ? 4 : 2), prec == kF64 ? 8 : 4, r0 != nullptr, r0_f32 ? 4 : 8) + (prec == kF16 ? h->rows * 8.0 : 0.0));
+    e = with_lanes(h->lanes, [&](auto Lc) -> hipError_t {
+    constexpr int L = decltype(Lc)::value;
+    constexpr int U = rows_in_flight<L>();
+    if (prec == kF64) {
+      const size_t lds = static_cast<size_t>(ts) * h->A * sizeof(double);
+      if (r0_f32)
+        k_bellman<L, U, double, double, false, float><<<nb, kBlock, lds, h->stream>>>(
+            h->S, h->A, ts, h->row_ptr, h->col, h->val, nullptr, h->cost,
+            static_cast<const double*>(v), h->gamma, Tv, pi, static_cast<float*>(r0), part);
+      else
+        k_bellman<L, U, double, double, false, double><<<nb, kBlock, lds, h->stream>>>(
+            h->S, h->A, ts, h->row_ptr, h->col, h->val, nullptr, h->cost,
+            static_cast<const double*>(v), h->gamma, Tv, pi, static_cast<double*>(r0), part);
+    } else if (prec == kF32) {
+      const size_t lds = static_cast<size_t>(ts) * h->A * sizeof(float);
+      k_bellman<L, U, float, float, false, float><<<nb, kBlock, lds, h->stream>>>(
+          h->S, h->A, ts, h->row_ptr, h->col, h->val32, nullptr, h->cost,
+          static_cast<const float*>(v), h->gamma, Tv, pi, static_cast<float*>(r0), part);
+    } else {
+      const size_t lds = static_cast<size_t>(ts) * h->A * sizeof(float);
+      k_bellman<L, U, __half, float, true, float><<<nb, kBlock, lds, h->stream>>>(
+          h->S, h->A, ts, h->row_ptr, h->col, h->val16, h->corr16, h->cost,
+          static_cast<const float*>(v), h->gamma, Tv, pi, static_cast<float*>(r0), part);
+    }
+    return hipGetLastError();
+  });
+  }
+  if (e != hipSuccess) return e;
+  return reduce_into_ctl(h, nb, red_mode, first_cycle, alpha, floor_rel);
+}
+
+hipError_t launch_apply(mdp_handle* h, int mode, const int32_t* pi, const double* x, void* y,
+                        bool y_f32, int red_mode, int first_cycle, double alpha,
+                        double floor_rel) {
+  const int nb = grid_for(h->S, kApplyTile);
+  auto* part = reinterpret_cast<double4*>(h->part.buf);
+  hipError_t e;
+  {
+    Prof pf(h, MDP_K_POLICY_APPLY, bytes_apply(h, 8, 8, y_f32 ? 4 : 8));
+    e = with_lanes(h->lanes, [&](auto Lc) -> hipError_t {
+    constexpr int L = decltype(Lc)::value;
+    constexpr int U = rows_in_flight<L>();
+#define MDP_APPLY_ARGS(YT)                                                                 \
+  h->S, h->A, h->row_ptr, h->col, h->val, nullptr, h->cost, pi, x, h->gamma,              \
+      static_cast<YT*>(y), part, nullptr, nullptr, nullptr, nullptr
+    if (mode == kApplyOp)
+      k_policy_apply<L, U, kApplyOp, double, double, double, false>
+          <<<nb, kBlock, 0, h->stream>>>(MDP_APPLY_ARGS(double));
+    else if (mode == kApplyT)
+      k_policy_apply<L, U, kApplyT, double, double, double, false>
+          <<<nb, kBlock, 0, h->stream>>>(MDP_APPLY_ARGS(double));
+    else if (y_f32)
+      k_policy_apply<L, U, kApplyRes, double, double, float, false>
+          <<<nb, kBlock, 0, h->stream>>>(MDP_APPLY_ARGS(float));
+    else
+      k_policy_apply<L, U, kApplyRes, double, double, double, false>
+          <<<nb, kBlock, 0, h->stream>>>(MDP_APPLY_ARGS(double));
+#undef MDP_APPLY_ARGS
+    return hipGetLastError();
+  });
+  }
+  if (e != hipSuccess) return e;
+  return reduce_into_ctl(h, nb, red_mode, first_cycle, alpha, floor_rel);
+}
+
+hipError_t launch_richardson_step(mdp_handle* h, const int32_t* pi, double* buf0, double* buf1) {
+  const int nb = grid_for(h->S, kApplyTile);
+  auto* part = reinterpret_cast<double4*>(h->part.buf);
+  hipError_t e;
+  {
+    Prof pf(h, MDP_K_POLICY_APPLY, bytes_apply(h, 8, 8, 8));
+    e = with_lanes(h->lanes, [&](auto Lc) -> hipError_t {
+    constexpr int L = decltype(Lc)::value;
+    constexpr int U = rows_in_flight<L>();
+    // current iterate in buf[rich_cur]; the kernel swaps roles when rich_cur == 1
+    k_policy_apply<L, U, kApplyT, double, double, double, false><<<nb, kBlock, 0, h->stream>>>(
+        h->S, h->A, h->row_ptr, h->col, h->val, nullptr, h->cost, pi, buf0, h->gamma, buf1,
+        part, h->ctl, &h->ctl->rich_cur, buf1, buf0);
+    return hipGetLastError();
+  });
+  }
+  if (e != hipSuccess) return e;
+  return reduce_into_ctl(h, nb, kRedRichardson, 0, 0.0, 0.0);
+}
+
+hipError_t launch_arnoldi_step(mdp_handle* h, Prec prec, const int32_t* pi, int j, int m) {
+  const int nb = grid_for(h->S, kApplyTile);
+  hipError_t e;
+  {
+    Prof pf(h, MDP_K_ARNOLDI_APPLY, bytes_arnoldi_apply(h, prec == kF64 ? 8 : (prec == kF32 ? 4 : 2), prec == kF64 ? 8 : 4, j) + (prec == kF16 ? h->S * 8.0 : 0.0));
+    e = with_lanes(h->lanes, [&](auto Lc) -> hipError_t {
+    constexpr int L = decltype(Lc)::value;
+    constexpr int U = rows_in_flight<L>();
+    if (prec == kF64)
+      k_arnoldi_apply<L, U, double, double, false><<<nb, kBlock, 0, h->stream>>>(
+          h->S, h->A, h->row_ptr, h->col, h->val, nullptr, pi, h->U64, h->ldu, j, h->gamma,
+          h->ctl, h->part.buf);
+    else if (prec == kF32)
+      k_arnoldi_apply<L, U, float, float, false><<<nb, kBlock, 0, h->stream>>>(
+          h->S, h->A, h->row_ptr, h->col, h->val32, nullptr, pi, h->U32, h->ldu, j, h->gamma,
+          h->ctl, h->part.buf);
+    else
+      k_arnoldi_apply<L, U, __half, float, true><<<nb, kBlock, 0, h->stream>>>(
+          h->S, h->A, h->row_ptr, h->col, h->val16, h->corr16, pi, h->U32, h->ldu, j, h->gamma,
+          h->ctl, h->part.buf);
+    return hipGetLastError();
+  });
+  }
+  if (e != hipSuccess) return e;
+  {
+    Prof pf(h, MDP_K_REDUCE, 0.0);
+    k_reduce_dots<<<j + 1, kBlock, 0, h->stream>>>(h->part.buf, nb, j, h->ctl);
+  }
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  const int nbu = grid_for(h->S, kUpdTile);
+  {
+  Prof pf(h, MDP_K_ARNOLDI_UPDATE, bytes_arnoldi_update(h, prec == kF64 ? 8 : 4, j));
+  if (prec == kF64)
+    k_arnoldi_update<double><<<nbu, kBlock, 0, h->stream>>>(h->S, h->U64, h->ldu, j, h->ctl,
+                                                             h->part.buf);
+  else
+    k_arnoldi_update<float><<<nbu, kBlock, 0, h->stream>>>(h->S, h->U32, h->ldu, j, h->ctl,
+                                                            h->part.buf);
+  }
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  Prof pf(h, MDP_K_REDUCE, 0.0);
+  k_norm_givens<<<1, kBlock, 0, h->stream>>>(h->part.buf, nbu, j, m, h->ctl);
+  return hipGetLastError();
+}
+
+hipError_t launch_gmres_update_x(mdp_handle* h, Prec prec, double* x) {
+  const int nbu = grid_for(h->S, kUpdTile);
+  Prof pf(h, MDP_K_GMRES_UPDATE_X, 0.0);
+  if (prec == kF64)
+    k_gmres_update_x<double, double><<<nbu, kBlock, 0, h->stream>>>(h->S, x, h->U64, h->ldu,
+                                                                     h->ctl);
+  else
+    k_gmres_update_x<float, double><<<nbu, kBlock, 0, h->stream>>>(h->S, x, h->U32, h->ldu,
+                                                                    h->ctl);
+  return hipGetLastError();
+}
+
+hipError_t launch_check_policy(mdp_handle* h, const int32_t* pi) {
+  Prof pf(h, MDP_K_OTHER, 0.0);
+  k_check_policy<<<grid_for(h->S, kBlock), kBlock, 0, h->stream>>>(h->S, h->A, pi, h->ctl);
+  return hipGetLastError();
+}
+
+hipError_t launch_ctl_reset(mdp_handle* h, double tol) {
+  Prof pf(h, MDP_K_OTHER, 0.0);
+  k_ctl_reset<<<1, 64, 0, h->stream>>>(h->ctl, tol);
+  return hipGetLastError();
+}
+
+hipError_t launch_rich_begin(mdp_handle* h, double tol, int cur, int steps) {
+  Prof pf(h, MDP_K_OTHER, 0.0);
+  k_rich_begin<<<1, 64, 0, h->stream>>>(h->ctl, tol, cur, steps);
+  return hipGetLastError();
+}
+
+hipError_t launch_build_lowp(mdp_handle* h, int which) {
+  if (which & MDP_BUILD_FP32) {
+    k_to_f32<<<grid_stride(h->nnz), kBlock, 0, h->stream>>>(h->val, h->val32, h->nnz);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  if (which & MDP_BUILD_FP16) {
+    k_to_f16_rows<<<grid_stride(h->rows), kBlock, 0, h->stream>>>(h->rows, h->row_ptr, h->val,
+                                                                   h->val16, h->corr16);
+    return hipGetLastError();
+  }
+  return hipSuccess;
+}
+
+hipError_t launch_cast_f32(hipStream_t st, const double* src, float* dst, int64_t n) {
+  k_to_f32<<<grid_stride(n), kBlock, 0, st>>>(src, dst, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_i64_to_i32(hipStream_t st, const int64_t* src, int32_t* dst, int64_t n) {
+  k_i64_to_i32<<<grid_stride(n), kBlock, 0, st>>>(src, dst, n);
+  return hipGetLastError();
+}
+
+}  // namespace mdp

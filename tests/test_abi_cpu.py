@@ -1,0 +1,118 @@
+"""CPU checks of the C ABI: the library loads, exports every symbol the header
+declares, and its host-side validation rejects bad MDPs before touching a GPU."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2502_14474_amd import native
+from workloads import config1
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _header_functions():
+    txt = open(os.path.join(ROOT, "include", "mdp.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(mdp_[a-z_0-9]+)\s*\(", txt)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = native.load()
+    names = _header_functions()
+    assert "mdp_create" in names and "mdp_solve" in names and len(names) >= 12
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(native.SIGNATURES), "binding and header disagree"
+
+
+def test_version_and_defaults():
+    lib = native.load()
+    assert b"gfx950" in lib.mdp_version()
+    o = native.SolveOpts()
+    lib.mdp_default_solve_opts(C.byref(o))
+    assert o.struct_size == C.sizeof(native.SolveOpts)
+    assert o.restart == 30 and o.alpha == 1e-4 and o.atol == 1e-8 and o.inner == 0
+    e = native.EvalOpts()
+    lib.mdp_default_eval_opts(C.byref(e))
+    assert e.struct_size == C.sizeof(native.EvalOpts) and e.max_iter == 10000
+    c = native.CreateOpts()
+    lib.mdp_default_create_opts(C.byref(c))
+    assert c.validate == 1 and c.device == -1
+
+
+def _create(S, A, rp, col, val, cost, gamma, **kw):
+    lib = native.load()
+    o = native.CreateOpts()
+    lib.mdp_default_create_opts(C.byref(o))
+    for k, v in kw.items():
+        setattr(o, k, v)
+    h = C.c_void_p()
+    st = lib.mdp_create(S, A, rp.ctypes.data, col.ctypes.data, val.ctypes.data,
+                        cost.ctypes.data, gamma, C.byref(o), C.byref(h))
+    return st, lib.mdp_last_error().decode(), h
+
+
+def _small():
+    inst = config1(S=20, A=3, k=4, seed=2)
+    return (inst.S, inst.A, inst.row_ptr.copy(), inst.col.copy(), inst.val.copy(),
+            inst.cost.copy(), inst.gamma)
+
+
+@pytest.mark.parametrize("mutate,expect", [
+    (lambda a: a.update(gamma=1.0), "gamma"),
+    (lambda a: a.update(gamma=-0.1), "gamma"),
+    (lambda a: a.update(gamma=float("nan")), "gamma"),
+    (lambda a: a.update(S=0), "at least 1"),
+    (lambda a: a["cost"].__setitem__(5, np.nan), "non-finite cost"),
+    (lambda a: a["col"].__setitem__(3, 20), "column index"),
+    (lambda a: a["col"].__setitem__(3, -1), "column index"),
+    (lambda a: a["val"].__setitem__(7, -0.01), "negative"),
+    (lambda a: a["val"].__setitem__(7, a["val"][7] + 1e-6), "sum to 1"),
+    (lambda a: a["rp"].__setitem__(4, a["rp"][3]), "row_ptr"),
+    (lambda a: a["rp"].__setitem__(0, 1), "row_ptr[0]"),
+])
+def test_validation_rejects_bad_mdp(mutate, expect):
+    S, A, rp, col, val, cost, gamma = _small()
+    a = dict(S=S, A=A, rp=rp, col=col, val=val, cost=cost, gamma=gamma)
+    mutate(a)
+    st, msg, h = _create(a["S"], A, a["rp"], a["col"], a["val"], a["cost"], a["gamma"])
+    assert st == native.MDP_E_INVAL, (st, msg)
+    assert expect in msg
+    assert not h.value
+
+
+def test_bad_options_rejected():
+    S, A, rp, col, val, cost, gamma = _small()
+    st, msg, _ = _create(S, A, rp, col, val, cost, gamma, lanes_per_row=12)
+    assert st == native.MDP_E_INVAL and "lanes_per_row" in msg
+    st, msg, _ = _create(S, A, rp, col, val, cost, gamma, low_precision=8)
+    assert st == native.MDP_E_INVAL
+    st, msg, _ = _create(S, 9000, rp, col, val, cost, gamma)
+    assert st == native.MDP_E_NOTSUP
+
+
+def test_null_handle_calls_fail_cleanly():
+    lib = native.load()
+    res = C.c_double()
+    v = np.zeros(4)
+    assert lib.mdp_bellman(None, v.ctypes.data, None, None, C.byref(res)) == native.MDP_E_INVAL
+    assert lib.mdp_solve(None, None, v.ctypes.data, v.ctypes.data, None, None) == native.MDP_E_INVAL
+    assert lib.mdp_destroy(None) == native.MDP_OK
+    assert "handle" in lib.mdp_last_error().decode().lower()
+
+
+def test_valid_create_without_gpu_reports_device_error():
+    """With no GPU the library must fail loudly (no CPU fallback)."""
+    try:
+        import torch
+        if torch.cuda.is_available():
+            pytest.skip("a GPU is present")
+    except ImportError:
+        pass
+    S, A, rp, col, val, cost, gamma = _small()
+    st, msg, h = _create(S, A, rp, col, val, cost, gamma)
+    assert st in (native.MDP_E_DEVICE, native.MDP_E_NOMEM), (st, msg)
+    assert not h.value

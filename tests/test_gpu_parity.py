@@ -1,0 +1,256 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle, on the
+same seeded inputs.  Tolerances follow the floating-point arithmetic of each
+step (stated next to each check)."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from workloads import (MDPInstance, config1, config2, config3, config4, deterministic_chain,
+                       random_dense_mdp)
+
+pytestmark = pytest.mark.gpu
+
+EPS = np.finfo(np.float64).eps
+
+
+def _mdp(inst, **kw):
+    import torch
+    assert torch.cuda.is_available(), "GPU test without a GPU"
+    import paper_2502_14474_amd as m
+    print(f"[case] {inst.name} S={inst.S} A={inst.A} nnz={inst.nnz} {kw}", flush=True)
+    sys.stdout.flush()
+    return m.MDP.from_instance(inst, **kw)
+
+
+def _row_bound(inst, v):
+    """Per-row rounding bound of Q(s,a) = g + gamma * sum p v for two
+    different summation orders of k terms: 2 (k + 2) eps (|g| + gamma max|v|)."""
+    k = np.diff(inst.row_ptr).astype(np.float64)
+    return 2.0 * (k + 2.0) * EPS * (np.abs(inst.cost) + inst.gamma * np.max(np.abs(v)))
+
+
+def _check_bellman(inst, h, v):
+    Tv, pi, res = h.bellman(v)
+    Q = oracle.q_values(inst, v)
+    bnd = _row_bound(inst, v).reshape(inst.S, inst.A).max(axis=1)
+    Tv_ref = Q.min(axis=1)
+    assert np.all(np.abs(Tv - Tv_ref) <= bnd), np.max(np.abs(Tv - Tv_ref) / bnd)
+    part = np.partition(Q, 1, axis=1) if inst.A > 1 else None
+    gap = (part[:, 1] - part[:, 0]) if inst.A > 1 else np.full(inst.S, np.inf)
+    clear = gap > 2 * bnd
+    ref_pi = Q.argmin(axis=1)
+    assert np.array_equal(pi[clear], ref_pi[clear])
+    # everywhere: the chosen action is optimal within the rounding bound
+    assert np.all(Q[np.arange(inst.S), pi] - Tv_ref <= 2 * bnd)
+    ref_res = np.max(np.abs(Tv_ref - v))
+    assert abs(res - ref_res) <= np.max(bnd) + 0.0
+    return Tv, pi, res
+
+
+INSTANCES = {
+    "c1": lambda: config1(),
+    "c2twin": lambda: config2(S=20000, A=8, seed=1),
+    "c3twin": lambda: config3(H=64, W=80, seed=1),
+    "c4twin": lambda: config4(S=12000, A=16, seed=1),
+    "ragged": lambda: random_dense_mdp(37, 3, 0.95, seed=5, density=0.3),
+}
+
+
+@pytest.mark.parametrize("name", list(INSTANCES))
+@pytest.mark.parametrize("lanes", [0, 2, 64])
+def test_bellman_sweep_matches_oracle(name, lanes):
+    inst = INSTANCES[name]()
+    rng = np.random.default_rng(7)
+    with _mdp(inst, lanes_per_row=lanes) as h:
+        for scale in (0.0, 1.0, 100.0):
+            v = scale * rng.standard_normal(inst.S)
+            _check_bellman(inst, h, v)
+
+
+def test_bellman_exact_ties_take_lowest_action():
+    # config-3 absorbing cells have A identical rows: ties must resolve to action 0
+    inst = config3(H=40, W=40, seed=2)
+    absorbing = inst.meta["obstacle"].copy()
+    absorbing[inst.meta["goal"]] = True
+    rng = np.random.default_rng(1)
+    with _mdp(inst) as h:
+        _, pi, _ = h.bellman(rng.standard_normal(inst.S))
+    assert np.all(pi[absorbing] == 0)
+
+
+@pytest.mark.parametrize("name", ["c1", "c2twin", "c3twin", "ragged"])
+def test_policy_apply_matches_oracle(name):
+    inst = INSTANCES[name]()
+    rng = np.random.default_rng(3)
+    pi = rng.integers(0, inst.A, inst.S).astype(np.int32)
+    x = rng.standard_normal(inst.S)
+    Ppi, gpi = oracle.policy_system(inst, pi)
+    k = np.diff(Ppi.indptr).astype(np.float64)
+    bnd = 2.0 * (k + 2) * EPS * (np.abs(x) + np.abs(gpi) + inst.gamma * np.max(np.abs(x)))
+    with _mdp(inst) as h:
+        y0 = h.policy_apply(pi, x, mode=0)
+        y1 = h.policy_apply(pi, x, mode=1)
+    assert np.all(np.abs(y0 - (x - inst.gamma * (Ppi @ x))) <= bnd)
+    assert np.all(np.abs(y1 - (gpi + inst.gamma * (Ppi @ x))) <= bnd)
+    # row-stochastic: P_pi 1 = 1, so (I - gamma P_pi) 1 = 1 - gamma
+    with _mdp(inst) as h:
+        ones = h.policy_apply(pi, np.ones(inst.S), mode=0)
+    assert np.max(np.abs(ones - (1 - inst.gamma))) <= 64 * EPS
+
+
+def test_policy_apply_rejects_bad_policy():
+    import paper_2502_14474_amd as m
+    inst = config1(S=50, seed=3)
+    with _mdp(inst) as h:
+        pi = np.zeros(inst.S, np.int32)
+        pi[7] = inst.A
+        with pytest.raises(m.MDPError) as e:
+            h.policy_apply(pi, np.zeros(inst.S))
+        assert e.value.status == m.native.MDP_E_INVAL
+
+
+@pytest.mark.parametrize("name", ["c1", "c2twin", "c4twin"])
+@pytest.mark.parametrize("inner", [0, 1])
+def test_policy_eval_matches_exact_solve(name, inner):
+    inst = INSTANCES[name]()
+    rng = np.random.default_rng(4)
+    pi = rng.integers(0, inst.A, inst.S).astype(np.int32)
+    v_ref, _ = oracle.evaluate_policy(inst, pi)
+    with _mdp(inst) as h:
+        v, st = h.policy_eval(pi, inner=inner, rtol=1e-13, max_iter=20000)
+    err = np.max(np.abs(v - v_ref)) / np.max(np.abs(v_ref))
+    # relative residual 1e-13 in the 2-norm (GMRES) or successive differences
+    # (Richardson) bounds the error by about cond * 1e-13
+    assert err <= 1e-9, (err, st)
+    assert st["status"] == 0, st
+
+
+def test_gmres_exact_in_few_steps_small_system():
+    # GMRES with m >= S terminates with the exact solution in at most S steps
+    inst = random_dense_mdp(12, 2, 0.9, seed=9, density=0.5)
+    pi = np.zeros(inst.S, np.int32)
+    v_ref = np.linalg.solve(np.eye(inst.S) - inst.gamma * oracle.policy_system(inst, pi)[0].toarray(),
+                            oracle.policy_system(inst, pi)[1])
+    with _mdp(inst) as h:
+        v, st = h.policy_eval(pi, restart=16, rtol=1e-14, max_iter=16)
+    assert st["inner_iters"] <= inst.S
+    assert np.max(np.abs(v - v_ref)) <= 1e-12 * np.max(np.abs(v_ref))
+
+
+def _solve_parity(inst, rel_tol, **kw):
+    ref = oracle.policy_iteration(inst, method="auto" if inst.S <= 2500 else "certified")
+    vstar = ref["v"]
+    with _mdp(inst) as h:
+        v, pi, st = h.solve(**kw)
+    assert st["status"] == 0, st
+    err = np.max(np.abs(v - vstar)) / np.max(np.abs(vstar))
+    assert err <= rel_tol, (err, st)
+    Q = oracle.q_values(inst, vstar)
+    delta = np.max(np.abs(v - vstar))
+    tau = max(1e-9, 2 * inst.gamma * (delta + 1e-11 * np.max(np.abs(vstar))))
+    pp = oracle.policy_parity(inst, Q, pi, ref["pi"], tau)
+    assert pp["mismatch_outside_band"] == 0 and pp["not_tau_optimal"] == 0, pp
+    return v, pi, st
+
+
+@pytest.mark.parametrize("name", ["c1", "c2twin", "c4twin"])
+def test_solve_fp64_gmres(name):
+    inst = INSTANCES[name]()
+    _solve_parity(inst, 1e-9, rtol_cert=1e-10)
+
+
+def test_solve_fp64_maze_gmres():
+    inst = config3(H=48, W=48, seed=4)
+    ref = oracle.policy_iteration(inst, method="sparse")
+    with _mdp(inst) as h:
+        v, pi, st = h.solve(rtol_cert=1e-10)
+    assert st["status"] == 0, st
+    assert np.max(np.abs(v - ref["v"])) / np.max(np.abs(ref["v"])) <= 1e-9
+    obst = inst.meta["obstacle"]
+    assert np.allclose(v[obst], 10 / (1 - inst.gamma), rtol=1e-9)
+    assert abs(v[inst.meta["goal"]]) <= 1e-9 * np.max(np.abs(v))
+
+
+@pytest.mark.parametrize("name", ["c1", "c2twin"])
+def test_solve_fp64_richardson(name):
+    inst = INSTANCES[name]()
+    _solve_parity(inst, 1e-9, inner=1, rtol_cert=1e-10, max_inner=500)
+
+
+def test_richardson_one_step_is_value_iteration_bitwise():
+    inst = config1(S=400, seed=6)
+    with _mdp(inst) as h:
+        v_vi = np.zeros(inst.S)
+        for _ in range(25):
+            Tv, pi_vi, res = h.bellman(v_vi)
+            v_vi = Tv
+        v, pi, st = h.solve(inner=1, max_inner=1, max_outer=25, atol=1e-300)
+    assert st["bellman_sweeps"] == 26 and st["status"] == 1
+    assert np.array_equal(v, v_vi)
+
+
+def test_solve_is_deterministic():
+    inst = INSTANCES["c2twin"]()
+    with _mdp(inst) as h:
+        a = h.solve()
+        b = h.solve()
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+    assert a[2]["inner_iters"] == b[2]["inner_iters"]
+
+
+@pytest.mark.parametrize("precision,tol", [(1, 1e-8), (2, 1e-8)])
+@pytest.mark.parametrize("name", ["c1", "c4twin"])
+def test_solve_mixed_precision(name, precision, tol):
+    inst = INSTANCES[name]()
+    _solve_parity(inst, tol, precision=precision, rtol_cert=1e-9)
+
+
+def test_edge_single_state_and_gamma_zero():
+    g = np.array([0.7, 0.3, 0.9, 0.3])
+    inst = MDPInstance(1, 4, np.arange(5, dtype=np.int64), np.zeros(4, np.int32), np.ones(4), g, 0.99)
+    with _mdp(inst) as h:
+        v, pi, st = h.solve(atol=1e-12)
+    assert pi[0] == 1 and abs(v[0] - 0.3 / 0.01) <= 1e-9 * 30
+    inst0 = config1(S=200, seed=2, gamma=0.0)
+    with _mdp(inst0) as h:
+        v, pi, st = h.solve()
+    Q = inst0.cost.reshape(inst0.S, inst0.A)
+    assert np.array_equal(v, Q.min(axis=1)) and np.array_equal(pi, Q.argmin(axis=1))
+
+
+def test_edge_single_action_and_chain():
+    inst = config1(S=300, A=1, k=5, seed=3)
+    ref = oracle.policy_iteration(inst)
+    with _mdp(inst) as h:
+        v, pi, st = h.solve(atol=1e-12)
+    assert np.all(pi == 0) and np.max(np.abs(v - ref["v"])) <= 1e-9 * np.max(np.abs(ref["v"]))
+    ch = deterministic_chain(50, c_adv=1.5, c_stay=2.0, gamma=0.95)
+    with _mdp(ch) as h:
+        v, pi, st = h.solve(atol=1e-12)
+    s = np.arange(50)
+    expect = 1.5 * (1 - 0.95 ** (49 - s)) / (1 - 0.95)
+    assert np.max(np.abs(v - expect)) <= 1e-9 * np.max(expect) and np.all(pi == 0)
+
+
+def test_device_pointer_round_trip():
+    """torch device tensors in and out through the C ABI."""
+    import torch
+    import paper_2502_14474_amd as m
+    inst = config1(S=500, seed=4)
+    dev = torch.device("cuda:0")
+    t = lambda a: torch.from_numpy(a).to(dev)  # noqa: E731
+    h = m.mdp_create(inst.S, inst.A, t(inst.row_ptr), t(inst.col), t(inst.val), t(inst.cost),
+                     inst.gamma)
+    try:
+        v = torch.zeros(inst.S, dtype=torch.float64, device=dev)
+        pi = torch.zeros(inst.S, dtype=torch.int32, device=dev)
+        st = m.mdp_solve(h, v, pi, rtol_cert=1e-10)
+        torch.cuda.synchronize()
+    finally:
+        m.mdp_destroy(h)
+    ref = oracle.policy_iteration(inst)
+    assert st["status"] == 0
+    assert np.max(np.abs(v.cpu().numpy() - ref["v"])) <= 1e-9 * np.max(np.abs(ref["v"]))
+    assert np.array_equal(pi.cpu().numpy(), ref["pi"])
