@@ -436,7 +436,7 @@ mdp_status mdp_create(int64_t S, int32_t A, const int64_t* row_ptr, const int32_
     o = *opt;
   }
   if (S < 1 || A < 1) return fail(MDP_E_INVAL, "S and A must be at least 1");
-  if (A > 8192) return fail(MDP_E_NOTSUP, "A above 8192 is not supported");
+  if (A > 4096) return fail(MDP_E_NOTSUP, "A above 4096 is not supported");
   if (S * static_cast<int64_t>(A) >= (int64_t{1} << 31) - 1)
     return fail(MDP_E_NOTSUP, "S*A must be below 2^31");
   if (!(gamma >= 0.0 && gamma < 1.0)) return fail(MDP_E_INVAL, "gamma must lie in [0,1)");

@@ -17,8 +17,17 @@ constexpr int kBlock = 256;       // threads per workgroup (4 wavefronts of 64)
 constexpr int kWave = 64;         // CDNA wavefront width
 constexpr int kNumXcd = 8;        // MI355X: 8 accelerator complex dies, one L2 each
 constexpr int kMaxRestart = 64;   // largest GMRES restart length
-constexpr int kApplyTile = 512;   // states per workgroup in the fused Arnoldi product
-constexpr int kUpdTile = 2048;    // states per workgroup in the Arnoldi update
+#ifndef MDP_APPLY_TILE
+#define MDP_APPLY_TILE 512
+#endif
+#ifndef MDP_UNROLL
+#define MDP_UNROLL 4
+#endif
+#ifndef MDP_SWEEP_ROWS
+#define MDP_SWEEP_ROWS 1024
+#endif
+constexpr int kApplyTile = MDP_APPLY_TILE;  // states per workgroup in the P_pi products
+constexpr int kUpdTile = 512;     // states per workgroup in the Arnoldi update
 
 // Device-resident control block of the inner solvers.  Kernels read and
 // write it so that the host only synchronises once per batch of steps.
@@ -145,7 +154,7 @@ enum Prec { kF64 = 0, kF32 = 1, kF16 = 2 };
 enum ReduceMode { kRedNone = -1, kRedPlain = 0, kRedGmresStart = 1, kRedRichardson = 2 };
 
 // Rows of the Bellman sweep handled by one workgroup (whole states).
-constexpr int kSweepRows = 1024;
+constexpr int kSweepRows = MDP_SWEEP_ROWS;
 inline int sweep_tile_states(int A) { return A >= kSweepRows ? 1 : kSweepRows / A; }
 size_t partials_doubles(int64_t S, int A, int m);
 

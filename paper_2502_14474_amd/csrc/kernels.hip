@@ -49,6 +49,30 @@ __device__ __forceinline__ double max_nan(double a, double b) {
   return a > b ? a : b;
 }
 
+// Gathers from the vector x go through a raw buffer resource: an index of -1
+// (empty lane) falls outside the buffer and reads as 0 without a branch, so
+// every gather stays unconditional and the prefetched loads keep flowing.
+// The third resource word is the raw-buffer setting for CDNA3/CDNA4.
+constexpr int kRawBufferWord3 = 0x00020000;
+
+template <typename T>
+struct Gather {
+  __amdgpu_buffer_rsrc_t r;
+  __device__ __forceinline__ Gather(const T* x, int64_t n)
+      : r(__builtin_amdgcn_make_buffer_rsrc(const_cast<T*>(x), static_cast<short>(0),
+                                            static_cast<int>(n * static_cast<int64_t>(sizeof(T))),
+                                            kRawBufferWord3)) {}
+  __device__ __forceinline__ T operator()(int c) const;
+};
+template <>
+__device__ __forceinline__ double Gather<double>::operator()(int c) const {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, c * 8, 0, 0));
+}
+template <>
+__device__ __forceinline__ float Gather<float>::operator()(int c) const {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, c * 4, 0, 0));
+}
+
 template <int L, typename T>
 __device__ __forceinline__ T group_sum(T v) {
 #pragma unroll
@@ -92,52 +116,106 @@ __device__ __forceinline__ void block_max_sum(double& mx, double& sm) {
   __syncthreads();
 }
 
-// Dot products of U rows held by one lane group (see the file comment).
-// st/en: entry range of each row (empty when st == en).  CORR additionally
-// sums the gathered x over the row (float16 row-sum correction).
-template <int L, int U, typename VT, typename XT, typename AT, bool CORR>
-__device__ __forceinline__ void rows_dot(const int (&st)[U], const int (&en)[U], int lane,
-                                         const int* __restrict__ col,
-                                         const VT* __restrict__ val,
-                                         const XT* __restrict__ x, AT (&acc)[U], AT (&xs)[U]) {
-  int c[U];
+// Row products of one workgroup, software pipelined.  `n` rows are handed out
+// to lane groups of L lanes: row idx = it*G*U + g + u*G (consecutive groups
+// take consecutive rows, so the CSR streams are read in order).  Lane l of a
+// group takes the row's entries l, l+L, l+2L, ... and the L partial sums meet
+// in an xor butterfly, so a row's summation order depends only on positions
+// inside the row.  The first entry of every row of iteration it+1 (column,
+// value, and the row's cost) is loaded before the gathers of iteration it are
+// consumed, which keeps streaming loads in flight behind the dependent gathers.
+//
+//   range(idx, st, en, ri): entry range [st, en) and global row index ri.
+//   sink(idx, pv, gcost, st, en, ri): called by every lane of the group with
+//     pv = P[ri,:] x (float16 copy: plus the row-sum correction) and
+//     gcost = cost[ri] (when NEEDCOST).
+template <int L, int U, typename VT, typename XT, typename AT, bool CORR, bool NEEDCOST,
+          typename RangeF, typename SinkF>
+__device__ __forceinline__ void pipelined_rows(int n, RangeF range, const int* __restrict__ col,
+                                               const VT* __restrict__ val,
+                                               const XT* __restrict__ x, int64_t nx,
+                                               const double* __restrict__ cost,
+                                               const double* __restrict__ corr, SinkF sink) {
+  constexpr int G = kBlock / L;
+  const Gather<XT> gx(x, nx);
+  constexpr int STEP = G * U;
+  const int g = threadIdx.x / L, lane = threadIdx.x % L;
+  const int n_it = (n + STEP - 1) / STEP;
+  int st[U], en[U], ri[U], c[U];
   AT p[U];
-  bool ok[U];
+  double gc[U];
+  // Loads are unconditional (out-of-range lanes read entry 0, which always
+  // exists) and masked afterwards with selects: a load under a branch makes
+  // the compiler wait for every outstanding load before the branch joins,
+  // which would drain the prefetched iteration.
+  auto fetch = [&](int it) {
 #pragma unroll
-  for (int u = 0; u < U; ++u) {
-    const int e = st[u] + lane;
-    ok[u] = e < en[u];
-    c[u] = ok[u] ? ld_col(col + e) : 0;
-    p[u] = ok[u] ? static_cast<AT>(ld_val(val + e)) : AT(0);
-  }
+    for (int u = 0; u < U; ++u) {
+      const int idx = it * STEP + g + u * G;
+      const bool valid = idx < n;
+      int a, b, r;
+      range(valid ? idx : 0, a, b, r);
+      st[u] = valid ? a : 0;
+      en[u] = valid ? b : 0;
+      ri[u] = valid ? r : 0;
+      const int e = st[u] + lane;
+      const bool ok = e < en[u];
+      const int es = ok ? e : 0;
+      const int craw = ld_col(col + es);
+      const AT praw = static_cast<AT>(ld_val(val + es));
+      c[u] = ok ? craw : -1;
+      p[u] = ok ? praw : AT(0);
+      if (NEEDCOST) gc[u] = cost[ri[u]];
+    }
+  };
+  if (n_it > 0) fetch(0);
+  for (int it = 0; it < n_it; ++it) {
+    int cst[U], cen[U], cri[U], cc[U];
+    AT cp[U];
+    double cgc[U];
 #pragma unroll
-  for (int u = 0; u < U; ++u) {
-    const AT xv = ok[u] ? static_cast<AT>(x[c[u]]) : AT(0);
-    acc[u] = ok[u] ? fma(p[u], xv, AT(0)) : AT(0);
-    if (CORR) xs[u] = xv;
-  }
+    for (int u = 0; u < U; ++u) {
+      cst[u] = st[u];
+      cen[u] = en[u];
+      cri[u] = ri[u];
+      cc[u] = c[u];
+      cp[u] = p[u];
+      cgc[u] = gc[u];
+    }
+    // Gathers of this iteration first, then the prefetch of the next one:
+    // loads complete in issue order, so waiting for the gathers then leaves
+    // the prefetch in flight.  The prefetch is unconditional (past the end
+    // the rows are empty): a branch would make the compiler drain the loads.
+    AT acc[U], xs[U];
+    AT xr[U];
 #pragma unroll
-  for (int u = 0; u < U; ++u) {
-    for (int e = st[u] + lane + L; e < en[u]; e += L) {
-      const AT xv = static_cast<AT>(x[ld_col(col + e)]);
-      acc[u] = fma(static_cast<AT>(ld_val(val + e)), xv, acc[u]);
-      if (CORR) xs[u] += xv;
+    for (int u = 0; u < U; ++u) xr[u] = static_cast<AT>(gx(cc[u]));  // 0 when cc = -1
+    fetch(it + 1);
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      acc[u] = fma(cp[u], xr[u], AT(0));  // cp = 0 on empty lanes
+      xs[u] = xr[u];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      for (int e = cst[u] + lane + L; e < cen[u]; e += L) {
+        const AT xv = static_cast<AT>(gx(ld_col(col + e)));
+        acc[u] = fma(static_cast<AT>(ld_val(val + e)), xv, acc[u]);
+        if (CORR) xs[u] += xv;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      acc[u] = group_sum<L>(acc[u]);
+      if (CORR) {
+        xs[u] = group_sum<L>(xs[u]);
+        const int len = cen[u] - cst[u];
+        if (len > 0) acc[u] += static_cast<AT>(corr[cri[u]]) * (xs[u] / static_cast<AT>(len));
+      }
+      const int idx = it * STEP + g + u * G;
+      if (idx < n) sink(idx, acc[u], cgc[u], cst[u], cen[u], cri[u]);
     }
   }
-#pragma unroll
-  for (int u = 0; u < U; ++u) {
-    acc[u] = group_sum<L>(acc[u]);
-    if (CORR) xs[u] = group_sum<L>(xs[u]);
-  }
-}
-
-// P[r,:] x for the row r, in the accumulation type; with the float16 copy the
-// row-sum correction c_r * mean_j x_j is added.
-template <bool CORR, typename AT>
-__device__ __forceinline__ AT row_value(AT acc, AT xs, const double* __restrict__ corr, int r,
-                                        int len) {
-  if (CORR) return acc + static_cast<AT>(corr[r]) * (xs / static_cast<AT>(len));
-  return acc;
 }
 
 template <typename T> struct Acc { using type = float; };
@@ -146,11 +224,12 @@ template <> struct Acc<double> { using type = double; };
 // ----------------------------------------------------------------------------
 // K1: fused Bellman sweep
 // ----------------------------------------------------------------------------
-// Workgroup = tile of `tile_states` states (all A rows of each).  Phase 1: lane
-// groups compute Q(s,a) = g(s,a) + gamma * (P v)(s,a) into LDS.  Phase 2: one
-// thread per state takes the minimum over a = 0..A-1 with a strict '<' (lowest
-// action wins ties), writes Tv, pi and r0 = Tv - v, and accumulates
-// max|Tv - v| and sum (Tv - v)^2 into this workgroup's partials.
+// Workgroup = tile of `tile_states` states (all A rows of each).  The tile's
+// row offsets are staged in LDS with one coalesced pass.  Phase 1: lane groups
+// compute Q(s,a) = g(s,a) + gamma * (P v)(s,a) into LDS.  Phase 2: one thread
+// per state takes the minimum over a = 0..A-1 with a strict '<' (lowest action
+// wins ties), writes Tv, pi and r0 = Tv - v, and accumulates max|Tv - v|,
+// sum (Tv - v)^2 and max|Tv| into this workgroup's partials.
 template <int L, int U, typename VT, typename XT, bool CORR, typename RT>
 __global__ __launch_bounds__(kBlock) void k_bellman(
     int64_t S, int A, int tile_states, const int* __restrict__ row_ptr,
@@ -159,41 +238,43 @@ __global__ __launch_bounds__(kBlock) void k_bellman(
     double* __restrict__ Tv, int* __restrict__ pi, RT* __restrict__ r0,
     double4* __restrict__ partials) {
   using AT = typename Acc<XT>::type;
-  extern __shared__ unsigned char lds_raw[];
-  AT* q = reinterpret_cast<AT*>(lds_raw);
-  constexpr int G = kBlock / L;
+  extern __shared__ double lds_d[];
+  const int tile_rows = tile_states * A;
+  AT* q = reinterpret_cast<AT*>(lds_d);
+  int* rp = reinterpret_cast<int*>(lds_d + tile_rows);  // tile_rows + 1 entries
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
   const int64_t s0 = static_cast<int64_t>(tile) * tile_states;
   const int ns = static_cast<int>(min<int64_t>(tile_states, S - s0));
   const int nrows = ns * A;
   const int64_t row0 = s0 * A;
-  const int g = threadIdx.x / L, lane = threadIdx.x % L;
   const AT gam = static_cast<AT>(gamma);
-
-  for (int base = 0; base < nrows; base += G * U) {
-    int st[U], en[U];
+  // stage the tile's row offsets: loads first (unconditional), then LDS
+  for (int base = 0; base <= nrows; base += 5 * kBlock) {
+    int buf[5];
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int rr = base + g + u * G;
-      if (rr < nrows) {
-        st[u] = row_ptr[row0 + rr];
-        en[u] = row_ptr[row0 + rr + 1];
-      } else {
-        st[u] = en[u] = 0;
-      }
+    for (int k = 0; k < 5; ++k) {
+      const int i = base + threadIdx.x + k * kBlock;
+      buf[k] = row_ptr[row0 + (i <= nrows ? i : 0)];
     }
-    AT acc[U], xs[U];
-    rows_dot<L, U, VT, XT, AT, CORR>(st, en, lane, col, val, v, acc, xs);
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int rr = base + g + u * G;
-      if (rr < nrows && lane == 0) {
-        const AT pv = row_value<CORR, AT>(acc[u], xs[u], corr, static_cast<int>(row0 + rr),
-                                           en[u] - st[u]);
-        q[rr] = fma(gam, pv, static_cast<AT>(cost[row0 + rr]));
-      }
+    for (int k = 0; k < 5; ++k) {
+      const int i = base + threadIdx.x + k * kBlock;
+      if (i <= nrows) rp[i] = buf[k];
     }
   }
+  __syncthreads();
+
+  pipelined_rows<L, U, VT, XT, AT, CORR, true>(
+      nrows,
+      [&](int idx, int& st, int& en, int& ri) {
+        st = rp[idx];
+        en = rp[idx + 1];
+        ri = static_cast<int>(row0 + idx);
+      },
+      col, val, v, S, cost, corr,
+      [&](int idx, AT pv, double gc, int, int, int) {
+        if ((threadIdx.x % L) == 0) q[idx] = fma(gam, pv, static_cast<AT>(gc));
+      });
   __syncthreads();
 
   double dmax = 0.0, dsum = 0.0, tmax = 0.0;
@@ -226,6 +307,39 @@ __global__ __launch_bounds__(kBlock) void k_bellman(
   if (threadIdx.x == 0) partials[tile] = make_double4(dmax, dsum, tmax, 0.0);
 }
 
+// Stage the selected rows of kApplyTile states: thread t loads pi(s0+t) and
+// the two row offsets of row s*A + pi(s) (all independent loads).
+__device__ __forceinline__ void stage_policy_rows(int64_t s0, int ns, int A,
+                                                  const int* __restrict__ row_ptr,
+                                                  const int* __restrict__ pi, int* st_l,
+                                                  int* en_l, int* rw_l) {
+  constexpr int KP = (kApplyTile + kBlock - 1) / kBlock;
+  int pv[KP], a[KP], b[KP];
+#pragma unroll
+  for (int k = 0; k < KP; ++k) {
+    const int t = threadIdx.x + k * kBlock;
+    pv[k] = pi[s0 + (t < ns ? t : 0)];
+  }
+#pragma unroll
+  for (int k = 0; k < KP; ++k) {
+    const int t = threadIdx.x + k * kBlock;
+    const int r = static_cast<int>((s0 + (t < ns ? t : 0)) * A + pv[k]);
+    pv[k] = r;
+    a[k] = row_ptr[r];
+    b[k] = row_ptr[r + 1];
+  }
+#pragma unroll
+  for (int k = 0; k < KP; ++k) {
+    const int t = threadIdx.x + k * kBlock;
+    if (t < ns) {
+      rw_l[t] = pv[k];
+      st_l[t] = a[k];
+      en_l[t] = b[k];
+    }
+  }
+  __syncthreads();
+}
+
 // ----------------------------------------------------------------------------
 // K2/K3/K10: products with P_pi, gathering rows s*A + pi(s)
 // ----------------------------------------------------------------------------
@@ -251,56 +365,42 @@ __global__ __launch_bounds__(kBlock) void k_policy_apply(
     y_alt = y;
     y = u;
   }
-  constexpr int G = kBlock / L;
+  __shared__ int st_l[kApplyTile], en_l[kApplyTile], rw_l[kApplyTile];
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
   const int64_t s0 = static_cast<int64_t>(tile) * kApplyTile;
   const int ns = static_cast<int>(min<int64_t>(kApplyTile, S - s0));
-  const int g = threadIdx.x / L, lane = threadIdx.x % L;
   const AT gam = static_cast<AT>(gamma);
+  stage_policy_rows(s0, ns, A, row_ptr, pi, st_l, en_l, rw_l);
   double dmax = 0.0, dsum = 0.0;
 
-  for (int base = 0; base < ns; base += G * U) {
-    int st[U], en[U], rw[U];
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int ss = base + g + u * G;
-      if (ss < ns) {
+  pipelined_rows<L, U, VT, XT, AT, CORR, MODE != kApplyOp>(
+      ns,
+      [&](int idx, int& st, int& en, int& ri) {
+        st = st_l[idx];
+        en = en_l[idx];
+        ri = rw_l[idx];
+      },
+      col, val, x, S, cost, corr,
+      [&](int ss, AT pv, double gc, int, int, int) {
+        if ((threadIdx.x % L) != 0) return;
         const int64_t s = s0 + ss;
-        rw[u] = static_cast<int>(s * A + pi[s]);
-        st[u] = row_ptr[rw[u]];
-        en[u] = row_ptr[rw[u] + 1];
-      } else {
-        rw[u] = 0;
-        st[u] = en[u] = 0;
-      }
-    }
-    AT acc[U], xs[U];
-    rows_dot<L, U, VT, XT, AT, CORR>(st, en, lane, col, val, x, acc, xs);
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int ss = base + g + u * G;
-      if (ss < ns && lane == 0) {
-        const int64_t s = s0 + ss;
-        const AT pv = row_value<CORR, AT>(acc[u], xs[u], corr, rw[u], en[u] - st[u]);
         const AT xs_own = static_cast<AT>(x[s]);
         if (MODE == kApplyOp) {
           y[s] = static_cast<YT>(xs_own - gam * pv);
         } else if (MODE == kApplyT) {
-          const AT yv = fma(gam, pv, static_cast<AT>(cost[rw[u]]));
+          const AT yv = fma(gam, pv, static_cast<AT>(gc));
           y[s] = static_cast<YT>(yv);
           const double d = static_cast<double>(yv) - static_cast<double>(xs_own);
           dmax = max_nan(dmax, fabs(d));
           dsum = fma(d, d, dsum);
         } else {
-          const double r = cost[rw[u]] - (static_cast<double>(xs_own) -
-                                          static_cast<double>(gam) * static_cast<double>(pv));
+          const double r = gc - (static_cast<double>(xs_own) -
+                                 static_cast<double>(gam) * static_cast<double>(pv));
           y[s] = static_cast<YT>(r);
           dmax = max_nan(dmax, fabs(r));
           dsum = fma(r, r, dsum);
         }
-      }
-    }
-  }
+      });
   if (MODE != kApplyOp) {
     block_max_sum(dmax, dsum);
     if (threadIdx.x == 0) partials[tile] = make_double4(dmax, dsum, 0.0, 0.0);
@@ -326,62 +426,62 @@ __global__ __launch_bounds__(kBlock) void k_arnoldi_apply(
   using AT = typename Acc<BT>::type;
   if (ctl->done) return;
   __shared__ double w_lds[kApplyTile];
+  __shared__ int st_l[kApplyTile], en_l[kApplyTile], rw_l[kApplyTile];
   __shared__ double red[kBlock / kWave][8];
-  constexpr int G = kBlock / L;
   const int nb = gridDim.x;
   const int tile = xcd_tile(blockIdx.x, nb);
   const int64_t s0 = static_cast<int64_t>(tile) * kApplyTile;
   const int ns = static_cast<int>(min<int64_t>(kApplyTile, S - s0));
-  const int g = threadIdx.x / L, lane = threadIdx.x % L;
   const AT gam = static_cast<AT>(gamma);
   const BT* __restrict__ xj = Ub + static_cast<int64_t>(j) * ldu;
   BT* __restrict__ w = Ub + static_cast<int64_t>(j + 1) * ldu;
   const double cj = ctl->scale[j];
+  stage_policy_rows(s0, ns, A, row_ptr, pi, st_l, en_l, rw_l);
 
-  for (int base = 0; base < ns; base += G * U) {
-    int st[U], en[U], rw[U];
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int ss = base + g + u * G;
-      if (ss < ns) {
+  pipelined_rows<L, U, VT, BT, AT, CORR, false>(
+      ns,
+      [&](int idx, int& st, int& en, int& ri) {
+        st = st_l[idx];
+        en = en_l[idx];
+        ri = rw_l[idx];
+      },
+      col, val, xj, S, nullptr, corr,
+      [&](int ss, AT pv, double, int, int, int) {
+        if ((threadIdx.x % L) != 0) return;
         const int64_t s = s0 + ss;
-        rw[u] = static_cast<int>(s * A + pi[s]);
-        st[u] = row_ptr[rw[u]];
-        en[u] = row_ptr[rw[u] + 1];
-      } else {
-        rw[u] = 0;
-        st[u] = en[u] = 0;
-      }
-    }
-    AT acc[U], xs[U];
-    rows_dot<L, U, VT, BT, AT, CORR>(st, en, lane, col, val, xj, acc, xs);
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int ss = base + g + u * G;
-      if (ss < ns && lane == 0) {
-        const int64_t s = s0 + ss;
-        const AT pv = row_value<CORR, AT>(acc[u], xs[u], corr, rw[u], en[u] - st[u]);
         const AT av = static_cast<AT>(xj[s]) - gam * pv;
         const BT wv = static_cast<BT>(cj * static_cast<double>(av));
         w[s] = wv;
         w_lds[ss] = static_cast<double>(wv);
-      }
-    }
-  }
+      });
   __syncthreads();
 
   const int wv_id = threadIdx.x / kWave;
+  constexpr int KS = kApplyTile / kBlock;
   for (int i0 = 0; i0 <= j; i0 += 8) {
     double a8[8];
 #pragma unroll
     for (int c = 0; c < 8; ++c) a8[c] = 0.0;
-    for (int t = threadIdx.x; t < ns; t += kBlock) {
-      const double wt = w_lds[t];
-      const int64_t s = s0 + t;
+    BT ub[KS][8];
 #pragma unroll
-      for (int c = 0; c < 8; ++c)
-        if (i0 + c <= j)
-          a8[c] = fma(static_cast<double>(Ub[static_cast<int64_t>(i0 + c) * ldu + s]), wt, a8[c]);
+    for (int k = 0; k < KS; ++k) {
+      const int t = threadIdx.x + k * kBlock;
+      const int64_t s = s0 + (t < ns ? t : 0);
+#pragma unroll
+      for (int c = 0; c < 8; ++c) {
+        const int col_i = i0 + c <= j ? i0 + c : j;
+        ub[k][c] = Ub[static_cast<int64_t>(col_i) * ldu + s];
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < KS; ++k) {
+      const int t = threadIdx.x + k * kBlock;
+      const double wt = t < ns ? w_lds[t] : 0.0;
+#pragma unroll
+      for (int c = 0; c < 8; ++c) {
+        const double prod = fma(static_cast<double>(ub[k][c]), wt, a8[c]);
+        a8[c] = (t < ns && i0 + c <= j) ? prod : a8[c];
+      }
     }
 #pragma unroll
     for (int c = 0; c < 8; ++c) a8[c] = wave_sum(a8[c]);
@@ -417,40 +517,52 @@ __global__ __launch_bounds__(kBlock) void k_reduce_dots(const double* __restrict
 }
 
 // K5: w <- w - sum_{i<=j} hc_i U_i, with the workgroup's partial ||w||^2.
+// kUpdTile states per workgroup, KU per thread; the basis loop is unrolled by
+// 4 so that 4*KU independent loads are in flight per thread.
 template <typename BT>
 __global__ __launch_bounds__(kBlock) void k_arnoldi_update(int64_t S, BT* __restrict__ Ub,
                                                            int64_t ldu, int j,
                                                            const Ctl* __restrict__ ctl,
                                                            double* __restrict__ partials) {
   if (ctl->done) return;
-  __shared__ double hc[kMaxRestart + 1];
-  if (threadIdx.x <= j) hc[threadIdx.x] = ctl->hc[threadIdx.x];
+  __shared__ double hc[kMaxRestart + 4];
+  if (threadIdx.x < kMaxRestart + 4) hc[threadIdx.x] = threadIdx.x <= j ? ctl->hc[threadIdx.x] : 0.0;
   __syncthreads();
-  constexpr int K = kUpdTile / kBlock;
+  constexpr int KU = kUpdTile / kBlock;
   const int64_t s0 = static_cast<int64_t>(blockIdx.x) * kUpdTile + threadIdx.x;
   BT* __restrict__ w = Ub + static_cast<int64_t>(j + 1) * ldu;
-  double acc[K];
+  double acc[KU];
+  bool in[KU];
 #pragma unroll
-  for (int k = 0; k < K; ++k) {
+  for (int k = 0; k < KU; ++k) {
     const int64_t s = s0 + k * kBlock;
-    acc[k] = s < S ? static_cast<double>(w[s]) : 0.0;
+    in[k] = s < S;
+    acc[k] = in[k] ? static_cast<double>(w[s]) : 0.0;
   }
-  for (int i = 0; i <= j; ++i) {
-    const double c = -hc[i];
-    const BT* __restrict__ ui = Ub + static_cast<int64_t>(i) * ldu;
+  for (int i = 0; i <= j; i += 4) {
+    BT u4[4][KU];
 #pragma unroll
-    for (int k = 0; k < K; ++k) {
-      const int64_t s = s0 + k * kBlock;
-      if (s < S) acc[k] = fma(c, static_cast<double>(ui[s]), acc[k]);
+    for (int q = 0; q < 4; ++q) {
+      const BT* __restrict__ ui = Ub + static_cast<int64_t>(i + q <= j ? i + q : j) * ldu;
+#pragma unroll
+      for (int k = 0; k < KU; ++k) u4[q][k] = ui[in[k] ? s0 + k * kBlock : 0];
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const double c = -hc[i + q];
+#pragma unroll
+      for (int k = 0; k < KU; ++k) {
+        const double t = fma(c, static_cast<double>(u4[q][k]), acc[k]);
+        acc[k] = i + q <= j ? t : acc[k];
+      }
     }
   }
   double sq = 0.0;
 #pragma unroll
-  for (int k = 0; k < K; ++k) {
-    const int64_t s = s0 + k * kBlock;
-    if (s < S) {
+  for (int k = 0; k < KU; ++k) {
+    if (in[k]) {
       const BT wv = static_cast<BT>(acc[k]);
-      w[s] = wv;
+      w[s0 + k * kBlock] = wv;
       const double wd = static_cast<double>(wv);
       sq = fma(wd, wd, sq);
     }
@@ -460,71 +572,76 @@ __global__ __launch_bounds__(kBlock) void k_arnoldi_update(int64_t S, BT* __rest
   if (threadIdx.x == 0) partials[blockIdx.x] = sq;
 }
 
-// Back substitution R y = g for the first n columns (single thread).
-__device__ void backsolve(Ctl* ctl, int n) {
-  for (int i = n - 1; i >= 0; --i) {
-    double t = ctl->g[i];
-    for (int k = i + 1; k < n; ++k) t -= ctl->H[i + k * (kMaxRestart + 1)] * ctl->y[k];
-    ctl->y[i] = t / ctl->H[i + i * (kMaxRestart + 1)];
-  }
-}
-
 // K6: ||w|| from the partials, then the Givens update of column j, the
-// residual estimate and the stop decision.  One workgroup.
+// residual estimate and the stop decision.  One workgroup; the back
+// substitution at the end of a cycle runs column by column over the threads.
 __global__ __launch_bounds__(kBlock) void k_norm_givens(const double* __restrict__ partials,
                                                         int nb, int j, int m,
                                                         Ctl* __restrict__ ctl) {
   if (ctl->done) return;
+  __shared__ int s_done;
+  __shared__ double s_t[kMaxRestart];
   double s = 0.0;
   for (int b = threadIdx.x; b < nb; b += kBlock) s += partials[b];
   double mx = 0.0;
   block_max_sum(mx, s);
-  if (threadIdx.x != 0) return;
   const int ld = kMaxRestart + 1;
-  double* h = ctl->H + j * ld;
-  const double hn = sqrt(s);
-  // size of the column before orthogonalisation, for the breakdown test
-  double colnorm2 = hn * hn;
-  for (int i = 0; i <= j; ++i) colnorm2 += h[i] * h[i];
-  for (int i = 0; i < j; ++i) {
-    const double t = ctl->cs[i] * h[i] + ctl->sn[i] * h[i + 1];
-    h[i + 1] = -ctl->sn[i] * h[i] + ctl->cs[i] * h[i + 1];
-    h[i] = t;
-  }
-  const double a = h[j], b = hn;
-  const double r = hypot(a, b);
-  double c = 1.0, sn = 0.0;
-  if (r > 0.0) {
-    c = a / r;
-    sn = b / r;
-  }
-  ctl->cs[j] = c;
-  ctl->sn[j] = sn;
-  h[j] = r;
-  h[j + 1] = 0.0;
-  const double gj = ctl->g[j];
-  ctl->g[j + 1] = -sn * gj;
-  ctl->g[j] = c * gj;
-  const double est = fabs(ctl->g[j + 1]);
-  ctl->res_est = est;
-  ctl->steps += 1;
-  const bool brk = !(hn > 1e-14 * sqrt(colnorm2));
-  ctl->scale[j + 1] = brk ? 0.0 : 1.0 / hn;
   const int n = j + 1;
-  ctl->j = n;
-  int done = 0;
-  if (est <= ctl->tol_cycle) done = 1;
-  if (est <= ctl->tol) ctl->converged = 1;
-  if (brk) {
-    ctl->breakdown = 1;
-    done = 1;
+  if (threadIdx.x == 0) {
+    double* h = ctl->H + j * ld;
+    const double hn = sqrt(s);
+    // size of the column before orthogonalisation, for the breakdown test
+    double colnorm2 = hn * hn;
+    for (int i = 0; i <= j; ++i) colnorm2 += h[i] * h[i];
+    for (int i = 0; i < j; ++i) {
+      const double t = ctl->cs[i] * h[i] + ctl->sn[i] * h[i + 1];
+      h[i + 1] = -ctl->sn[i] * h[i] + ctl->cs[i] * h[i + 1];
+      h[i] = t;
+    }
+    const double a = h[j], b = hn;
+    const double r = hypot(a, b);
+    double c = 1.0, sn = 0.0;
+    if (r > 0.0) {
+      c = a / r;
+      sn = b / r;
+    }
+    ctl->cs[j] = c;
+    ctl->sn[j] = sn;
+    h[j] = r;
+    h[j + 1] = 0.0;
+    const double gj = ctl->g[j];
+    ctl->g[j + 1] = -sn * gj;
+    ctl->g[j] = c * gj;
+    const double est = fabs(ctl->g[j + 1]);
+    ctl->res_est = est;
+    ctl->steps += 1;
+    const bool brk = !(hn > 1e-14 * sqrt(colnorm2));
+    ctl->scale[j + 1] = brk ? 0.0 : 1.0 / hn;
+    ctl->j = n;
+    int done = 0;
+    if (est <= ctl->tol_cycle) done = 1;
+    if (est <= ctl->tol) ctl->converged = 1;
+    if (brk) {
+      ctl->breakdown = 1;
+      done = 1;
+    }
+    if (n >= m) done = 1;
+    if (!(est == est)) done = 1;
+    s_done = done;
   }
-  if (n >= m) done = 1;
-  if (!(est == est)) done = 1;
-  if (done) {
-    backsolve(ctl, n);
-    ctl->done = 1;
+  __syncthreads();
+  if (!s_done) return;
+  // back substitution R y = g, R = H[0:n, 0:n] upper triangular
+  if (threadIdx.x < n) s_t[threadIdx.x] = ctl->g[threadIdx.x];
+  __syncthreads();
+  for (int i = n - 1; i >= 0; --i) {
+    const double yi = s_t[i] / ctl->H[i + i * ld];
+    __syncthreads();
+    if (threadIdx.x == 0) ctl->y[i] = yi;
+    if (threadIdx.x < i) s_t[threadIdx.x] -= ctl->H[threadIdx.x + i * ld] * yi;
+    __syncthreads();
   }
+  if (threadIdx.x == 0) ctl->done = 1;
 }
 
 // K7: x += sum_{i < n} y_i scale_i U_i for the n = ctl->j completed columns.
@@ -535,27 +652,39 @@ __global__ __launch_bounds__(kBlock) void k_gmres_update_x(int64_t S, XT* __rest
                                                            const Ctl* __restrict__ ctl) {
   const int n = ctl->j;
   if (n == 0) return;
-  __shared__ double coef[kMaxRestart];
-  if (threadIdx.x < n) coef[threadIdx.x] = ctl->y[threadIdx.x] * ctl->scale[threadIdx.x];
+  __shared__ double coef[kMaxRestart + 4];
+  if (threadIdx.x < kMaxRestart + 4)
+    coef[threadIdx.x] = threadIdx.x < n ? ctl->y[threadIdx.x] * ctl->scale[threadIdx.x] : 0.0;
   __syncthreads();
-  constexpr int K = kUpdTile / kBlock;
+  constexpr int KU = kUpdTile / kBlock;
   const int64_t s0 = static_cast<int64_t>(blockIdx.x) * kUpdTile + threadIdx.x;
-  double d[K];
+  double d[KU];
+  bool in[KU];
 #pragma unroll
-  for (int k = 0; k < K; ++k) d[k] = 0.0;
-  for (int i = 0; i < n; ++i) {
-    const double c = coef[i];
-    const BT* __restrict__ ui = Ub + static_cast<int64_t>(i) * ldu;
+  for (int k = 0; k < KU; ++k) {
+    d[k] = 0.0;
+    in[k] = s0 + k * kBlock < S;
+  }
+  for (int i = 0; i < n; i += 4) {
+    BT u4[4][KU];
 #pragma unroll
-    for (int k = 0; k < K; ++k) {
-      const int64_t s = s0 + k * kBlock;
-      if (s < S) d[k] = fma(c, static_cast<double>(ui[s]), d[k]);
+    for (int q = 0; q < 4; ++q) {
+      const BT* __restrict__ ui = Ub + static_cast<int64_t>(i + q < n ? i + q : n - 1) * ldu;
+#pragma unroll
+      for (int k = 0; k < KU; ++k) u4[q][k] = ui[in[k] ? s0 + k * kBlock : 0];
     }
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int k = 0; k < KU; ++k) {
+        const double t = fma(coef[i + q], static_cast<double>(u4[q][k]), d[k]);
+        d[k] = i + q < n ? t : d[k];
+      }
   }
 #pragma unroll
-  for (int k = 0; k < K; ++k) {
+  for (int k = 0; k < KU; ++k) {
     const int64_t s = s0 + k * kBlock;
-    if (s < S) x[s] = static_cast<XT>(static_cast<double>(x[s]) + d[k]);
+    if (in[k]) x[s] = static_cast<XT>(static_cast<double>(x[s]) + d[k]);
   }
 }
 
@@ -744,7 +873,7 @@ struct Prof {
   ~Prof() { prof_end(h, kind, a, bytes); }
 };
 
-template <int L> constexpr int rows_in_flight() { return L >= 32 ? 2 : 4; }
+template <int L> constexpr int rows_in_flight() { return L >= 32 ? 2 : MDP_UNROLL; }
 
 template <typename F>
 hipError_t with_lanes(int L, F&& f) {
@@ -800,7 +929,8 @@ hipError_t launch_bellman(mdp_handle* h, Prec prec, const void* v, double* Tv, i
     constexpr int L = decltype(Lc)::value;
     constexpr int U = rows_in_flight<L>();
     if (prec == kF64) {
-      const size_t lds = static_cast<size_t>(ts) * h->A * sizeof(double);
+      const size_t lds = static_cast<size_t>(ts) * h->A * sizeof(double) +
+                         (static_cast<size_t>(ts) * h->A + 1) * sizeof(int);
       if (r0_f32)
         k_bellman<L, U, double, double, false, float><<<nb, kBlock, lds, h->stream>>>(
             h->S, h->A, ts, h->row_ptr, h->col, h->val, nullptr, h->cost,
@@ -810,12 +940,14 @@ hipError_t launch_bellman(mdp_handle* h, Prec prec, const void* v, double* Tv, i
             h->S, h->A, ts, h->row_ptr, h->col, h->val, nullptr, h->cost,
             static_cast<const double*>(v), h->gamma, Tv, pi, static_cast<double*>(r0), part);
     } else if (prec == kF32) {
-      const size_t lds = static_cast<size_t>(ts) * h->A * sizeof(float);
+      const size_t lds = static_cast<size_t>(ts) * h->A * sizeof(double) +
+                         (static_cast<size_t>(ts) * h->A + 1) * sizeof(int);
       k_bellman<L, U, float, float, false, float><<<nb, kBlock, lds, h->stream>>>(
           h->S, h->A, ts, h->row_ptr, h->col, h->val32, nullptr, h->cost,
           static_cast<const float*>(v), h->gamma, Tv, pi, static_cast<float*>(r0), part);
     } else {
-      const size_t lds = static_cast<size_t>(ts) * h->A * sizeof(float);
+      const size_t lds = static_cast<size_t>(ts) * h->A * sizeof(double) +
+                         (static_cast<size_t>(ts) * h->A + 1) * sizeof(int);
       k_bellman<L, U, __half, float, true, float><<<nb, kBlock, lds, h->stream>>>(
           h->S, h->A, ts, h->row_ptr, h->col, h->val16, h->corr16, h->cost,
           static_cast<const float*>(v), h->gamma, Tv, pi, static_cast<float*>(r0), part);

@@ -92,6 +92,13 @@ def load(path=LIB_PATH):
     if not os.path.exists(path):
         raise RuntimeError(f"{path} is not built; run __graft_entry__.build() "
                            "(python paper_2502_14474_amd/build.py)")
+    # PyTorch ships its own HIP runtime under the same soname.  Loading torch
+    # first lets libmdp.so bind to that one copy; loading libmdp.so first would
+    # put a second HIP runtime into the process, and only one can own the GPU.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = C.CDLL(path)
     for name, (res, args) in SIGNATURES.items():
         fn = getattr(lib, name)
