@@ -16,6 +16,7 @@ tolerance).
 from .mdp_oracle import (  # noqa: F401
     to_csr,
     q_values,
+    q_values_states,
     bellman,
     policy_system,
     evaluate_policy,

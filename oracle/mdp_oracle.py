@@ -43,6 +43,21 @@ def q_values(inst, v, P=None):
     return (inst.cost + inst.gamma * (P @ v)).reshape(inst.S, inst.A)
 
 
+def q_values_states(inst, v, states):
+    """Q_v(s, a) for the given states only, shape (len(states), A): each row's
+    sum over its stored entries, taken straight from the CSR arrays.  For
+    spot checks on instances too large to handle whole."""
+    v = np.asarray(v, np.float64)
+    states = np.asarray(states, np.int64)
+    Q = np.empty((states.size, inst.A))
+    for i, s in enumerate(states):
+        for a in range(inst.A):
+            r = s * inst.A + a
+            lo, hi = inst.row_ptr[r], inst.row_ptr[r + 1]
+            Q[i, a] = inst.cost[r] + inst.gamma * np.dot(inst.val[lo:hi], v[inst.col[lo:hi]])
+    return Q
+
+
 def bellman(inst, v, P=None):
     """One Bellman sweep: (T v, greedy policy, ||T v - v||_inf).
 

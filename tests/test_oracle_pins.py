@@ -315,3 +315,12 @@ def test_policy_parity_rule():
     assert ok["mismatch_outside_band"] == 0 and ok["not_tau_optimal"] == 0 and ok["ties_1e9"] == 1
     bad = oracle.policy_parity(None, Q, np.array([0, 0]), pi_star, tau=1e-9)
     assert bad["mismatch_outside_band"] == 1 and bad["not_tau_optimal"] == 1
+
+
+def test_q_values_states_matches_full_q():
+    inst = config2(S=2000, A=4, seed=9)
+    v = np.random.default_rng(2).standard_normal(inst.S)
+    states = np.array([0, 5, 1999, 777])
+    Q = oracle.q_values(inst, v)
+    np.testing.assert_allclose(oracle.q_values_states(inst, v, states), Q[states], rtol=1e-13,
+                               atol=1e-13)
