@@ -158,6 +158,19 @@ mdp_status mdp_policy_eval(mdp_t h, const int32_t* policy, const double* v0, dou
 mdp_status mdp_solve(mdp_t h, const double* v0, double* v, int32_t* policy,
                      const mdp_solve_opts* opt, mdp_stats* stats);
 
+/* Batched inexact policy iteration: solve n MDPs (handles on one device)
+ * together.  Each round advances every unfinished MDP by one phase (a Bellman
+ * sweep, or one GMRES cycle with its restart) in persistent kernels that walk
+ * a table of (MDP, tile) work items; the cycle's Arnoldi steps are replayed
+ * from captured HIP graphs.  Every MDP gets bitwise the same v, policy and
+ * statistics as mdp_solve would give it alone (same kernels bodies, tiling,
+ * reduction order and decisions).  v0 may be NULL (all zero) or hold n
+ * pointers (each NULL or double[S_i]); v[i] (double[S_i]) and policy[i]
+ * (int32[S_i]) receive the results; stats may be NULL or point to n structs.
+ * GMRES only (MDP_E_NOTSUP for Richardson).  Runs on handles[0]'s stream. */
+mdp_status mdp_solve_batch(mdp_t* handles, int32_t n, const double* const* v0, double* const* v,
+                           int32_t* const* policy, const mdp_solve_opts* opt, mdp_stats* stats);
+
 /* Sizes and placement of a handle (any pointer may be NULL). */
 mdp_status mdp_info(mdp_t h, int64_t* S, int32_t* A, int64_t* nnz, int32_t* lanes_per_row,
                     int64_t* device_bytes);

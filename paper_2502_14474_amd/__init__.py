@@ -14,6 +14,7 @@ from .native import (MDP_FP64, MDP_MIXED_FP32, MDP_MIXED_FP16, MDP_INNER_GMRES, 
                      MDP_W_MAXITER, MDPError)
 
 __all__ = ["mdp_create", "mdp_bellman", "mdp_policy_apply", "mdp_policy_eval", "mdp_solve",
+           "mdp_solve_batch",
            "mdp_destroy", "mdp_info", "mdp_autotune", "mdp_profile", "mdp_profile_read",
            "mdp_last_error", "MDP", "MDPError"]
 
@@ -157,6 +158,40 @@ def mdp_solve(h, v, policy, v0=None, inner=MDP_INNER_GMRES, restart=30, precisio
     d = _stats_dict(st, hist)
     d["status"] = status
     return d
+
+
+def _solve_opts(lib, inner=MDP_INNER_GMRES, restart=30, precision=MDP_FP64, alpha=1e-4, atol=1e-8,
+                rtol_cert=0.0, max_outer=1000, max_inner=10000, sync_every=0):
+    o = native.SolveOpts()
+    lib.mdp_default_solve_opts(C.byref(o))
+    o.inner, o.restart, o.precision, o.alpha, o.atol = inner, restart, precision, alpha, atol
+    o.rtol_cert, o.max_outer, o.max_inner, o.sync_every = rtol_cert, max_outer, max_inner, sync_every
+    return o
+
+
+def mdp_solve_batch(handles, vs, pis, v0s=None, history_cap=1024, **opts):
+    """Solve several MDPs together; vs/pis are per-handle outputs.  Returns
+    (status, list of per-MDP stats dicts)."""
+    lib = native.load()
+    n = len(handles)
+    o = _solve_opts(lib, **opts)
+    H = (C.c_void_p * n)(*[h.value if isinstance(h, C.c_void_p) else h for h in handles])
+    V = (C.c_void_p * n)(*[_ptr(x, np.float64, name="v") for x in vs])
+    P = (C.c_void_p * n)(*[_ptr(x, np.int32, name="policy") for x in pis])
+    V0 = None if v0s is None else (C.c_void_p * n)(*[_ptr(x, np.float64, name="v0") for x in v0s])
+    stats = (native.Stats * n)()
+    hists = []
+    for i in range(n):
+        stats[i].struct_size = C.sizeof(native.Stats)
+        if history_cap:
+            hb = (C.c_double * history_cap)()
+            hists.append(hb)
+            stats[i].history = C.cast(hb, C.POINTER(C.c_double))
+            stats[i].history_cap = history_cap
+        else:
+            hists.append(None)
+    status = native.check(lib.mdp_solve_batch(H, n, V0, V, P, C.byref(o), stats))
+    return status, [_stats_dict(stats[i], hists[i]) for i in range(n)]
 
 
 class MDP:

@@ -6,9 +6,11 @@
 #include <cmath>
 #include <cstring>
 #include <limits>
+#include <memory>
 #include <thread>
 #include <vector>
 
+#include "batch.h"
 #include "internal.h"
 
 namespace mdp {
@@ -31,17 +33,6 @@ struct BusyGuard {
 double now_ms() {
   using namespace std::chrono;
   return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
-}
-
-bool is_device_ptr(const void* p) {
-  if (!p) return false;
-  hipPointerAttribute_t a;
-  std::memset(&a, 0, sizeof(a));
-  if (hipPointerGetAttributes(&a, p) != hipSuccess) {
-    (void)hipGetLastError();
-    return false;
-  }
-  return a.type == hipMemoryTypeDevice;
 }
 
 template <typename T>
@@ -101,41 +92,6 @@ mdp_status validate_host(int64_t S, int32_t A, const int64_t* rp, const int32_t*
   return MDP_OK;
 }
 
-mdp_status sync_ctl(mdp_handle* h) {
-  MDP_HIP(hipMemcpyAsync(h->ctl_host, h->ctl, kCtlHeaderBytes, hipMemcpyDeviceToHost, h->stream));
-  MDP_HIP(hipStreamSynchronize(h->stream));
-  return MDP_OK;
-}
-
-mdp_status ensure_basis(mdp_handle* h, Prec prec, int m) {
-  if (prec == kF64) {
-    if (h->basis_m64 >= m) return MDP_OK;
-    dev_free(h->U64);
-    MDP_HIP(dev_alloc(h, &h->U64, static_cast<size_t>(m + 1) * h->ldu));
-    h->basis_m64 = m;
-  } else {
-    if (h->basis_m32 >= m) return MDP_OK;
-    dev_free(h->U32);
-    MDP_HIP(dev_alloc(h, &h->U32, static_cast<size_t>(m + 1) * h->ldu));
-    h->basis_m32 = m;
-  }
-  return MDP_OK;
-}
-
-mdp_status ensure_lowp(mdp_handle* h, Prec prec) {
-  if (prec == kF32 && !h->val32) {
-    MDP_HIP(dev_alloc(h, &h->val32, h->nnz));
-    MDP_HIP(launch_build_lowp(h, MDP_BUILD_FP32));
-  }
-  if (prec == kF16 && !h->val16) {
-    MDP_HIP(dev_alloc(h, &h->val16, h->nnz));
-    MDP_HIP(dev_alloc(h, &h->corr16, h->rows));
-    MDP_HIP(launch_build_lowp(h, MDP_BUILD_FP16));
-  }
-  if (prec != kF64 && !h->v32) MDP_HIP(dev_alloc(h, &h->v32, h->S));
-  return MDP_OK;
-}
-
 // Copy a caller policy to device memory and check its range.
 mdp_status load_policy(mdp_handle* h, const int32_t* policy, int32_t* dst) {
   if (!policy) return fail(MDP_E_INVAL, "policy is NULL");
@@ -173,10 +129,6 @@ int default_lanes(double mean_row) {
   while (L < 64 && L < mean_row) L <<= 1;
   return L;
 }
-
-Prec prec_of(int p) { return p == MDP_MIXED_FP16 ? kF16 : (p == MDP_MIXED_FP32 ? kF32 : kF64); }
-int bval_of(Prec p) { return p == kF64 ? 8 : (p == kF32 ? 4 : 2); }
-double floor_of(Prec p) { return p == kF64 ? 0.0 : (p == kF32 ? 1e-6 : 1e-3); }
 
 struct InnerResult {
   int64_t steps = 0;
@@ -274,6 +226,56 @@ void stats_begin(mdp_stats* st) {
 bool stats_ok(const mdp_stats* st) { return !st || st->struct_size >= sizeof(mdp_stats); }
 
 }  // namespace
+
+bool is_device_ptr(const void* p) {
+  if (!p) return false;
+  hipPointerAttribute_t a;
+  std::memset(&a, 0, sizeof(a));
+  if (hipPointerGetAttributes(&a, p) != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  return a.type == hipMemoryTypeDevice;
+}
+
+mdp_status sync_ctl(mdp_handle* h) {
+  MDP_HIP(hipMemcpyAsync(h->ctl_host, h->ctl, kCtlHeaderBytes, hipMemcpyDeviceToHost, h->stream));
+  MDP_HIP(hipStreamSynchronize(h->stream));
+  return MDP_OK;
+}
+
+mdp_status ensure_basis(mdp_handle* h, Prec prec, int m) {
+  if (prec == kF64) {
+    if (h->basis_m64 >= m) return MDP_OK;
+    dev_free(h->U64);
+    MDP_HIP(dev_alloc(h, &h->U64, static_cast<size_t>(m + 1) * h->ldu));
+    h->basis_m64 = m;
+  } else {
+    if (h->basis_m32 >= m) return MDP_OK;
+    dev_free(h->U32);
+    MDP_HIP(dev_alloc(h, &h->U32, static_cast<size_t>(m + 1) * h->ldu));
+    h->basis_m32 = m;
+  }
+  return MDP_OK;
+}
+
+mdp_status ensure_lowp(mdp_handle* h, Prec prec) {
+  if (prec == kF32 && !h->val32) {
+    MDP_HIP(dev_alloc(h, &h->val32, h->nnz));
+    MDP_HIP(launch_build_lowp(h, MDP_BUILD_FP32));
+  }
+  if (prec == kF16 && !h->val16) {
+    MDP_HIP(dev_alloc(h, &h->val16, h->nnz));
+    MDP_HIP(dev_alloc(h, &h->corr16, h->rows));
+    MDP_HIP(launch_build_lowp(h, MDP_BUILD_FP16));
+  }
+  if (prec != kF64 && !h->v32) MDP_HIP(dev_alloc(h, &h->v32, h->S));
+  return MDP_OK;
+}
+
+Prec prec_of(int p) { return p == MDP_MIXED_FP16 ? kF16 : (p == MDP_MIXED_FP32 ? kF32 : kF64); }
+int bval_of(Prec p) { return p == kF64 ? 8 : (p == kF32 ? 4 : 2); }
+double floor_of(Prec p) { return p == kF64 ? 0.0 : (p == kF32 ? 1e-6 : 1e-3); }
 
 double bytes_sweep(const mdp_handle* h, int bval, int bv, bool r0, int br) {
   // CSR values + columns, row offsets, costs, v gathered (counted once), Tv and pi out
@@ -788,6 +790,94 @@ mdp_status mdp_solve(mdp_t h, const double* v0, double* v, int32_t* policy,
     stats->time_ms = now_ms() - t0;
   }
   return converged ? MDP_OK : MDP_W_MAXITER;
+}
+
+mdp_status mdp_solve_batch(mdp_t* handles, int32_t n, const double* const* v0, double* const* v,
+                           int32_t* const* policy, const mdp_solve_opts* opt, mdp_stats* stats) {
+  clear_error();
+  const double t0 = now_ms();
+  if (!handles || n < 1 || !v || !policy) return fail(MDP_E_INVAL, "bad batch arguments");
+  mdp_solve_opts o;
+  mdp_default_solve_opts(&o);
+  if (opt) {
+    if (opt->struct_size < sizeof(mdp_solve_opts)) return fail(MDP_E_INVAL, "mdp_solve_opts.struct_size too small");
+    o = *opt;
+  }
+  if (o.inner != MDP_INNER_GMRES) return fail(MDP_E_NOTSUP, "batched solves use GMRES");
+  if (o.restart < 1 || o.restart > kMaxRestart) return fail(MDP_E_INVAL, "restart must lie in [1,64]");
+  if (o.precision < MDP_FP64 || o.precision > MDP_MIXED_FP16) return fail(MDP_E_INVAL, "unknown precision");
+  if (!(o.alpha > 0.0 && o.alpha < 1.0)) return fail(MDP_E_INVAL, "alpha must lie in (0,1)");
+  if (!(o.atol > 0.0) || o.max_outer < 0 || o.max_inner < 1) return fail(MDP_E_INVAL, "bad tolerance or caps");
+  for (int i = 0; i < n; ++i) {
+    if (!handles[i] || !v[i] || !policy[i]) return fail(MDP_E_INVAL, "NULL handle or output in batch");
+    if (handles[i]->device != handles[0]->device) return fail(MDP_E_INVAL, "batch spans devices");
+    for (int j = 0; j < i; ++j)
+      if (handles[j] == handles[i]) return fail(MDP_E_INVAL, "handle listed twice in batch");
+    if (stats && !stats_ok(stats + i)) return fail(MDP_E_INVAL, "mdp_stats.struct_size too small");
+  }
+  std::vector<std::unique_ptr<BusyGuard>> guards;
+  for (int i = 0; i < n; ++i) {
+    guards.emplace_back(new BusyGuard(handles[i]));
+    if (!guards.back()->ok) return fail(MDP_E_STATE, "handle in batch is busy");
+  }
+  const Prec prec = prec_of(o.precision);
+  std::vector<BatchItem> items(n);
+  for (int i = 0; i < n; ++i) {
+    mdp_handle* h = handles[i];
+    if (stats) stats_begin(stats + i);
+    MDP_TRY(ensure_basis(h, prec == kF64 ? kF64 : kF32, o.restart));
+    if (prec != kF64) MDP_TRY(ensure_lowp(h, prec));
+    MDP_TRY(load_vec(h, v0 ? v0[i] : nullptr, h->v));
+    MDP_HIP(launch_ctl_reset(h, 0.0));
+    MDP_HIP(hipStreamSynchronize(h->stream));
+    BatchItem& it = items[i];
+    it.h = h;
+    it.alpha = o.alpha;
+    it.prev_res = std::numeric_limits<double>::infinity();
+    it.prev_lowp_res = std::numeric_limits<double>::infinity();
+    it.lowp_sweep = prec != kF64;
+  }
+  BatchEngine eng;
+  eng.stream = handles[0]->stream;
+  eng.prec = prec;
+  MDP_TRY(eng.reserve(n));
+  for (auto& it : items) eng.items.push_back(&it);
+  for (;;) {
+    bool left = false;
+    for (auto& it : items) left = left || it.state != BatchItem::kDone;
+    if (!left) break;
+    MDP_TRY(eng.round(o));
+  }
+  mdp_status worst = MDP_OK;
+  for (int i = 0; i < n; ++i) {
+    BatchItem& it = items[i];
+    mdp_handle* h = it.h;
+    MDP_HIP(hipMemcpyAsync(v[i], h->v, h->S * sizeof(double), hipMemcpyDefault, eng.stream));
+    MDP_HIP(hipMemcpyAsync(policy[i], h->pi, h->S * sizeof(int32_t), hipMemcpyDefault, eng.stream));
+    if (it.status < 0 && worst >= 0) {
+      worst = it.status;
+      fail(it.status, "batch item " + std::to_string(i) + " failed with a non-finite residual");
+    } else if (it.status == MDP_W_MAXITER && worst == MDP_OK) {
+      worst = MDP_W_MAXITER;
+    }
+    if (stats) {
+      mdp_stats* st = stats + i;
+      st->outer_iters = it.k;
+      st->inner_iters = it.inner;
+      st->bellman_sweeps = it.sweeps;
+      st->policy_applies = it.applies;
+      st->refinements = it.refinements;
+      st->residual = it.res;
+      st->bytes = it.bytes;
+      for (double r : it.history)
+        if (st->history && st->history_len < st->history_cap) st->history[st->history_len++] = r;
+    }
+  }
+  MDP_HIP(hipStreamSynchronize(eng.stream));
+  const double dt = now_ms() - t0;
+  if (stats)
+    for (int i = 0; i < n; ++i) stats[i].time_ms = dt;
+  return worst;
 }
 
 mdp_status mdp_profile(mdp_t h, int32_t enable) {

@@ -158,6 +158,15 @@ constexpr int kSweepRows = MDP_SWEEP_ROWS;
 inline int sweep_tile_states(int A) { return A >= kSweepRows ? 1 : kSweepRows / A; }
 size_t partials_doubles(int64_t S, int A, int m);
 
+// Host helpers shared by the single and the batched drivers (api.cpp).
+bool is_device_ptr(const void* p);
+mdp_status sync_ctl(mdp_handle* h);
+mdp_status ensure_basis(mdp_handle* h, Prec prec, int m);
+mdp_status ensure_lowp(mdp_handle* h, Prec prec);
+Prec prec_of(int p);
+int bval_of(Prec p);
+double floor_of(Prec p);
+
 // Algorithmic bytes of one launch (P_pi row count estimated by the mean row length).
 double bytes_sweep(const mdp_handle* h, int bval, int bv, bool r0, int br);
 double bytes_apply(const mdp_handle* h, int bval, int bx, int by);

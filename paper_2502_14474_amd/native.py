@@ -71,6 +71,9 @@ SIGNATURES = {
                                   C.POINTER(EvalOpts), C.POINTER(Stats)]),
     "mdp_solve": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                             C.POINTER(SolveOpts), C.POINTER(Stats)]),
+    "mdp_solve_batch": (C.c_int, [C.POINTER(C.c_void_p), C.c_int32, C.POINTER(C.c_void_p),
+                                  C.POINTER(C.c_void_p), C.POINTER(C.c_void_p),
+                                  C.POINTER(SolveOpts), C.POINTER(Stats)]),
     "mdp_info": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int32),
                            C.POINTER(C.c_int64), C.POINTER(C.c_int32), C.POINTER(C.c_int64)]),
     "mdp_autotune": (C.c_int, [C.c_void_p, C.POINTER(C.c_int32)]),

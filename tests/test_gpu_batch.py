@@ -1,0 +1,83 @@
+"""Batched solves: every MDP must come out bitwise the same alone and in the
+batch (same kernels bodies, tiling, reduction order and decisions), and match
+the oracle."""
+import numpy as np
+import pytest
+
+import oracle
+from workloads import config1, config2, config3, config4, config5_instance, config5_requests
+
+pytestmark = pytest.mark.gpu
+
+
+def _mix():
+    reqs = [r for r in config5_requests(400, seed=3) if r["S"] <= 30000][:5]
+    insts = [config5_instance(r) for r in reqs]
+    insts += [config1(S=700, A=3, k=6, seed=4), config2(S=9000, A=4, seed=5),
+              config3(H=40, W=50, seed=6), config4(S=5000, A=8, seed=7)]
+    return insts
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_batch_bitwise_equals_alone(precision):
+    import paper_2502_14474_amd as m
+    insts = _mix()
+    print(f"[case] batch of {len(insts)} MDPs precision={precision}", flush=True)
+    handles = [m.mdp_create(i.S, i.A, i.row_ptr, i.col, i.val, i.cost, i.gamma,
+                            low_precision=1 if precision else 0) for i in insts]
+    try:
+        alone = []
+        for inst, h in zip(insts, handles):
+            v = np.empty(inst.S)
+            pi = np.empty(inst.S, np.int32)
+            st = m.mdp_solve(h, v, pi, precision=precision, alpha=1e-2, max_inner=20000)
+            alone.append((v, pi, st))
+        vs = [np.empty(i.S) for i in insts]
+        pis = [np.empty(i.S, np.int32) for i in insts]
+        status, sts = m.mdp_solve_batch(handles, vs, pis, precision=precision, alpha=1e-2,
+                                        max_inner=20000)
+    finally:
+        for h in handles:
+            m.mdp_destroy(h)
+    assert status == 0
+    for k, (inst, (v, pi, st)) in enumerate(zip(insts, alone)):
+        assert st["status"] == 0
+        assert np.array_equal(vs[k], v), (k, inst.name, np.max(np.abs(vs[k] - v)))
+        assert np.array_equal(pis[k], pi), k
+        for key in ("outer_iters", "inner_iters", "bellman_sweeps", "policy_applies"):
+            assert sts[k][key] == st[key], (k, key, sts[k][key], st[key])
+        assert sts[k]["history"] == st["history"]
+
+
+def test_batch_matches_oracle():
+    import paper_2502_14474_amd as m
+    insts = [config1(S=500, seed=s) for s in range(6)] + [config2(S=4000, A=3, seed=9)]
+    handles = [m.mdp_create(i.S, i.A, i.row_ptr, i.col, i.val, i.cost, i.gamma) for i in insts]
+    try:
+        vs = [np.empty(i.S) for i in insts]
+        pis = [np.empty(i.S, np.int32) for i in insts]
+        status, sts = m.mdp_solve_batch(handles, vs, pis, rtol_cert=1e-10)
+    finally:
+        for h in handles:
+            m.mdp_destroy(h)
+    assert status == 0
+    for inst, v, pi in zip(insts, vs, pis):
+        ref = oracle.policy_iteration(inst, method="auto" if inst.S <= 2500 else "certified")
+        assert np.max(np.abs(v - ref["v"])) / np.max(np.abs(ref["v"])) <= 1e-9
+        Q = oracle.q_values(inst, ref["v"])
+        pp = oracle.policy_parity(inst, Q, pi, ref["pi"], 1e-9)
+        assert pp["mismatch_outside_band"] == 0 and pp["not_tau_optimal"] == 0
+
+
+def test_batch_rejects_bad_input():
+    import paper_2502_14474_amd as m
+    inst = config1(S=100, seed=1)
+    h = m.mdp_create(inst.S, inst.A, inst.row_ptr, inst.col, inst.val, inst.cost, inst.gamma)
+    try:
+        v, pi = np.empty(inst.S), np.empty(inst.S, np.int32)
+        with pytest.raises(m.MDPError):
+            m.mdp_solve_batch([h, h], [v, v], [pi, pi])
+        with pytest.raises(m.MDPError):
+            m.mdp_solve_batch([h], [v], [pi], inner=1)
+    finally:
+        m.mdp_destroy(h)
