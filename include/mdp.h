@@ -171,6 +171,57 @@ mdp_status mdp_solve(mdp_t h, const double* v0, double* v, int32_t* policy,
 mdp_status mdp_solve_batch(mdp_t* handles, int32_t n, const double* const* v0, double* const* v,
                            int32_t* const* policy, const mdp_solve_opts* opt, mdp_stats* stats);
 
+/* ---- serving: continuous batching of solve requests ----------------------
+ * A server owns a worker thread on one GPU.  Submitted MDPs wait in a queue;
+ * the worker admits them while the estimated device footprint of the resident
+ * set stays within hbm_budget_bytes and at most max_batch are resident, keeps
+ * admitted MDPs and their iterates resident, and advances all of them with
+ * the batched engine (see mdp_solve_batch), one round at a time.  Requests
+ * that arrive while others run join at the next round; finished ones leave,
+ * freeing their memory.  A request's v and policy are bitwise those of
+ * mdp_solve on the same MDP with the server's solve options. */
+typedef struct mdp_server* mdp_server_t;
+
+typedef struct {
+  size_t struct_size;        /* sizeof(mdp_server_opts) */
+  void* stream;              /* hipStream_t for the worker; NULL: its own */
+  int64_t hbm_budget_bytes;  /* admission limit on resident device bytes (default 64 GiB) */
+  int32_t device;            /* HIP device; -1: the current device */
+  int32_t max_batch;         /* most MDPs resident at once (default 256) */
+  mdp_solve_opts solve;      /* GMRES only; default precision MDP_MIXED_FP32 */
+} mdp_server_opts;
+
+typedef struct {
+  size_t struct_size;        /* sizeof(mdp_request_stats) */
+  double submit_ms;          /* server clock (ms since creation) at submission */
+  double admit_ms;           /* ... when the MDP became resident */
+  double finish_ms;          /* ... when its result was ready */
+  int64_t outer_iters, inner_iters, bellman_sweeps;
+  double residual;           /* final ||T v - v||_inf */
+  double bytes;              /* algorithmic bytes of its kernels */
+} mdp_request_stats;
+
+void mdp_default_server_opts(mdp_server_opts* o);
+mdp_status mdp_server_create(const mdp_server_opts* opt, mdp_server_t* out);
+/* Queue a solve.  The MDP (host arrays, layout as for mdp_create) is copied
+ * and validated-by-shape at submission; *request_id identifies it.
+ * MDP_E_NOMEM if its footprint alone exceeds the budget. */
+mdp_status mdp_server_submit(mdp_server_t s, int64_t S, int32_t A, const int64_t* row_ptr,
+                             const int32_t* col, const double* val, const double* cost,
+                             double gamma, int64_t* request_id);
+/* *done = 1 once the request's result is ready. */
+mdp_status mdp_server_poll(mdp_server_t s, int64_t request_id, int32_t* done);
+/* Block until the request is done, copy v (double[S]) and policy (int32[S])
+ * to host memory (either may be NULL), fill stats (may be NULL) and forget
+ * the request.  Returns the request's solve status. */
+mdp_status mdp_server_wait(mdp_server_t s, int64_t request_id, double* v, int32_t* policy,
+                           mdp_request_stats* stats);
+/* Queue length, resident count and bytes, rounds run so far (any may be NULL). */
+mdp_status mdp_server_info(mdp_server_t s, int64_t* queued, int64_t* resident,
+                           int64_t* resident_bytes, int64_t* rounds);
+/* Finish the resident requests, drop queued ones, stop the worker, free all. */
+mdp_status mdp_server_destroy(mdp_server_t s);
+
 /* Sizes and placement of a handle (any pointer may be NULL). */
 mdp_status mdp_info(mdp_t h, int64_t* S, int32_t* A, int64_t* nnz, int32_t* lanes_per_row,
                     int64_t* device_bytes);

@@ -14,7 +14,7 @@ from .native import (MDP_FP64, MDP_MIXED_FP32, MDP_MIXED_FP16, MDP_INNER_GMRES, 
                      MDP_W_MAXITER, MDPError)
 
 __all__ = ["mdp_create", "mdp_bellman", "mdp_policy_apply", "mdp_policy_eval", "mdp_solve",
-           "mdp_solve_batch",
+           "mdp_solve_batch", "Server",
            "mdp_destroy", "mdp_info", "mdp_autotune", "mdp_profile", "mdp_profile_read",
            "mdp_last_error", "MDP", "MDPError"]
 
@@ -249,3 +249,61 @@ class MDP:
         st = mdp_solve(self.h, v, pi, None if v0 is None else np.ascontiguousarray(v0, np.float64),
                        **kw)
         return v, pi, st
+
+
+class Server:
+    """Continuous-batching solve server (mdp_server_* in include/mdp.h)."""
+
+    def __init__(self, hbm_budget_bytes=64 << 30, max_batch=256, device=-1, stream=None,
+                 **solve_opts):
+        lib = native.load()
+        o = native.ServerOpts()
+        lib.mdp_default_server_opts(C.byref(o))
+        o.hbm_budget_bytes, o.max_batch, o.device, o.stream = hbm_budget_bytes, max_batch, device, stream
+        solve_opts.setdefault("precision", MDP_MIXED_FP32)
+        o.solve = _solve_opts(lib, **solve_opts)
+        self.s = C.c_void_p()
+        native.check(lib.mdp_server_create(C.byref(o), C.byref(self.s)))
+        self.S = {}
+
+    def submit(self, inst):
+        rid = C.c_int64()
+        native.check(native.load().mdp_server_submit(
+            self.s, inst.S, inst.A, _ptr(inst.row_ptr, np.int64), _ptr(inst.col, np.int32),
+            _ptr(inst.val, np.float64), _ptr(inst.cost, np.float64), inst.gamma, C.byref(rid)))
+        self.S[rid.value] = inst.S
+        return rid.value
+
+    def poll(self, rid):
+        d = C.c_int32()
+        native.check(native.load().mdp_server_poll(self.s, rid, C.byref(d)))
+        return bool(d.value)
+
+    def wait(self, rid):
+        S = self.S.pop(rid)
+        v = np.empty(S)
+        pi = np.empty(S, np.int32)
+        st = native.RequestStats()
+        st.struct_size = C.sizeof(native.RequestStats)
+        status = native.check(native.load().mdp_server_wait(self.s, rid, v.ctypes.data,
+                                                            pi.ctypes.data, C.byref(st)))
+        d = {k: getattr(st, k) for k, _ in native.RequestStats._fields_ if k != "struct_size"}
+        d["status"] = status
+        return v, pi, d
+
+    def info(self):
+        q, r, b, n = C.c_int64(), C.c_int64(), C.c_int64(), C.c_int64()
+        native.check(native.load().mdp_server_info(self.s, C.byref(q), C.byref(r), C.byref(b),
+                                                   C.byref(n)))
+        return dict(queued=q.value, resident=r.value, resident_bytes=b.value, rounds=n.value)
+
+    def close(self):
+        if self.s is not None and self.s.value:
+            native.check(native.load().mdp_server_destroy(self.s))
+        self.s = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()

@@ -49,49 +49,6 @@ void dev_free(T*& p) {
   p = nullptr;
 }
 
-// ---- validation on host arrays ----------------------------------------------
-mdp_status validate_host(int64_t S, int32_t A, const int64_t* rp, const int32_t* col,
-                         const double* val, const double* cost) {
-  const int64_t rows = S * A;
-  if (rp[0] != 0) return fail(MDP_E_INVAL, "row_ptr[0] must be 0");
-  for (int64_t r = 0; r < rows; ++r)
-    if (rp[r + 1] <= rp[r])
-      return fail(MDP_E_INVAL, "row_ptr must increase (row " + std::to_string(r) +
-                                   " of state " + std::to_string(r / A) + " is empty or decreasing)");
-  const int64_t nnz = rp[rows];
-  if (nnz >= (int64_t{1} << 31)) return fail(MDP_E_NOTSUP, "nnz must be below 2^31");
-  for (int64_t r = 0; r < rows; ++r)
-    if (!std::isfinite(cost[r])) return fail(MDP_E_INVAL, "non-finite cost at row " + std::to_string(r));
-  const unsigned nt = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
-  std::vector<int64_t> bad(nt, -1);
-  std::vector<int> why(nt, 0);
-  std::vector<std::thread> th;
-  for (unsigned t = 0; t < nt; ++t) {
-    th.emplace_back([&, t]() {
-      const int64_t r0 = rows * t / nt, r1 = rows * (t + 1) / nt;
-      for (int64_t r = r0; r < r1; ++r) {
-        double sum = 0.0;
-        for (int64_t e = rp[r]; e < rp[r + 1]; ++e) {
-          if (col[e] < 0 || col[e] >= S) { bad[t] = r; why[t] = 1; return; }
-          if (!(val[e] >= 0.0) || !std::isfinite(val[e])) { bad[t] = r; why[t] = 2; return; }
-          sum += val[e];
-        }
-        const double len = static_cast<double>(rp[r + 1] - rp[r]);
-        if (std::fabs(sum - 1.0) > 1e-12 * std::max(1.0, len)) { bad[t] = r; why[t] = 3; return; }
-      }
-    });
-  }
-  for (auto& x : th) x.join();
-  for (unsigned t = 0; t < nt; ++t) {
-    if (bad[t] < 0) continue;
-    const char* w = why[t] == 1 ? "column index outside [0,S)"
-                    : why[t] == 2 ? "negative or non-finite probability"
-                                  : "row does not sum to 1";
-    return fail(MDP_E_INVAL, std::string(w) + " in row " + std::to_string(bad[t]));
-  }
-  return MDP_OK;
-}
-
 // Copy a caller policy to device memory and check its range.
 mdp_status load_policy(mdp_handle* h, const int32_t* policy, int32_t* dst) {
   if (!policy) return fail(MDP_E_INVAL, "policy is NULL");
@@ -226,6 +183,49 @@ void stats_begin(mdp_stats* st) {
 bool stats_ok(const mdp_stats* st) { return !st || st->struct_size >= sizeof(mdp_stats); }
 
 }  // namespace
+
+// ---- validation on host arrays ----------------------------------------------
+mdp_status validate_host(int64_t S, int32_t A, const int64_t* rp, const int32_t* col,
+                         const double* val, const double* cost) {
+  const int64_t rows = S * A;
+  if (rp[0] != 0) return fail(MDP_E_INVAL, "row_ptr[0] must be 0");
+  for (int64_t r = 0; r < rows; ++r)
+    if (rp[r + 1] <= rp[r])
+      return fail(MDP_E_INVAL, "row_ptr must increase (row " + std::to_string(r) +
+                                   " of state " + std::to_string(r / A) + " is empty or decreasing)");
+  const int64_t nnz = rp[rows];
+  if (nnz >= (int64_t{1} << 31)) return fail(MDP_E_NOTSUP, "nnz must be below 2^31");
+  for (int64_t r = 0; r < rows; ++r)
+    if (!std::isfinite(cost[r])) return fail(MDP_E_INVAL, "non-finite cost at row " + std::to_string(r));
+  const unsigned nt = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+  std::vector<int64_t> bad(nt, -1);
+  std::vector<int> why(nt, 0);
+  std::vector<std::thread> th;
+  for (unsigned t = 0; t < nt; ++t) {
+    th.emplace_back([&, t]() {
+      const int64_t r0 = rows * t / nt, r1 = rows * (t + 1) / nt;
+      for (int64_t r = r0; r < r1; ++r) {
+        double sum = 0.0;
+        for (int64_t e = rp[r]; e < rp[r + 1]; ++e) {
+          if (col[e] < 0 || col[e] >= S) { bad[t] = r; why[t] = 1; return; }
+          if (!(val[e] >= 0.0) || !std::isfinite(val[e])) { bad[t] = r; why[t] = 2; return; }
+          sum += val[e];
+        }
+        const double len = static_cast<double>(rp[r + 1] - rp[r]);
+        if (std::fabs(sum - 1.0) > 1e-12 * std::max(1.0, len)) { bad[t] = r; why[t] = 3; return; }
+      }
+    });
+  }
+  for (auto& x : th) x.join();
+  for (unsigned t = 0; t < nt; ++t) {
+    if (bad[t] < 0) continue;
+    const char* w = why[t] == 1 ? "column index outside [0,S)"
+                    : why[t] == 2 ? "negative or non-finite probability"
+                                  : "row does not sum to 1";
+    return fail(MDP_E_INVAL, std::string(w) + " in row " + std::to_string(bad[t]));
+  }
+  return MDP_OK;
+}
 
 bool is_device_ptr(const void* p) {
   if (!p) return false;

@@ -160,6 +160,8 @@ size_t partials_doubles(int64_t S, int A, int m);
 
 // Host helpers shared by the single and the batched drivers (api.cpp).
 bool is_device_ptr(const void* p);
+mdp_status validate_host(int64_t S, int32_t A, const int64_t* rp, const int32_t* col,
+                         const double* val, const double* cost);
 mdp_status sync_ctl(mdp_handle* h);
 mdp_status ensure_basis(mdp_handle* h, Prec prec, int m);
 mdp_status ensure_lowp(mdp_handle* h, Prec prec);

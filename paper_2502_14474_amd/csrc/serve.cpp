@@ -1,0 +1,389 @@
+// Serving loop: continuous batching of MDP solve requests on one GPU.
+//
+// Submitted requests wait in a host queue.  A worker thread admits them while
+// the estimated device footprint of the resident set stays within the HBM
+// budget (and the resident count within max_batch), keeps each admitted MDP's
+// CSR data and iterates resident, and advances all resident MDPs together one
+// round at a time with the batch engine.  Requests that arrive while others
+// are on the GPU join at the next round boundary; finished ones are copied
+// out, their memory released, and their slots reused.  Because the batch
+// engine is batch-invariant, a request's result does not depend on what else
+// was resident.
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <limits>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <thread>
+#include <vector>
+
+#include "batch.h"
+#include "internal.h"
+
+namespace mdp {
+
+struct Request {
+  int64_t id = 0;
+  int64_t S = 0;
+  int32_t A = 0;
+  double gamma = 0;
+  std::vector<int64_t> row_ptr;
+  std::vector<int32_t> col;
+  std::vector<double> val, cost;
+  int64_t footprint = 0;
+  // results
+  std::vector<double> v;
+  std::vector<int32_t> pi;
+  mdp_request_stats st{};
+  bool done = false;
+  mdp_status status = MDP_OK;
+  std::string error;
+  // while resident
+  mdp_handle* h = nullptr;
+  BatchItem item;
+};
+
+static double clock_ms() {
+  using namespace std::chrono;
+  return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
+}
+
+// Device bytes a request will hold while resident (CSR, costs, vectors,
+// GMRES basis, reduced-precision copies, partials).
+static int64_t footprint_of(int64_t S, int32_t A, int64_t nnz, const mdp_solve_opts& o) {
+  const int64_t rows = S * A;
+  const int64_t ldu = (S + 255) / 256 * 256;
+  const bool mixed = o.precision != MDP_FP64;
+  int64_t b = nnz * 12 + (rows + 1) * 4 + rows * 8;          // CSR + costs
+  b += S * (8 * 4 + 4 * 2);                                   // v, Tv, x2, io, pi, pi_io
+  b += static_cast<int64_t>(o.restart + 1) * ldu * (mixed ? 4 : 8);
+  if (o.precision == MDP_MIXED_FP32) b += nnz * 4 + S * 4;
+  if (o.precision == MDP_MIXED_FP16) b += nnz * 2 + rows * 8 + S * 4;
+  b += static_cast<int64_t>(partials_doubles(S, A, kMaxRestart)) * 8 + sizeof(Ctl);
+  return b;
+}
+
+}  // namespace mdp
+
+struct mdp_server {
+  mdp_server_opts opts{};
+  int device = 0;
+  hipStream_t stream = nullptr;
+  std::mutex mu;
+  std::condition_variable cv_work, cv_done;
+  std::deque<mdp::Request*> queue;
+  std::map<int64_t, std::unique_ptr<mdp::Request>> all;
+  std::vector<mdp::Request*> resident;
+  int64_t next_id = 1;
+  int64_t resident_bytes = 0;
+  bool stop = false;
+  double t0 = 0;
+  std::thread worker;
+  mdp::BatchEngine eng;
+  std::string fatal;
+  int64_t rounds = 0;
+
+  void run();
+  mdp_status admit_one(mdp::Request* r);
+  void retire(mdp::Request* r);
+};
+
+using namespace mdp;
+
+void mdp_server::run() {
+  hipSetDevice(device);
+  std::unique_lock<std::mutex> lk(mu);
+  for (;;) {
+    // admission
+    while (!queue.empty() && static_cast<int>(resident.size()) < opts.max_batch) {
+      Request* r = queue.front();
+      if (!resident.empty() && resident_bytes + r->footprint > opts.hbm_budget_bytes) break;
+      queue.pop_front();
+      lk.unlock();
+      const mdp_status st = admit_one(r);
+      lk.lock();
+      if (st < 0) {
+        r->status = st;
+        r->error = mdp_last_error();
+        r->done = true;
+        r->st.finish_ms = clock_ms() - t0;
+        cv_done.notify_all();
+        continue;
+      }
+      resident.push_back(r);
+      resident_bytes += r->footprint;
+    }
+    if (resident.empty()) {
+      if (stop) return;
+      cv_work.wait(lk);
+      continue;
+    }
+    // one round over the resident set
+    eng.items.clear();
+    for (Request* r : resident) eng.items.push_back(&r->item);
+    lk.unlock();
+    const mdp_status st = eng.round(opts.solve);
+    lk.lock();
+    ++rounds;
+    if (st < 0) {
+      fatal = mdp_last_error();
+      for (Request* r : resident) {
+        r->status = st;
+        r->error = fatal;
+        r->done = true;
+      }
+      resident.clear();
+      cv_done.notify_all();
+      continue;
+    }
+    std::vector<Request*> keep;
+    for (Request* r : resident) {
+      if (r->item.state == BatchItem::kDone) {
+        lk.unlock();
+        retire(r);
+        lk.lock();
+        resident_bytes -= r->footprint;
+        cv_done.notify_all();
+      } else {
+        keep.push_back(r);
+      }
+    }
+    resident.swap(keep);
+  }
+}
+
+mdp_status mdp_server::admit_one(Request* r) {
+  mdp_create_opts co;
+  mdp_default_create_opts(&co);
+  co.stream = stream;
+  co.device = device;
+  co.validate = 0;  // validated at submission
+  mdp_handle* h = nullptr;
+  MDP_TRY(mdp_create(r->S, r->A, r->row_ptr.data(), r->col.data(), r->val.data(), r->cost.data(),
+                     r->gamma, &co, &h));
+  r->h = h;
+  const Prec prec = prec_of(opts.solve.precision);
+  mdp_status st = ensure_basis(h, prec == kF64 ? kF64 : kF32, opts.solve.restart);
+  if (st >= 0 && prec != kF64) st = ensure_lowp(h, prec);
+  if (st < 0) {
+    mdp_destroy(h);
+    r->h = nullptr;
+    return st;
+  }
+  hipError_t e = hipMemsetAsync(h->v, 0, h->S * sizeof(double), stream);
+  if (e == hipSuccess) e = launch_ctl_reset(h, 0.0);
+  if (e != hipSuccess) {
+    mdp_destroy(h);
+    r->h = nullptr;
+    return fail(MDP_E_DEVICE, std::string("admission: ") + hipGetErrorString(e));
+  }
+  // host copies are no longer needed once the MDP is resident
+  std::vector<int64_t>().swap(r->row_ptr);
+  std::vector<int32_t>().swap(r->col);
+  std::vector<double>().swap(r->val);
+  std::vector<double>().swap(r->cost);
+  BatchItem& it = r->item;
+  it = BatchItem();
+  it.h = h;
+  it.alpha = opts.solve.alpha;
+  it.prev_res = std::numeric_limits<double>::infinity();
+  it.prev_lowp_res = std::numeric_limits<double>::infinity();
+  it.lowp_sweep = prec != kF64;
+  r->st.admit_ms = clock_ms() - t0;
+  return MDP_OK;
+}
+
+void mdp_server::retire(Request* r) {
+  mdp_handle* h = r->h;
+  r->v.resize(h->S);
+  r->pi.resize(h->S);
+  hipError_t e = hipMemcpyAsync(r->v.data(), h->v, h->S * sizeof(double), hipMemcpyDeviceToHost, stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(r->pi.data(), h->pi, h->S * sizeof(int32_t), hipMemcpyDeviceToHost, stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(stream);
+  const BatchItem& it = r->item;
+  r->status = e != hipSuccess ? MDP_E_DEVICE : it.status;
+  if (e != hipSuccess) r->error = hipGetErrorString(e);
+  r->st.outer_iters = it.k;
+  r->st.inner_iters = it.inner;
+  r->st.bellman_sweeps = it.sweeps;
+  r->st.residual = it.res;
+  r->st.bytes = it.bytes;
+  mdp_destroy(h);
+  r->h = nullptr;
+  r->st.finish_ms = clock_ms() - t0;
+  std::lock_guard<std::mutex> g(mu);
+  r->done = true;
+}
+
+extern "C" {
+
+void mdp_default_server_opts(mdp_server_opts* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->struct_size = sizeof(*o);
+  o->device = -1;
+  o->stream = nullptr;
+  o->hbm_budget_bytes = int64_t{64} << 30;
+  o->max_batch = 256;
+  mdp_default_solve_opts(&o->solve);
+  o->solve.precision = MDP_MIXED_FP32;
+}
+
+mdp_status mdp_server_create(const mdp_server_opts* opt, mdp_server_t* out) {
+  clear_error();
+  if (!out) return fail(MDP_E_INVAL, "out is NULL");
+  *out = nullptr;
+  mdp_server_opts o;
+  mdp_default_server_opts(&o);
+  if (opt) {
+    if (opt->struct_size < sizeof(mdp_server_opts)) return fail(MDP_E_INVAL, "mdp_server_opts.struct_size too small");
+    o = *opt;
+  }
+  if (o.max_batch < 1 || o.max_batch > 65536 || o.hbm_budget_bytes <= 0)
+    return fail(MDP_E_INVAL, "bad server limits");
+  if (o.solve.inner != MDP_INNER_GMRES) return fail(MDP_E_NOTSUP, "the server uses GMRES");
+  if (o.solve.restart < 1 || o.solve.restart > kMaxRestart) return fail(MDP_E_INVAL, "restart must lie in [1,64]");
+  if (o.solve.precision < MDP_FP64 || o.solve.precision > MDP_MIXED_FP16) return fail(MDP_E_INVAL, "unknown precision");
+  if (!(o.solve.alpha > 0.0 && o.solve.alpha < 1.0) || !(o.solve.atol > 0.0))
+    return fail(MDP_E_INVAL, "bad tolerances");
+  auto* s = new mdp_server();
+  s->opts = o;
+  if (o.device >= 0) {
+    if (hipSetDevice(o.device) != hipSuccess) {
+      delete s;
+      return fail(MDP_E_DEVICE, "hipSetDevice failed");
+    }
+  }
+  if (hipGetDevice(&s->device) != hipSuccess) {
+    delete s;
+    return fail(MDP_E_DEVICE, "no HIP device");
+  }
+  if (o.stream) {
+    s->stream = static_cast<hipStream_t>(o.stream);
+  } else if (hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking) != hipSuccess) {
+    delete s;
+    return fail(MDP_E_DEVICE, "stream creation failed");
+  }
+  s->eng.stream = s->stream;
+  s->eng.prec = prec_of(o.solve.precision);
+  mdp_status st = s->eng.reserve(o.max_batch);
+  if (st < 0) {
+    if (!o.stream) (void)hipStreamDestroy(s->stream);
+    delete s;
+    return st;
+  }
+  s->t0 = clock_ms();
+  s->worker = std::thread([s]() { s->run(); });
+  *out = s;
+  return MDP_OK;
+}
+
+mdp_status mdp_server_submit(mdp_server_t s, int64_t S, int32_t A, const int64_t* row_ptr,
+                             const int32_t* col, const double* val, const double* cost,
+                             double gamma, int64_t* request_id) {
+  clear_error();
+  if (!s || !request_id) return fail(MDP_E_INVAL, "NULL argument");
+  if (S < 1 || A < 1 || !row_ptr || !col || !val || !cost) return fail(MDP_E_INVAL, "bad MDP");
+  if (!(gamma >= 0.0 && gamma < 1.0)) return fail(MDP_E_INVAL, "gamma must lie in [0,1)");
+  if (A > 4096 || S * static_cast<int64_t>(A) >= (int64_t{1} << 31) - 1)
+    return fail(MDP_E_NOTSUP, "MDP too large for one request");
+  const int64_t rows = S * A;
+  const int64_t nnz = row_ptr[rows];
+  if (nnz < rows || nnz >= (int64_t{1} << 31)) return fail(MDP_E_INVAL, "bad row_ptr");
+  MDP_TRY(validate_host(S, A, row_ptr, col, val, cost));
+  auto r = std::make_unique<Request>();
+  r->S = S;
+  r->A = A;
+  r->gamma = gamma;
+  r->row_ptr.assign(row_ptr, row_ptr + rows + 1);
+  r->col.assign(col, col + nnz);
+  r->val.assign(val, val + nnz);
+  r->cost.assign(cost, cost + rows);
+  r->footprint = footprint_of(S, A, nnz, s->opts.solve);
+  if (r->footprint > s->opts.hbm_budget_bytes)
+    return fail(MDP_E_NOMEM, "request footprint exceeds the server's HBM budget");
+  Request* raw = r.get();
+  std::lock_guard<std::mutex> g(s->mu);
+  raw->id = s->next_id++;
+  raw->st.struct_size = sizeof(mdp_request_stats);
+  raw->st.submit_ms = clock_ms() - s->t0;
+  s->all[raw->id] = std::move(r);
+  s->queue.push_back(raw);
+  *request_id = raw->id;
+  s->cv_work.notify_all();
+  return MDP_OK;
+}
+
+mdp_status mdp_server_poll(mdp_server_t s, int64_t id, int32_t* done) {
+  clear_error();
+  if (!s || !done) return fail(MDP_E_INVAL, "NULL argument");
+  std::lock_guard<std::mutex> g(s->mu);
+  auto it = s->all.find(id);
+  if (it == s->all.end()) return fail(MDP_E_INVAL, "unknown request id");
+  *done = it->second->done ? 1 : 0;
+  return MDP_OK;
+}
+
+mdp_status mdp_server_wait(mdp_server_t s, int64_t id, double* v, int32_t* policy,
+                           mdp_request_stats* stats) {
+  clear_error();
+  if (!s) return fail(MDP_E_INVAL, "NULL server");
+  if (stats && stats->struct_size < sizeof(mdp_request_stats))
+    return fail(MDP_E_INVAL, "mdp_request_stats.struct_size too small");
+  std::unique_ptr<Request> r;
+  {
+    std::unique_lock<std::mutex> lk(s->mu);
+    auto it = s->all.find(id);
+    if (it == s->all.end()) return fail(MDP_E_INVAL, "unknown request id");
+    Request* raw = it->second.get();
+    s->cv_done.wait(lk, [&]() { return raw->done; });
+    r = std::move(it->second);
+    s->all.erase(it);
+  }
+  if (r->status < 0) return fail(r->status, "request failed: " + r->error);
+  if (v) std::memcpy(v, r->v.data(), r->v.size() * sizeof(double));
+  if (policy) std::memcpy(policy, r->pi.data(), r->pi.size() * sizeof(int32_t));
+  if (stats) *stats = r->st;
+  return r->status;
+}
+
+mdp_status mdp_server_info(mdp_server_t s, int64_t* queued, int64_t* resident,
+                           int64_t* resident_bytes, int64_t* rounds) {
+  clear_error();
+  if (!s) return fail(MDP_E_INVAL, "NULL server");
+  std::lock_guard<std::mutex> g(s->mu);
+  if (queued) *queued = static_cast<int64_t>(s->queue.size());
+  if (resident) *resident = static_cast<int64_t>(s->resident.size());
+  if (resident_bytes) *resident_bytes = s->resident_bytes;
+  if (rounds) *rounds = s->rounds;
+  return MDP_OK;
+}
+
+mdp_status mdp_server_destroy(mdp_server_t s) {
+  if (!s) return MDP_OK;
+  {
+    std::lock_guard<std::mutex> g(s->mu);
+    s->stop = true;
+    // requests still queued are dropped
+    for (Request* r : s->queue) {
+      r->status = MDP_E_STATE;
+      r->error = "server destroyed";
+      r->done = true;
+    }
+    s->queue.clear();
+    s->cv_work.notify_all();
+  }
+  if (s->worker.joinable()) s->worker.join();
+  for (auto& kv : s->all)
+    if (kv.second->h) mdp_destroy(kv.second->h);
+  s->eng.release();
+  if (!s->opts.stream && s->stream) (void)hipStreamDestroy(s->stream);
+  delete s;
+  return MDP_OK;
+}
+
+}  // extern "C"

@@ -56,6 +56,18 @@ class KernelProfile(C.Structure):
                 ("ms", C.c_double * NUM_KERNEL_KINDS), ("bytes", C.c_double * NUM_KERNEL_KINDS)]
 
 
+class ServerOpts(C.Structure):
+    _fields_ = [("struct_size", C.c_size_t), ("stream", C.c_void_p),
+                ("hbm_budget_bytes", C.c_int64), ("device", C.c_int32), ("max_batch", C.c_int32),
+                ("solve", SolveOpts)]
+
+
+class RequestStats(C.Structure):
+    _fields_ = [("struct_size", C.c_size_t), ("submit_ms", C.c_double), ("admit_ms", C.c_double),
+                ("finish_ms", C.c_double), ("outer_iters", C.c_int64), ("inner_iters", C.c_int64),
+                ("bellman_sweeps", C.c_int64), ("residual", C.c_double), ("bytes", C.c_double)]
+
+
 # name -> (restype, argtypes); the exported symbols of include/mdp.h
 SIGNATURES = {
     "mdp_default_create_opts": (None, [C.POINTER(CreateOpts)]),
@@ -79,6 +91,16 @@ SIGNATURES = {
     "mdp_autotune": (C.c_int, [C.c_void_p, C.POINTER(C.c_int32)]),
     "mdp_profile": (C.c_int, [C.c_void_p, C.c_int32]),
     "mdp_profile_read": (C.c_int, [C.c_void_p, C.POINTER(KernelProfile)]),
+    "mdp_default_server_opts": (None, [C.POINTER(ServerOpts)]),
+    "mdp_server_create": (C.c_int, [C.POINTER(ServerOpts), C.POINTER(C.c_void_p)]),
+    "mdp_server_submit": (C.c_int, [C.c_void_p, C.c_int64, C.c_int32, C.c_void_p, C.c_void_p,
+                                    C.c_void_p, C.c_void_p, C.c_double, C.POINTER(C.c_int64)]),
+    "mdp_server_poll": (C.c_int, [C.c_void_p, C.c_int64, C.POINTER(C.c_int32)]),
+    "mdp_server_wait": (C.c_int, [C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p,
+                                  C.POINTER(RequestStats)]),
+    "mdp_server_info": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int64),
+                                  C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
+    "mdp_server_destroy": (C.c_int, [C.c_void_p]),
     "mdp_destroy": (C.c_int, [C.c_void_p]),
     "mdp_last_error": (C.c_char_p, []),
     "mdp_version": (C.c_char_p, []),

@@ -1,0 +1,71 @@
+"""Serving: continuous batching.  Requests submitted while others run are
+admitted as memory frees up; each result equals the request solved alone."""
+import time
+
+import numpy as np
+import pytest
+
+from workloads import config1, config2, config4, config5_instance, config5_requests
+
+pytestmark = pytest.mark.gpu
+
+
+def _requests():
+    reqs = [r for r in config5_requests(300, seed=8) if r["S"] <= 40000][:8]
+    insts = [config5_instance(r) for r in reqs]
+    insts += [config1(S=800, seed=2), config2(S=7000, A=4, seed=3), config4(S=6000, A=6, seed=4)]
+    return insts
+
+
+def _alone(inst, precision):
+    import paper_2502_14474_amd as m
+    with m.MDP.from_instance(inst, low_precision=1 if precision == 1 else 0) as h:
+        return h.solve(precision=precision, alpha=1e-2)
+
+
+@pytest.mark.parametrize("precision", [1, 0])
+def test_server_results_equal_alone_with_staggered_arrivals(precision):
+    import paper_2502_14474_amd as m
+    insts = _requests()
+    print(f"[case] server precision={precision} with {len(insts)} requests", flush=True)
+    ref = [_alone(i, precision) for i in insts]
+    with m.Server(precision=precision, alpha=1e-2, max_batch=4) as srv:
+        ids = []
+        for k, inst in enumerate(insts):
+            ids.append(srv.submit(inst))
+            if k % 3 == 2:
+                time.sleep(0.01)  # later requests arrive while earlier ones run
+        outs = [srv.wait(i) for i in ids]
+        info = srv.info()
+    assert info["resident"] == 0 and info["queued"] == 0 and info["rounds"] > 0
+    for k, ((v, pi, st), (vr, pir, str_)) in enumerate(zip(outs, ref)):
+        assert st["status"] == 0 and str_["status"] == 0
+        assert np.array_equal(v, vr), (k, np.max(np.abs(v - vr)))
+        assert np.array_equal(pi, pir), k
+        assert st["bellman_sweeps"] == str_["bellman_sweeps"]
+        assert st["inner_iters"] == str_["inner_iters"]
+        assert st["submit_ms"] <= st["admit_ms"] <= st["finish_ms"]
+
+
+def test_server_admission_under_small_budget():
+    import paper_2502_14474_amd as m
+    insts = [config1(S=3000, seed=s) for s in range(5)]
+    # a budget that holds about one request at a time: all must still finish
+    with m.Server(hbm_budget_bytes=3 << 20, max_batch=8, alpha=1e-2) as srv:
+        ids = [srv.submit(i) for i in insts]
+        outs = [srv.wait(i) for i in ids]
+    for (v, pi, st), inst in zip(outs, insts):
+        vr, pir, _ = _alone(inst, 1)
+        assert np.array_equal(v, vr) and np.array_equal(pi, pir)
+    # admissions are serialised by the budget
+    admits = sorted(st["admit_ms"] for _, _, st in outs)
+    finishes = sorted(st["finish_ms"] for _, _, st in outs)
+    assert all(a >= f - 1e-6 for a, f in zip(admits[1:], finishes[:-1]))
+
+
+def test_server_rejects_oversized_request():
+    import paper_2502_14474_amd as m
+    with m.Server(hbm_budget_bytes=1 << 16) as srv:
+        with pytest.raises(m.MDPError) as e:
+            srv.submit(config1(S=2000, seed=1))
+        assert e.value.status == m.native.MDP_E_NOMEM
