@@ -18,6 +18,32 @@ sys.path.insert(0, ROOT)
 METRIC = ("Bellman sweeps/s + HBM GB/s (% peak); solve time to ‖Tv−v‖∞≤1e-8, "
           "FP64 vs mixed")
 HBM_PEAK_GBS = 8000.0
+KERNEL_SOURCES = ("paper_2502_14474_amd/csrc/device.h", "paper_2502_14474_amd/csrc/kernels.hip")
+COUNTERS_FILE = os.path.join(ROOT, "profiles", "counters_config2_fp64.json")
+
+
+def kernel_source_sha():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def counter_traffic(kind, workload):
+    """HBM bytes per launch of a kernel class from the committed rocprofv3
+    FETCH_SIZE / WRITE_SIZE runs, or None when they were taken on other
+    kernel sources or another workload."""
+    try:
+        with open(COUNTERS_FILE) as f:
+            d = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if d.get("source_sha") != kernel_source_sha() or d.get("workload") != workload:
+        return None
+    k = d.get("kernels", {}).get(kind)
+    return None if k is None else k.get("traffic_bytes_per_launch")
 
 
 def log(*a):
@@ -36,6 +62,10 @@ def make_instance(args):
     if args.config == 4:
         return config4(S=args.S or 4_000_000, seed=args.seed)
     raise SystemExit("unknown config")
+
+
+def workload_key(inst):
+    return f"{inst.name}:S={inst.S}:A={inst.A}:nnz={inst.nnz}:seed={inst.meta.get('seed')}"
 
 
 def workload_name(inst, args):
@@ -70,6 +100,54 @@ def cpu_baseline(args, full_inst):
             "seconds_sample": dt}
 
 
+def serving_leg(args, m):
+    """Config-5 style serving load: requests from the seeded stream (S
+    log-uniform in [1e3, 1e6], A in 2..16, nnz/row in 4..32, gamma in
+    {0.9, 0.99, 0.999}), solved in mixed precision with float64 refinement by
+    the continuous-batching server.  A pool of distinct requests is generated
+    up front and cycled; first a closed-loop run measures capacity C, then an
+    open-loop Poisson stream at 0.7 C gives the latency percentiles."""
+    import numpy as np
+
+    from workloads import config5_instance, config5_requests
+    reqs = config5_requests(args.serve_pool * 4, seed=args.seed)
+    reqs = [r for r in reqs if r["S"] <= args.serve_max_states][:args.serve_pool]
+    t = time.time()
+    pool = [config5_instance(r, workers=16) for r in reqs]
+    log(f"[serve] pool of {len(pool)} requests, {sum(p.nnz for p in pool)/1e6:.0f}M nnz, "
+        f"generated in {time.time()-t:.1f}s")
+    n = args.serve_requests
+
+    def run(gaps):
+        with m.Server(precision=m.MDP_MIXED_FP32, alpha=args.alpha, atol=args.atol,
+                      max_batch=args.serve_max_batch) as srv:
+            ids = []
+            t0 = time.perf_counter()
+            nxt = t0
+            for i in range(n):
+                if gaps is not None:
+                    nxt += gaps[i]
+                    dt = nxt - time.perf_counter()
+                    if dt > 0:
+                        time.sleep(dt)
+                ids.append(srv.submit(pool[i % len(pool)]))
+            outs = [srv.wait(r) for r in ids]
+            t1 = time.perf_counter()
+        lat = np.array([o[2]["finish_ms"] - o[2]["submit_ms"] for o in outs])
+        ok = all(o[2]["status"] == 0 for o in outs)
+        return dict(solves_per_s=n / (t1 - t0), p50_ms=float(np.percentile(lat, 50)),
+                    p99_ms=float(np.percentile(lat, 99)), ok=ok, wall_s=t1 - t0)
+
+    closed = run(None)
+    cap = closed["solves_per_s"]
+    rng_gaps = np.array([r["gap"] for r in config5_requests(n, seed=args.seed + 1)])
+    open70 = run(rng_gaps / (0.7 * cap))
+    log(f"[serve] closed {closed}; open@0.7C {open70}")
+    return {"requests": n, "pool": len(pool), "pool_nnz": int(sum(p.nnz for p in pool)),
+            "precision": "mixed fp32 + fp64 refinement", "closed_loop": closed,
+            "open_loop_0.7C": open70}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -79,13 +157,21 @@ def main():
     ap.add_argument("--S", type=int, default=0)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--restart", type=int, default=30)
-    ap.add_argument("--alpha", type=float, default=1e-4)
+    ap.add_argument("--alpha", type=float, default=1e-2)
     ap.add_argument("--atol", type=float, default=1e-8)
     ap.add_argument("--sweeps", type=int, default=20)
     ap.add_argument("--lanes", type=int, default=0)
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--mixed", choices=["fp32", "fp16"], default="fp32")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-states", type=int, default=250_000)
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--copy-calib", action="store_true",
+                    help="also run a plain 1 GiB device copy (counter calibration)")
+    ap.add_argument("--serve-pool", type=int, default=24)
+    ap.add_argument("--serve-max-states", type=int, default=200_000)
+    ap.add_argument("--serve-requests", type=int, default=96)
+    ap.add_argument("--serve-max-batch", type=int, default=32)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported (the "
@@ -101,6 +187,15 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
 
+    if args.copy_calib:
+        a = torch.ones(1 << 27, dtype=torch.float64, device=dev)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+        log("[bench] copy calibration: 3 copies of 1 GiB")
+
     t = time.time()
     inst = make_instance(args)
     log(f"[bench] generated {inst.name} S={inst.S} A={inst.A} nnz={inst.nnz} in {time.time()-t:.1f}s")
@@ -108,7 +203,8 @@ def main():
     t = time.time()
     h = m.mdp_create(inst.S, inst.A, inst.row_ptr, inst.col, inst.val, inst.cost, inst.gamma,
                      stream=stream.cuda_stream, device=0, lanes_per_row=args.lanes,
-                     low_precision=0 if args.no_mixed else m.MDP_BUILD_FP32)
+                     low_precision=0 if args.no_mixed else (
+                         m.MDP_BUILD_FP32 if args.mixed == "fp32" else m.MDP_BUILD_FP16))
     info = m.mdp_info(h)
     log(f"[bench] created handle in {time.time()-t:.1f}s: {info}")
     v = torch.zeros(inst.S, dtype=torch.float64, device=dev)
@@ -120,11 +216,14 @@ def main():
 
     for _ in range(args.warmup):
         st = solve(m.MDP_FP64)
+        assert st["status"] == m.MDP_OK, st
         log(f"[bench] warmup solve: {st['time_ms']:.2f} ms, sweeps {st['bellman_sweeps']}, "
             f"inner {st['inner_iters']}, res {st['residual']:.3e}")
 
     # ---- timed region: K full float64 solves ---------------------------------
-    m.mdp_profile(h, True)
+    # HIP events bracket the two heaviest kernel classes only (fewer events,
+    # less host overhead inside the timed region)
+    m.mdp_profile(h, kinds=["bellman", "arnoldi_apply"])
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     stats = []
@@ -154,7 +253,7 @@ def main():
 
     # ---- Bellman sweep rate ---------------------------------------------------
     Tv = torch.empty_like(v)
-    m.mdp_profile(h, True)
+    m.mdp_profile(h, kinds=["bellman"])
     torch.cuda.synchronize()
     ts0 = time.perf_counter()
     for _ in range(args.sweeps):
@@ -169,11 +268,12 @@ def main():
     # ---- mixed precision --------------------------------------------------------
     mixed = None
     if not args.no_mixed:
+        mp = m.MDP_MIXED_FP32 if args.mixed == "fp32" else m.MDP_MIXED_FP16
         for _ in range(args.warmup):
-            solve(m.MDP_MIXED_FP32)
+            solve(mp)
         torch.cuda.synchronize()
         tm0 = time.perf_counter()
-        mst = [solve(m.MDP_MIXED_FP32) for _ in range(args.steps)]
+        mst = [solve(mp) for _ in range(args.steps)]
         torch.cuda.synchronize()
         tm1 = time.perf_counter()
         vm = v.cpu().numpy()
@@ -184,6 +284,10 @@ def main():
                  "refinements": mst[-1]["refinements"],
                  "rel_diff_vs_fp64": float(np.max(np.abs(vm - v64)) / np.max(np.abs(v64)))}
         log(f"[bench] mixed: {mixed}")
+
+    serve = None
+    if not args.no_serve:
+        serve = serving_leg(args, m)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -208,15 +312,20 @@ def main():
                    "nnz": inst.nnz, "gamma": inst.gamma, "inner": f"gmres({args.restart})",
                    "alpha": args.alpha, "atol": args.atol, "lanes_per_row": info["lanes_per_row"]},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": dom},
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": counter_traffic(dom, workload_key(inst)),
+                     "kernel": dom,
+                     "bytes_per_launch": kernels[dom]["bytes_per_launch"],
+                     "avg_us": kernels[dom]["avg_us"]},
         "cpu_baseline": cpu,
         "bellman_sweeps_per_s": args.sweeps / (ts1 - ts0),
         "bellman_kernel": {"avg_us": 1e3 * sweep_avg_ms, "gbs": sweep_gbs,
                            "frac": sweep_gbs / HBM_PEAK_GBS,
-                           "bytes_per_launch": sprof["bytes"] / sprof["launches"]},
+                           "bytes_per_launch": sprof["bytes"] / sprof["launches"],
+                           "traffic": counter_traffic("bellman", workload_key(inst))},
         "solve": {"sweeps": last["bellman_sweeps"], "inner": last["inner_iters"],
                   "residual": last["residual"], "history": last.get("history")},
-        "mixed_fp32": mixed,
+        "mixed": dict(mixed, precision=args.mixed) if mixed else None,
+        "serving": serve,
         "kernels": kernels,
     }
     if cpu:

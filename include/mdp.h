@@ -249,8 +249,10 @@ typedef struct {
   double bytes[MDP_NUM_KERNEL_KINDS];        /* summed algorithmic bytes of those launches */
 } mdp_kernel_profile;
 
-/* Start (enable != 0, counters cleared) or stop recording a HIP event pair
- * around every kernel launch of the handle. */
+/* Start (counters cleared) or stop recording a HIP event pair around kernel
+ * launches of the handle: enable < 0 records every class, enable > 0 is a
+ * bit mask (bit k records class k), 0 stops.  Arnoldi steps enqueued past
+ * the end of a GMRES cycle exit at once and are not counted. */
 mdp_status mdp_profile(mdp_t h, int32_t enable);
 
 /* Wait for the recorded launches and return the accumulated counters. */

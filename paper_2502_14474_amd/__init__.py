@@ -80,8 +80,13 @@ def mdp_autotune(h):
     return L.value
 
 
-def mdp_profile(h, enable=True):
-    return native.check(native.load().mdp_profile(h, 1 if enable else 0))
+def mdp_profile(h, enable=True, kinds=None):
+    """Record kernel durations: all classes (enable=True), the named classes
+    (kinds, names as in native.KERNEL_KINDS), or stop (enable=False)."""
+    mask = 0
+    if enable:
+        mask = -1 if kinds is None else sum(1 << native.KERNEL_KINDS.index(k) for k in kinds)
+    return native.check(native.load().mdp_profile(h, mask))
 
 
 def mdp_profile_read(h):

@@ -105,14 +105,34 @@ mdp_status gmres_inner(mdp_handle* h, Prec prec, const int32_t* pi, double* x, i
   const int bb = bprec == kF64 ? 8 : 4;
   for (;;) {
     int j = 0;
+    const size_t rec0 = h->prof_pending.size();
     MDP_TRY(sync_ctl(h));
+    // Steps are enqueued in chunks between host checks.  After the first
+    // chunk the chunk length follows the observed contraction of the
+    // residual estimate, so that few steps are enqueued past the end of the
+    // cycle (they exit at once, but each still costs a launch).
+    int chunk = sync_every;
+    int j_prev = 0;
+    double est_prev = h->ctl_host->beta;
     while (!h->ctl_host->done && j < m) {
-      for (int b = 0; b < sync_every && j < m; ++b, ++j) {
+      for (int b = 0; b < chunk && j < m; ++b, ++j) {
         MDP_HIP(launch_arnoldi_step(h, prec, pi, j, m));
       }
       MDP_TRY(sync_ctl(h));
+      const double est = h->ctl_host->res_est, goal = h->ctl_host->tol_cycle;
+      chunk = sync_every;
+      if (j > j_prev && est > 0.0 && est < est_prev && goal > 0.0) {
+        const double rate = std::pow(est / est_prev, 1.0 / (j - j_prev));
+        if (rate < 1.0) {
+          const double need = std::ceil(std::log(goal / est) / std::log(rate));
+          chunk = static_cast<int>(std::min(16.0, std::max(1.0, need)));
+        }
+      }
+      j_prev = j;
+      est_prev = est;
     }
     const int done_j = h->ctl_host->j;
+    prof_discard_steps(h, rec0, done_j);
     for (int jj = 0; jj < done_j; ++jj)
       out->bytes += bytes_arnoldi_apply(h, bval_of(prec), bb, jj) + bytes_arnoldi_update(h, bb, jj);
     out->applies += done_j;
@@ -297,9 +317,9 @@ double bytes_arnoldi_update(const mdp_handle* h, int bb, int j) {
   return h->S * static_cast<double>(bb) * (j + 3);
 }
 
-void prof_begin(mdp_handle* h, hipEvent_t* a) {
+void prof_begin(mdp_handle* h, int kind, hipEvent_t* a) {
   *a = nullptr;
-  if (!h->prof_on) return;
+  if (!(h->prof_mask & (1 << kind))) return;
   if (h->prof_pool.empty()) {
     hipEvent_t e;
     if (hipEventCreate(&e) != hipSuccess) return;
@@ -310,8 +330,8 @@ void prof_begin(mdp_handle* h, hipEvent_t* a) {
   (void)hipEventRecord(*a, h->stream);
 }
 
-void prof_end(mdp_handle* h, int kind, hipEvent_t a, double bytes) {
-  if (!h->prof_on || !a) return;
+void prof_end(mdp_handle* h, int kind, hipEvent_t a, double bytes, int tag) {
+  if (!a) return;
   hipEvent_t b;
   if (h->prof_pool.empty()) {
     if (hipEventCreate(&b) != hipSuccess) return;
@@ -320,8 +340,23 @@ void prof_end(mdp_handle* h, int kind, hipEvent_t a, double bytes) {
     h->prof_pool.pop_back();
   }
   (void)hipEventRecord(b, h->stream);
-  h->prof_pending.push_back({kind, a, b, bytes});
-  if (h->prof_pending.size() >= 16384) prof_resolve(h);
+  h->prof_pending.push_back({kind, tag, a, b, bytes});
+  if (h->prof_pending.size() >= (size_t{1} << 20)) prof_resolve(h);
+}
+
+void prof_discard_steps(mdp_handle* h, size_t from, int min_tag) {
+  if (from > h->prof_pending.size()) return;  // resolved in between: keep
+  size_t w = from;
+  for (size_t r = from; r < h->prof_pending.size(); ++r) {
+    auto& rec = h->prof_pending[r];
+    if (rec.tag >= 0 && rec.tag >= min_tag) {
+      h->prof_pool.push_back(rec.a);
+      h->prof_pool.push_back(rec.b);
+    } else {
+      h->prof_pending[w++] = rec;
+    }
+  }
+  h->prof_pending.resize(w);
 }
 
 void prof_resolve(mdp_handle* h) {
@@ -893,7 +928,7 @@ mdp_status mdp_profile(mdp_t h, int32_t enable) {
       h->prof_bytes[k] = 0.0;
     }
   }
-  h->prof_on = enable != 0;
+  h->prof_mask = enable < 0 ? (1 << MDP_NUM_KERNEL_KINDS) - 1 : enable;
   return MDP_OK;
 }
 
@@ -923,8 +958,8 @@ mdp_status mdp_autotune(mdp_t h, int32_t* lanes) {
   MDP_HIP(hipMemsetAsync(h->io, 0, h->S * sizeof(double), h->stream));
   float best_ms = std::numeric_limits<float>::infinity();
   int best = h->lanes;
-  const bool prof_was = h->prof_on;
-  h->prof_on = false;
+  const int prof_was = h->prof_mask;
+  h->prof_mask = 0;
   for (int L = 2; L <= 64; L <<= 1) {
     h->lanes = L;
     for (int w = 0; w < 2; ++w)
@@ -942,7 +977,7 @@ mdp_status mdp_autotune(mdp_t h, int32_t* lanes) {
     }
   }
   h->lanes = best;
-  h->prof_on = prof_was;
+  h->prof_mask = prof_was;
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (lanes) *lanes = best;

@@ -115,10 +115,11 @@ struct mdp_handle {
   // profiler: one event pair per launch while enabled
   struct ProfRec {
     int kind;
+    int tag;  // Arnoldi step index, or -1
     hipEvent_t a, b;
     double bytes;
   };
-  bool prof_on = false;
+  int prof_mask = 0;  // bit k: record kernel class k
   std::vector<ProfRec> prof_pending;
   std::vector<hipEvent_t> prof_pool;
   int64_t prof_launches[MDP_NUM_KERNEL_KINDS] = {};
@@ -175,10 +176,13 @@ double bytes_apply(const mdp_handle* h, int bval, int bx, int by);
 double bytes_arnoldi_apply(const mdp_handle* h, int bval, int bb, int j);
 double bytes_arnoldi_update(const mdp_handle* h, int bb, int j);
 
-// Profiler hooks: bracket one launch with events when h->prof_on.
-void prof_begin(mdp_handle* h, hipEvent_t* a);
-void prof_end(mdp_handle* h, int kind, hipEvent_t a, double bytes);
+// Profiler hooks: bracket one launch with events when its class is selected.
+void prof_begin(mdp_handle* h, int kind, hipEvent_t* a);
+void prof_end(mdp_handle* h, int kind, hipEvent_t a, double bytes, int tag);
 void prof_resolve(mdp_handle* h);
+// Drop pending records from index `from` on whose tag is >= min_tag (Arnoldi
+// steps enqueued past the end of a cycle exit at once and did no work).
+void prof_discard_steps(mdp_handle* h, size_t from, int min_tag);
 
 // K1 fused Bellman sweep on v (double* for kF64, float* otherwise) with the P
 // copy of `prec`.  Writes Tv (may be null), pi (may be null) and r0 = Tv - v

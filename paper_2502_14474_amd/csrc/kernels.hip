@@ -177,9 +177,12 @@ struct Prof {
   mdp_handle* h;
   int kind;
   double bytes;
+  int tag;
   hipEvent_t a;
-  Prof(mdp_handle* hh, int k, double b) : h(hh), kind(k), bytes(b) { prof_begin(h, &a); }
-  ~Prof() { prof_end(h, kind, a, bytes); }
+  Prof(mdp_handle* hh, int k, double b, int t = -1) : h(hh), kind(k), bytes(b), tag(t) {
+    prof_begin(h, kind, &a);
+  }
+  ~Prof() { prof_end(h, kind, a, bytes, tag); }
 };
 
 template <int L> constexpr int rows_in_flight() { return L >= 32 ? 2 : MDP_UNROLL; }
@@ -326,7 +329,7 @@ hipError_t launch_arnoldi_step(mdp_handle* h, Prec prec, const int32_t* pi, int 
   const int nb = grid_for(h->S, kApplyTile);
   hipError_t e;
   {
-    Prof pf(h, MDP_K_ARNOLDI_APPLY, bytes_arnoldi_apply(h, prec == kF64 ? 8 : (prec == kF32 ? 4 : 2), prec == kF64 ? 8 : 4, j) + (prec == kF16 ? h->S * 8.0 : 0.0));
+    Prof pf(h, MDP_K_ARNOLDI_APPLY, bytes_arnoldi_apply(h, prec == kF64 ? 8 : (prec == kF32 ? 4 : 2), prec == kF64 ? 8 : 4, j) + (prec == kF16 ? h->S * 8.0 : 0.0), j);
     e = with_lanes(h->lanes, [&](auto Lc) -> hipError_t {
     constexpr int L = decltype(Lc)::value;
     constexpr int U = rows_in_flight<L>();
@@ -347,13 +350,13 @@ hipError_t launch_arnoldi_step(mdp_handle* h, Prec prec, const int32_t* pi, int 
   }
   if (e != hipSuccess) return e;
   {
-    Prof pf(h, MDP_K_REDUCE, 0.0);
+    Prof pf(h, MDP_K_REDUCE, 0.0, j);
     k_reduce_dots<<<j + 1, kBlock, 0, h->stream>>>(h->part.buf, nb, j, h->ctl);
   }
   if ((e = hipGetLastError()) != hipSuccess) return e;
   const int nbu = grid_for(h->S, kUpdTile);
   {
-  Prof pf(h, MDP_K_ARNOLDI_UPDATE, bytes_arnoldi_update(h, prec == kF64 ? 8 : 4, j));
+  Prof pf(h, MDP_K_ARNOLDI_UPDATE, bytes_arnoldi_update(h, prec == kF64 ? 8 : 4, j), j);
   if (prec == kF64)
     k_arnoldi_update<double><<<nbu, kBlock, 0, h->stream>>>(h->S, h->U64, h->ldu, j, h->ctl,
                                                              h->part.buf);
@@ -362,7 +365,7 @@ hipError_t launch_arnoldi_step(mdp_handle* h, Prec prec, const int32_t* pi, int 
                                                             h->part.buf);
   }
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  Prof pf(h, MDP_K_REDUCE, 0.0);
+  Prof pf(h, MDP_K_REDUCE, 0.0, j);
   k_norm_givens<<<1, kBlock, 0, h->stream>>>(h->part.buf, nbu, j, m, h->ctl);
   return hipGetLastError();
 }
