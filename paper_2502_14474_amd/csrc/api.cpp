@@ -532,6 +532,12 @@ mdp_status mdp_create(int64_t S, int32_t A, const int64_t* row_ptr, const int32_
   h->nnz = nnz;
   h->gamma = gamma;
   h->lanes = o.lanes_per_row ? o.lanes_per_row : default_lanes(static_cast<double>(nnz) / rows);
+  {
+    const int64_t k0 = rp_host[1] - rp_host[0];
+    bool uniform = k0 > 0 && rp_host[rows] == k0 * rows;
+    for (int64_t r = 0; uniform && r <= rows; ++r) uniform = rp_host[r] == r * k0;
+    h->kfix = uniform ? static_cast<int32_t>(k0) : 0;
+  }
   if (o.device >= 0) CHK(hipSetDevice(o.device));
   CHK(hipGetDevice(&h->device));
   if (o.stream) {

@@ -15,6 +15,7 @@ struct BDesc {
   int64_t S;
   int A;
   int basis_f32;  // basis and r0 stored in float32 (mixed precision)
+  int kfix;       // common row length, or 0
   double gamma;
   const int* row_ptr;
   const int* col;

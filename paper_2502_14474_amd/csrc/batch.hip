@@ -72,20 +72,20 @@ __global__ __launch_bounds__(kBlock) void kb_bellman(const BDesc* __restrict__ d
     auto* part = reinterpret_cast<double4*>(D.part);
     if (PREC == kF64) {
       if (GM && D.basis_f32)
-        bellman_tile<L, U, double, double, false, float>(D.S, D.A, ts, D.row_ptr, D.col, D.val,
+        bellman_tile<L, U, double, double, false, float>(D.S, D.A, ts, RowIndex{D.row_ptr, D.kfix}, D.col, D.val,
                                                          nullptr, D.cost, D.v, D.gamma, nullptr,
                                                          D.pi, D.U32, part, tl, lds_d);
       else
-        bellman_tile<L, U, double, double, false, double>(D.S, D.A, ts, D.row_ptr, D.col, D.val,
+        bellman_tile<L, U, double, double, false, double>(D.S, D.A, ts, RowIndex{D.row_ptr, D.kfix}, D.col, D.val,
                                                           nullptr, D.cost, D.v, D.gamma, nullptr,
                                                           D.pi, GM ? D.U64 : nullptr, part, tl,
                                                           lds_d);
     } else if (PREC == kF32) {
-      bellman_tile<L, U, float, float, false, float>(D.S, D.A, ts, D.row_ptr, D.col, D.val32,
+      bellman_tile<L, U, float, float, false, float>(D.S, D.A, ts, RowIndex{D.row_ptr, D.kfix}, D.col, D.val32,
                                                      nullptr, D.cost, D.v32, D.gamma, nullptr,
                                                      D.pi, D.U32, part, tl, lds_d);
     } else {
-      bellman_tile<L, U, __half, float, true, float>(D.S, D.A, ts, D.row_ptr, D.col, D.val16,
+      bellman_tile<L, U, __half, float, true, float>(D.S, D.A, ts, RowIndex{D.row_ptr, D.kfix}, D.col, D.val16,
                                                      D.corr16, D.cost, D.v32, D.gamma, nullptr,
                                                      D.pi, D.U32, part, tl, lds_d);
     }
@@ -117,10 +117,10 @@ __global__ __launch_bounds__(kBlock) void kb_residual(const BDesc* __restrict__ 
     auto* part = reinterpret_cast<double4*>(D.part);
     if (D.basis_f32)
       apply_tile<L, U, kApplyRes, double, double, float, false>(
-          D.S, D.A, D.row_ptr, D.col, D.val, nullptr, D.cost, D.pi, D.v, D.gamma, D.U32, part, tl);
+          D.S, D.A, RowIndex{D.row_ptr, D.kfix}, D.col, D.val, nullptr, D.cost, D.pi, D.v, D.gamma, D.U32, part, tl);
     else
       apply_tile<L, U, kApplyRes, double, double, double, false>(
-          D.S, D.A, D.row_ptr, D.col, D.val, nullptr, D.cost, D.pi, D.v, D.gamma, D.U64, part, tl);
+          D.S, D.A, RowIndex{D.row_ptr, D.kfix}, D.col, D.val, nullptr, D.cost, D.pi, D.v, D.gamma, D.U64, part, tl);
     __syncthreads();
   });
 }
@@ -133,15 +133,15 @@ __global__ __launch_bounds__(kBlock) void kb_arnoldi_apply(const BDesc* __restri
     const BDesc& D = d[wl->it(k)];
     if (D.ctl->done) return;
     if (PREC == kF64)
-      arnoldi_apply_tile<L, U, double, double, false>(D.S, D.A, D.row_ptr, D.col, D.val, nullptr,
+      arnoldi_apply_tile<L, U, double, double, false>(D.S, D.A, RowIndex{D.row_ptr, D.kfix}, D.col, D.val, nullptr,
                                                       D.pi, D.U64, D.ldu, j, D.gamma, D.ctl,
                                                       D.part, tl, D.nb_apply);
     else if (PREC == kF32)
-      arnoldi_apply_tile<L, U, float, float, false>(D.S, D.A, D.row_ptr, D.col, D.val32, nullptr,
+      arnoldi_apply_tile<L, U, float, float, false>(D.S, D.A, RowIndex{D.row_ptr, D.kfix}, D.col, D.val32, nullptr,
                                                     D.pi, D.U32, D.ldu, j, D.gamma, D.ctl, D.part,
                                                     tl, D.nb_apply);
     else
-      arnoldi_apply_tile<L, U, __half, float, true>(D.S, D.A, D.row_ptr, D.col, D.val16,
+      arnoldi_apply_tile<L, U, __half, float, true>(D.S, D.A, RowIndex{D.row_ptr, D.kfix}, D.col, D.val16,
                                                     D.corr16, D.pi, D.U32, D.ldu, j, D.gamma,
                                                     D.ctl, D.part, tl, D.nb_apply);
     __syncthreads();
@@ -298,6 +298,7 @@ void BatchEngine::fill_desc(int i) {
   D.A = h->A;
   D.gamma = h->gamma;
   D.row_ptr = h->row_ptr;
+  D.kfix = h->kfix;
   D.col = h->col;
   D.val = h->val;
   D.val32 = h->val32;

@@ -127,12 +127,14 @@ __device__ __forceinline__ void block_max_sum(double& mx, double& sm) {
 // value, and the row's cost) is loaded before the gathers of iteration it are
 // consumed, which keeps streaming loads in flight behind the dependent gathers.
 //
-//   range(idx, st, en, ri): entry range [st, en) and global row index ri.
-//   sink(idx, pv, gcost, st, en, ri): called by every lane of the group with
-//     pv = P[ri,:] x (float16 copy: plus the row-sum correction) and
-//     gcost = cost[ri] (when NEEDCOST).
+//   range(idx, st, en, ri, si): entry range [st, en), global row index ri and
+//     the state si whose own value x[si] the sink needs (NEEDOWN).
+//   sink(idx, pv, gcost, xown): called by every lane of the group with
+//     pv = P[ri,:] x (float16 copy: plus the row-sum correction),
+//     gcost = cost[ri] (NEEDCOST) and xown = x[si] (NEEDOWN), all prefetched
+//     with the row so that the sink issues no load of its own.
 template <int L, int U, typename VT, typename XT, typename AT, bool CORR, bool NEEDCOST,
-          typename RangeF, typename SinkF>
+          bool NEEDOWN, typename RangeF, typename SinkF>
 __device__ __forceinline__ void pipelined_rows(int n, RangeF range, const int* __restrict__ col,
                                                const VT* __restrict__ val,
                                                const XT* __restrict__ x, int64_t nx,
@@ -143,9 +145,10 @@ __device__ __forceinline__ void pipelined_rows(int n, RangeF range, const int* _
   constexpr int STEP = G * U;
   const int g = threadIdx.x / L, lane = threadIdx.x % L;
   const int n_it = (n + STEP - 1) / STEP;
-  int st[U], en[U], ri[U], c[U];
+  int st[U], en[U], ri[U], c[U], si[U];
   AT p[U];
   double gc[U];
+  XT xo[U];
   // Loads are unconditional (out-of-range lanes read entry 0, which always
   // exists) and masked afterwards with selects: a load under a branch makes
   // the compiler wait for every outstanding load before the branch joins,
@@ -155,11 +158,12 @@ __device__ __forceinline__ void pipelined_rows(int n, RangeF range, const int* _
     for (int u = 0; u < U; ++u) {
       const int idx = it * STEP + g + u * G;
       const bool valid = idx < n;
-      int a, b, r;
-      range(valid ? idx : 0, a, b, r);
+      int a, b, r, o;
+      range(valid ? idx : 0, a, b, r, o);
       st[u] = valid ? a : 0;
       en[u] = valid ? b : 0;
       ri[u] = valid ? r : 0;
+      si[u] = valid ? o : -1;
       const int e = st[u] + lane;
       const bool ok = e < en[u];
       const int es = ok ? e : 0;
@@ -168,6 +172,7 @@ __device__ __forceinline__ void pipelined_rows(int n, RangeF range, const int* _
       c[u] = ok ? craw : -1;
       p[u] = ok ? praw : AT(0);
       if (NEEDCOST) gc[u] = cost[ri[u]];
+      if (NEEDOWN) xo[u] = gx(si[u]);
     }
   };
   if (n_it > 0) fetch(0);
@@ -175,6 +180,7 @@ __device__ __forceinline__ void pipelined_rows(int n, RangeF range, const int* _
     int cst[U], cen[U], cri[U], cc[U];
     AT cp[U];
     double cgc[U];
+    XT cxo[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       cst[u] = st[u];
@@ -183,6 +189,7 @@ __device__ __forceinline__ void pipelined_rows(int n, RangeF range, const int* _
       cc[u] = c[u];
       cp[u] = p[u];
       cgc[u] = gc[u];
+      cxo[u] = xo[u];
     }
     // Gathers of this iteration first, then the prefetch of the next one:
     // loads complete in issue order, so waiting for the gathers then leaves
@@ -215,13 +222,21 @@ __device__ __forceinline__ void pipelined_rows(int n, RangeF range, const int* _
         if (len > 0) acc[u] += static_cast<AT>(corr[cri[u]]) * (xs[u] / static_cast<AT>(len));
       }
       const int idx = it * STEP + g + u * G;
-      if (idx < n) sink(idx, acc[u], cgc[u], cst[u], cen[u], cri[u]);
+      if (idx < n) sink(idx, acc[u], cgc[u], cxo[u]);
     }
   }
 }
 
 template <typename T> struct Acc { using type = float; };
 template <> struct Acc<double> { using type = double; };
+
+// Row offsets of the CSR matrix.  When every row holds the same number of
+// entries (kfix > 0) row r spans [r*kfix, (r+1)*kfix) and no offset is read,
+// which spares the scattered row_ptr reads of the policy products.
+struct RowIndex {
+  const int* row_ptr;
+  int kfix;
+};
 
 // ----------------------------------------------------------------------------
 // K1: fused Bellman sweep
@@ -234,7 +249,7 @@ template <> struct Acc<double> { using type = double; };
 // sum (Tv - v)^2 and max|Tv| into this workgroup's partials.
 template <int L, int U, typename VT, typename XT, bool CORR, typename RT>
 __device__ __forceinline__ void bellman_tile(
-    int64_t S, int A, int tile_states, const int* __restrict__ row_ptr,
+    int64_t S, int A, int tile_states, RowIndex rix,
     const int* __restrict__ col, const VT* __restrict__ val, const double* __restrict__ corr,
     const double* __restrict__ cost, const XT* __restrict__ v, double gamma,
     double* __restrict__ Tv, int* __restrict__ pi, RT* __restrict__ r0,
@@ -249,30 +264,40 @@ __device__ __forceinline__ void bellman_tile(
   const int64_t row0 = s0 * A;
   const AT gam = static_cast<AT>(gamma);
   // stage the tile's row offsets: loads first (unconditional), then LDS
-  for (int base = 0; base <= nrows; base += 5 * kBlock) {
-    int buf[5];
+  const int* __restrict__ row_ptr = rix.row_ptr;
+  const int kfix = rix.kfix;
+  if (kfix == 0) {
+    for (int base = 0; base <= nrows; base += 5 * kBlock) {
+      int buf[5];
 #pragma unroll
-    for (int k = 0; k < 5; ++k) {
-      const int i = base + threadIdx.x + k * kBlock;
-      buf[k] = row_ptr[row0 + (i <= nrows ? i : 0)];
-    }
+      for (int k = 0; k < 5; ++k) {
+        const int i = base + threadIdx.x + k * kBlock;
+        buf[k] = row_ptr[row0 + (i <= nrows ? i : 0)];
+      }
 #pragma unroll
-    for (int k = 0; k < 5; ++k) {
-      const int i = base + threadIdx.x + k * kBlock;
-      if (i <= nrows) rp[i] = buf[k];
+      for (int k = 0; k < 5; ++k) {
+        const int i = base + threadIdx.x + k * kBlock;
+        if (i <= nrows) rp[i] = buf[k];
+      }
     }
+    __syncthreads();
   }
-  __syncthreads();
 
-  pipelined_rows<L, U, VT, XT, AT, CORR, true>(
+  pipelined_rows<L, U, VT, XT, AT, CORR, true, false>(
       nrows,
-      [&](int idx, int& st, int& en, int& ri) {
-        st = rp[idx];
-        en = rp[idx + 1];
+      [&](int idx, int& st, int& en, int& ri, int& si) {
         ri = static_cast<int>(row0 + idx);
+        if (kfix > 0) {
+          st = ri * kfix;
+          en = st + kfix;
+        } else {
+          st = rp[idx];
+          en = rp[idx + 1];
+        }
+        si = -1;
       },
       col, val, v, S, cost, corr,
-      [&](int idx, AT pv, double gc, int, int, int) {
+      [&](int idx, AT pv, double gc, XT) {
         if ((threadIdx.x % L) == 0) q[idx] = fma(gam, pv, static_cast<AT>(gc));
       });
   __syncthreads();
@@ -309,8 +334,7 @@ __device__ __forceinline__ void bellman_tile(
 
 // Stage the selected rows of kApplyTile states: thread t loads pi(s0+t) and
 // the two row offsets of row s*A + pi(s) (all independent loads).
-__device__ __forceinline__ void stage_policy_rows(int64_t s0, int ns, int A,
-                                                  const int* __restrict__ row_ptr,
+__device__ __forceinline__ void stage_policy_rows(int64_t s0, int ns, int A, RowIndex rix,
                                                   const int* __restrict__ pi, int* st_l,
                                                   int* en_l, int* rw_l) {
   constexpr int KP = (kApplyTile + kBlock - 1) / kBlock;
@@ -325,8 +349,13 @@ __device__ __forceinline__ void stage_policy_rows(int64_t s0, int ns, int A,
     const int t = threadIdx.x + k * kBlock;
     const int r = static_cast<int>((s0 + (t < ns ? t : 0)) * A + pv[k]);
     pv[k] = r;
-    a[k] = row_ptr[r];
-    b[k] = row_ptr[r + 1];
+    if (rix.kfix > 0) {
+      a[k] = r * rix.kfix;
+      b[k] = a[k] + rix.kfix;
+    } else {
+      a[k] = rix.row_ptr[r];
+      b[k] = rix.row_ptr[r + 1];
+    }
   }
 #pragma unroll
   for (int k = 0; k < KP; ++k) {
@@ -349,7 +378,7 @@ __device__ __forceinline__ void stage_policy_rows(int64_t s0, int ns, int A,
 // Each workgroup owns kApplyTile consecutive states.
 template <int L, int U, int MODE, typename VT, typename XT, typename YT, bool CORR>
 __device__ __forceinline__ void apply_tile(
-    int64_t S, int A, const int* __restrict__ row_ptr, const int* __restrict__ col,
+    int64_t S, int A, RowIndex rix, const int* __restrict__ col,
     const VT* __restrict__ val, const double* __restrict__ corr,
     const double* __restrict__ cost, const int* __restrict__ pi, const XT* __restrict__ x,
     double gamma, YT* __restrict__ y, double4* __restrict__ partials, int tile) {
@@ -358,21 +387,22 @@ __device__ __forceinline__ void apply_tile(
   const int64_t s0 = static_cast<int64_t>(tile) * kApplyTile;
   const int ns = static_cast<int>(min<int64_t>(kApplyTile, S - s0));
   const AT gam = static_cast<AT>(gamma);
-  stage_policy_rows(s0, ns, A, row_ptr, pi, st_l, en_l, rw_l);
+  stage_policy_rows(s0, ns, A, rix, pi, st_l, en_l, rw_l);
   double dmax = 0.0, dsum = 0.0;
 
-  pipelined_rows<L, U, VT, XT, AT, CORR, MODE != kApplyOp>(
+  pipelined_rows<L, U, VT, XT, AT, CORR, MODE != kApplyOp, true>(
       ns,
-      [&](int idx, int& st, int& en, int& ri) {
+      [&](int idx, int& st, int& en, int& ri, int& si) {
         st = st_l[idx];
         en = en_l[idx];
         ri = rw_l[idx];
+        si = static_cast<int>(s0 + idx);
       },
       col, val, x, S, cost, corr,
-      [&](int ss, AT pv, double gc, int, int, int) {
+      [&](int ss, AT pv, double gc, XT xown) {
         if ((threadIdx.x % L) != 0) return;
         const int64_t s = s0 + ss;
-        const AT xs_own = static_cast<AT>(x[s]);
+        const AT xs_own = static_cast<AT>(xown);
         if (MODE == kApplyOp) {
           y[s] = static_cast<YT>(xs_own - gam * pv);
         } else if (MODE == kApplyT) {
@@ -407,7 +437,7 @@ __device__ __forceinline__ void apply_tile(
 // Gram-Schmidt, one pass over the basis).  partials[i * nb + tile].
 template <int L, int U, typename VT, typename BT, bool CORR>
 __device__ __forceinline__ void arnoldi_apply_tile(
-    int64_t S, int A, const int* __restrict__ row_ptr, const int* __restrict__ col,
+    int64_t S, int A, RowIndex rix, const int* __restrict__ col,
     const VT* __restrict__ val, const double* __restrict__ corr, const int* __restrict__ pi,
     BT* __restrict__ Ub, int64_t ldu, int j, double gamma, const Ctl* __restrict__ ctl,
     double* __restrict__ partials, int tile, int nb) {
@@ -421,20 +451,21 @@ __device__ __forceinline__ void arnoldi_apply_tile(
   const BT* __restrict__ xj = Ub + static_cast<int64_t>(j) * ldu;
   BT* __restrict__ w = Ub + static_cast<int64_t>(j + 1) * ldu;
   const double cj = ctl->scale[j];
-  stage_policy_rows(s0, ns, A, row_ptr, pi, st_l, en_l, rw_l);
+  stage_policy_rows(s0, ns, A, rix, pi, st_l, en_l, rw_l);
 
-  pipelined_rows<L, U, VT, BT, AT, CORR, false>(
+  pipelined_rows<L, U, VT, BT, AT, CORR, false, true>(
       ns,
-      [&](int idx, int& st, int& en, int& ri) {
+      [&](int idx, int& st, int& en, int& ri, int& si) {
         st = st_l[idx];
         en = en_l[idx];
         ri = rw_l[idx];
+        si = static_cast<int>(s0 + idx);
       },
       col, val, xj, S, nullptr, corr,
-      [&](int ss, AT pv, double, int, int, int) {
+      [&](int ss, AT pv, double, BT xown) {
         if ((threadIdx.x % L) != 0) return;
         const int64_t s = s0 + ss;
-        const AT av = static_cast<AT>(xj[s]) - gam * pv;
+        const AT av = static_cast<AT>(xown) - gam * pv;
         const BT wv = static_cast<BT>(cj * static_cast<double>(av));
         w[s] = wv;
         w_lds[ss] = static_cast<double>(wv);

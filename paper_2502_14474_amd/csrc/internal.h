@@ -77,6 +77,7 @@ struct mdp_handle {
   int64_t rows = 0, nnz = 0;
   double gamma = 0;
   int32_t lanes = 16;
+  int32_t kfix = 0;  // every row holds kfix entries (0: rows differ)
 
   // CSR on the device (int32 row offsets: nnz < 2^31)
   int32_t* row_ptr = nullptr;

@@ -7,20 +7,20 @@ namespace mdp {
 
 template <int L, int U, typename VT, typename XT, bool CORR, typename RT>
 __global__ __launch_bounds__(kBlock) void k_bellman(
-    int64_t S, int A, int tile_states, const int* __restrict__ row_ptr,
+    int64_t S, int A, int tile_states, const int* __restrict__ row_ptr, int kfix,
     const int* __restrict__ col, const VT* __restrict__ val, const double* __restrict__ corr,
     const double* __restrict__ cost, const XT* __restrict__ v, double gamma,
     double* __restrict__ Tv, int* __restrict__ pi, RT* __restrict__ r0,
     double4* __restrict__ partials) {
   extern __shared__ double lds_d[];
-  bellman_tile<L, U, VT, XT, CORR, RT>(S, A, tile_states, row_ptr, col, val, corr, cost, v, gamma,
+  bellman_tile<L, U, VT, XT, CORR, RT>(S, A, tile_states, RowIndex{row_ptr, kfix}, col, val, corr, cost, v, gamma,
                                        Tv, pi, r0, partials, xcd_tile(blockIdx.x, gridDim.x),
                                        lds_d);
 }
 
 template <int L, int U, int MODE, typename VT, typename XT, typename YT, bool CORR>
 __global__ __launch_bounds__(kBlock) void k_policy_apply(
-    int64_t S, int A, const int* __restrict__ row_ptr, const int* __restrict__ col,
+    int64_t S, int A, const int* __restrict__ row_ptr, int kfix, const int* __restrict__ col,
     const VT* __restrict__ val, const double* __restrict__ corr,
     const double* __restrict__ cost, const int* __restrict__ pi, const XT* __restrict__ x,
     double gamma, YT* __restrict__ y, double4* __restrict__ partials,
@@ -35,18 +35,18 @@ __global__ __launch_bounds__(kBlock) void k_policy_apply(
     y_alt = y;
     y = u;
   }
-  apply_tile<L, U, MODE, VT, XT, YT, CORR>(S, A, row_ptr, col, val, corr, cost, pi, x, gamma, y,
+  apply_tile<L, U, MODE, VT, XT, YT, CORR>(S, A, RowIndex{row_ptr, kfix}, col, val, corr, cost, pi, x, gamma, y,
                                            partials, xcd_tile(blockIdx.x, gridDim.x));
 }
 
 template <int L, int U, typename VT, typename BT, bool CORR>
 __global__ __launch_bounds__(kBlock) void k_arnoldi_apply(
-    int64_t S, int A, const int* __restrict__ row_ptr, const int* __restrict__ col,
+    int64_t S, int A, const int* __restrict__ row_ptr, int kfix, const int* __restrict__ col,
     const VT* __restrict__ val, const double* __restrict__ corr, const int* __restrict__ pi,
     BT* __restrict__ Ub, int64_t ldu, int j, double gamma, const Ctl* __restrict__ ctl,
     double* __restrict__ partials) {
   if (ctl->done) return;
-  arnoldi_apply_tile<L, U, VT, BT, CORR>(S, A, row_ptr, col, val, corr, pi, Ub, ldu, j, gamma,
+  arnoldi_apply_tile<L, U, VT, BT, CORR>(S, A, RowIndex{row_ptr, kfix}, col, val, corr, pi, Ub, ldu, j, gamma,
                                          ctl, partials, xcd_tile(blockIdx.x, gridDim.x),
                                          gridDim.x);
 }
@@ -245,23 +245,23 @@ hipError_t launch_bellman(mdp_handle* h, Prec prec, const void* v, double* Tv, i
                          (static_cast<size_t>(ts) * h->A + 1) * sizeof(int);
       if (r0_f32)
         k_bellman<L, U, double, double, false, float><<<nb, kBlock, lds, h->stream>>>(
-            h->S, h->A, ts, h->row_ptr, h->col, h->val, nullptr, h->cost,
+            h->S, h->A, ts, h->row_ptr, h->kfix, h->col, h->val, nullptr, h->cost,
             static_cast<const double*>(v), h->gamma, Tv, pi, static_cast<float*>(r0), part);
       else
         k_bellman<L, U, double, double, false, double><<<nb, kBlock, lds, h->stream>>>(
-            h->S, h->A, ts, h->row_ptr, h->col, h->val, nullptr, h->cost,
+            h->S, h->A, ts, h->row_ptr, h->kfix, h->col, h->val, nullptr, h->cost,
             static_cast<const double*>(v), h->gamma, Tv, pi, static_cast<double*>(r0), part);
     } else if (prec == kF32) {
       const size_t lds = static_cast<size_t>(ts) * h->A * sizeof(double) +
                          (static_cast<size_t>(ts) * h->A + 1) * sizeof(int);
       k_bellman<L, U, float, float, false, float><<<nb, kBlock, lds, h->stream>>>(
-          h->S, h->A, ts, h->row_ptr, h->col, h->val32, nullptr, h->cost,
+          h->S, h->A, ts, h->row_ptr, h->kfix, h->col, h->val32, nullptr, h->cost,
           static_cast<const float*>(v), h->gamma, Tv, pi, static_cast<float*>(r0), part);
     } else {
       const size_t lds = static_cast<size_t>(ts) * h->A * sizeof(double) +
                          (static_cast<size_t>(ts) * h->A + 1) * sizeof(int);
       k_bellman<L, U, __half, float, true, float><<<nb, kBlock, lds, h->stream>>>(
-          h->S, h->A, ts, h->row_ptr, h->col, h->val16, h->corr16, h->cost,
+          h->S, h->A, ts, h->row_ptr, h->kfix, h->col, h->val16, h->corr16, h->cost,
           static_cast<const float*>(v), h->gamma, Tv, pi, static_cast<float*>(r0), part);
     }
     return hipGetLastError();
@@ -283,7 +283,7 @@ hipError_t launch_apply(mdp_handle* h, int mode, const int32_t* pi, const double
     constexpr int L = decltype(Lc)::value;
     constexpr int U = rows_in_flight<L>();
 #define MDP_APPLY_ARGS(YT)                                                                 \
-  h->S, h->A, h->row_ptr, h->col, h->val, nullptr, h->cost, pi, x, h->gamma,              \
+  h->S, h->A, h->row_ptr, h->kfix, h->col, h->val, nullptr, h->cost, pi, x, h->gamma,              \
       static_cast<YT*>(y), part, nullptr, nullptr, nullptr, nullptr
     if (mode == kApplyOp)
       k_policy_apply<L, U, kApplyOp, double, double, double, false>
@@ -316,7 +316,7 @@ hipError_t launch_richardson_step(mdp_handle* h, const int32_t* pi, double* buf0
     constexpr int U = rows_in_flight<L>();
     // current iterate in buf[rich_cur]; the kernel swaps roles when rich_cur == 1
     k_policy_apply<L, U, kApplyT, double, double, double, false><<<nb, kBlock, 0, h->stream>>>(
-        h->S, h->A, h->row_ptr, h->col, h->val, nullptr, h->cost, pi, buf0, h->gamma, buf1,
+        h->S, h->A, h->row_ptr, h->kfix, h->col, h->val, nullptr, h->cost, pi, buf0, h->gamma, buf1,
         part, h->ctl, &h->ctl->rich_cur, buf1, buf0);
     return hipGetLastError();
   });
@@ -335,15 +335,15 @@ hipError_t launch_arnoldi_step(mdp_handle* h, Prec prec, const int32_t* pi, int 
     constexpr int U = rows_in_flight<L>();
     if (prec == kF64)
       k_arnoldi_apply<L, U, double, double, false><<<nb, kBlock, 0, h->stream>>>(
-          h->S, h->A, h->row_ptr, h->col, h->val, nullptr, pi, h->U64, h->ldu, j, h->gamma,
+          h->S, h->A, h->row_ptr, h->kfix, h->col, h->val, nullptr, pi, h->U64, h->ldu, j, h->gamma,
           h->ctl, h->part.buf);
     else if (prec == kF32)
       k_arnoldi_apply<L, U, float, float, false><<<nb, kBlock, 0, h->stream>>>(
-          h->S, h->A, h->row_ptr, h->col, h->val32, nullptr, pi, h->U32, h->ldu, j, h->gamma,
+          h->S, h->A, h->row_ptr, h->kfix, h->col, h->val32, nullptr, pi, h->U32, h->ldu, j, h->gamma,
           h->ctl, h->part.buf);
     else
       k_arnoldi_apply<L, U, __half, float, true><<<nb, kBlock, 0, h->stream>>>(
-          h->S, h->A, h->row_ptr, h->col, h->val16, h->corr16, pi, h->U32, h->ldu, j, h->gamma,
+          h->S, h->A, h->row_ptr, h->kfix, h->col, h->val16, h->corr16, pi, h->U32, h->ldu, j, h->gamma,
           h->ctl, h->part.buf);
     return hipGetLastError();
   });
