@@ -130,7 +130,7 @@ def serving_leg(args, m):
                     dt = nxt - time.perf_counter()
                     if dt > 0:
                         time.sleep(dt)
-                ids.append(srv.submit(pool[i % len(pool)]))
+                ids.append(srv.submit(pool[i % len(pool)], borrow=True))
             outs = [srv.wait(r) for r in ids]
             t1 = time.perf_counter()
         lat = np.array([o[2]["finish_ms"] - o[2]["submit_ms"] for o in outs])

@@ -188,6 +188,8 @@ typedef struct {
   int64_t hbm_budget_bytes;  /* admission limit on resident device bytes (default 64 GiB) */
   int32_t device;            /* HIP device; -1: the current device */
   int32_t max_batch;         /* most MDPs resident at once (default 256) */
+  int32_t admit_threads;     /* threads copying new MDPs to the device (default 4) */
+  int32_t retire_threads;    /* threads copying results out and freeing (default 2) */
   mdp_solve_opts solve;      /* GMRES only; default precision MDP_MIXED_FP32 */
 } mdp_server_opts;
 
@@ -209,6 +211,14 @@ mdp_status mdp_server_create(const mdp_server_opts* opt, mdp_server_t* out);
 mdp_status mdp_server_submit(mdp_server_t s, int64_t S, int32_t A, const int64_t* row_ptr,
                              const int32_t* col, const double* val, const double* cost,
                              double gamma, int64_t* request_id);
+/* As mdp_server_submit, without the copy: the arrays are read (and
+ * validated) when the request is admitted, so the caller keeps them valid and
+ * unchanged until mdp_server_wait returns for this request.  An invalid MDP
+ * then fails at mdp_server_wait with MDP_E_INVAL. */
+mdp_status mdp_server_submit_borrowed(mdp_server_t s, int64_t S, int32_t A,
+                                      const int64_t* row_ptr, const int32_t* col,
+                                      const double* val, const double* cost, double gamma,
+                                      int64_t* request_id);
 /* *done = 1 once the request's result is ready. */
 mdp_status mdp_server_poll(mdp_server_t s, int64_t request_id, int32_t* done);
 /* Block until the request is done, copy v (double[S]) and policy (int32[S])

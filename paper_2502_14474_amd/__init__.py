@@ -260,23 +260,28 @@ class Server:
     """Continuous-batching solve server (mdp_server_* in include/mdp.h)."""
 
     def __init__(self, hbm_budget_bytes=64 << 30, max_batch=256, device=-1, stream=None,
-                 **solve_opts):
+                 admit_threads=4, retire_threads=2, **solve_opts):
         lib = native.load()
         o = native.ServerOpts()
         lib.mdp_default_server_opts(C.byref(o))
         o.hbm_budget_bytes, o.max_batch, o.device, o.stream = hbm_budget_bytes, max_batch, device, stream
+        o.admit_threads, o.retire_threads = admit_threads, retire_threads
         solve_opts.setdefault("precision", MDP_MIXED_FP32)
         o.solve = _solve_opts(lib, **solve_opts)
         self.s = C.c_void_p()
         native.check(lib.mdp_server_create(C.byref(o), C.byref(self.s)))
         self.S = {}
 
-    def submit(self, inst):
+    def submit(self, inst, borrow=False):
+        """Queue a solve.  borrow=True skips the host copy: the instance's
+        arrays must stay alive and unchanged until wait() returns (the
+        server keeps a reference to them until then)."""
         rid = C.c_int64()
-        native.check(native.load().mdp_server_submit(
-            self.s, inst.S, inst.A, _ptr(inst.row_ptr, np.int64), _ptr(inst.col, np.int32),
-            _ptr(inst.val, np.float64), _ptr(inst.cost, np.float64), inst.gamma, C.byref(rid)))
-        self.S[rid.value] = inst.S
+        fn = native.load().mdp_server_submit_borrowed if borrow else native.load().mdp_server_submit
+        native.check(fn(self.s, inst.S, inst.A, _ptr(inst.row_ptr, np.int64),
+                        _ptr(inst.col, np.int32), _ptr(inst.val, np.float64),
+                        _ptr(inst.cost, np.float64), inst.gamma, C.byref(rid)))
+        self.S[rid.value] = (inst.S, inst if borrow else None)
         return rid.value
 
     def poll(self, rid):
@@ -285,13 +290,16 @@ class Server:
         return bool(d.value)
 
     def wait(self, rid):
-        S = self.S.pop(rid)
+        S, _keep = self.S[rid]
         v = np.empty(S)
         pi = np.empty(S, np.int32)
         st = native.RequestStats()
         st.struct_size = C.sizeof(native.RequestStats)
-        status = native.check(native.load().mdp_server_wait(self.s, rid, v.ctypes.data,
-                                                            pi.ctypes.data, C.byref(st)))
+        try:
+            status = native.check(native.load().mdp_server_wait(self.s, rid, v.ctypes.data,
+                                                                pi.ctypes.data, C.byref(st)))
+        finally:
+            del self.S[rid]
         d = {k: getattr(st, k) for k, _ in native.RequestStats._fields_ if k != "struct_size"}
         d["status"] = status
         return v, pi, d

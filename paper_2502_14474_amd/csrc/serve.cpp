@@ -33,6 +33,12 @@ struct Request {
   std::vector<int64_t> row_ptr;
   std::vector<int32_t> col;
   std::vector<double> val, cost;
+  // borrowed submission: caller arrays, read at admission
+  const int64_t* b_row_ptr = nullptr;
+  const int32_t* b_col = nullptr;
+  const double* b_val = nullptr;
+  const double* b_cost = nullptr;
+  bool borrowed = false;
   int64_t footprint = 0;
   // results
   std::vector<double> v;
@@ -73,52 +79,82 @@ struct mdp_server {
   int device = 0;
   hipStream_t stream = nullptr;
   std::mutex mu;
-  std::condition_variable cv_work, cv_done;
-  std::deque<mdp::Request*> queue;
+  std::condition_variable cv_admit, cv_work, cv_reap, cv_done;
+  std::deque<mdp::Request*> queue;     // submitted, not yet admitted
+  std::vector<mdp::Request*> ready;    // admitted, joining at the next round
+  std::vector<mdp::Request*> resident; // advanced by the rounds
+  std::deque<mdp::Request*> retiring;  // finished, results being copied out
   std::map<int64_t, std::unique_ptr<mdp::Request>> all;
-  std::vector<mdp::Request*> resident;
   int64_t next_id = 1;
-  int64_t resident_bytes = 0;
-  bool stop = false;
+  int64_t held_bytes = 0;              // footprint of admitting + resident + retiring
+  int admitting = 0;
+  bool stop = false, worker_done = false;
   double t0 = 0;
+  std::vector<std::thread> admitters, reapers;
   std::thread worker;
+  int reapers_left = 0;
   mdp::BatchEngine eng;
   std::string fatal;
   int64_t rounds = 0;
 
-  void run();
+  void admit_loop();
+  void work_loop();
+  void reap_loop();
   mdp_status admit_one(mdp::Request* r);
   void retire(mdp::Request* r);
 };
 
 using namespace mdp;
 
-void mdp_server::run() {
-  hipSetDevice(device);
+// Admission runs beside the rounds: device allocations and host-to-device
+// copies of a new MDP happen on its own stream while the worker keeps the
+// resident set busy.  A request is admitted while the held footprint
+// (admitting + resident + retiring) stays within the budget, or when nothing
+// is held at all.
+void mdp_server::admit_loop() {
+  (void)hipSetDevice(device);
   std::unique_lock<std::mutex> lk(mu);
   for (;;) {
-    // admission
-    while (!queue.empty() && static_cast<int>(resident.size()) < opts.max_batch) {
-      Request* r = queue.front();
-      if (!resident.empty() && resident_bytes + r->footprint > opts.hbm_budget_bytes) break;
-      queue.pop_front();
-      lk.unlock();
-      const mdp_status st = admit_one(r);
-      lk.lock();
-      if (st < 0) {
-        r->status = st;
-        r->error = mdp_last_error();
-        r->done = true;
-        r->st.finish_ms = clock_ms() - t0;
-        cv_done.notify_all();
-        continue;
-      }
-      resident.push_back(r);
-      resident_bytes += r->footprint;
+    cv_admit.wait(lk, [&]() {
+      if (stop) return true;
+      if (queue.empty()) return false;
+      const int count = admitting + static_cast<int>(ready.size() + resident.size());
+      if (count >= opts.max_batch) return false;
+      return held_bytes == 0 || held_bytes + queue.front()->footprint <= opts.hbm_budget_bytes;
+    });
+    if (stop) return;
+    Request* r = queue.front();
+    queue.pop_front();
+    held_bytes += r->footprint;
+    ++admitting;
+    lk.unlock();
+    const mdp_status st = admit_one(r);
+    lk.lock();
+    --admitting;
+    if (st < 0) {
+      held_bytes -= r->footprint;
+      r->status = st;
+      r->error = mdp_last_error();
+      r->done = true;
+      r->st.finish_ms = clock_ms() - t0;
+      cv_done.notify_all();
+      cv_admit.notify_all();
+      continue;
     }
+    ready.push_back(r);
+    cv_work.notify_all();
+  }
+}
+
+void mdp_server::work_loop() {
+  (void)hipSetDevice(device);
+  std::unique_lock<std::mutex> lk(mu);
+  for (;;) {
+    cv_work.wait(lk, [&]() { return !ready.empty() || !resident.empty() || (stop && admitting == 0); });
+    for (Request* r : ready) resident.push_back(r);
+    ready.clear();
     if (resident.empty()) {
-      if (stop) return;
-      cv_work.wait(lk);
+      if (stop && admitting == 0) break;
       continue;
     }
     // one round over the resident set
@@ -131,39 +167,59 @@ void mdp_server::run() {
     if (st < 0) {
       fatal = mdp_last_error();
       for (Request* r : resident) {
-        r->status = st;
-        r->error = fatal;
-        r->done = true;
+        r->item.status = st;
+        r->item.state = BatchItem::kDone;
       }
-      resident.clear();
-      cv_done.notify_all();
-      continue;
     }
     std::vector<Request*> keep;
     for (Request* r : resident) {
-      if (r->item.state == BatchItem::kDone) {
-        lk.unlock();
-        retire(r);
-        lk.lock();
-        resident_bytes -= r->footprint;
-        cv_done.notify_all();
-      } else {
-        keep.push_back(r);
-      }
+      if (r->item.state == BatchItem::kDone) retiring.push_back(r);
+      else keep.push_back(r);
     }
     resident.swap(keep);
+    cv_reap.notify_all();
+  }
+  worker_done = true;
+  cv_reap.notify_all();
+}
+
+// Retirement copies results out and frees device memory off the round loop.
+void mdp_server::reap_loop() {
+  (void)hipSetDevice(device);
+  std::unique_lock<std::mutex> lk(mu);
+  for (;;) {
+    cv_reap.wait(lk, [&]() { return !retiring.empty() || worker_done; });
+    if (retiring.empty() && worker_done) {
+      --reapers_left;
+      return;
+    }
+    Request* r = retiring.front();
+    retiring.pop_front();
+    lk.unlock();
+    retire(r);
+    lk.lock();
+    held_bytes -= r->footprint;
+    r->done = true;
+    cv_done.notify_all();
+    cv_admit.notify_all();
   }
 }
 
 mdp_status mdp_server::admit_one(Request* r) {
   mdp_create_opts co;
   mdp_default_create_opts(&co);
-  co.stream = stream;
+  co.stream = nullptr;  // the handle's own stream: admission overlaps the rounds
   co.device = device;
-  co.validate = 0;  // validated at submission
+  co.validate = 0;      // validated at submission
   mdp_handle* h = nullptr;
-  MDP_TRY(mdp_create(r->S, r->A, r->row_ptr.data(), r->col.data(), r->val.data(), r->cost.data(),
-                     r->gamma, &co, &h));
+  if (r->borrowed) {
+    // validation runs here, off the caller's thread
+    MDP_TRY(validate_host(r->S, r->A, r->b_row_ptr, r->b_col, r->b_val, r->b_cost));
+    MDP_TRY(mdp_create(r->S, r->A, r->b_row_ptr, r->b_col, r->b_val, r->b_cost, r->gamma, &co, &h));
+  } else {
+    MDP_TRY(mdp_create(r->S, r->A, r->row_ptr.data(), r->col.data(), r->val.data(),
+                       r->cost.data(), r->gamma, &co, &h));
+  }
   r->h = h;
   const Prec prec = prec_of(opts.solve.precision);
   mdp_status st = ensure_basis(h, prec == kF64 ? kF64 : kF32, opts.solve.restart);
@@ -173,8 +229,9 @@ mdp_status mdp_server::admit_one(Request* r) {
     r->h = nullptr;
     return st;
   }
-  hipError_t e = hipMemsetAsync(h->v, 0, h->S * sizeof(double), stream);
+  hipError_t e = hipMemsetAsync(h->v, 0, h->S * sizeof(double), h->stream);
   if (e == hipSuccess) e = launch_ctl_reset(h, 0.0);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
   if (e != hipSuccess) {
     mdp_destroy(h);
     r->h = nullptr;
@@ -198,15 +255,19 @@ mdp_status mdp_server::admit_one(Request* r) {
 
 void mdp_server::retire(Request* r) {
   mdp_handle* h = r->h;
+  const BatchItem& it = r->item;
   r->v.resize(h->S);
   r->pi.resize(h->S);
-  hipError_t e = hipMemcpyAsync(r->v.data(), h->v, h->S * sizeof(double), hipMemcpyDeviceToHost, stream);
+  // the worker synchronised its stream before handing the request over
+  hipError_t e = hipMemcpyAsync(r->v.data(), h->v, h->S * sizeof(double), hipMemcpyDeviceToHost,
+                                h->stream);
   if (e == hipSuccess)
-    e = hipMemcpyAsync(r->pi.data(), h->pi, h->S * sizeof(int32_t), hipMemcpyDeviceToHost, stream);
-  if (e == hipSuccess) e = hipStreamSynchronize(stream);
-  const BatchItem& it = r->item;
+    e = hipMemcpyAsync(r->pi.data(), h->pi, h->S * sizeof(int32_t), hipMemcpyDeviceToHost, h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  r->st.finish_ms = clock_ms() - t0;  // results are on the host
   r->status = e != hipSuccess ? MDP_E_DEVICE : it.status;
   if (e != hipSuccess) r->error = hipGetErrorString(e);
+  else if (it.status < 0) r->error = fatal.empty() ? "non-finite residual" : fatal;
   r->st.outer_iters = it.k;
   r->st.inner_iters = it.inner;
   r->st.bellman_sweeps = it.sweeps;
@@ -214,9 +275,6 @@ void mdp_server::retire(Request* r) {
   r->st.bytes = it.bytes;
   mdp_destroy(h);
   r->h = nullptr;
-  r->st.finish_ms = clock_ms() - t0;
-  std::lock_guard<std::mutex> g(mu);
-  r->done = true;
 }
 
 extern "C" {
@@ -229,6 +287,8 @@ void mdp_default_server_opts(mdp_server_opts* o) {
   o->stream = nullptr;
   o->hbm_budget_bytes = int64_t{64} << 30;
   o->max_batch = 256;
+  o->admit_threads = 4;
+  o->retire_threads = 2;
   mdp_default_solve_opts(&o->solve);
   o->solve.precision = MDP_MIXED_FP32;
 }
@@ -243,7 +303,8 @@ mdp_status mdp_server_create(const mdp_server_opts* opt, mdp_server_t* out) {
     if (opt->struct_size < sizeof(mdp_server_opts)) return fail(MDP_E_INVAL, "mdp_server_opts.struct_size too small");
     o = *opt;
   }
-  if (o.max_batch < 1 || o.max_batch > 65536 || o.hbm_budget_bytes <= 0)
+  if (o.max_batch < 1 || o.max_batch > 65536 || o.hbm_budget_bytes <= 0 ||
+      o.admit_threads < 1 || o.admit_threads > 64 || o.retire_threads < 1 || o.retire_threads > 64)
     return fail(MDP_E_INVAL, "bad server limits");
   if (o.solve.inner != MDP_INNER_GMRES) return fail(MDP_E_NOTSUP, "the server uses GMRES");
   if (o.solve.restart < 1 || o.solve.restart > kMaxRestart) return fail(MDP_E_INVAL, "restart must lie in [1,64]");
@@ -277,14 +338,17 @@ mdp_status mdp_server_create(const mdp_server_opts* opt, mdp_server_t* out) {
     return st;
   }
   s->t0 = clock_ms();
-  s->worker = std::thread([s]() { s->run(); });
+  for (int i = 0; i < o.admit_threads; ++i) s->admitters.emplace_back([s]() { s->admit_loop(); });
+  s->worker = std::thread([s]() { s->work_loop(); });
+  s->reapers_left = o.retire_threads;
+  for (int i = 0; i < o.retire_threads; ++i) s->reapers.emplace_back([s]() { s->reap_loop(); });
   *out = s;
   return MDP_OK;
 }
 
-mdp_status mdp_server_submit(mdp_server_t s, int64_t S, int32_t A, const int64_t* row_ptr,
-                             const int32_t* col, const double* val, const double* cost,
-                             double gamma, int64_t* request_id) {
+static mdp_status submit_common(mdp_server_t s, int64_t S, int32_t A, const int64_t* row_ptr,
+                                const int32_t* col, const double* val, const double* cost,
+                                double gamma, int64_t* request_id, bool borrow) {
   clear_error();
   if (!s || !request_id) return fail(MDP_E_INVAL, "NULL argument");
   if (S < 1 || A < 1 || !row_ptr || !col || !val || !cost) return fail(MDP_E_INVAL, "bad MDP");
@@ -294,18 +358,26 @@ mdp_status mdp_server_submit(mdp_server_t s, int64_t S, int32_t A, const int64_t
   const int64_t rows = S * A;
   const int64_t nnz = row_ptr[rows];
   if (nnz < rows || nnz >= (int64_t{1} << 31)) return fail(MDP_E_INVAL, "bad row_ptr");
-  MDP_TRY(validate_host(S, A, row_ptr, col, val, cost));
   auto r = std::make_unique<Request>();
   r->S = S;
   r->A = A;
   r->gamma = gamma;
-  r->row_ptr.assign(row_ptr, row_ptr + rows + 1);
-  r->col.assign(col, col + nnz);
-  r->val.assign(val, val + nnz);
-  r->cost.assign(cost, cost + rows);
   r->footprint = footprint_of(S, A, nnz, s->opts.solve);
   if (r->footprint > s->opts.hbm_budget_bytes)
     return fail(MDP_E_NOMEM, "request footprint exceeds the server's HBM budget");
+  if (borrow) {
+    r->borrowed = true;
+    r->b_row_ptr = row_ptr;
+    r->b_col = col;
+    r->b_val = val;
+    r->b_cost = cost;
+  } else {
+    MDP_TRY(validate_host(S, A, row_ptr, col, val, cost));
+    r->row_ptr.assign(row_ptr, row_ptr + rows + 1);
+    r->col.assign(col, col + nnz);
+    r->val.assign(val, val + nnz);
+    r->cost.assign(cost, cost + rows);
+  }
   Request* raw = r.get();
   std::lock_guard<std::mutex> g(s->mu);
   raw->id = s->next_id++;
@@ -314,8 +386,21 @@ mdp_status mdp_server_submit(mdp_server_t s, int64_t S, int32_t A, const int64_t
   s->all[raw->id] = std::move(r);
   s->queue.push_back(raw);
   *request_id = raw->id;
-  s->cv_work.notify_all();
+  s->cv_admit.notify_all();
   return MDP_OK;
+}
+
+mdp_status mdp_server_submit(mdp_server_t s, int64_t S, int32_t A, const int64_t* row_ptr,
+                             const int32_t* col, const double* val, const double* cost,
+                             double gamma, int64_t* request_id) {
+  return submit_common(s, S, A, row_ptr, col, val, cost, gamma, request_id, false);
+}
+
+mdp_status mdp_server_submit_borrowed(mdp_server_t s, int64_t S, int32_t A,
+                                      const int64_t* row_ptr, const int32_t* col,
+                                      const double* val, const double* cost, double gamma,
+                                      int64_t* request_id) {
+  return submit_common(s, S, A, row_ptr, col, val, cost, gamma, request_id, true);
 }
 
 mdp_status mdp_server_poll(mdp_server_t s, int64_t id, int32_t* done) {
@@ -357,8 +442,8 @@ mdp_status mdp_server_info(mdp_server_t s, int64_t* queued, int64_t* resident,
   if (!s) return fail(MDP_E_INVAL, "NULL server");
   std::lock_guard<std::mutex> g(s->mu);
   if (queued) *queued = static_cast<int64_t>(s->queue.size());
-  if (resident) *resident = static_cast<int64_t>(s->resident.size());
-  if (resident_bytes) *resident_bytes = s->resident_bytes;
+  if (resident) *resident = static_cast<int64_t>(s->resident.size() + s->ready.size());
+  if (resident_bytes) *resident_bytes = s->held_bytes;
   if (rounds) *rounds = s->rounds;
   return MDP_OK;
 }
@@ -368,16 +453,24 @@ mdp_status mdp_server_destroy(mdp_server_t s) {
   {
     std::lock_guard<std::mutex> g(s->mu);
     s->stop = true;
-    // requests still queued are dropped
+    // requests still queued are dropped; admitted ones finish
     for (Request* r : s->queue) {
       r->status = MDP_E_STATE;
       r->error = "server destroyed";
       r->done = true;
     }
     s->queue.clear();
+    s->cv_admit.notify_all();
+    s->cv_work.notify_all();
+    s->cv_done.notify_all();
+  }
+  for (auto& t : s->admitters) t.join();
+  {
+    std::lock_guard<std::mutex> g(s->mu);
     s->cv_work.notify_all();
   }
   if (s->worker.joinable()) s->worker.join();
+  for (auto& t : s->reapers) t.join();
   for (auto& kv : s->all)
     if (kv.second->h) mdp_destroy(kv.second->h);
   s->eng.release();

@@ -59,6 +59,7 @@ class KernelProfile(C.Structure):
 class ServerOpts(C.Structure):
     _fields_ = [("struct_size", C.c_size_t), ("stream", C.c_void_p),
                 ("hbm_budget_bytes", C.c_int64), ("device", C.c_int32), ("max_batch", C.c_int32),
+                ("admit_threads", C.c_int32), ("retire_threads", C.c_int32),
                 ("solve", SolveOpts)]
 
 
@@ -95,6 +96,9 @@ SIGNATURES = {
     "mdp_server_create": (C.c_int, [C.POINTER(ServerOpts), C.POINTER(C.c_void_p)]),
     "mdp_server_submit": (C.c_int, [C.c_void_p, C.c_int64, C.c_int32, C.c_void_p, C.c_void_p,
                                     C.c_void_p, C.c_void_p, C.c_double, C.POINTER(C.c_int64)]),
+    "mdp_server_submit_borrowed": (C.c_int, [C.c_void_p, C.c_int64, C.c_int32, C.c_void_p,
+                                             C.c_void_p, C.c_void_p, C.c_void_p, C.c_double,
+                                             C.POINTER(C.c_int64)]),
     "mdp_server_poll": (C.c_int, [C.c_void_p, C.c_int64, C.POINTER(C.c_int32)]),
     "mdp_server_wait": (C.c_int, [C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p,
                                   C.POINTER(RequestStats)]),

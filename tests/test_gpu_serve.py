@@ -32,7 +32,7 @@ def test_server_results_equal_alone_with_staggered_arrivals(precision):
     with m.Server(precision=precision, alpha=1e-2, max_batch=4) as srv:
         ids = []
         for k, inst in enumerate(insts):
-            ids.append(srv.submit(inst))
+            ids.append(srv.submit(inst, borrow=(k % 2 == 1)))
             if k % 3 == 2:
                 time.sleep(0.01)  # later requests arrive while earlier ones run
         outs = [srv.wait(i) for i in ids]
@@ -69,3 +69,19 @@ def test_server_rejects_oversized_request():
         with pytest.raises(m.MDPError) as e:
             srv.submit(config1(S=2000, seed=1))
         assert e.value.status == m.native.MDP_E_NOMEM
+
+
+def test_server_borrowed_invalid_request_fails_at_wait():
+    import paper_2502_14474_amd as m
+    inst = config1(S=200, seed=3)
+    bad = config1(S=200, seed=3)
+    bad.val = bad.val.copy()
+    bad.val[5] = -0.5
+    with m.Server(alpha=1e-2) as srv:
+        good = srv.submit(inst, borrow=True)
+        rid = srv.submit(bad, borrow=True)
+        with pytest.raises(m.MDPError) as e:
+            srv.wait(rid)
+        assert e.value.status == m.native.MDP_E_INVAL
+        v, pi, st = srv.wait(good)
+        assert st["status"] == 0
