@@ -540,6 +540,10 @@ mdp_status mdp_create(int64_t S, int32_t A, const int64_t* row_ptr, const int32_
   }
   if (o.device >= 0) CHK(hipSetDevice(o.device));
   CHK(hipGetDevice(&h->device));
+  if (o.lanes_per_row == 0) {
+    const int tuned = tune_lookup(h);  // width measured earlier for this class, if any
+    if (tuned) h->lanes = tuned;
+  }
   if (o.stream) {
     h->stream = static_cast<hipStream_t>(o.stream);
   } else {
@@ -962,22 +966,40 @@ mdp_status mdp_autotune(mdp_t h, int32_t* lanes) {
   MDP_HIP(hipEventCreate(&e0));
   MDP_HIP(hipEventCreate(&e1));
   MDP_HIP(hipMemsetAsync(h->io, 0, h->S * sizeof(double), h->stream));
-  float best_ms = std::numeric_limits<float>::infinity();
-  int best = h->lanes;
+  MDP_HIP(hipMemsetAsync(h->pi_io, 0, h->S * sizeof(int32_t), h->stream));
   const int prof_was = h->prof_mask;
   h->prof_mask = 0;
-  for (int L = 2; L <= 64; L <<= 1) {
+  // cost of a width: one sweep plus four policy products (a solve runs
+  // several Arnoldi steps per sweep)
+  auto time_width = [&](int L, float* out) -> mdp_status {
     h->lanes = L;
-    for (int w = 0; w < 2; ++w)
+    for (int w = 0; w < 2; ++w) {
       MDP_HIP(launch_bellman(h, kF64, h->io, h->Tv, h->pi, nullptr, false, kRedNone, 0, 0, 0));
+      MDP_HIP(launch_apply(h, kApplyOp, h->pi_io, h->io, h->x2, false, kRedNone, 0, 0, 0));
+    }
+    float ms_s = 0, ms_a = 0;
     MDP_HIP(hipEventRecord(e0, h->stream));
-    for (int r = 0; r < 5; ++r)
+    for (int r = 0; r < 3; ++r)
       MDP_HIP(launch_bellman(h, kF64, h->io, h->Tv, h->pi, nullptr, false, kRedNone, 0, 0, 0));
     MDP_HIP(hipEventRecord(e1, h->stream));
     MDP_HIP(hipEventSynchronize(e1));
+    MDP_HIP(hipEventElapsedTime(&ms_s, e0, e1));
+    MDP_HIP(hipEventRecord(e0, h->stream));
+    for (int r = 0; r < 3; ++r)
+      MDP_HIP(launch_apply(h, kApplyOp, h->pi_io, h->io, h->x2, false, kRedNone, 0, 0, 0));
+    MDP_HIP(hipEventRecord(e1, h->stream));
+    MDP_HIP(hipEventSynchronize(e1));
+    MDP_HIP(hipEventElapsedTime(&ms_a, e0, e1));
+    *out = ms_s + 4.0f * ms_a;
+    return MDP_OK;
+  };
+  float best_ms = std::numeric_limits<float>::infinity();
+  int best = h->lanes;
+  mdp_status st = MDP_OK;
+  for (int L = 2; L <= 64 && st == MDP_OK; L <<= 1) {
     float ms = 0;
-    MDP_HIP(hipEventElapsedTime(&ms, e0, e1));
-    if (ms < best_ms) {
+    st = time_width(L, &ms);
+    if (st == MDP_OK && ms < best_ms) {
       best_ms = ms;
       best = L;
     }
@@ -986,6 +1008,8 @@ mdp_status mdp_autotune(mdp_t h, int32_t* lanes) {
   h->prof_mask = prof_was;
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
+  if (st < 0) return st;
+  tune_store(h, best);
   if (lanes) *lanes = best;
   return MDP_OK;
 }

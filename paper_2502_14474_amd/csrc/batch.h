@@ -3,6 +3,7 @@
 #pragma once
 
 #include <map>
+#include <shared_mutex>
 #include <tuple>
 #include <vector>
 
@@ -81,10 +82,11 @@ struct ChunkGraphs {
 class BatchEngine {
  public:
   static constexpr int kMaxClasses = 6;  // lane widths 2..64
+  // sweep groups are (lane width, sweep precision): up to 3 * kMaxClasses
   enum {
     kListSweep0 = 0,
-    kListApply0 = kMaxClasses,
-    kListAll = 2 * kMaxClasses,
+    kListApply0 = 3 * kMaxClasses,
+    kListAll = 4 * kMaxClasses,
     kListGm,
     kListGmUpd,
     kListCast,
@@ -93,6 +95,10 @@ class BatchEngine {
   hipStream_t stream = nullptr;
   Prec prec = kF64;
   bool use_graphs = true;
+  // Held exclusively while a graph is captured: threads that allocate or
+  // free device or pinned memory take it shared, since such calls from
+  // another thread can invalidate a capture in progress.
+  std::shared_mutex* capture_lock = nullptr;
   std::vector<BatchItem*> items;
 
   ~BatchEngine();
@@ -103,7 +109,7 @@ class BatchEngine {
  private:
   int cap = 0;
   BDesc* descs_d = nullptr;
-  std::vector<BDesc> descs_h;
+  BDesc* descs_h = nullptr;  // pinned, so uploads never queue behind pageable copies
   void* lists_d = nullptr;
   void* lists_h = nullptr;
   Ctl* hdr_d = nullptr;

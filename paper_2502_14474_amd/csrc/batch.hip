@@ -21,6 +21,8 @@
 #include <cstring>
 #include <limits>
 #include <map>
+#include <mutex>
+#include <shared_mutex>
 #include <vector>
 
 #include "batch.h"
@@ -260,6 +262,8 @@ void BatchEngine::release() {
   if (hdr_d) (void)hipFree(hdr_d);
   if (hdr_h) (void)hipHostFree(hdr_h);
   if (lists_h) (void)hipHostFree(lists_h);
+  if (descs_h) (void)hipHostFree(descs_h);
+  descs_h = nullptr;
   descs_d = nullptr;
   lists_d = nullptr;
   hdr_d = nullptr;
@@ -279,7 +283,9 @@ mdp_status BatchEngine::reserve(int n) {
   MDP_HIP(hipHostMalloc(reinterpret_cast<void**>(&hdr_h), sizeof(Ctl) * cap, hipHostMallocDefault));
   MDP_HIP(hipHostMalloc(reinterpret_cast<void**>(&lists_h), list_bytes * kNumLists,
                         hipHostMallocDefault));
-  descs_h.resize(cap);
+  MDP_HIP(hipHostMalloc(reinterpret_cast<void**>(&descs_h), sizeof(BDesc) * cap,
+                        hipHostMallocDefault));
+  std::memset(descs_h, 0, sizeof(BDesc) * cap);
   return MDP_OK;
 }
 
@@ -338,7 +344,7 @@ int BatchEngine::build_list(int slot, const std::vector<int>& idx, int kind) {
 }
 
 mdp_status BatchEngine::upload(int nitems, int nlists) {
-  MDP_HIP(hipMemcpyAsync(descs_d, descs_h.data(), sizeof(BDesc) * nitems, hipMemcpyHostToDevice,
+  MDP_HIP(hipMemcpyAsync(descs_d, descs_h, sizeof(BDesc) * nitems, hipMemcpyHostToDevice,
                          stream));
   MDP_HIP(hipMemcpyAsync(lists_d, lists_h, WorkList::bytes(cap) * nlists, hipMemcpyHostToDevice,
                          stream));
@@ -356,6 +362,13 @@ mdp_status BatchEngine::headers(int slot, int n) {
 
 static int persistent_grid(int total) { return std::max(1, std::min(total, 2048)); }
 
+// Fixed grids of the captured Arnoldi steps (graph replays keep their launch
+// shapes): enough workgroups for 4 per CU on the big kernels, few on the
+// per-MDP reductions so that idle workgroups cost little in small batches.
+constexpr int kGraphGridBig = 1024;
+constexpr int kGraphGridReduce = 512;
+constexpr int kGraphGridSmall = 64;
+
 // Arnoldi steps [j0, j1) of the current cycle for the lanes classes `cls`.
 hipError_t BatchEngine::enqueue_steps(const std::vector<int>& cls_lanes, int j0, int j1, int m,
                                       bool fixed, int tiles_apply_max, int tiles_upd,
@@ -369,7 +382,7 @@ hipError_t BatchEngine::enqueue_steps(const std::vector<int>& cls_lanes, int j0,
       hipError_t e = with_lanes_b(L, [&](auto Lc) -> hipError_t {
         constexpr int LL = decltype(Lc)::value;
         constexpr int UU = rows_in_flight_b<LL>();
-        const int g = grid(tiles_apply_max, 2048);
+        const int g = grid(tiles_apply_max, kGraphGridBig);
         if (prec == kF64)
           kb_arnoldi_apply<LL, UU, kF64><<<g, kBlock, 0, stream>>>(descs_d, list_d(kListApply0 + c), j);
         else if (prec == kF32)
@@ -380,13 +393,13 @@ hipError_t BatchEngine::enqueue_steps(const std::vector<int>& cls_lanes, int j0,
       });
       if (e != hipSuccess) return e;
     }
-    kb_reduce_dots<<<grid(n_items * (j + 1), 1024), kBlock, 0, stream>>>(descs_d, list_d(kListGm), j);
-    const int gu = grid(tiles_upd, 2048);
+    kb_reduce_dots<<<grid(n_items * (j + 1), kGraphGridReduce), kBlock, 0, stream>>>(descs_d, list_d(kListGm), j);
+    const int gu = grid(tiles_upd, kGraphGridBig);
     if (prec == kF64)
       kb_arnoldi_update<double><<<gu, kBlock, 0, stream>>>(descs_d, list_d(kListGmUpd), j);
     else
       kb_arnoldi_update<float><<<gu, kBlock, 0, stream>>>(descs_d, list_d(kListGmUpd), j);
-    kb_norm_givens<<<grid(n_items, 256), kBlock, 0, stream>>>(descs_d, list_d(kListGm), j, m);
+    kb_norm_givens<<<grid(n_items, kGraphGridSmall), kBlock, 0, stream>>>(descs_d, list_d(kListGm), j, m);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
@@ -402,7 +415,7 @@ mdp_status BatchEngine::sweep_phase(const mdp_solve_opts& o, std::vector<int>& n
     int slot = kListSweep0;
     std::vector<std::pair<std::pair<int, int>, int>> launch;
     for (auto& g : groups) {
-      if (slot >= kListSweep0 + kMaxClasses) return fail(MDP_E_NOTSUP, "too many sweep classes in a batch");
+      if (slot >= kListSweep0 + 3 * kMaxClasses) return fail(MDP_E_NOTSUP, "too many sweep classes in a batch");
       const int tiles = build_list(slot, g.second, 0);
       launch.push_back({g.first, tiles});
       ++slot;
@@ -512,7 +525,7 @@ mdp_status BatchEngine::cycle_phase(const mdp_solve_opts& o, std::vector<int>& g
   const int tiles_upd = build_list(kListGmUpd, gm, 2);
   MDP_TRY(upload(static_cast<int>(items.size()), kNumLists));
   const int n = static_cast<int>(gm.size());
-  const int se = std::max(1, o.sync_every > 0 ? o.sync_every : 4);
+  const int se = std::max(1, o.sync_every > 0 ? o.sync_every : 6);
 
   // The Arnoldi steps come from HIP graphs captured once per configuration
   // (precision, lane classes, m, chunk length, grid sizes) and replayed each
@@ -520,6 +533,8 @@ mdp_status BatchEngine::cycle_phase(const mdp_solve_opts& o, std::vector<int>& g
   GraphKey key{static_cast<int>(prec), lanes, m, se};
   auto git = graphs.find(key);
   if (use_graphs && git == graphs.end()) {
+    std::unique_lock<std::shared_mutex> cap_guard;
+    if (capture_lock) cap_guard = std::unique_lock<std::shared_mutex>(*capture_lock);
     ChunkGraphs cg;
     for (int j0 = 0; j0 < m; j0 += se) {
       hipGraph_t g;

@@ -177,6 +177,11 @@ double bytes_apply(const mdp_handle* h, int bval, int bx, int by);
 double bytes_arnoldi_apply(const mdp_handle* h, int bval, int bb, int j);
 double bytes_arnoldi_update(const mdp_handle* h, int bb, int j);
 
+// Autotuner cache (tune.cpp): class key, stored lane width (0: none), store.
+std::string tune_key(const mdp_handle* h);
+int tune_lookup(const mdp_handle* h);
+void tune_store(const mdp_handle* h, int lanes);
+
 // Profiler hooks: bracket one launch with events when its class is selected.
 void prof_begin(mdp_handle* h, int kind, hipEvent_t* a);
 void prof_end(mdp_handle* h, int kind, hipEvent_t a, double bytes, int tag);

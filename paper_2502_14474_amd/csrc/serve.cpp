@@ -9,6 +9,7 @@
 // out, their memory released, and their slots reused.  Because the batch
 // engine is batch-invariant, a request's result does not depend on what else
 // was resident.
+#include <algorithm>
 #include <chrono>
 #include <condition_variable>
 #include <cstring>
@@ -17,6 +18,7 @@
 #include <map>
 #include <memory>
 #include <mutex>
+#include <shared_mutex>
 #include <thread>
 #include <vector>
 
@@ -79,6 +81,7 @@ struct mdp_server {
   int device = 0;
   hipStream_t stream = nullptr;
   std::mutex mu;
+  std::shared_mutex alloc_mu;  // see BatchEngine::capture_lock
   std::condition_variable cv_admit, cv_work, cv_reap, cv_done;
   std::deque<mdp::Request*> queue;     // submitted, not yet admitted
   std::vector<mdp::Request*> ready;    // admitted, joining at the next round
@@ -212,14 +215,14 @@ mdp_status mdp_server::admit_one(Request* r) {
   co.device = device;
   co.validate = 0;      // validated at submission
   mdp_handle* h = nullptr;
-  if (r->borrowed) {
-    // validation runs here, off the caller's thread
-    MDP_TRY(validate_host(r->S, r->A, r->b_row_ptr, r->b_col, r->b_val, r->b_cost));
-    MDP_TRY(mdp_create(r->S, r->A, r->b_row_ptr, r->b_col, r->b_val, r->b_cost, r->gamma, &co, &h));
-  } else {
-    MDP_TRY(mdp_create(r->S, r->A, r->row_ptr.data(), r->col.data(), r->val.data(),
-                       r->cost.data(), r->gamma, &co, &h));
-  }
+  const int64_t* rp = r->borrowed ? r->b_row_ptr : r->row_ptr.data();
+  const int32_t* cl = r->borrowed ? r->b_col : r->col.data();
+  const double* vl = r->borrowed ? r->b_val : r->val.data();
+  const double* cs = r->borrowed ? r->b_cost : r->cost.data();
+  // validation runs here, off the caller's thread
+  if (r->borrowed) MDP_TRY(validate_host(r->S, r->A, rp, cl, vl, cs));
+  std::shared_lock<std::shared_mutex> alloc_guard(alloc_mu);
+  MDP_TRY(mdp_create(r->S, r->A, rp, cl, vl, cs, r->gamma, &co, &h));
   r->h = h;
   const Prec prec = prec_of(opts.solve.precision);
   mdp_status st = ensure_basis(h, prec == kF64 ? kF64 : kF32, opts.solve.restart);
@@ -254,6 +257,7 @@ mdp_status mdp_server::admit_one(Request* r) {
 }
 
 void mdp_server::retire(Request* r) {
+  std::shared_lock<std::shared_mutex> alloc_guard(alloc_mu);
   mdp_handle* h = r->h;
   const BatchItem& it = r->item;
   r->v.resize(h->S);
@@ -331,6 +335,7 @@ mdp_status mdp_server_create(const mdp_server_opts* opt, mdp_server_t* out) {
   }
   s->eng.stream = s->stream;
   s->eng.prec = prec_of(o.solve.precision);
+  s->eng.capture_lock = &s->alloc_mu;
   mdp_status st = s->eng.reserve(o.max_batch);
   if (st < 0) {
     if (!o.stream) (void)hipStreamDestroy(s->stream);

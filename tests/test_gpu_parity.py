@@ -257,3 +257,27 @@ def test_device_pointer_round_trip():
     assert st["status"] == 0
     assert np.max(np.abs(v.cpu().numpy() - ref["v"])) <= 1e-9 * np.max(np.abs(ref["v"]))
     assert np.array_equal(pi.cpu().numpy(), ref["pi"])
+
+
+def test_autotune_remembers_width_per_class(tmp_path, monkeypatch):
+    """The autotuner picks one of the candidate widths, stores it under the
+    handle's class key and a later handle of that class starts from it; the
+    tuned handle's sweep still matches the oracle."""
+    import json
+    import paper_2502_14474_amd as m
+    cache = tmp_path / "tune.json"
+    monkeypatch.setenv("MDP_TUNE_CACHE", str(cache))
+    inst = config2(S=20000, A=8, seed=3)
+    with _mdp(inst) as h:
+        L = m.mdp_autotune(h.h)
+        assert L in (2, 4, 8, 16, 32, 64)
+        assert h.info()["lanes_per_row"] == L
+        _check_bellman(inst, h, np.random.default_rng(0).standard_normal(inst.S))
+    stored = json.loads(cache.read_text())
+    assert len(stored) == 1
+    (key, val), = stored.items()
+    assert key.startswith("gfx") and key.endswith(":A8_k16") and val == L
+    with _mdp(config2(S=5000, A=8, seed=4)) as h2:
+        assert h2.info()["lanes_per_row"] == L
+    with _mdp(config2(S=5000, A=8, seed=4), lanes_per_row=2) as h3:
+        assert h3.info()["lanes_per_row"] == 2
