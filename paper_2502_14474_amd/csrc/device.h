@@ -75,24 +75,54 @@ __device__ __forceinline__ float Gather<float>::operator()(int c) const {
   return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, c * 4, 0, 0));
 }
 
+// Lane exchange inside a row of 16 lanes through the DPP crossbar (no LDS):
+// lane i reads lane i' of the same row as selected by the DPP control word.
+template <int CTRL, typename T>
+__device__ __forceinline__ T dpp_read(T v) {
+  static_assert(sizeof(T) == 4 || sizeof(T) == 8, "4- or 8-byte values");
+  if constexpr (sizeof(T) == 4) {
+    return __builtin_bit_cast(T, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), CTRL, 0xF, 0xF, false));
+  } else {
+    const long long b = __builtin_bit_cast(long long, v);
+    const int lo = __builtin_amdgcn_mov_dpp(static_cast<int>(b), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_mov_dpp(static_cast<int>(b >> 32), CTRL, 0xF, 0xF, false);
+    return __builtin_bit_cast(T, (static_cast<long long>(hi) << 32) | static_cast<unsigned int>(lo));
+  }
+}
+
+// Butterfly combine over aligned groups of L lanes (L a power of two, <= 64).
+// Stage k pairs lane i with lane i xor k.  Stages k = 32 and 16 cross 16-lane
+// rows and use the LDS permute.  Inside a row, k = 8 is a DPP row rotation by
+// 8 (exactly i xor 8); k = 4 is a rotation by 4 when the k = 8 stage ran
+// before it (every lane then holds the value of its class mod 8, so lane
+// i+4 mod 16 carries the same value as i xor 4), and otherwise (L = 8, where
+// the rotation would leave the group) the LDS permute; k = 2 and 1 are quad
+// permutations.  The result is bitwise that of the plain xor butterfly, and
+// every lane ends with it.
+template <int L, typename T, typename Op>
+__device__ __forceinline__ T group_combine(T v, Op op) {
+  if constexpr (L >= 64) v = op(v, __shfl_xor(v, 32, kWave));
+  if constexpr (L >= 32) v = op(v, __shfl_xor(v, 16, kWave));
+  if constexpr (L >= 16) v = op(v, dpp_read<0x128>(v));  // row_ror:8
+  if constexpr (L >= 16) v = op(v, dpp_read<0x124>(v));  // row_ror:4
+  if constexpr (L == 8) v = op(v, __shfl_xor(v, 4, kWave));
+  if constexpr (L >= 4) v = op(v, dpp_read<0x4E>(v));    // quad_perm [2,3,0,1]
+  if constexpr (L >= 2) v = op(v, dpp_read<0xB1>(v));    // quad_perm [1,0,3,2]
+  return v;
+}
+
 template <int L, typename T>
 __device__ __forceinline__ T group_sum(T v) {
-#pragma unroll
-  for (int off = L / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
-  return v;
+  return group_combine<L>(v, [](T a, T b) { return a + b; });
 }
 
 template <typename T>
 __device__ __forceinline__ T wave_sum(T v) {
-#pragma unroll
-  for (int off = kWave / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
-  return v;
+  return group_sum<kWave>(v);
 }
 
 __device__ __forceinline__ double wave_max_nan(double v) {
-#pragma unroll
-  for (int off = kWave / 2; off > 0; off >>= 1) v = max_nan(v, __shfl_xor(v, off, kWave));
-  return v;
+  return group_combine<kWave>(v, [](double a, double b) { return max_nan(a, b); });
 }
 
 // (max, sum) over the workgroup; the result is valid in thread 0.
