@@ -125,6 +125,23 @@ __device__ __forceinline__ double wave_max_nan(double v) {
   return group_combine<kWave>(v, [](double a, double b) { return max_nan(a, b); });
 }
 
+// s + p[t] + p[t + kBlock] + p[t + 2 kBlock] + ... for t = threadIdx.x, in that
+// order, with the loads of KB terms issued before their additions.
+template <int KB = 8>
+__device__ __forceinline__ double strided_sum(const double* __restrict__ p, int n, double s) {
+  for (int b0 = threadIdx.x; b0 < n; b0 += KB * kBlock) {
+    double v[KB];
+#pragma unroll
+    for (int k = 0; k < KB; ++k) {
+      const int b = b0 + k * kBlock;
+      v[k] = p[b < n ? b : b0];
+    }
+#pragma unroll
+    for (int k = 0; k < KB; ++k) s = b0 + k * kBlock < n ? s + v[k] : s;
+  }
+  return s;
+}
+
 // (max, sum) over the workgroup; the result is valid in thread 0.
 __device__ __forceinline__ void block_max_sum(double& mx, double& sm) {
   __shared__ double s_mx[kBlock / kWave], s_sm[kBlock / kWave];
@@ -549,8 +566,7 @@ __device__ __forceinline__ void arnoldi_apply_tile(
 // Reduce column i (= blockIdx.x) of the dot partials: H[i, j] = scale_i * sum.
 __device__ __forceinline__ void reduce_dots_body(const double* __restrict__ partials, int nb,
                                                  int j, Ctl* __restrict__ ctl, int i) {
-  double s = 0.0;
-  for (int b = threadIdx.x; b < nb; b += kBlock) s += partials[static_cast<int64_t>(i) * nb + b];
+  double s = strided_sum(partials + static_cast<int64_t>(i) * nb, nb, 0.0);
   double mx = 0.0;
   block_max_sum(mx, s);
   if (threadIdx.x == 0) {
@@ -621,24 +637,32 @@ __device__ __forceinline__ void norm_givens_body(const double* __restrict__ part
                                                  int j, int m, Ctl* __restrict__ ctl) {
   __shared__ int s_done;
   __shared__ double s_t[kMaxRestart];
-  double s = 0.0;
-  for (int b = threadIdx.x; b < nb; b += kBlock) s += partials[b];
-  double mx = 0.0;
-  block_max_sum(mx, s);
+  __shared__ double s_h[kMaxRestart + 2], s_cs[kMaxRestart], s_sn[kMaxRestart];
   const int ld = kMaxRestart + 1;
   const int n = j + 1;
+  // the column and the earlier rotations, staged with one parallel round trip
+  if (threadIdx.x <= j) s_h[threadIdx.x] = ctl->H[threadIdx.x + j * ld];
+  if (threadIdx.x < j) {
+    s_cs[threadIdx.x] = ctl->cs[threadIdx.x];
+    s_sn[threadIdx.x] = ctl->sn[threadIdx.x];
+  }
+  double s = strided_sum(partials, nb, 0.0);
+  double mx = 0.0;
+  block_max_sum(mx, s);  // its barriers also publish the staged values
   if (threadIdx.x == 0) {
-    double* h = ctl->H + j * ld;
     const double hn = sqrt(s);
     // size of the column before orthogonalisation, for the breakdown test
     double colnorm2 = hn * hn;
-    for (int i = 0; i <= j; ++i) colnorm2 += h[i] * h[i];
+    for (int i = 0; i <= j; ++i) colnorm2 += s_h[i] * s_h[i];
+    // apply the earlier rotations; `carry` is entry i of the partly rotated column
+    double carry = s_h[0];
     for (int i = 0; i < j; ++i) {
-      const double t = ctl->cs[i] * h[i] + ctl->sn[i] * h[i + 1];
-      h[i + 1] = -ctl->sn[i] * h[i] + ctl->cs[i] * h[i + 1];
-      h[i] = t;
+      const double nx = s_h[i + 1];
+      const double t = s_cs[i] * carry + s_sn[i] * nx;
+      carry = -s_sn[i] * carry + s_cs[i] * nx;
+      s_h[i] = t;
     }
-    const double a = h[j], b = hn;
+    const double a = carry, b = hn;
     const double r = hypot(a, b);
     double c = 1.0, sn = 0.0;
     if (r > 0.0) {
@@ -647,8 +671,8 @@ __device__ __forceinline__ void norm_givens_body(const double* __restrict__ part
     }
     ctl->cs[j] = c;
     ctl->sn[j] = sn;
-    h[j] = r;
-    h[j + 1] = 0.0;
+    s_h[j] = r;
+    s_h[j + 1] = 0.0;
     const double gj = ctl->g[j];
     ctl->g[j + 1] = -sn * gj;
     ctl->g[j] = c * gj;
@@ -670,15 +694,19 @@ __device__ __forceinline__ void norm_givens_body(const double* __restrict__ part
     s_done = done;
   }
   __syncthreads();
+  if (threadIdx.x <= j + 1) ctl->H[threadIdx.x + j * ld] = s_h[threadIdx.x];
   if (!s_done) return;
+  __syncthreads();
   // back substitution R y = g, R = H[0:n, 0:n] upper triangular
   if (threadIdx.x < n) s_t[threadIdx.x] = ctl->g[threadIdx.x];
   __syncthreads();
   for (int i = n - 1; i >= 0; --i) {
-    const double yi = s_t[i] / ctl->H[i + i * ld];
+    // column j is read from LDS, the earlier columns come from earlier launches
+    const double* hcol = i == j ? s_h : ctl->H + i * ld;
+    const double yi = s_t[i] / hcol[i];
     __syncthreads();
     if (threadIdx.x == 0) ctl->y[i] = yi;
-    if (threadIdx.x < i) s_t[threadIdx.x] -= ctl->H[threadIdx.x + i * ld] * yi;
+    if (threadIdx.x < i) s_t[threadIdx.x] -= hcol[threadIdx.x] * yi;
     __syncthreads();
   }
   if (threadIdx.x == 0) ctl->done = 1;
