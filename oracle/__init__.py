@@ -18,6 +18,7 @@ from .mdp_oracle import (  # noqa: F401
     q_values,
     q_values_states,
     bellman,
+    bellman_streamed,
     policy_system,
     evaluate_policy,
     policy_iteration,

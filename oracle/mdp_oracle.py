@@ -22,6 +22,8 @@ from __future__ import annotations
 
 import itertools
 
+from concurrent.futures import ThreadPoolExecutor
+
 import numpy as np
 import scipy.linalg
 import scipy.sparse as sp
@@ -67,6 +69,40 @@ def bellman(inst, v, P=None):
     Tv = Q.min(axis=1)
     pi = Q.argmin(axis=1).astype(np.int32)
     res = float(np.max(np.abs(Tv - np.asarray(v, np.float64)))) if inst.S else 0.0
+    return Tv, pi, res
+
+
+def bellman_streamed(inst, v, block_rows=1 << 22, workers=1):
+    """The same sweep as bellman() (the problem statement's Bellman operator:
+    minimum over actions of cost plus discounted expected value), computed
+    straight from the CSR arrays a block of rows at a time, so that matrices
+    with billions of stored entries need no scipy copy.  Blocks are
+    independent; `workers` threads may take them.  Returns
+    (T v, greedy policy, ||T v - v||_inf)."""
+    v = np.asarray(v, np.float64)
+    rows = inst.S * inst.A
+    Q = np.empty(rows)
+
+    def block(r0):
+        r1 = min(rows, r0 + block_rows)
+        lo, hi = int(inst.row_ptr[r0]), int(inst.row_ptr[r1])
+        if np.any(np.diff(inst.row_ptr[r0:r1 + 1]) <= 0):
+            raise ValueError("empty row")
+        terms = inst.val[lo:hi] * v[inst.col[lo:hi]]
+        starts = (inst.row_ptr[r0:r1] - lo).astype(np.int64)
+        Q[r0:r1] = inst.cost[r0:r1] + inst.gamma * np.add.reduceat(terms, starts)
+
+    starts = range(0, rows, block_rows)
+    if workers > 1:
+        with ThreadPoolExecutor(workers) as ex:
+            list(ex.map(block, starts))
+    else:
+        for r0 in starts:
+            block(r0)
+    Q = Q.reshape(inst.S, inst.A)
+    Tv = Q.min(axis=1)
+    pi = Q.argmin(axis=1).astype(np.int32)
+    res = float(np.max(np.abs(Tv - v))) if inst.S else 0.0
     return Tv, pi, res
 
 

@@ -9,7 +9,7 @@ import numpy as np
 import pytest
 
 import oracle
-from workloads import config2, config3
+from workloads import config2, config3, config4
 
 pytestmark = pytest.mark.gpu
 
@@ -105,3 +105,46 @@ def test_config3_full_maze():
     assert rel <= 1e-9
     rng = np.random.default_rng(5)
     _sampled_bellman_check(inst, Tv, pi, v, rng)
+
+
+@pytest.fixture(scope="module")
+def c4():
+    t = time.time()
+    inst = config4()
+    _log(f"[case] config4 full S={inst.S} nnz={inst.nnz} generated in {time.time() - t:.1f}s")
+    return inst
+
+
+def _certify(inst, v, limit, label):
+    t = time.time()
+    Tv, pi_ref, res = oracle.bellman_streamed(inst, v, workers=8)
+    _log(f"[cert] {label}: oracle sweep in {time.time() - t:.1f}s")
+    rel = res / (1.0 - inst.gamma) / np.max(np.abs(Tv))
+    _log(f"[cert] {label}: oracle residual {res:.3e}, certified relative error <= {rel:.3e}")
+    assert rel <= limit
+    return Tv
+
+
+def test_config4_full_solve_fp64_and_sampled_sweep(c4):
+    """1.5G nonzeros: the float64 solve certified by the oracle's own sweep at
+    full size, and the GPU sweep at the solution checked state by state on a
+    sample."""
+    import paper_2502_14474_amd as m
+    inst = c4
+    with m.MDP.from_instance(inst, validate=False) as h:
+        v, pi, st = h.solve(alpha=1e-2, rtol_cert=1e-10)
+        assert st["status"] == 0, st
+        Tv_gpu, pi_gpu, _ = h.bellman(v)
+    _certify(inst, v, 1e-9, "config4 fp64")
+    _sampled_bellman_check(inst, Tv_gpu, pi_gpu, v, np.random.default_rng(7))
+
+
+def test_config4_full_mixed_fp16(c4):
+    """The float16 copy with its per-row sum correction, float32 inner solves
+    and float64 refinement reach the mixed-precision target at full size."""
+    import paper_2502_14474_amd as m
+    inst = c4
+    with m.MDP.from_instance(inst, validate=False, low_precision=m.MDP_BUILD_FP16) as h:
+        v, pi, st = h.solve(alpha=1e-2, precision=m.MDP_MIXED_FP16, rtol_cert=1e-9)
+    assert st["status"] == 0, st
+    _certify(inst, v, 1e-8, "config4 mixed fp16")

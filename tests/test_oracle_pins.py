@@ -324,3 +324,30 @@ def test_q_values_states_matches_full_q():
     Q = oracle.q_values(inst, v)
     np.testing.assert_allclose(oracle.q_values_states(inst, v, states), Q[states], rtol=1e-13,
                                atol=1e-13)
+
+
+@pytest.mark.parametrize("block_rows", [1, 7, 1 << 22])
+def test_bellman_streamed_matches_statewise_definition(block_rows):
+    """The block-streamed sweep against the state-by-state definition (a dot
+    product per stored row) on ragged and banded instances, for block sizes
+    that cut rows of one state apart and that hold the whole matrix."""
+    for inst in (random_dense_mdp(23, 3, 0.9, seed=4, density=0.4), config2(S=600, A=3, seed=2)):
+        v = np.random.default_rng(8).standard_normal(inst.S)
+        Tv, pi, res = oracle.bellman_streamed(inst, v, block_rows=block_rows)
+        Tv2, pi2, res2 = oracle.bellman_streamed(inst, v, block_rows=block_rows, workers=3)
+        assert np.array_equal(Tv, Tv2) and np.array_equal(pi, pi2) and res == res2
+        Q = oracle.q_values_states(inst, v, np.arange(inst.S))
+        np.testing.assert_allclose(Tv, Q.min(axis=1), rtol=1e-13, atol=1e-13)
+        part = np.partition(Q, 1, axis=1)
+        clear = part[:, 1] - part[:, 0] > 1e-12
+        assert np.array_equal(pi[clear], Q.argmin(axis=1)[clear])
+        assert abs(res - np.max(np.abs(Q.min(axis=1) - v))) <= 1e-13
+
+
+def test_bellman_streamed_rejects_empty_rows():
+    inst = random_dense_mdp(5, 2, 0.9, seed=1)
+    rp = inst.row_ptr.copy()
+    rp[3] = rp[2]  # row 2 loses its entries
+    bad = MDPInstance(inst.S, inst.A, rp, inst.col, inst.val, inst.cost, inst.gamma)
+    with pytest.raises(ValueError):
+        oracle.bellman_streamed(bad, np.zeros(inst.S))
