@@ -161,6 +161,8 @@ def main():
     ap.add_argument("--atol", type=float, default=1e-8)
     ap.add_argument("--sweeps", type=int, default=20)
     ap.add_argument("--lanes", type=int, default=0)
+    ap.add_argument("--autotune", action="store_true",
+                    help="time the lane widths on this MDP (mdp_autotune) before the timed solves")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--mixed", choices=["fp32", "fp16"], default="fp32")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -205,6 +207,10 @@ def main():
                      stream=stream.cuda_stream, device=0, lanes_per_row=args.lanes,
                      low_precision=0 if args.no_mixed else (
                          m.MDP_BUILD_FP32 if args.mixed == "fp32" else m.MDP_BUILD_FP16))
+    if args.autotune:
+        t1 = time.time()
+        lanes = m.mdp_autotune(h)
+        log(f"[bench] autotuned lanes per row: {lanes} in {time.time()-t1:.1f}s")
     info = m.mdp_info(h)
     log(f"[bench] created handle in {time.time()-t:.1f}s: {info}")
     v = torch.zeros(inst.S, dtype=torch.float64, device=dev)
