@@ -148,6 +148,61 @@ def serving_leg(args, m):
             "open_loop_0.7C": open70}
 
 
+def rows_leg(args, m, h, inst, v, pi):
+    """Times the path's other steps on the solved MDP: the policy product on
+    its own (20 launches at the greedy policy of the solution), a solve with
+    Richardson inner iterations, and the per-kernel breakdown of one float64
+    GMRES solve.  Rates use the library's algorithmic byte counts."""
+    import torch
+
+    def summary(prof):
+        out = {}
+        for k, d in prof.items():
+            if d["launches"]:
+                avg = d["ms"] / d["launches"]
+                gbs = d["bytes"] / d["launches"] / (avg * 1e-3) / 1e9 if d["bytes"] else None
+                out[k] = {"launches": d["launches"], "avg_us": 1e3 * avg,
+                          "gbs": gbs, "frac": gbs / HBM_PEAK_GBS if gbs else None}
+        return out
+
+    rows = {}
+    y = torch.empty_like(v)
+    m.mdp_policy_apply(h, pi, v, y, 0)
+    m.mdp_profile(h, kinds=["policy_apply"])
+    for _ in range(20):
+        m.mdp_policy_apply(h, pi, v, y, 0)
+    torch.cuda.synchronize()
+    rows["policy_product"] = summary(m.mdp_profile_read(h))["policy_apply"]
+    m.mdp_profile(h, False)
+
+    if inst.gamma <= 0.99:
+        w = torch.zeros_like(v)
+        p2 = torch.zeros_like(pi)
+        m.mdp_profile(h, True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st = m.mdp_solve(h, w, p2, inner=m.MDP_INNER_RICHARDSON, alpha=args.alpha, atol=args.atol,
+                         max_inner=200000)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        rows["richardson_solve"] = {"ms": 1e3 * (t1 - t0), "status": st["status"],
+                                    "sweeps": st["bellman_sweeps"], "inner": st["inner_iters"],
+                                    "residual": st["residual"],
+                                    "kernels": summary(m.mdp_profile_read(h))}
+        m.mdp_profile(h, False)
+
+    w = torch.zeros_like(v)
+    p2 = torch.zeros_like(pi)
+    m.mdp_profile(h, True)
+    st = m.mdp_solve(h, w, p2, restart=args.restart, alpha=args.alpha, atol=args.atol)
+    torch.cuda.synchronize()
+    rows["gmres_solve_kernels"] = summary(m.mdp_profile_read(h))
+    m.mdp_profile(h, False)
+    log(f"[bench] rows: policy product {rows['policy_product']['avg_us']:.1f} us, "
+        f"richardson {rows.get('richardson_solve', {}).get('ms', float('nan')):.1f} ms")
+    return rows
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -168,6 +223,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-states", type=int, default=250_000)
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-rows", action="store_true",
+                    help="skip the per-row leg (policy product, Richardson solve, GMRES kernel breakdown)")
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration)")
     ap.add_argument("--serve-pool", type=int, default=24)
@@ -271,6 +328,9 @@ def main():
     sweep_avg_ms = sprof["ms"] / sprof["launches"]
     sweep_gbs = sprof["bytes"] / sprof["launches"] / (sweep_avg_ms * 1e-3) / 1e9
 
+    # ---- the other rows of the path, each on its own ----------------------------
+    rows = None if args.no_rows else rows_leg(args, m, h, inst, v, pi)
+
     # ---- mixed precision --------------------------------------------------------
     mixed = None
     if not args.no_mixed:
@@ -331,6 +391,7 @@ def main():
         "solve": {"sweeps": last["bellman_sweeps"], "inner": last["inner_iters"],
                   "residual": last["residual"], "history": last.get("history")},
         "mixed": dict(mixed, precision=args.mixed) if mixed else None,
+        "rows": rows,
         "serving": serve,
         "kernels": kernels,
     }

@@ -75,6 +75,14 @@ typedef struct {
   int32_t validate;       /* nonzero: check the MDP data (see the layout above) */
   int32_t low_precision;  /* MDP_BUILD_* bits */
   int32_t lanes_per_row;  /* 0: chosen from the mean row length; else 1,2,4,...,64 */
+  int32_t col_blocks;     /* column-blocked copy of P for the float64 sweep: -1 (default)
+                             builds one when S >= 2^21 and at least half of the entries lie
+                             outside their row's column slice (slices of 4 MB of v);
+                             0: never; n >= 1: always, with n slices (MDP_E_NOTSUP if a
+                             row holds more than 255 entries of one slice, its columns are
+                             not in increasing slice order, or A > 1024).  The blocked
+                             sweep takes a row's sum slice by slice, so its rounding
+                             differs from the plain sweep's within the usual bound. */
 } mdp_create_opts;
 
 typedef struct {

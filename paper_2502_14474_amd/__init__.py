@@ -45,10 +45,11 @@ def mdp_last_error():
 
 
 def mdp_create(S, A, row_ptr, col, val, cost, gamma, stream=None, device=-1, validate=True,
-               low_precision=0, lanes_per_row=0):
+               low_precision=0, lanes_per_row=0, col_blocks=-1):
     lib = native.load()
     o = native.CreateOpts()
     lib.mdp_default_create_opts(C.byref(o))
+    o.col_blocks = col_blocks
     o.stream = stream
     o.device = device
     o.validate = 1 if validate else 0

@@ -399,6 +399,7 @@ void mdp_default_create_opts(mdp_create_opts* o) {
   o->validate = 1;
   o->low_precision = 0;
   o->lanes_per_row = 0;
+  o->col_blocks = -1;
 }
 
 void mdp_default_eval_opts(mdp_eval_opts* o) {
@@ -439,6 +440,11 @@ mdp_status mdp_destroy(mdp_t h) {
   dev_free(h->val16);
   dev_free(h->corr16);
   dev_free(h->cost32);
+  dev_free(h->cb_col);
+  dev_free(h->cb_val);
+  dev_free(h->cb_rel);
+  dev_free(h->cb_off);
+  dev_free(h->cb_acc);
   dev_free(h->v);
   dev_free(h->Tv);
   dev_free(h->x2);
@@ -483,6 +489,8 @@ mdp_status mdp_create(int64_t S, int32_t A, const int64_t* row_ptr, const int32_
     return fail(MDP_E_INVAL, "lanes_per_row must be 0 or a power of two in [2,64]");
   if (o.low_precision & ~(MDP_BUILD_FP32 | MDP_BUILD_FP16))
     return fail(MDP_E_INVAL, "unknown low_precision bits");
+  if (o.col_blocks < -1 || o.col_blocks > kMaxColBlocks)
+    return fail(MDP_E_INVAL, "col_blocks must be -1, 0 or 1.." + std::to_string(kMaxColBlocks));
   const int64_t rows = S * A;
 
   const bool dev_in = is_device_ptr(row_ptr) || is_device_ptr(col) || is_device_ptr(val) ||
@@ -589,6 +597,27 @@ mdp_status mdp_create(int64_t S, int32_t A, const int64_t* row_ptr, const int32_
   if (o.low_precision & MDP_BUILD_FP16) {
     mdp_status st = ensure_lowp(h, kF16);
     if (st < 0) return bail(st);
+  }
+  {
+    // column-blocked copy for the float64 sweep: forced, or automatic when v
+    // spans several L2s and most columns lie outside the row's own slice
+    const int64_t slice_states = kColSliceBytes / static_cast<int64_t>(sizeof(double));
+    const bool tiles_fit = static_cast<int64_t>(sweep_tile_states(A)) * A <= 4 * kBlock;
+    int blocks = 0;
+    if (o.col_blocks > 0) {
+      blocks = o.col_blocks;
+      if (!tiles_fit) return bail(fail(MDP_E_NOTSUP, "col_blocks needs A <= 1024"));
+    } else if (o.col_blocks < 0 && tiles_fit && S >= kColBlockMinStates) {
+      blocks = static_cast<int>(std::min<int64_t>(kMaxColBlocks, (S + slice_states - 1) / slice_states));
+    }
+    if (blocks > 0) {
+      bool built = false;
+      double far = 0.0;
+      CHK(build_colblocks(h, blocks, o.col_blocks > 0, &built, &far));
+      if (o.col_blocks > 0 && !built)
+        return bail(fail(MDP_E_NOTSUP, "col_blocks: a row holds more than 255 entries of one column "
+                                       "slice, or its columns are not in increasing slice order"));
+    }
   }
   CHK(hipStreamSynchronize(h->stream));
 #undef CHK
@@ -756,8 +785,9 @@ mdp_status mdp_solve(mdp_t h, const double* v0, double* v, int32_t* policy,
   int64_t k = 0, sweeps = 0, inner = 0, applies = 0, refinements = 0;
   double bytes = 0.0;
   bool converged = false;
-  // mixed precision: low-precision sweeps until the residual is small relative to |v|
-  bool lowp_sweep = iprec != kF64;
+  // mixed precision: low-precision sweeps until the residual is small relative to |v|;
+  // with a column-blocked copy the float64 sweep is the faster one and is used throughout
+  bool lowp_sweep = iprec != kF64 && h->cb_blocks == 0;
   double prev_lowp_res = std::numeric_limits<double>::infinity();
   for (;;) {
     const Prec sp = lowp_sweep ? iprec : kF64;

@@ -1,0 +1,340 @@
+// Column-blocked float64 Bellman sweep.
+//
+// When the gathered vector v is much larger than one XCD's L2 (4 MB) and most
+// columns of a row lie far from its own state, every gather of a plain CSR
+// sweep pulls a line from the Infinity Cache.  Cutting the columns into
+// slices of at most 4 MB of v (one XCD's L2) and making one pass per slice
+// keeps most of each pass's gathers inside L2; the price is a float64 partial sum per row carried from
+// pass to pass (read and written once per pass).
+//
+// Storage (built once at mdp_create): the entries of slice b form one
+// segment; inside it, the sweep tiles follow each other and inside a tile the
+// rows, each row keeping its entries in CSR order.  off[b][t] is the first
+// entry of tile t in slice b (off[b][ntiles] the end of the slice) and
+// rel[b][r] the first entry of row r relative to its tile's start (16 bits).
+// Rows holding more than 255 entries of one slice, rows whose slices are not
+// in increasing order and tiles holding more than 65535 entries of one slice
+// are not supported: the copy is then not built.
+//
+// The slices of a row are short (a row's k entries spread over all slices),
+// so one thread takes a whole row segment: it loads the first E entries
+// unconditionally (E about twice the mean segment length) and sums them in
+// CSR order.  A row's sum is the sum of its
+// slice parts in slice order, so the result is deterministic and identical
+// rows give identical sums.
+#include "device.h"
+
+namespace mdp {
+
+namespace {
+
+// cnt[b][r] for every row; *far += entries outside the row's own slice;
+// *bad = 1 when a row is not supported.
+__global__ __launch_bounds__(kBlock) void k_cb_count(int64_t rows, int A, const int* __restrict__ rp,
+                                                     const int* __restrict__ col, int slice,
+                                                     uint8_t* __restrict__ cnt,
+                                                     unsigned long long* __restrict__ far,
+                                                     int* __restrict__ bad) {
+  const int64_t r = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+  unsigned long long f = 0;
+  int b_bad = 0;
+  if (r < rows) {
+    const int own = static_cast<int>((r / A) / slice);
+    int cur = -1, run = 0;
+    for (int e = rp[r]; e < rp[r + 1]; ++e) {
+      const int b = col[e] / slice;
+      if (b != cur) {
+        if (cur >= 0) cnt[static_cast<int64_t>(cur) * rows + r] = static_cast<uint8_t>(run);
+        if (b < cur) b_bad = 1;
+        cur = b;
+        run = 0;
+      }
+      run = run < 255 ? run + 1 : (b_bad = 1, run);
+      f += b != own ? 1ull : 0ull;
+    }
+    if (cur >= 0) cnt[static_cast<int64_t>(cur) * rows + r] = static_cast<uint8_t>(run);
+  }
+  f = wave_sum(f);
+  b_bad = wave_sum(b_bad);
+  if ((threadIdx.x & (kWave - 1)) == 0) {
+    if (f) atomicAdd(far, f);
+    if (b_bad) atomicOr(bad, 1);
+  }
+}
+
+// tsum[b][t] = entries of tile t in slice b.
+__global__ __launch_bounds__(kBlock) void k_cb_tile_sums(int64_t rows, int tile_rows, int ntiles,
+                                                         const uint8_t* __restrict__ cnt,
+                                                         int* __restrict__ tsum) {
+  const int t = blockIdx.x, b = blockIdx.y;
+  const int64_t r0 = static_cast<int64_t>(t) * tile_rows;
+  const int nr = static_cast<int>(min<int64_t>(tile_rows, rows - r0));
+  double s = 0.0, mx = 0.0;  // exact: at most 255 * 1024 per tile
+  for (int i = threadIdx.x; i < nr; i += kBlock) s += cnt[static_cast<int64_t>(b) * rows + r0 + i];
+  block_max_sum(mx, s);
+  if (threadIdx.x == 0) tsum[static_cast<int64_t>(b) * ntiles + t] = static_cast<int>(s);
+}
+
+// Copy the entries of each row to their blocked positions and record each
+// row's start inside its tile.  One workgroup per tile; each thread owns up to
+// 4 rows and walks them slice by slice.
+__global__ __launch_bounds__(kBlock) void k_cb_scatter(int64_t rows, int tile_rows, int ntiles,
+                                                       int nblk, int slice,
+                                                       const int* __restrict__ rp,
+                                                       const int* __restrict__ col,
+                                                       const double* __restrict__ val,
+                                                       const uint8_t* __restrict__ cnt,
+                                                       const int* __restrict__ off,
+                                                       int* __restrict__ cb_col,
+                                                       double* __restrict__ cb_val,
+                                                       uint16_t* __restrict__ rel) {
+  __shared__ int pos[4 * kBlock + 1];
+  const int t = blockIdx.x;
+  const int64_t r0 = static_cast<int64_t>(t) * tile_rows;
+  const int nr = static_cast<int>(min<int64_t>(tile_rows, rows - r0));
+  int cur[4], end[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int i = threadIdx.x + j * kBlock;
+    cur[j] = i < nr ? rp[r0 + i] : 0;
+    end[j] = i < nr ? rp[r0 + i + 1] : 0;
+  }
+  for (int b = 0; b < nblk; ++b) {
+    for (int i = threadIdx.x; i < nr; i += kBlock) pos[i] = cnt[static_cast<int64_t>(b) * rows + r0 + i];
+    __syncthreads();
+    block_exclusive_scan(pos, nr);
+    const int base = off[static_cast<int64_t>(b) * (ntiles + 1) + t];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int i = threadIdx.x + j * kBlock;
+      if (i >= nr) continue;
+      rel[static_cast<int64_t>(b) * rows + r0 + i] = static_cast<uint16_t>(pos[i]);
+      int d = base + pos[i];
+      while (cur[j] < end[j] && col[cur[j]] / slice == b) {
+        cb_col[d] = col[cur[j]];
+        cb_val[d] = val[cur[j]];
+        ++d;
+        ++cur[j];
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// One pass of the blocked sweep over slice b for one tile of states; thread
+// i takes rows i, i + kBlock, ... of the tile.  Passes before the last add the
+// slice's part of each row into acc; the last pass forms
+// Q = g + gamma * (acc + part) in LDS and finishes the tile like the plain
+// sweep.
+template <int E, bool FIRST, bool LAST, typename RT>
+__global__ __launch_bounds__(kBlock) void k_bellman_cb(
+    int64_t S, int A, int tile_states, int ntiles, int b, const uint16_t* __restrict__ rel,
+    const int* __restrict__ off, const int* __restrict__ cb_col, const double* __restrict__ cb_val,
+    const double* __restrict__ cost, const double* __restrict__ v, double gamma,
+    double* __restrict__ acc, double* __restrict__ Tv, int* __restrict__ pi, RT* __restrict__ r0,
+    double4* __restrict__ partials) {
+  extern __shared__ double q[];  // LAST: one value per row of the tile
+  constexpr int RPT = 4;         // rows per thread: tiles hold at most 4 * kBlock rows
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  const int64_t rows = S * A;
+  const int64_t s0 = static_cast<int64_t>(tile) * tile_states;
+  const int ns = static_cast<int>(min<int64_t>(tile_states, S - s0));
+  const int nrows = ns * A;
+  const int64_t row0 = s0 * A;
+  const int64_t ob = static_cast<int64_t>(b) * (ntiles + 1) + tile;
+  const int base = off[ob], tend = off[ob + 1];
+  const uint16_t* __restrict__ rl = rel + static_cast<int64_t>(b) * rows + row0;
+  const Gather<double> gx(v, S);
+  int st[RPT], en[RPT];
+  double prev[RPT];
+#pragma unroll
+  for (int k = 0; k < RPT; ++k) {
+    const int i = threadIdx.x + k * kBlock;
+    const bool valid = i < nrows;
+    const int a = rl[valid ? i : 0];
+    const int z = rl[i + 1 < nrows ? i + 1 : 0];
+    st[k] = valid ? base + a : 0;
+    en[k] = valid ? (i + 1 < nrows ? base + z : tend) : 0;
+    if (!FIRST) prev[k] = acc[row0 + (valid ? i : 0)];
+  }
+  int c[RPT][E];
+  double p[RPT][E];
+#pragma unroll
+  for (int k = 0; k < RPT; ++k)
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int idx = st[k] + e;
+      const bool ok = idx < en[k];
+      const int is = ok ? idx : 0;
+      const int cv = ld_col(cb_col + is);
+      const double pv = ld_val(cb_val + is);
+      c[k][e] = ok ? cv : -1;
+      p[k][e] = ok ? pv : 0.0;
+    }
+  double sum[RPT];
+#pragma unroll
+  for (int k = 0; k < RPT; ++k) {
+    double sk = 0.0;
+#pragma unroll
+    for (int e = 0; e < E; ++e) sk = fma(p[k][e], gx(c[k][e]), sk);  // 0 for empty slots
+    for (int idx = st[k] + E; idx < en[k]; ++idx)
+      sk = fma(ld_val(cb_val + idx), gx(ld_col(cb_col + idx)), sk);
+    sum[k] = sk;
+  }
+#pragma unroll
+  for (int k = 0; k < RPT; ++k) {
+    const int i = threadIdx.x + k * kBlock;
+    if (i >= nrows) continue;
+    const double total = FIRST ? sum[k] : prev[k] + sum[k];
+    if (LAST) {
+      q[i] = fma(gamma, total, cost[row0 + i]);
+    } else {
+      acc[row0 + i] = total;
+    }
+  }
+  if (LAST) {
+    __syncthreads();
+    sweep_finish<double, double, RT>(s0, ns, A, q, v, Tv, pi, r0, partials, tile);
+  }
+}
+
+template <typename F>
+hipError_t with_cb_width(int width, F&& f) {
+  switch (width) {
+    case 2: return f(std::integral_constant<int, 2>{});
+    case 4: return f(std::integral_constant<int, 4>{});
+    default: return f(std::integral_constant<int, 8>{});
+  }
+}
+
+template <typename RT>
+hipError_t cb_passes(mdp_handle* h, const double* v, double* Tv, int32_t* pi, RT* r0,
+                     double4* part, int nb) {
+  const int ts = sweep_tile_states(h->A);
+  const int nblk = h->cb_blocks;
+  const size_t lds_last = static_cast<size_t>(ts) * h->A * sizeof(double);
+  return with_cb_width(h->cb_width, [&](auto Ec) -> hipError_t {
+    constexpr int E = decltype(Ec)::value;
+#define MDP_CB_ARGS(B)                                                                     \
+  h->S, h->A, ts, nb, (B), h->cb_rel, h->cb_off, h->cb_col, h->cb_val, h->cost, v, h->gamma, \
+      h->cb_acc, Tv, pi, r0, part
+    if (nblk == 1) {
+      k_bellman_cb<E, true, true, RT><<<nb, kBlock, lds_last, h->stream>>>(MDP_CB_ARGS(0));
+      return hipGetLastError();
+    }
+    k_bellman_cb<E, true, false, RT><<<nb, kBlock, 0, h->stream>>>(MDP_CB_ARGS(0));
+    for (int b = 1; b + 1 < nblk; ++b)
+      k_bellman_cb<E, false, false, RT><<<nb, kBlock, 0, h->stream>>>(MDP_CB_ARGS(b));
+    k_bellman_cb<E, false, true, RT><<<nb, kBlock, lds_last, h->stream>>>(MDP_CB_ARGS(nblk - 1));
+#undef MDP_CB_ARGS
+    return hipGetLastError();
+  });
+}
+
+}  // namespace
+
+hipError_t launch_bellman_cb(mdp_handle* h, const double* v, double* Tv, int32_t* pi, void* r0,
+                             bool r0_f32, double4* part, int nb) {
+  if (r0_f32) return cb_passes<float>(h, v, Tv, pi, static_cast<float*>(r0), part, nb);
+  return cb_passes<double>(h, v, Tv, pi, static_cast<double*>(r0), part, nb);
+}
+
+hipError_t build_colblocks(mdp_handle* h, int blocks, bool require, bool* built, double* far_frac) {
+  *built = false;
+  *far_frac = 0.0;
+  const int64_t rows = h->rows;
+  const int slice = static_cast<int>((h->S + blocks - 1) / blocks);
+  const int ts = sweep_tile_states(h->A);
+  const int tile_rows = ts * h->A;
+  const int ntiles = static_cast<int>((h->S + ts - 1) / ts);
+  uint8_t* cnt = nullptr;
+  void* scratch = nullptr;  // far counter + bad flag
+  int* tsum = nullptr;
+  int* off = nullptr;
+  uint16_t* rel = nullptr;
+  int* cb_col = nullptr;
+  double* cb_val = nullptr;
+  double* acc = nullptr;
+  auto done = [&](hipError_t r) {
+    (void)hipStreamSynchronize(h->stream);
+    if (scratch) (void)hipFree(scratch);
+    if (tsum) (void)hipFree(tsum);
+    if (cnt) (void)hipFree(cnt);
+    if (!*built) {
+      if (off) (void)hipFree(off);
+      if (rel) (void)hipFree(rel);
+      if (cb_col) (void)hipFree(cb_col);
+      if (cb_val) (void)hipFree(cb_val);
+      if (acc) (void)hipFree(acc);
+    }
+    return r;
+  };
+  hipError_t e = hipSuccess;
+#define CB_CHK(call)                              \
+  do {                                            \
+    if ((e = (call)) != hipSuccess) return done(e); \
+  } while (0)
+  const size_t cnt_bytes = static_cast<size_t>(blocks) * rows;
+  CB_CHK(hipMalloc(reinterpret_cast<void**>(&cnt), cnt_bytes));
+  CB_CHK(hipMalloc(&scratch, 16));
+  CB_CHK(hipMemsetAsync(cnt, 0, cnt_bytes, h->stream));
+  CB_CHK(hipMemsetAsync(scratch, 0, 16, h->stream));
+  auto* far = static_cast<unsigned long long*>(scratch);
+  int* bad = reinterpret_cast<int*>(static_cast<char*>(scratch) + 8);
+  k_cb_count<<<static_cast<unsigned>((rows + kBlock - 1) / kBlock), kBlock, 0, h->stream>>>(
+      rows, h->A, h->row_ptr, h->col, slice, cnt, far, bad);
+  CB_CHK(hipGetLastError());
+  unsigned long long far_h = 0;
+  int bad_h = 0;
+  CB_CHK(hipMemcpyAsync(&far_h, far, 8, hipMemcpyDeviceToHost, h->stream));
+  CB_CHK(hipMemcpyAsync(&bad_h, bad, 4, hipMemcpyDeviceToHost, h->stream));
+  CB_CHK(hipStreamSynchronize(h->stream));
+  *far_frac = static_cast<double>(far_h) / static_cast<double>(h->nnz);
+  if (bad_h || (!require && *far_frac < 0.5)) return done(hipSuccess);
+
+  const size_t nt = static_cast<size_t>(blocks) * ntiles;
+  CB_CHK(hipMalloc(reinterpret_cast<void**>(&tsum), nt * sizeof(int)));
+  k_cb_tile_sums<<<dim3(ntiles, blocks), kBlock, 0, h->stream>>>(rows, tile_rows, ntiles, cnt, tsum);
+  CB_CHK(hipGetLastError());
+  std::vector<int> ts_h(nt), off_h(static_cast<size_t>(blocks) * (ntiles + 1));
+  CB_CHK(hipMemcpyAsync(ts_h.data(), tsum, nt * sizeof(int), hipMemcpyDeviceToHost, h->stream));
+  CB_CHK(hipStreamSynchronize(h->stream));
+  int64_t run = 0;
+  for (int b = 0; b < blocks; ++b) {
+    for (int t = 0; t < ntiles; ++t) {
+      const int n = ts_h[static_cast<size_t>(b) * ntiles + t];
+      if (n > 65535) return done(hipSuccess);  // 16-bit row starts would overflow
+      off_h[static_cast<size_t>(b) * (ntiles + 1) + t] = static_cast<int>(run);
+      run += n;
+    }
+    off_h[static_cast<size_t>(b) * (ntiles + 1) + ntiles] = static_cast<int>(run);
+  }
+  if (run != h->nnz) return done(hipErrorInvalidValue);
+  CB_CHK(hipMalloc(reinterpret_cast<void**>(&off), off_h.size() * sizeof(int)));
+  CB_CHK(hipMemcpyAsync(off, off_h.data(), off_h.size() * sizeof(int), hipMemcpyHostToDevice, h->stream));
+  CB_CHK(hipMalloc(reinterpret_cast<void**>(&rel), cnt_bytes * sizeof(uint16_t)));
+  CB_CHK(hipMalloc(reinterpret_cast<void**>(&cb_col), h->nnz * sizeof(int)));
+  CB_CHK(hipMalloc(reinterpret_cast<void**>(&cb_val), h->nnz * sizeof(double)));
+  CB_CHK(hipMalloc(reinterpret_cast<void**>(&acc), rows * sizeof(double)));
+  k_cb_scatter<<<ntiles, kBlock, 0, h->stream>>>(rows, tile_rows, ntiles, blocks, slice, h->row_ptr,
+                                                 h->col, h->val, cnt, off, cb_col, cb_val, rel);
+  CB_CHK(hipGetLastError());
+  CB_CHK(hipStreamSynchronize(h->stream));
+#undef CB_CHK
+  h->cb_blocks = blocks;
+  h->cb_slice = slice;
+  h->cb_rel = rel;
+  h->cb_off = off;
+  h->cb_col = cb_col;
+  h->cb_val = cb_val;
+  h->cb_acc = acc;
+  const double mean = static_cast<double>(h->nnz) / static_cast<double>(rows) / blocks;
+  // slots loaded per row segment: about twice the mean segment length
+  h->cb_width = mean <= 1.0 ? 2 : (mean <= 2.0 ? 4 : 8);
+  h->device_bytes += static_cast<int64_t>(cnt_bytes * sizeof(uint16_t) + off_h.size() * sizeof(int) +
+                                          h->nnz * 12 + rows * 8);
+  *built = true;
+  return done(hipSuccess);
+}
+
+}  // namespace mdp

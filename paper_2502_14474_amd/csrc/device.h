@@ -285,6 +285,77 @@ struct RowIndex {
   int kfix;
 };
 
+// Second phase of a sweep tile: q holds Q(s, a) of the tile's ns states
+// (row-major, A per state).  One thread per state takes the minimum over
+// a = 0..A-1 with a strict '<' (lowest action wins ties), writes Tv, pi and
+// r0 = Tv - v, and accumulates max|Tv - v|, sum (Tv - v)^2 and max|Tv| into
+// the tile's partials.
+template <typename AT, typename XT, typename RT>
+__device__ __forceinline__ void sweep_finish(int64_t s0, int ns, int A, const AT* q,
+                                             const XT* __restrict__ v, double* __restrict__ Tv,
+                                             int* __restrict__ pi, RT* __restrict__ r0,
+                                             double4* __restrict__ partials, int tile) {
+  double dmax = 0.0, dsum = 0.0, tmax = 0.0;
+  for (int t = threadIdx.x; t < ns; t += kBlock) {
+    const int64_t s = s0 + t;
+    const AT* qs = q + t * A;
+    AT best = qs[0];
+    int arg = 0;
+    bool nan = best != best;
+    for (int a = 1; a < A; ++a) {
+      const AT qa = qs[a];
+      nan |= qa != qa;
+      if (qa < best) {
+        best = qa;
+        arg = a;
+      }
+    }
+    const double tv = nan ? NAN : static_cast<double>(best);
+    if (Tv) Tv[s] = tv;
+    if (pi) pi[s] = arg;
+    const double d = tv - static_cast<double>(v[s]);
+    if (r0) r0[s] = static_cast<RT>(d);
+    dmax = max_nan(dmax, fabs(d));
+    dsum = fma(d, d, dsum);
+    tmax = max_nan(tmax, fabs(tv));
+  }
+  block_max_sum(dmax, dsum);
+  double tm2 = 0.0;
+  block_max_sum(tmax, tm2);
+  if (threadIdx.x == 0) partials[tile] = make_double4(dmax, dsum, tmax, 0.0);
+}
+
+// Exclusive prefix sum of c[0..n) in LDS (n <= 4 * kBlock), in place;
+// c[n] receives the total.  Every thread of the workgroup must call it.
+__device__ __forceinline__ void block_exclusive_scan(int* c, int n) {
+  __shared__ int wsum[kBlock];
+  constexpr int P = 4;
+  const int t = threadIdx.x;
+  int loc[P], run = 0;
+#pragma unroll
+  for (int k = 0; k < P; ++k) {
+    const int i = t * P + k;
+    loc[k] = run;
+    run += i < n ? c[i] : 0;
+  }
+  wsum[t] = run;
+  __syncthreads();
+  for (int off = 1; off < kBlock; off <<= 1) {
+    const int add = t >= off ? wsum[t - off] : 0;
+    __syncthreads();
+    wsum[t] += add;
+    __syncthreads();
+  }
+  const int before = t > 0 ? wsum[t - 1] : 0;
+#pragma unroll
+  for (int k = 0; k < P; ++k) {
+    const int i = t * P + k;
+    if (i < n) c[i] = before + loc[k];
+  }
+  if (t == kBlock - 1) c[n] = wsum[kBlock - 1];
+  __syncthreads();
+}
+
 // ----------------------------------------------------------------------------
 // K1: fused Bellman sweep
 // ----------------------------------------------------------------------------
@@ -348,35 +419,7 @@ __device__ __forceinline__ void bellman_tile(
         if ((threadIdx.x % L) == 0) q[idx] = fma(gam, pv, static_cast<AT>(gc));
       });
   __syncthreads();
-
-  double dmax = 0.0, dsum = 0.0, tmax = 0.0;
-  for (int t = threadIdx.x; t < ns; t += kBlock) {
-    const int64_t s = s0 + t;
-    const AT* qs = q + t * A;
-    AT best = qs[0];
-    int arg = 0;
-    bool nan = best != best;
-    for (int a = 1; a < A; ++a) {
-      const AT qa = qs[a];
-      nan |= qa != qa;
-      if (qa < best) {
-        best = qa;
-        arg = a;
-      }
-    }
-    const double tv = nan ? NAN : static_cast<double>(best);
-    if (Tv) Tv[s] = tv;
-    if (pi) pi[s] = arg;
-    const double d = tv - static_cast<double>(v[s]);
-    if (r0) r0[s] = static_cast<RT>(d);
-    dmax = max_nan(dmax, fabs(d));
-    dsum = fma(d, d, dsum);
-    tmax = max_nan(tmax, fabs(tv));
-  }
-  block_max_sum(dmax, dsum);
-  double tm2 = 0.0;
-  block_max_sum(tmax, tm2);
-  if (threadIdx.x == 0) partials[tile] = make_double4(dmax, dsum, tmax, 0.0);
+  sweep_finish<AT, XT, RT>(s0, ns, A, q, v, Tv, pi, r0, partials, tile);
 }
 
 // Stage the selected rows of kApplyTile states: thread t loads pi(s0+t) and

@@ -89,6 +89,19 @@ struct mdp_handle {
   double* corr16 = nullptr;     // per-row correction 1 - sum fp16(p)
   float* cost32 = nullptr;      // float32 costs
 
+  // Column-blocked copy of P for the float64 sweep (cb_blocks == 0: none).
+  // Columns are cut into cb_blocks slices of cb_slice states; the entries of
+  // slice b are stored together, tile by tile and row by row inside a tile,
+  // so that one pass over slice b gathers only from an L2-sized piece of v.
+  int32_t cb_blocks = 0;
+  int32_t cb_slice = 0;
+  int32_t cb_width = 4;         // entries per row segment loaded unconditionally
+  int32_t* cb_col = nullptr;    // nnz
+  double* cb_val = nullptr;     // nnz
+  uint16_t* cb_rel = nullptr;   // cb_blocks x rows: row start inside its (slice, tile) segment
+  int32_t* cb_off = nullptr;    // cb_blocks x (sweep tiles + 1): first entry of (slice, tile)
+  double* cb_acc = nullptr;     // rows: row sums over the slices done so far
+
   // float64 vectors
   double* v = nullptr;       // current value iterate
   double* Tv = nullptr;      // Bellman sweep output
@@ -157,6 +170,11 @@ enum ReduceMode { kRedNone = -1, kRedPlain = 0, kRedGmresStart = 1, kRedRichards
 
 // Rows of the Bellman sweep handled by one workgroup (whole states).
 constexpr int kSweepRows = MDP_SWEEP_ROWS;
+// Column-blocked sweep: slices of at most 4 MB of the float64 vector (one
+// XCD's L2), built automatically from 2^21 states (16 MB of v) up.
+constexpr int64_t kColSliceBytes = int64_t{4} << 20;
+constexpr int64_t kColBlockMinStates = int64_t{1} << 21;
+constexpr int kMaxColBlocks = 64;
 inline int sweep_tile_states(int A) { return A >= kSweepRows ? 1 : kSweepRows / A; }
 size_t partials_doubles(int64_t S, int A, int m);
 
@@ -195,6 +213,13 @@ void prof_discard_steps(mdp_handle* h, size_t from, int min_tag);
 // (may be null; float when r0_f32).  Then reduces max|Tv-v|, sum (Tv-v)^2 and
 // max|Tv| into ctl with the given ReduceMode (kRedGmresStart starts a GMRES
 // cycle from r0; first_cycle fixes the inner tolerance alpha*||r0||_2).
+// Column-blocked float64 sweep (colblock.hip): build the blocked copy with
+// `blocks` slices (returns false in *built when the rows do not allow it) and
+// run a sweep over it with the arguments of launch_bellman.
+hipError_t build_colblocks(mdp_handle* h, int blocks, bool require, bool* built, double* far_frac);
+hipError_t launch_bellman_cb(mdp_handle* h, const double* v, double* Tv, int32_t* pi, void* r0,
+                             bool r0_f32, double4* part, int nb);
+
 hipError_t launch_bellman(mdp_handle* h, Prec prec, const void* v, double* Tv, int32_t* pi,
                           void* r0, bool r0_f32, int red_mode, int first_cycle, double alpha,
                           double floor_rel);

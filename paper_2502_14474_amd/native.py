@@ -21,7 +21,7 @@ MDP_BUILD_FP32, MDP_BUILD_FP16 = 1, 2
 class CreateOpts(C.Structure):
     _fields_ = [("struct_size", C.c_size_t), ("stream", C.c_void_p), ("device", C.c_int32),
                 ("validate", C.c_int32), ("low_precision", C.c_int32),
-                ("lanes_per_row", C.c_int32)]
+                ("lanes_per_row", C.c_int32), ("col_blocks", C.c_int32)]
 
 
 class EvalOpts(C.Structure):

@@ -281,3 +281,55 @@ def test_autotune_remembers_width_per_class(tmp_path, monkeypatch):
         assert h2.info()["lanes_per_row"] == L
     with _mdp(config2(S=5000, A=8, seed=4), lanes_per_row=2) as h3:
         assert h3.info()["lanes_per_row"] == 2
+
+
+CB_CASES = {
+    "c4twin_b4": (lambda: config4(S=12000, A=16, seed=1), 4),
+    "c4twin_b7": (lambda: config4(S=12000, A=16, seed=2), 7),
+    "c2twin_b3": (lambda: config2(S=20000, A=8, seed=1), 3),
+    "ragged_b2": (lambda: random_dense_mdp(37, 3, 0.95, seed=5, density=0.3), 2),
+}
+
+
+@pytest.mark.parametrize("name", sorted(CB_CASES))
+def test_colblocked_sweep_matches_oracle(name):
+    """The column-blocked sweep (forced on small instances, slices of uneven
+    width included) against the oracle's sweep, with the rounding bound of two
+    summation orders."""
+    make, blocks = CB_CASES[name]
+    inst = make()
+    v = 3.0 * np.random.default_rng(4).standard_normal(inst.S)
+    with _mdp(inst, col_blocks=blocks) as h:
+        _check_bellman(inst, h, v)
+        # a second sweep on the same copy (the running sums are overwritten per pass)
+        _check_bellman(inst, h, -v)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_colblocked_solve_certified(precision):
+    """Whole solves over the blocked sweep reach the oracle's fixed point."""
+    import paper_2502_14474_amd as m
+    inst = config4(S=12000, A=16, seed=1)
+    kw = dict(col_blocks=5)
+    if precision:
+        kw["low_precision"] = m.MDP_BUILD_FP32
+    with _mdp(inst, **kw) as h:
+        v, pi, st = h.solve(alpha=1e-2, precision=precision, rtol_cert=1e-10 if precision == 0 else 1e-9)
+    assert st["status"] == 0, st
+    Tv, pi_ref, res = oracle.bellman(inst, v)
+    rel = res / (1.0 - inst.gamma) / np.max(np.abs(Tv))
+    assert rel <= (1e-9 if precision == 0 else 1e-8)
+
+
+def test_colblocks_option_rules():
+    """Forced blocks cost device memory, the automatic rule leaves small
+    matrices alone, and unsupported rows are refused."""
+    import paper_2502_14474_amd as m
+    inst = config2(S=20000, A=8, seed=1)
+    with _mdp(inst, col_blocks=0) as h0, _mdp(inst, col_blocks=-1) as ha, _mdp(inst, col_blocks=2) as h2:
+        assert ha.info()["device_bytes"] == h0.info()["device_bytes"]
+        assert h2.info()["device_bytes"] > h0.info()["device_bytes"] + inst.nnz * 12
+    dense = random_dense_mdp(300, 2, 0.9, seed=3, density=1.0)  # 300 entries per row
+    with pytest.raises(m.MDPError) as ei:
+        m.MDP.from_instance(dense, col_blocks=1)
+    assert ei.value.status == m.native.MDP_E_NOTSUP
