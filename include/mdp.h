@@ -277,6 +277,11 @@ typedef struct {
  * the end of a GMRES cycle exit at once and are not counted. */
 mdp_status mdp_profile(mdp_t h, int32_t enable);
 
+/* As mdp_profile, but only the first of every `every` launches (>= 1) of each
+ * class gets its event pair, so that a timed run pays for few of the
+ * event records (each costs a few microseconds of idle GPU time). */
+mdp_status mdp_profile_sampled(mdp_t h, int32_t enable, int32_t every);
+
 /* Wait for the recorded launches and return the accumulated counters. */
 mdp_status mdp_profile_read(mdp_t h, mdp_kernel_profile* out);
 

@@ -81,13 +81,14 @@ def mdp_autotune(h):
     return L.value
 
 
-def mdp_profile(h, enable=True, kinds=None):
+def mdp_profile(h, enable=True, kinds=None, every=1):
     """Record kernel durations: all classes (enable=True), the named classes
-    (kinds, names as in native.KERNEL_KINDS), or stop (enable=False)."""
+    (kinds, names as in native.KERNEL_KINDS), or stop (enable=False); with
+    every > 1 only one launch in `every` of each class is timed."""
     mask = 0
     if enable:
         mask = -1 if kinds is None else sum(1 << native.KERNEL_KINDS.index(k) for k in kinds)
-    return native.check(native.load().mdp_profile(h, mask))
+    return native.check(native.load().mdp_profile_sampled(h, mask, int(every)))
 
 
 def mdp_profile_read(h):

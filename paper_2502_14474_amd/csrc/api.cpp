@@ -111,26 +111,41 @@ mdp_status gmres_inner(mdp_handle* h, Prec prec, const int32_t* pi, double* x, i
     // chunk the chunk length follows the observed contraction of the
     // residual estimate, so that few steps are enqueued past the end of the
     // cycle (they exit at once, but each still costs a launch).
+    //
+    // While the host reads a snapshot of the control header, one more step is
+    // already queued behind it, so the device does not idle during the host's
+    // round trip; a step queued past the end of the cycle exits at once and
+    // leaves the control block unchanged.
     int chunk = sync_every;
     int j_prev = 0;
     double est_prev = h->ctl_host->beta;
+    bool stale = false;  // steps were queued after the last snapshot
     while (!h->ctl_host->done && j < m) {
       for (int b = 0; b < chunk && j < m; ++b, ++j) {
         MDP_HIP(launch_arnoldi_step(h, prec, pi, j, m));
       }
-      MDP_TRY(sync_ctl(h));
+      const int j_snap = j;
+      MDP_TRY(ctl_snapshot(h));
+      if (j < m) {
+        MDP_HIP(launch_arnoldi_step(h, prec, pi, j, m));
+        ++j;
+      }
+      stale = j > j_snap;
+      MDP_TRY(ctl_wait(h));
       const double est = h->ctl_host->res_est, goal = h->ctl_host->tol_cycle;
       chunk = sync_every;
-      if (j > j_prev && est > 0.0 && est < est_prev && goal > 0.0) {
-        const double rate = std::pow(est / est_prev, 1.0 / (j - j_prev));
+      if (j_snap > j_prev && est > 0.0 && est < est_prev && goal > 0.0) {
+        const double rate = std::pow(est / est_prev, 1.0 / (j_snap - j_prev));
         if (rate < 1.0) {
-          const double need = std::ceil(std::log(goal / est) / std::log(rate));
+          const double need = std::ceil(std::log(goal / est) / std::log(rate)) - (j - j_snap);
           chunk = static_cast<int>(std::min(16.0, std::max(1.0, need)));
         }
       }
-      j_prev = j;
+      j_prev = j_snap;
       est_prev = est;
     }
+    // the header is final unless the last snapshot missed queued steps that did work
+    if (stale && !h->ctl_host->done) MDP_TRY(sync_ctl(h));
     const int done_j = h->ctl_host->j;
     prof_discard_steps(h, rec0, done_j);
     for (int jj = 0; jj < done_j; ++jj)
@@ -264,6 +279,17 @@ mdp_status sync_ctl(mdp_handle* h) {
   return MDP_OK;
 }
 
+mdp_status ctl_snapshot(mdp_handle* h) {
+  MDP_HIP(hipMemcpyAsync(h->ctl_host, h->ctl, kCtlHeaderBytes, hipMemcpyDeviceToHost, h->stream));
+  MDP_HIP(hipEventRecord(h->ctl_event, h->stream));
+  return MDP_OK;
+}
+
+mdp_status ctl_wait(mdp_handle* h) {
+  MDP_HIP(hipEventSynchronize(h->ctl_event));
+  return MDP_OK;
+}
+
 mdp_status ensure_basis(mdp_handle* h, Prec prec, int m) {
   if (prec == kF64) {
     if (h->basis_m64 >= m) return MDP_OK;
@@ -320,6 +346,7 @@ double bytes_arnoldi_update(const mdp_handle* h, int bb, int j) {
 void prof_begin(mdp_handle* h, int kind, hipEvent_t* a) {
   *a = nullptr;
   if (!(h->prof_mask & (1 << kind))) return;
+  if (h->prof_seen[kind]++ % h->prof_every != 0) return;
   if (h->prof_pool.empty()) {
     hipEvent_t e;
     if (hipEventCreate(&e) != hipSuccess) return;
@@ -459,6 +486,7 @@ mdp_status mdp_destroy(mdp_t h) {
   dev_free(h->part.buf);
   dev_free(h->ctl);
   if (h->ctl_host) (void)hipHostFree(h->ctl_host);
+  if (h->ctl_event) (void)hipEventDestroy(h->ctl_event);
   prof_resolve(h);
   for (auto e : h->prof_pool) (void)hipEventDestroy(e);
   if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
@@ -588,6 +616,7 @@ mdp_status mdp_create(int64_t S, int32_t A, const int64_t* row_ptr, const int32_
   CHK(dev_alloc(h, &h->part.buf, h->part.cap));
   CHK(dev_alloc(h, &h->ctl, 1));
   CHK(hipHostMalloc(reinterpret_cast<void**>(&h->ctl_host), sizeof(Ctl), hipHostMallocDefault));
+  CHK(hipEventCreateWithFlags(&h->ctl_event, hipEventDisableTiming));
   std::memset(h->ctl_host, 0, sizeof(Ctl));
   CHK(hipMemsetAsync(h->ctl, 0, sizeof(Ctl), h->stream));
   if (o.low_precision & MDP_BUILD_FP32) {
@@ -955,9 +984,10 @@ mdp_status mdp_solve_batch(mdp_t* handles, int32_t n, const double* const* v0, d
   return worst;
 }
 
-mdp_status mdp_profile(mdp_t h, int32_t enable) {
+mdp_status mdp_profile_sampled(mdp_t h, int32_t enable, int32_t every) {
   clear_error();
   if (!h) return fail(MDP_E_INVAL, "NULL handle");
+  if (every < 1) return fail(MDP_E_INVAL, "every must be at least 1");
   BusyGuard g(h);
   if (!g.ok) return fail(MDP_E_STATE, "handle is busy");
   prof_resolve(h);
@@ -966,11 +996,15 @@ mdp_status mdp_profile(mdp_t h, int32_t enable) {
       h->prof_launches[k] = 0;
       h->prof_ms[k] = 0.0;
       h->prof_bytes[k] = 0.0;
+      h->prof_seen[k] = 0;
     }
   }
   h->prof_mask = enable < 0 ? (1 << MDP_NUM_KERNEL_KINDS) - 1 : enable;
+  h->prof_every = every;
   return MDP_OK;
 }
+
+mdp_status mdp_profile(mdp_t h, int32_t enable) { return mdp_profile_sampled(h, enable, 1); }
 
 mdp_status mdp_profile_read(mdp_t h, mdp_kernel_profile* out) {
   clear_error();

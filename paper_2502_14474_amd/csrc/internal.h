@@ -123,6 +123,7 @@ struct mdp_handle {
   mdp::Partials part{};
   mdp::Ctl* ctl = nullptr;        // device
   mdp::Ctl* ctl_host = nullptr;   // pinned host mirror of the header
+  hipEvent_t ctl_event = nullptr; // marks the header copy of a snapshot
 
   int64_t device_bytes = 0;
 
@@ -134,6 +135,8 @@ struct mdp_handle {
     double bytes;
   };
   int prof_mask = 0;  // bit k: record kernel class k
+  int prof_every = 1;                                // record one launch in prof_every per class
+  int64_t prof_seen[MDP_NUM_KERNEL_KINDS] = {};      // launches of each class since enabling
   std::vector<ProfRec> prof_pending;
   std::vector<hipEvent_t> prof_pool;
   int64_t prof_launches[MDP_NUM_KERNEL_KINDS] = {};
@@ -183,6 +186,9 @@ bool is_device_ptr(const void* p);
 mdp_status validate_host(int64_t S, int32_t A, const int64_t* rp, const int32_t* col,
                          const double* val, const double* cost);
 mdp_status sync_ctl(mdp_handle* h);
+// Enqueue a copy of the control header into the host mirror, and wait for it.
+mdp_status ctl_snapshot(mdp_handle* h);
+mdp_status ctl_wait(mdp_handle* h);
 mdp_status ensure_basis(mdp_handle* h, Prec prec, int m);
 mdp_status ensure_lowp(mdp_handle* h, Prec prec);
 Prec prec_of(int p);

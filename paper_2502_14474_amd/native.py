@@ -91,6 +91,7 @@ SIGNATURES = {
                            C.POINTER(C.c_int64), C.POINTER(C.c_int32), C.POINTER(C.c_int64)]),
     "mdp_autotune": (C.c_int, [C.c_void_p, C.POINTER(C.c_int32)]),
     "mdp_profile": (C.c_int, [C.c_void_p, C.c_int32]),
+    "mdp_profile_sampled": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32]),
     "mdp_profile_read": (C.c_int, [C.c_void_p, C.POINTER(KernelProfile)]),
     "mdp_default_server_opts": (None, [C.POINTER(ServerOpts)]),
     "mdp_server_create": (C.c_int, [C.POINTER(ServerOpts), C.POINTER(C.c_void_p)]),
