@@ -117,8 +117,19 @@ def serving_leg(args, m):
     log(f"[serve] pool of {len(pool)} requests, {sum(p.nnz for p in pool)/1e6:.0f}M nnz, "
         f"generated in {time.time()-t:.1f}s")
     n = args.serve_requests
+    pageable = pool
+    if not args.serve_pageable:
+        # the client holds its requests in page-locked host memory, so that the
+        # server's uploads go straight to the copy engines (no staging copy)
+        import torch
+        from workloads import MDPInstance
 
-    def run(gaps):
+        def pin(a):
+            return torch.from_numpy(a).pin_memory().numpy()
+        pool = [MDPInstance(p.S, p.A, pin(p.row_ptr), pin(p.col), pin(p.val), pin(p.cost), p.gamma,
+                            name=p.name, meta=p.meta) for p in pageable]
+
+    def run(gaps, pool=pool):
         with m.Server(precision=m.MDP_MIXED_FP32, alpha=args.alpha, atol=args.atol,
                       max_batch=args.serve_max_batch) as srv:
             ids = []
@@ -143,9 +154,14 @@ def serving_leg(args, m):
     rng_gaps = np.array([r["gap"] for r in config5_requests(n, seed=args.seed + 1)])
     open70 = run(rng_gaps / (0.7 * cap))
     log(f"[serve] closed {closed}; open@0.7C {open70}")
-    return {"requests": n, "pool": len(pool), "pool_nnz": int(sum(p.nnz for p in pool)),
-            "precision": "mixed fp32 + fp64 refinement", "closed_loop": closed,
-            "open_loop_0.7C": open70}
+    out = {"requests": n, "pool": len(pool), "pool_nnz": int(sum(p.nnz for p in pool)),
+           "precision": "mixed fp32 + fp64 refinement",
+           "client_memory": "pageable" if args.serve_pageable else "page-locked",
+           "closed_loop": closed, "open_loop_0.7C": open70}
+    if not args.serve_pageable:
+        out["closed_loop_pageable_client"] = run(None, pageable)
+        log(f"[serve] closed, pageable client arrays: {out['closed_loop_pageable_client']}")
+    return out
 
 
 def rows_leg(args, m, h, inst, v, pi):
@@ -233,6 +249,8 @@ def main():
     ap.add_argument("--serve-max-states", type=int, default=200_000)
     ap.add_argument("--serve-requests", type=int, default=96)
     ap.add_argument("--serve-max-batch", type=int, default=32)
+    ap.add_argument("--serve-pageable", action="store_true",
+                    help="keep the client's request arrays in pageable memory")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported (the "
