@@ -248,7 +248,7 @@ def main():
     ap.add_argument("--serve-pool", type=int, default=24)
     ap.add_argument("--serve-max-states", type=int, default=200_000)
     ap.add_argument("--serve-requests", type=int, default=96)
-    ap.add_argument("--serve-max-batch", type=int, default=32)
+    ap.add_argument("--serve-max-batch", type=int, default=64)
     ap.add_argument("--serve-pageable", action="store_true",
                     help="keep the client's request arrays in pageable memory")
     args = ap.parse_args()

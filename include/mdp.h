@@ -196,7 +196,8 @@ typedef struct {
   int64_t hbm_budget_bytes;  /* admission limit on resident device bytes (default 64 GiB) */
   int32_t device;            /* HIP device; -1: the current device */
   int32_t max_batch;         /* most MDPs resident at once (default 256) */
-  int32_t admit_threads;     /* threads copying new MDPs to the device (default 4) */
+  int32_t admit_threads;     /* threads copying new MDPs to the device (default 2: uploads
+                                from more threads contend for the copy engines) */
   int32_t retire_threads;    /* threads copying results out and freeing (default 2) */
   mdp_solve_opts solve;      /* GMRES only; default precision MDP_MIXED_FP32 */
 } mdp_server_opts;
