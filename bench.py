@@ -166,9 +166,10 @@ def serving_leg(args, m):
 
 def rows_leg(args, m, h, inst, v, pi):
     """Times the path's other steps on the solved MDP: the policy product on
-    its own (20 launches at the greedy policy of the solution), a solve with
-    Richardson inner iterations, and the per-kernel breakdown of one float64
-    GMRES solve.  Rates use the library's algorithmic byte counts."""
+    its own (20 launches at the greedy policy of the solution), solves with
+    Richardson and with BiCGSTAB inner iterations, and the per-kernel
+    breakdown of one float64 GMRES solve.  Rates use the library's
+    algorithmic byte counts."""
     import torch
 
     def summary(prof):
@@ -209,13 +210,29 @@ def rows_leg(args, m, h, inst, v, pi):
 
     w = torch.zeros_like(v)
     p2 = torch.zeros_like(pi)
+    m.mdp_solve(h, w, p2, inner=m.MDP_INNER_BICGSTAB, alpha=args.alpha, atol=args.atol)  # warm-up
+    w.zero_()
+    m.mdp_profile(h, True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st = m.mdp_solve(h, w, p2, inner=m.MDP_INNER_BICGSTAB, alpha=args.alpha, atol=args.atol)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    rows["bicgstab_solve"] = {"ms": 1e3 * (t1 - t0), "status": st["status"],
+                              "sweeps": st["bellman_sweeps"], "inner": st["inner_iters"],
+                              "residual": st["residual"], "kernels": summary(m.mdp_profile_read(h))}
+    m.mdp_profile(h, False)
+
+    w = torch.zeros_like(v)
+    p2 = torch.zeros_like(pi)
     m.mdp_profile(h, True)
     st = m.mdp_solve(h, w, p2, restart=args.restart, alpha=args.alpha, atol=args.atol)
     torch.cuda.synchronize()
     rows["gmres_solve_kernels"] = summary(m.mdp_profile_read(h))
     m.mdp_profile(h, False)
     log(f"[bench] rows: policy product {rows['policy_product']['avg_us']:.1f} us, "
-        f"richardson {rows.get('richardson_solve', {}).get('ms', float('nan')):.1f} ms")
+        f"richardson {rows.get('richardson_solve', {}).get('ms', float('nan')):.1f} ms, "
+        f"bicgstab {rows['bicgstab_solve']['ms']:.1f} ms ({rows['bicgstab_solve']['inner']} its)")
     return rows
 
 

@@ -62,8 +62,11 @@ enum {
   MDP_MIXED_FP16 = 2   /* as MIXED_FP32 but P held in float16 with a float64 per-row sum correction */
 };
 
-/* Inner solver of the approximate policy evaluation. */
-enum { MDP_INNER_GMRES = 0, MDP_INNER_RICHARDSON = 1 };
+/* Inner solver of the approximate policy evaluation (the paper leaves the
+ * choice of iterative solver for the linear system of policy evaluation open,
+ * section "Problem Setting and Solution Methods"): restarted GMRES, the
+ * Richardson / T_pi iteration, or BiCGSTAB (van der Vorst 1992). */
+enum { MDP_INNER_GMRES = 0, MDP_INNER_RICHARDSON = 1, MDP_INNER_BICGSTAB = 2 };
 
 /* Bits of mdp_create_opts.low_precision: which reduced-precision copies of P to build. */
 enum { MDP_BUILD_FP32 = 1, MDP_BUILD_FP16 = 2 };
@@ -87,12 +90,13 @@ typedef struct {
 
 typedef struct {
   size_t struct_size;     /* sizeof(mdp_eval_opts) */
-  int32_t inner;          /* MDP_INNER_GMRES or MDP_INNER_RICHARDSON */
+  int32_t inner;          /* MDP_INNER_GMRES, MDP_INNER_RICHARDSON or MDP_INNER_BICGSTAB
+                             (BiCGSTAB: float64 only, two products per iteration) */
   int32_t restart;        /* GMRES restart length m, 1..64 (default 30) */
   int32_t precision;      /* MDP_FP64, MDP_MIXED_FP32 or MDP_MIXED_FP16 */
   int32_t sync_every;     /* inner steps enqueued between host checks; 0: default */
-  double rtol;            /* stop when ||r|| <= rtol*||r0|| (GMRES: 2-norm of the residual;
-                             Richardson: max-norm of successive differences) */
+  double rtol;            /* stop when ||r|| <= rtol*||r0|| (GMRES, BiCGSTAB: 2-norm of the
+                             residual; Richardson: max-norm of successive differences) */
   int64_t max_iter;       /* cap on inner steps (default 10000) */
 } mdp_eval_opts;
 

@@ -204,6 +204,28 @@ mdp_status richardson_inner(mdp_handle* h, const int32_t* pi, double* buf0, doub
   return MDP_OK;
 }
 
+// BiCGSTAB from x (residual r0 in basis slot 0, its norm and the tolerance in
+// ctl); stops at ctl->tol, at a breakdown, or after max_iter iterations.
+mdp_status bicgstab_inner(mdp_handle* h, const int32_t* pi, double* x, int64_t max_iter,
+                          int sync_every, InnerResult* out) {
+  MDP_HIP(launch_bicgstab_init(h));
+  MDP_TRY(sync_ctl(h));
+  int64_t launched = 0;
+  while (!h->ctl_host->done && launched < max_iter) {
+    const int64_t n = std::min<int64_t>(sync_every, max_iter - launched);
+    for (int64_t i = 0; i < n; ++i) MDP_HIP(launch_bicgstab_step(h, pi, x));
+    launched += n;
+    MDP_TRY(sync_ctl(h));
+    if (!std::isfinite(h->ctl_host->res_est)) return fail(MDP_E_NUMERIC, "non-finite BiCGSTAB residual");
+  }
+  out->steps = h->ctl_host->steps;
+  out->applies += 2 * out->steps;
+  // two products, two dot passes (2 and 4 vectors), s (3), x/r (7 vectors), p (4)
+  out->bytes += out->steps * (2.0 * bytes_apply(h, 8, 8, 8) + 20.0 * h->S * 8.0);
+  out->converged = h->ctl_host->converged != 0;
+  return MDP_OK;
+}
+
 void stats_begin(mdp_stats* st) {
   if (!st) return;
   double* hist = st->history;
@@ -726,7 +748,10 @@ mdp_status mdp_policy_eval(mdp_t h, const int32_t* policy, const double* v0, dou
     if (opt->struct_size < sizeof(mdp_eval_opts)) return fail(MDP_E_INVAL, "mdp_eval_opts.struct_size too small");
     o = *opt;
   }
-  if (o.inner != MDP_INNER_GMRES && o.inner != MDP_INNER_RICHARDSON) return fail(MDP_E_INVAL, "unknown inner solver");
+  if (o.inner != MDP_INNER_GMRES && o.inner != MDP_INNER_RICHARDSON && o.inner != MDP_INNER_BICGSTAB)
+    return fail(MDP_E_INVAL, "unknown inner solver");
+  if (o.inner == MDP_INNER_BICGSTAB && o.precision != MDP_FP64)
+    return fail(MDP_E_NOTSUP, "BiCGSTAB runs in float64 only");
   if (o.restart < 1 || o.restart > kMaxRestart) return fail(MDP_E_INVAL, "restart must lie in [1,64]");
   if (o.precision < MDP_FP64 || o.precision > MDP_MIXED_FP16) return fail(MDP_E_INVAL, "unknown precision");
   if (o.inner == MDP_INNER_RICHARDSON && o.precision != MDP_FP64)
@@ -742,7 +767,13 @@ mdp_status mdp_policy_eval(mdp_t h, const int32_t* policy, const double* v0, dou
   InnerResult ir;
   double* result = h->v;
   double rel = 0.0;
-  if (o.inner == MDP_INNER_GMRES) {
+  if (o.inner == MDP_INNER_BICGSTAB) {
+    MDP_TRY(ensure_basis(h, kF64, std::max(o.restart, 5)));
+    MDP_HIP(launch_apply(h, kApplyRes, h->pi, h->v, h->U64, false, kRedGmresStart, 1, o.rtol, 0.0));
+    ir.applies += 1;
+    MDP_TRY(bicgstab_inner(h, h->pi, h->v, o.max_iter, sync_every, &ir));
+    rel = h->ctl_host->beta0 > 0 ? h->ctl_host->res_est / h->ctl_host->beta0 : 0.0;
+  } else if (o.inner == MDP_INNER_GMRES) {
     const Prec prec = prec_of(o.precision);
     MDP_TRY(ensure_basis(h, prec == kF64 ? kF64 : kF32, o.restart));
     if (prec != kF64) MDP_TRY(ensure_lowp(h, prec));
@@ -790,7 +821,10 @@ mdp_status mdp_solve(mdp_t h, const double* v0, double* v, int32_t* policy,
     if (opt->struct_size < sizeof(mdp_solve_opts)) return fail(MDP_E_INVAL, "mdp_solve_opts.struct_size too small");
     o = *opt;
   }
-  if (o.inner != MDP_INNER_GMRES && o.inner != MDP_INNER_RICHARDSON) return fail(MDP_E_INVAL, "unknown inner solver");
+  if (o.inner != MDP_INNER_GMRES && o.inner != MDP_INNER_RICHARDSON && o.inner != MDP_INNER_BICGSTAB)
+    return fail(MDP_E_INVAL, "unknown inner solver");
+  if (o.inner == MDP_INNER_BICGSTAB && o.precision != MDP_FP64)
+    return fail(MDP_E_NOTSUP, "BiCGSTAB runs in float64 only");
   if (o.restart < 1 || o.restart > kMaxRestart) return fail(MDP_E_INVAL, "restart must lie in [1,64]");
   if (o.precision < MDP_FP64 || o.precision > MDP_MIXED_FP16) return fail(MDP_E_INVAL, "unknown precision");
   if (o.inner == MDP_INNER_RICHARDSON && o.precision != MDP_FP64)
@@ -803,7 +837,9 @@ mdp_status mdp_solve(mdp_t h, const double* v0, double* v, int32_t* policy,
   const int sync_every = o.sync_every > 0 ? o.sync_every : 4;
   const Prec iprec = prec_of(o.precision);
   const bool gm = o.inner == MDP_INNER_GMRES;
+  const bool bi = o.inner == MDP_INNER_BICGSTAB;
   if (gm) MDP_TRY(ensure_basis(h, iprec == kF64 ? kF64 : kF32, o.restart));
+  if (bi) MDP_TRY(ensure_basis(h, kF64, std::max(o.restart, 5)));
   if (iprec != kF64) MDP_TRY(ensure_lowp(h, iprec));
   MDP_TRY(load_vec(h, v0, h->v));
   MDP_HIP(launch_ctl_reset(h, 0.0));
@@ -826,12 +862,14 @@ mdp_status mdp_solve(mdp_t h, const double* v0, double* v, int32_t* policy,
       vin = h->v32;
     }
     const bool r0f32 = iprec != kF64;
-    void* r0 = gm ? (iprec == kF64 ? static_cast<void*>(h->U64) : static_cast<void*>(h->U32)) : nullptr;
-    double* tv_out = gm ? nullptr : h->x2;
-    MDP_HIP(launch_bellman(h, sp, vin, tv_out, h->pi, r0, r0f32, gm ? kRedGmresStart : kRedPlain, 1,
+    // GMRES and BiCGSTAB start from r0 = T v - v, which the sweep writes into basis slot 0
+    const bool keep_r0 = gm || bi;
+    void* r0 = keep_r0 ? (iprec == kF64 ? static_cast<void*>(h->U64) : static_cast<void*>(h->U32)) : nullptr;
+    double* tv_out = keep_r0 ? nullptr : h->x2;
+    MDP_HIP(launch_bellman(h, sp, vin, tv_out, h->pi, r0, r0f32, keep_r0 ? kRedGmresStart : kRedPlain, 1,
                            alpha, floor_of(iprec)));
     ++sweeps;
-    bytes += bytes_sweep(h, bval_of(sp), sp == kF64 ? 8 : 4, gm, r0f32 ? 4 : 8);
+    bytes += bytes_sweep(h, bval_of(sp), sp == kF64 ? 8 : 4, keep_r0, r0f32 ? 4 : 8);
     MDP_TRY(sync_ctl(h));
     res = h->ctl_host->res_max;
     tv_max = h->ctl_host->aux_max;
@@ -862,6 +900,8 @@ mdp_status mdp_solve(mdp_t h, const double* v0, double* v, int32_t* policy,
     InnerResult ir;
     if (gm) {
       MDP_TRY(gmres_inner(h, iprec, h->pi, h->v, o.restart, o.max_inner, sync_every, alpha, &ir));
+    } else if (bi) {
+      MDP_TRY(bicgstab_inner(h, h->pi, h->v, o.max_inner, sync_every, &ir));
     } else {
       // x1 = T v_k is already in x2; continue T_pi from there
       double* last = h->x2;
