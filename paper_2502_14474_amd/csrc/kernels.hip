@@ -433,234 +433,3 @@ hipError_t launch_i64_to_i32(hipStream_t st, const int64_t* src, int32_t* dst, i
 }
 
 }  // namespace mdp
-
-// ----------------------------------------------------------------------------
-// BiCGSTAB (van der Vorst, 1992) on A x = g_pi with A = I - gamma P_pi, in
-// float64.  Every kernel exits at once when ctl->done is set, so steps
-// enqueued past convergence cost only their launches.  Scalars live in ctl;
-// each reduction is per-workgroup partials (kUpdTile entries each) summed in
-// a fixed order by one workgroup, so the iteration is deterministic.
-// ----------------------------------------------------------------------------
-namespace mdp {
-
-namespace {
-
-constexpr int kBiPer = kUpdTile / kBlock;
-
-__global__ __launch_bounds__(kBlock) void k_bi_init(int64_t S, double* __restrict__ U, int64_t ldu,
-                                                    Ctl* __restrict__ ctl) {
-  if (ctl->done) return;
-  const double* r = U;
-  double* rh = U + ldu;
-  double* p = U + 2 * ldu;
-  for (int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; i < S;
-       i += static_cast<int64_t>(gridDim.x) * kBlock) {
-    rh[i] = r[i];
-    p[i] = r[i];
-  }
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    ctl->bi_rho = ctl->sumsq;  // (r^, r0) = ||r0||^2
-    ctl->bi_alpha = 1.0;
-    ctl->bi_omega = 1.0;
-    ctl->bi_beta = 0.0;
-  }
-}
-
-// partials[blk] = sum over the workgroup's entries of a*b (and of c*d in .y)
-template <bool TWO>
-__global__ __launch_bounds__(kBlock) void k_bi_dot(int64_t S, const double* __restrict__ a,
-                                                   const double* __restrict__ b,
-                                                   const double* __restrict__ c,
-                                                   const double* __restrict__ d,
-                                                   double2* __restrict__ partials,
-                                                   const Ctl* __restrict__ ctl) {
-  if (ctl->done) return;
-  const int64_t base = static_cast<int64_t>(blockIdx.x) * kUpdTile + threadIdx.x;
-  double s1 = 0.0, s2 = 0.0;
-#pragma unroll
-  for (int k = 0; k < kBiPer; ++k) {
-    const int64_t i = base + k * kBlock;
-    if (i < S) {
-      s1 = fma(a[i], b[i], s1);
-      if (TWO) s2 = fma(c[i], d[i], s2);
-    }
-  }
-  double m1 = 0.0, m2 = 0.0;
-  block_max_sum(m1, s1);
-  if (TWO) block_max_sum(m2, s2);
-  if (threadIdx.x == 0) partials[blockIdx.x] = make_double2(s1, s2);
-}
-
-__device__ __forceinline__ double2 sum_partials2(const double2* __restrict__ partials, int nb) {
-  double s1 = 0.0, s2 = 0.0;
-  for (int b = threadIdx.x; b < nb; b += kBlock) {
-    s1 += partials[b].x;
-    s2 += partials[b].y;
-  }
-  double m1 = 0.0, m2 = 0.0;
-  block_max_sum(m1, s1);
-  block_max_sum(m2, s2);
-  return make_double2(s1, s2);  // valid in thread 0
-}
-
-// alpha = rho / (r^, v); a zero or non-finite quotient ends the solve
-__global__ __launch_bounds__(kBlock) void k_bi_alpha(const double2* __restrict__ partials, int nb,
-                                                     Ctl* __restrict__ ctl) {
-  if (ctl->done) return;
-  const double2 s = sum_partials2(partials, nb);
-  if (threadIdx.x != 0) return;
-  const double a = ctl->bi_rho / s.x;
-  if (!(s.x != 0.0) || !std::isfinite(a)) {
-    ctl->breakdown = 1;
-    ctl->done = 1;
-    return;
-  }
-  ctl->bi_alpha = a;
-}
-
-// s = r - alpha v
-__global__ __launch_bounds__(kBlock) void k_bi_s(int64_t S, const double* __restrict__ r,
-                                                 const double* __restrict__ v, double* __restrict__ s,
-                                                 const Ctl* __restrict__ ctl) {
-  if (ctl->done) return;
-  const double a = ctl->bi_alpha;
-  const int64_t base = static_cast<int64_t>(blockIdx.x) * kUpdTile + threadIdx.x;
-#pragma unroll
-  for (int k = 0; k < kBiPer; ++k) {
-    const int64_t i = base + k * kBlock;
-    if (i < S) s[i] = fma(-a, v[i], r[i]);
-  }
-}
-
-// omega = (t, s) / (t, t); t = 0 (s = 0) gives omega = 0
-__global__ __launch_bounds__(kBlock) void k_bi_omega(const double2* __restrict__ partials, int nb,
-                                                     Ctl* __restrict__ ctl) {
-  if (ctl->done) return;
-  const double2 s = sum_partials2(partials, nb);
-  if (threadIdx.x != 0) return;
-  ctl->bi_omega = s.y > 0.0 ? s.x / s.y : 0.0;
-}
-
-// x += alpha p + omega s;  r = s - omega t;  partials ((r^, r), (r, r))
-__global__ __launch_bounds__(kBlock) void k_bi_xr(int64_t S, double* __restrict__ x,
-                                                  const double* __restrict__ p,
-                                                  const double* __restrict__ s,
-                                                  const double* __restrict__ t,
-                                                  double* __restrict__ r,
-                                                  const double* __restrict__ rh,
-                                                  double2* __restrict__ partials,
-                                                  const Ctl* __restrict__ ctl) {
-  if (ctl->done) return;
-  const double a = ctl->bi_alpha, w = ctl->bi_omega;
-  const int64_t base = static_cast<int64_t>(blockIdx.x) * kUpdTile + threadIdx.x;
-  double s1 = 0.0, s2 = 0.0;
-#pragma unroll
-  for (int k = 0; k < kBiPer; ++k) {
-    const int64_t i = base + k * kBlock;
-    if (i < S) {
-      x[i] = fma(w, s[i], fma(a, p[i], x[i]));
-      const double ri = fma(-w, t[i], s[i]);
-      r[i] = ri;
-      s1 = fma(rh[i], ri, s1);
-      s2 = fma(ri, ri, s2);
-    }
-  }
-  double m1 = 0.0, m2 = 0.0;
-  block_max_sum(m1, s1);
-  block_max_sum(m2, s2);
-  if (threadIdx.x == 0) partials[blockIdx.x] = make_double2(s1, s2);
-}
-
-// rho' = (r^, r), ||r||; stop test; beta = (rho'/rho)(alpha/omega)
-__global__ __launch_bounds__(kBlock) void k_bi_rho(const double2* __restrict__ partials, int nb,
-                                                   Ctl* __restrict__ ctl) {
-  if (ctl->done) return;
-  const double2 s = sum_partials2(partials, nb);
-  if (threadIdx.x != 0) return;
-  const double res = sqrt(s.y);
-  ctl->res_est = res;
-  ctl->steps += 1;
-  if (!std::isfinite(res)) {
-    ctl->done = 1;
-    return;
-  }
-  if (res <= ctl->tol) {
-    ctl->converged = 1;
-    ctl->done = 1;
-    return;
-  }
-  const double beta = (s.x / ctl->bi_rho) * (ctl->bi_alpha / ctl->bi_omega);
-  if (!(ctl->bi_omega != 0.0) || !(s.x != 0.0) || !std::isfinite(beta)) {
-    ctl->breakdown = 1;
-    ctl->done = 1;
-    return;
-  }
-  ctl->bi_rho = s.x;
-  ctl->bi_beta = beta;
-}
-
-// p = r + beta (p - omega v)
-__global__ __launch_bounds__(kBlock) void k_bi_p(int64_t S, double* __restrict__ p,
-                                                 const double* __restrict__ r,
-                                                 const double* __restrict__ v,
-                                                 const Ctl* __restrict__ ctl) {
-  if (ctl->done) return;
-  const double b = ctl->bi_beta, w = ctl->bi_omega;
-  const int64_t base = static_cast<int64_t>(blockIdx.x) * kUpdTile + threadIdx.x;
-#pragma unroll
-  for (int k = 0; k < kBiPer; ++k) {
-    const int64_t i = base + k * kBlock;
-    if (i < S) p[i] = fma(b, fma(-w, v[i], p[i]), r[i]);
-  }
-}
-
-}  // namespace
-
-hipError_t launch_bicgstab_init(mdp_handle* h) {
-  k_bi_init<<<grid_stride(h->S), kBlock, 0, h->stream>>>(h->S, h->U64, h->ldu, h->ctl);
-  return hipGetLastError();
-}
-
-hipError_t launch_bicgstab_step(mdp_handle* h, const int32_t* pi, double* x) {
-  const int64_t S = h->S, ld = h->ldu;
-  double* r = h->U64;
-  double* rh = h->U64 + ld;
-  double* p = h->U64 + 2 * ld;
-  double* v = h->U64 + 3 * ld;
-  double* s = h->U64 + 4 * ld;
-  double* t = h->U64 + 5 * ld;
-  auto* part = reinterpret_cast<double2*>(h->part.buf);
-  const int nbu = grid_for(S, kUpdTile);
-  const int nba = grid_for(S, kApplyTile);
-  auto product = [&](const double* in, double* out) -> hipError_t {
-    Prof pf(h, MDP_K_POLICY_APPLY, bytes_apply(h, 8, 8, 8));
-    return with_lanes(h->lanes, [&](auto Lc) -> hipError_t {
-      constexpr int L = decltype(Lc)::value;
-      constexpr int U = rows_in_flight<L>();
-      k_policy_apply<L, U, kApplyOp, double, double, double, false><<<nba, kBlock, 0, h->stream>>>(
-          S, h->A, h->row_ptr, h->kfix, h->col, h->val, nullptr, h->cost, pi, in, h->gamma, out,
-          nullptr, h->ctl, nullptr, nullptr, nullptr);
-      return hipGetLastError();
-    });
-  };
-  hipError_t e;
-  if ((e = product(p, v)) != hipSuccess) return e;
-  {
-    Prof pf(h, MDP_K_REDUCE, 0.0);
-    k_bi_dot<false><<<nbu, kBlock, 0, h->stream>>>(S, rh, v, nullptr, nullptr, part, h->ctl);
-    k_bi_alpha<<<1, kBlock, 0, h->stream>>>(part, nbu, h->ctl);
-    k_bi_s<<<nbu, kBlock, 0, h->stream>>>(S, r, v, s, h->ctl);
-  }
-  if ((e = product(s, t)) != hipSuccess) return e;
-  {
-    Prof pf(h, MDP_K_REDUCE, 0.0);
-    k_bi_dot<true><<<nbu, kBlock, 0, h->stream>>>(S, t, s, t, t, part, h->ctl);
-    k_bi_omega<<<1, kBlock, 0, h->stream>>>(part, nbu, h->ctl);
-    k_bi_xr<<<nbu, kBlock, 0, h->stream>>>(S, x, p, s, t, r, rh, part, h->ctl);
-    k_bi_rho<<<1, kBlock, 0, h->stream>>>(part, nbu, h->ctl);
-    k_bi_p<<<nbu, kBlock, 0, h->stream>>>(S, p, r, v, h->ctl);
-  }
-  return hipGetLastError();
-}
-
-}  // namespace mdp
