@@ -62,6 +62,9 @@ enum {
   MDP_MIXED_FP16 = 2   /* as MIXED_FP32 but P held in float16 with a float64 per-row sum correction */
 };
 
+/* Objective of mdp_create_opts.objective. */
+enum { MDP_MINIMIZE_COST = 0, MDP_MAXIMIZE_REWARD = 1 };
+
 /* Inner solver of the approximate policy evaluation (the paper leaves the
  * choice of iterative solver for the linear system of policy evaluation open,
  * section "Problem Setting and Solution Methods"): restarted GMRES, the
@@ -86,6 +89,12 @@ typedef struct {
                              not in increasing slice order, or A > 1024).  The blocked
                              sweep takes a row's sum slice by slice, so its rounding
                              differs from the plain sweep's within the usual bound. */
+  int32_t objective;      /* MDP_MINIMIZE_COST (default): minimise expected discounted cost, as
+                             in the paper's problem statement; MDP_MAXIMIZE_REWARD: `cost`
+                             holds rewards and every value vector passed in or out (v0, v,
+                             Tv, x, y) is in reward terms.  Internally the rewards are stored
+                             negated, so the two give bitwise the same arithmetic.  Batched
+                             solves accept such handles; the server does not build them. */
 } mdp_create_opts;
 
 typedef struct {

@@ -198,18 +198,20 @@ def evaluate_policy_fixed_point(inst, pi, P=None, tol=1e-14, max_iter=1_000_000)
     raise RuntimeError("fixed-point evaluation did not converge")
 
 
-def brute_force(inst):
-    """v* as the elementwise minimum of v_pi over all A**S deterministic
-    policies (each evaluated by fixed-point iteration), and the set of optimal
-    actions per state.  For S*log(A) small only."""
+def brute_force(inst, maximize=False):
+    """v* as the elementwise minimum (maximize=True: maximum, with inst.cost
+    read as rewards) of v_pi over all A**S deterministic policies (each
+    evaluated by fixed-point iteration), and every (policy, v_pi) pair.
+    For S*log(A) small only."""
     P = to_csr(inst)
     best = None
     vals = []
+    pick = np.maximum if maximize else np.minimum
     for pol in itertools.product(range(inst.A), repeat=inst.S):
         pi = np.asarray(pol, np.int32)
         v = evaluate_policy_fixed_point(inst, pi, P)
         vals.append((pi, v))
-        best = v.copy() if best is None else np.minimum(best, v)
+        best = v.copy() if best is None else pick(best, v)
     return best, vals
 
 

@@ -10,7 +10,8 @@ import numpy as np
 
 from . import native
 from .native import (MDP_FP64, MDP_MIXED_FP32, MDP_MIXED_FP16, MDP_INNER_GMRES,  # noqa: F401
-                     MDP_INNER_RICHARDSON, MDP_INNER_BICGSTAB, MDP_BUILD_FP32, MDP_BUILD_FP16, MDP_OK,
+                     MDP_INNER_RICHARDSON, MDP_INNER_BICGSTAB, MDP_MINIMIZE_COST, MDP_MAXIMIZE_REWARD,
+                     MDP_BUILD_FP32, MDP_BUILD_FP16, MDP_OK,
                      MDP_W_MAXITER, MDPError)
 
 __all__ = ["mdp_create", "mdp_bellman", "mdp_policy_apply", "mdp_policy_eval", "mdp_solve",
@@ -45,11 +46,15 @@ def mdp_last_error():
 
 
 def mdp_create(S, A, row_ptr, col, val, cost, gamma, stream=None, device=-1, validate=True,
-               low_precision=0, lanes_per_row=0, col_blocks=-1):
+               low_precision=0, lanes_per_row=0, col_blocks=-1, objective=0):
+    """objective: native.MDP_MINIMIZE_COST (cost holds costs) or
+    native.MDP_MAXIMIZE_REWARD (cost holds rewards; values come back in
+    reward terms)."""
     lib = native.load()
     o = native.CreateOpts()
     lib.mdp_default_create_opts(C.byref(o))
     o.col_blocks = col_blocks
+    o.objective = objective
     o.stream = stream
     o.device = device
     o.validate = 1 if validate else 0

@@ -69,16 +69,25 @@ mdp_status load_policy(mdp_handle* h, const int32_t* policy, int32_t* dst) {
 }
 
 mdp_status load_vec(mdp_handle* h, const double* src, double* dst) {
-  if (src)
+  if (src) {
     MDP_HIP(hipMemcpyAsync(dst, src, h->S * sizeof(double), hipMemcpyDefault, h->stream));
-  else
+    if (h->maximize) MDP_HIP(launch_negate(h->stream, dst, h->S));
+  } else {
     MDP_HIP(hipMemsetAsync(dst, 0, h->S * sizeof(double), h->stream));
+  }
   return MDP_OK;
 }
 
 mdp_status store(mdp_handle* h, void* dst, const void* src, size_t bytes) {
   if (dst && dst != src) MDP_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyDefault, h->stream));
   return MDP_OK;
+}
+
+// Copy a value vector out; src is device scratch of the handle and is turned
+// into reward terms in place first when the handle maximises.
+mdp_status store_values(mdp_handle* h, double* dst, double* src) {
+  if (h->maximize) MDP_HIP(launch_negate(h->stream, src, h->S));
+  return store(h, dst, src, h->S * sizeof(double));
 }
 
 int default_lanes(double mean_row) {
@@ -539,6 +548,8 @@ mdp_status mdp_create(int64_t S, int32_t A, const int64_t* row_ptr, const int32_
     return fail(MDP_E_INVAL, "lanes_per_row must be 0 or a power of two in [2,64]");
   if (o.low_precision & ~(MDP_BUILD_FP32 | MDP_BUILD_FP16))
     return fail(MDP_E_INVAL, "unknown low_precision bits");
+  if (o.objective != MDP_MINIMIZE_COST && o.objective != MDP_MAXIMIZE_REWARD)
+    return fail(MDP_E_INVAL, "unknown objective");
   if (o.col_blocks < -1 || o.col_blocks > kMaxColBlocks)
     return fail(MDP_E_INVAL, "col_blocks must be -1, 0 or 1.." + std::to_string(kMaxColBlocks));
   const int64_t rows = S * A;
@@ -628,6 +639,8 @@ mdp_status mdp_create(int64_t S, int32_t A, const int64_t* row_ptr, const int32_
   CHK(hipMemcpyAsync(h->col, col, nnz * sizeof(int32_t), hipMemcpyDefault, h->stream));
   CHK(hipMemcpyAsync(h->val, val, nnz * sizeof(double), hipMemcpyDefault, h->stream));
   CHK(hipMemcpyAsync(h->cost, cost, rows * sizeof(double), hipMemcpyDefault, h->stream));
+  h->maximize = o.objective == MDP_MAXIMIZE_REWARD;
+  if (h->maximize) CHK(launch_negate(h->stream, h->cost, rows));  // rewards -> costs
   CHK(dev_alloc(h, &h->v, S));
   CHK(dev_alloc(h, &h->Tv, S));
   CHK(dev_alloc(h, &h->x2, S));
@@ -696,14 +709,17 @@ mdp_status mdp_bellman(mdp_t h, const double* v, double* Tv, int32_t* policy, do
   if (!g.ok) return fail(MDP_E_STATE, "handle is busy");
   const size_t vb = h->S * sizeof(double), pb = h->S * sizeof(int32_t);
   const double* vin = v;
-  if (!is_device_ptr(v) || v == Tv) {
-    MDP_HIP(hipMemcpyAsync(h->io, v, vb, hipMemcpyDefault, h->stream));
+  if (!is_device_ptr(v) || v == Tv || h->maximize) {
+    MDP_TRY(load_vec(h, v, h->io));  // negated into cost terms when the handle maximises
     vin = h->io;
   }
   double* tv_dev = (Tv && is_device_ptr(Tv)) ? Tv : h->Tv;
   int32_t* pi_dev = (policy && is_device_ptr(policy)) ? policy : h->pi;
   MDP_HIP(launch_bellman(h, kF64, vin, tv_dev, pi_dev, nullptr, false, kRedPlain, 0, 0.0, 0.0));
-  if (Tv) MDP_TRY(store(h, Tv, tv_dev, vb));
+  if (Tv) {
+    if (h->maximize) MDP_HIP(launch_negate(h->stream, tv_dev, h->S));
+    MDP_TRY(store(h, Tv, tv_dev, vb));
+  }
   if (policy) MDP_TRY(store(h, policy, pi_dev, pb));
   MDP_TRY(sync_ctl(h));
   const double res = h->ctl_host->res_max;
@@ -723,13 +739,14 @@ mdp_status mdp_policy_apply(mdp_t h, const int32_t* policy, const double* x, dou
   MDP_TRY(load_policy(h, policy, h->pi_io));
   const size_t vb = h->S * sizeof(double);
   const double* xin = x;
-  if (!is_device_ptr(x) || x == y) {
-    MDP_HIP(hipMemcpyAsync(h->io, x, vb, hipMemcpyDefault, h->stream));
+  if (!is_device_ptr(x) || x == y || h->maximize) {
+    MDP_TRY(load_vec(h, x, h->io));
     xin = h->io;
   }
   double* ydev = is_device_ptr(y) ? y : h->Tv;
   MDP_HIP(launch_apply(h, mode == 0 ? kApplyOp : kApplyT, h->pi_io, xin, ydev, false, kRedNone, 0,
                        0.0, 0.0));
+  if (h->maximize) MDP_HIP(launch_negate(h->stream, ydev, h->S));
   MDP_TRY(store(h, y, ydev, vb));
   MDP_HIP(hipStreamSynchronize(h->stream));
   return MDP_OK;
@@ -795,7 +812,7 @@ mdp_status mdp_policy_eval(mdp_t h, const int32_t* policy, const double* v0, dou
     }
     rel = ir.converged ? 0.0 : 1.0;
   }
-  MDP_TRY(store(h, v, result, h->S * sizeof(double)));
+  MDP_TRY(store_values(h, v, result));
   MDP_HIP(hipStreamSynchronize(h->stream));
   if (stats) {
     stats->inner_iters = ir.steps;
@@ -920,7 +937,7 @@ mdp_status mdp_solve(mdp_t h, const double* v0, double* v, int32_t* policy,
     bytes += ir.bytes;
     ++k;
   }
-  MDP_TRY(store(h, v, h->v, h->S * sizeof(double)));
+  MDP_TRY(store_values(h, v, h->v));
   MDP_TRY(store(h, policy, h->pi, h->S * sizeof(int32_t)));
   MDP_HIP(hipStreamSynchronize(h->stream));
   if (stats) {
@@ -996,6 +1013,7 @@ mdp_status mdp_solve_batch(mdp_t* handles, int32_t n, const double* const* v0, d
   for (int i = 0; i < n; ++i) {
     BatchItem& it = items[i];
     mdp_handle* h = it.h;
+    if (h->maximize) MDP_HIP(launch_negate(eng.stream, h->v, h->S));
     MDP_HIP(hipMemcpyAsync(v[i], h->v, h->S * sizeof(double), hipMemcpyDefault, eng.stream));
     MDP_HIP(hipMemcpyAsync(policy[i], h->pi, h->S * sizeof(int32_t), hipMemcpyDefault, eng.stream));
     if (it.status < 0 && worst >= 0) {

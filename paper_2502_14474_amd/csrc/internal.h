@@ -80,6 +80,7 @@ struct mdp_handle {
   double gamma = 0;
   int32_t lanes = 16;
   int32_t kfix = 0;  // every row holds kfix entries (0: rows differ)
+  bool maximize = false;  // costs hold rewards: stored negated, value vectors negated at the ABI
 
   // CSR on the device (int32 row offsets: nnz < 2^31)
   int32_t* row_ptr = nullptr;
@@ -224,6 +225,9 @@ void prof_discard_steps(mdp_handle* h, size_t from, int min_tag);
 // Column-blocked float64 sweep (colblock.hip): build the blocked copy with
 // `blocks` slices (returns false in *built when the rows do not allow it) and
 // run a sweep over it with the arguments of launch_bellman.
+// x <- -x on the stream (vecops.hip).
+hipError_t launch_negate(hipStream_t st, double* x, int64_t n);
+
 hipError_t build_colblocks(mdp_handle* h, int blocks, bool require, bool* built, double* far_frac);
 hipError_t launch_bellman_cb(mdp_handle* h, const double* v, double* Tv, int32_t* pi, void* r0,
                              bool r0_f32, double4* part, int nb);

@@ -16,12 +16,13 @@ STATUS_NAMES = {0: "MDP_OK", 1: "MDP_W_MAXITER", -1: "MDP_E_INVAL", -2: "MDP_E_N
 MDP_FP64, MDP_MIXED_FP32, MDP_MIXED_FP16 = 0, 1, 2
 MDP_INNER_GMRES, MDP_INNER_RICHARDSON, MDP_INNER_BICGSTAB = 0, 1, 2
 MDP_BUILD_FP32, MDP_BUILD_FP16 = 1, 2
+MDP_MINIMIZE_COST, MDP_MAXIMIZE_REWARD = 0, 1
 
 
 class CreateOpts(C.Structure):
     _fields_ = [("struct_size", C.c_size_t), ("stream", C.c_void_p), ("device", C.c_int32),
                 ("validate", C.c_int32), ("low_precision", C.c_int32),
-                ("lanes_per_row", C.c_int32), ("col_blocks", C.c_int32)]
+                ("lanes_per_row", C.c_int32), ("col_blocks", C.c_int32), ("objective", C.c_int32)]
 
 
 class EvalOpts(C.Structure):

@@ -355,3 +355,38 @@ def test_colblocks_option_rules():
     with pytest.raises(m.MDPError) as ei:
         m.MDP.from_instance(dense, col_blocks=1)
     assert ei.value.status == m.native.MDP_E_NOTSUP
+
+
+def test_maximize_reward_matches_brute_force():
+    """Reward maximisation against the oracle's enumeration of all policies."""
+    import paper_2502_14474_amd as m
+    inst = random_dense_mdp(5, 3, 0.9, seed=7, density=0.6)
+    best, vals = oracle.brute_force(inst, maximize=True)
+    with _mdp(inst, objective=m.MDP_MAXIMIZE_REWARD) as h:
+        v, pi, st = h.solve(rtol_cert=1e-12, atol=1e-12)
+    assert st["status"] == 0, st
+    np.testing.assert_allclose(v, best, rtol=1e-10, atol=1e-10)
+    v_pi = dict((tuple(p.tolist()), vv) for p, vv in vals)[tuple(pi.tolist())]
+    np.testing.assert_allclose(v_pi, best, rtol=1e-10, atol=1e-10)
+
+
+def test_maximize_is_negated_minimize_bitwise():
+    """Rewards r maximised and costs -r minimised run the same arithmetic: every
+    value vector agrees bit for bit up to its sign, policies exactly."""
+    import paper_2502_14474_amd as m
+    inst = config2(S=20000, A=8, seed=1)
+    neg = MDPInstance(inst.S, inst.A, inst.row_ptr, inst.col, inst.val, -inst.cost, inst.gamma)
+    x = np.random.default_rng(3).standard_normal(inst.S)
+    pol = np.random.default_rng(4).integers(0, inst.A, inst.S).astype(np.int32)
+    with _mdp(neg, objective=m.MDP_MAXIMIZE_REWARD) as hmax, _mdp(inst) as hmin:
+        vmax, pmax, _ = hmax.solve(alpha=1e-2)
+        vmin, pmin, _ = hmin.solve(alpha=1e-2)
+        assert np.array_equal(vmax, -vmin) and np.array_equal(pmax, pmin)
+        Tmax, qmax, rmax = hmax.bellman(-x)
+        Tmin, qmin, rmin = hmin.bellman(x)
+        assert np.array_equal(Tmax, -Tmin) and np.array_equal(qmax, qmin) and rmax == rmin
+        for mode in (0, 1):
+            assert np.array_equal(hmax.policy_apply(pol, -x, mode), -hmin.policy_apply(pol, x, mode))
+        emax, _ = hmax.policy_eval(pol, rtol=1e-10)
+        emin, _ = hmin.policy_eval(pol, rtol=1e-10)
+        assert np.array_equal(emax, -emin)

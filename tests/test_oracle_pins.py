@@ -85,6 +85,20 @@ def test_brute_force_enumeration(S, A, seed):
     np.testing.assert_allclose(v_pi, best, rtol=1e-12, atol=1e-12)
 
 
+@pytest.mark.parametrize("S,A,seed", [(3, 3, 1), (4, 3, 2)])
+def test_brute_force_maximize(S, A, seed):
+    """Maximising rewards r gives v* = -(v* minimising costs -r), and a single
+    state reaches max_a r(a) / (1 - gamma)."""
+    inst = random_dense_mdp(S, A, gamma=0.9, seed=seed, density=0.6)
+    best_max, _ = oracle.brute_force(inst, maximize=True)
+    neg = MDPInstance(inst.S, inst.A, inst.row_ptr, inst.col, inst.val, -inst.cost, inst.gamma)
+    best_min, _ = oracle.brute_force(neg)
+    np.testing.assert_allclose(best_max, -best_min, rtol=1e-12, atol=1e-12)
+    one = random_dense_mdp(1, 4, gamma=0.8, seed=3)
+    v1, _ = oracle.brute_force(one, maximize=True)
+    np.testing.assert_allclose(v1, [one.cost.max() / (1 - 0.8)], rtol=1e-12)
+
+
 # ---------------------------------------------------------------- invariants
 
 def test_policy_iteration_trajectory_config1():
