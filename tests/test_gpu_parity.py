@@ -390,3 +390,42 @@ def test_maximize_is_negated_minimize_bitwise():
         emax, _ = hmax.policy_eval(pol, rtol=1e-10)
         emin, _ = hmin.policy_eval(pol, rtol=1e-10)
         assert np.array_equal(emax, -emin)
+
+
+def test_bicgstab_edge_cases():
+    """BiCGSTAB on the degenerate systems: one state (A x = g with A = 1 - gamma
+    p_ss), gamma = 0 (A = I), and a warm start close to the solution."""
+    import paper_2502_14474_amd as m
+    one = MDPInstance(1, 2, np.array([0, 1, 2]), np.array([0, 0], np.int32), np.array([1.0, 1.0]),
+                      np.array([0.7, 0.3]), 0.9)
+    with _mdp(one) as h:
+        v, pi, st = h.solve(inner=m.MDP_INNER_BICGSTAB, atol=1e-12)
+    assert st["status"] == 0 and pi[0] == 1
+    assert abs(v[0] - 0.3 / (1 - 0.9)) <= 4 * EPS * 3.0
+    inst = random_dense_mdp(40, 3, 0.0, seed=2, density=0.3)
+    with _mdp(inst) as h:
+        v, pi, st = h.solve(inner=m.MDP_INNER_BICGSTAB)
+    assert st["status"] == 0
+    np.testing.assert_array_equal(v, inst.cost.reshape(inst.S, inst.A).min(axis=1))
+    inst = config1(S=300, seed=3)
+    pol = np.random.default_rng(1).integers(0, inst.A, inst.S).astype(np.int32)
+    v_ref, _ = oracle.evaluate_policy(inst, pol)
+    v0 = v_ref + 1e-3 * np.random.default_rng(2).standard_normal(inst.S)
+    with _mdp(inst) as h:
+        v, st = h.policy_eval(pol, v0=v0, inner=m.MDP_INNER_BICGSTAB, rtol=1e-12)
+    assert st["status"] == 0, st
+    assert np.max(np.abs(v - v_ref)) <= 1e-10 * np.max(np.abs(v_ref))
+
+
+def test_colblocked_with_maximize_and_bicgstab():
+    """The options compose: a blocked sweep, reward maximisation and BiCGSTAB
+    together reach the oracle's fixed point of the negated problem."""
+    import paper_2502_14474_amd as m
+    inst = config4(S=12000, A=16, seed=3)
+    neg = MDPInstance(inst.S, inst.A, inst.row_ptr, inst.col, inst.val, -inst.cost, inst.gamma)
+    with _mdp(neg, col_blocks=4, objective=m.MDP_MAXIMIZE_REWARD) as h:
+        v, pi, st = h.solve(inner=m.MDP_INNER_BICGSTAB, alpha=1e-2, rtol_cert=1e-10)
+    assert st["status"] == 0, st
+    Tv, pi_ref, res = oracle.bellman(inst, -v)
+    rel = res / (1.0 - inst.gamma) / np.max(np.abs(Tv))
+    assert rel <= 1e-9
