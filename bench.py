@@ -167,7 +167,7 @@ def serving_leg(args, m):
 def rows_leg(args, m, h, inst, v, pi):
     """Times the path's other steps on the solved MDP: the policy product on
     its own (20 launches at the greedy policy of the solution), solves with
-    Richardson and with BiCGSTAB inner iterations, and the per-kernel
+    Richardson, BiCGSTAB and TFQMR inner iterations, and the per-kernel
     breakdown of one float64 GMRES solve.  Rates use the library's
     algorithmic byte counts."""
     import torch
@@ -223,6 +223,20 @@ def rows_leg(args, m, h, inst, v, pi):
                               "residual": st["residual"], "kernels": summary(m.mdp_profile_read(h))}
     m.mdp_profile(h, False)
 
+    w.zero_()
+    m.mdp_solve(h, w, p2, inner=m.MDP_INNER_TFQMR, alpha=args.alpha, atol=args.atol)  # warm-up
+    w.zero_()
+    m.mdp_profile(h, True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st = m.mdp_solve(h, w, p2, inner=m.MDP_INNER_TFQMR, alpha=args.alpha, atol=args.atol)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    rows["tfqmr_solve"] = {"ms": 1e3 * (t1 - t0), "status": st["status"],
+                           "sweeps": st["bellman_sweeps"], "inner": st["inner_iters"],
+                           "residual": st["residual"], "kernels": summary(m.mdp_profile_read(h))}
+    m.mdp_profile(h, False)
+
     w = torch.zeros_like(v)
     p2 = torch.zeros_like(pi)
     m.mdp_profile(h, True)
@@ -232,7 +246,8 @@ def rows_leg(args, m, h, inst, v, pi):
     m.mdp_profile(h, False)
     log(f"[bench] rows: policy product {rows['policy_product']['avg_us']:.1f} us, "
         f"richardson {rows.get('richardson_solve', {}).get('ms', float('nan')):.1f} ms, "
-        f"bicgstab {rows['bicgstab_solve']['ms']:.1f} ms ({rows['bicgstab_solve']['inner']} its)")
+        f"bicgstab {rows['bicgstab_solve']['ms']:.1f} ms ({rows['bicgstab_solve']['inner']} its), "
+        f"tfqmr {rows['tfqmr_solve']['ms']:.1f} ms ({rows['tfqmr_solve']['inner']} its)")
     return rows
 
 

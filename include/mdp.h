@@ -68,8 +68,9 @@ enum { MDP_MINIMIZE_COST = 0, MDP_MAXIMIZE_REWARD = 1 };
 /* Inner solver of the approximate policy evaluation (the paper leaves the
  * choice of iterative solver for the linear system of policy evaluation open,
  * section "Problem Setting and Solution Methods"): restarted GMRES, the
- * Richardson / T_pi iteration, or BiCGSTAB (van der Vorst 1992). */
-enum { MDP_INNER_GMRES = 0, MDP_INNER_RICHARDSON = 1, MDP_INNER_BICGSTAB = 2 };
+ * Richardson / T_pi iteration, BiCGSTAB (van der Vorst 1992) or TFQMR (Freund
+ * 1993; stops on its residual bound tau * sqrt(m + 1)). */
+enum { MDP_INNER_GMRES = 0, MDP_INNER_RICHARDSON = 1, MDP_INNER_BICGSTAB = 2, MDP_INNER_TFQMR = 3 };
 
 /* Bits of mdp_create_opts.low_precision: which reduced-precision copies of P to build. */
 enum { MDP_BUILD_FP32 = 1, MDP_BUILD_FP16 = 2 };
@@ -99,8 +100,8 @@ typedef struct {
 
 typedef struct {
   size_t struct_size;     /* sizeof(mdp_eval_opts) */
-  int32_t inner;          /* MDP_INNER_GMRES, MDP_INNER_RICHARDSON or MDP_INNER_BICGSTAB
-                             (BiCGSTAB: float64 only, two products per iteration) */
+  int32_t inner;          /* MDP_INNER_GMRES, _RICHARDSON, _BICGSTAB or _TFQMR (BiCGSTAB and
+                             TFQMR: float64 only, two products per iteration) */
   int32_t restart;        /* GMRES restart length m, 1..64 (default 30) */
   int32_t precision;      /* MDP_FP64, MDP_MIXED_FP32 or MDP_MIXED_FP16 */
   int32_t sync_every;     /* inner steps enqueued between host checks; 0: default */

@@ -10,7 +10,7 @@ import numpy as np
 
 from . import native
 from .native import (MDP_FP64, MDP_MIXED_FP32, MDP_MIXED_FP16, MDP_INNER_GMRES,  # noqa: F401
-                     MDP_INNER_RICHARDSON, MDP_INNER_BICGSTAB, MDP_MINIMIZE_COST, MDP_MAXIMIZE_REWARD,
+                     MDP_INNER_RICHARDSON, MDP_INNER_BICGSTAB, MDP_INNER_TFQMR, MDP_MINIMIZE_COST, MDP_MAXIMIZE_REWARD,
                      MDP_BUILD_FP32, MDP_BUILD_FP16, MDP_OK,
                      MDP_W_MAXITER, MDPError)
 

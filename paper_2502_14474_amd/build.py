@@ -7,7 +7,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmdp.so")
-SOURCES = ["kernels.hip", "colblock.hip", "bicgstab.hip", "vecops.hip", "batch.hip", "api.cpp", "serve.cpp", "tune.cpp"]
+SOURCES = ["kernels.hip", "colblock.hip", "krylov.hip", "vecops.hip", "batch.hip", "api.cpp", "serve.cpp", "tune.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

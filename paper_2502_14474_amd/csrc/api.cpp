@@ -213,19 +213,28 @@ mdp_status richardson_inner(mdp_handle* h, const int32_t* pi, double* buf0, doub
   return MDP_OK;
 }
 
-// BiCGSTAB from x (residual r0 in basis slot 0, its norm and the tolerance in
-// ctl); stops at ctl->tol, at a breakdown, or after max_iter iterations.
+// BiCGSTAB (or TFQMR) from x (residual r0 in basis slot 0, its norm and the
+// tolerance in ctl); stops at ctl->tol, at a breakdown, or after max_iter
+// iterations.
 mdp_status bicgstab_inner(mdp_handle* h, const int32_t* pi, double* x, int64_t max_iter,
-                          int sync_every, InnerResult* out) {
-  MDP_HIP(launch_bicgstab_init(h));
+                          int sync_every, InnerResult* out, bool tfqmr = false) {
+  if (tfqmr)
+    MDP_HIP(launch_tfqmr_init(h, pi));
+  else
+    MDP_HIP(launch_bicgstab_init(h));
   MDP_TRY(sync_ctl(h));
   int64_t launched = 0;
   while (!h->ctl_host->done && launched < max_iter) {
     const int64_t n = std::min<int64_t>(sync_every, max_iter - launched);
-    for (int64_t i = 0; i < n; ++i) MDP_HIP(launch_bicgstab_step(h, pi, x));
+    for (int64_t i = 0; i < n; ++i) {
+      if (tfqmr)
+        MDP_HIP(launch_tfqmr_step(h, pi, x));
+      else
+        MDP_HIP(launch_bicgstab_step(h, pi, x));
+    }
     launched += n;
     MDP_TRY(sync_ctl(h));
-    if (!std::isfinite(h->ctl_host->res_est)) return fail(MDP_E_NUMERIC, "non-finite BiCGSTAB residual");
+    if (!std::isfinite(h->ctl_host->res_est)) return fail(MDP_E_NUMERIC, "non-finite Krylov residual");
   }
   out->steps = h->ctl_host->steps;
   out->applies += 2 * out->steps;
@@ -765,10 +774,9 @@ mdp_status mdp_policy_eval(mdp_t h, const int32_t* policy, const double* v0, dou
     if (opt->struct_size < sizeof(mdp_eval_opts)) return fail(MDP_E_INVAL, "mdp_eval_opts.struct_size too small");
     o = *opt;
   }
-  if (o.inner != MDP_INNER_GMRES && o.inner != MDP_INNER_RICHARDSON && o.inner != MDP_INNER_BICGSTAB)
-    return fail(MDP_E_INVAL, "unknown inner solver");
-  if (o.inner == MDP_INNER_BICGSTAB && o.precision != MDP_FP64)
-    return fail(MDP_E_NOTSUP, "BiCGSTAB runs in float64 only");
+  if (o.inner < MDP_INNER_GMRES || o.inner > MDP_INNER_TFQMR) return fail(MDP_E_INVAL, "unknown inner solver");
+  if ((o.inner == MDP_INNER_BICGSTAB || o.inner == MDP_INNER_TFQMR) && o.precision != MDP_FP64)
+    return fail(MDP_E_NOTSUP, "BiCGSTAB and TFQMR run in float64 only");
   if (o.restart < 1 || o.restart > kMaxRestart) return fail(MDP_E_INVAL, "restart must lie in [1,64]");
   if (o.precision < MDP_FP64 || o.precision > MDP_MIXED_FP16) return fail(MDP_E_INVAL, "unknown precision");
   if (o.inner == MDP_INNER_RICHARDSON && o.precision != MDP_FP64)
@@ -784,11 +792,11 @@ mdp_status mdp_policy_eval(mdp_t h, const int32_t* policy, const double* v0, dou
   InnerResult ir;
   double* result = h->v;
   double rel = 0.0;
-  if (o.inner == MDP_INNER_BICGSTAB) {
-    MDP_TRY(ensure_basis(h, kF64, std::max(o.restart, 5)));
+  if (o.inner == MDP_INNER_BICGSTAB || o.inner == MDP_INNER_TFQMR) {
+    MDP_TRY(ensure_basis(h, kF64, std::max(o.restart, 7)));
     MDP_HIP(launch_apply(h, kApplyRes, h->pi, h->v, h->U64, false, kRedGmresStart, 1, o.rtol, 0.0));
     ir.applies += 1;
-    MDP_TRY(bicgstab_inner(h, h->pi, h->v, o.max_iter, sync_every, &ir));
+    MDP_TRY(bicgstab_inner(h, h->pi, h->v, o.max_iter, sync_every, &ir, o.inner == MDP_INNER_TFQMR));
     rel = h->ctl_host->beta0 > 0 ? h->ctl_host->res_est / h->ctl_host->beta0 : 0.0;
   } else if (o.inner == MDP_INNER_GMRES) {
     const Prec prec = prec_of(o.precision);
@@ -838,10 +846,9 @@ mdp_status mdp_solve(mdp_t h, const double* v0, double* v, int32_t* policy,
     if (opt->struct_size < sizeof(mdp_solve_opts)) return fail(MDP_E_INVAL, "mdp_solve_opts.struct_size too small");
     o = *opt;
   }
-  if (o.inner != MDP_INNER_GMRES && o.inner != MDP_INNER_RICHARDSON && o.inner != MDP_INNER_BICGSTAB)
-    return fail(MDP_E_INVAL, "unknown inner solver");
-  if (o.inner == MDP_INNER_BICGSTAB && o.precision != MDP_FP64)
-    return fail(MDP_E_NOTSUP, "BiCGSTAB runs in float64 only");
+  if (o.inner < MDP_INNER_GMRES || o.inner > MDP_INNER_TFQMR) return fail(MDP_E_INVAL, "unknown inner solver");
+  if ((o.inner == MDP_INNER_BICGSTAB || o.inner == MDP_INNER_TFQMR) && o.precision != MDP_FP64)
+    return fail(MDP_E_NOTSUP, "BiCGSTAB and TFQMR run in float64 only");
   if (o.restart < 1 || o.restart > kMaxRestart) return fail(MDP_E_INVAL, "restart must lie in [1,64]");
   if (o.precision < MDP_FP64 || o.precision > MDP_MIXED_FP16) return fail(MDP_E_INVAL, "unknown precision");
   if (o.inner == MDP_INNER_RICHARDSON && o.precision != MDP_FP64)
@@ -854,9 +861,9 @@ mdp_status mdp_solve(mdp_t h, const double* v0, double* v, int32_t* policy,
   const int sync_every = o.sync_every > 0 ? o.sync_every : 4;
   const Prec iprec = prec_of(o.precision);
   const bool gm = o.inner == MDP_INNER_GMRES;
-  const bool bi = o.inner == MDP_INNER_BICGSTAB;
+  const bool bi = o.inner == MDP_INNER_BICGSTAB || o.inner == MDP_INNER_TFQMR;
   if (gm) MDP_TRY(ensure_basis(h, iprec == kF64 ? kF64 : kF32, o.restart));
-  if (bi) MDP_TRY(ensure_basis(h, kF64, std::max(o.restart, 5)));
+  if (bi) MDP_TRY(ensure_basis(h, kF64, std::max(o.restart, 7)));
   if (iprec != kF64) MDP_TRY(ensure_lowp(h, iprec));
   MDP_TRY(load_vec(h, v0, h->v));
   MDP_HIP(launch_ctl_reset(h, 0.0));
@@ -918,7 +925,7 @@ mdp_status mdp_solve(mdp_t h, const double* v0, double* v, int32_t* policy,
     if (gm) {
       MDP_TRY(gmres_inner(h, iprec, h->pi, h->v, o.restart, o.max_inner, sync_every, alpha, &ir));
     } else if (bi) {
-      MDP_TRY(bicgstab_inner(h, h->pi, h->v, o.max_inner, sync_every, &ir));
+      MDP_TRY(bicgstab_inner(h, h->pi, h->v, o.max_inner, sync_every, &ir, o.inner == MDP_INNER_TFQMR));
     } else {
       // x1 = T v_k is already in x2; continue T_pi from there
       double* last = h->x2;

@@ -56,8 +56,10 @@ struct Ctl {
   double cs[kMaxRestart], sn[kMaxRestart];     // Givens rotations
   double H[(kMaxRestart + 1) * kMaxRestart];   // Hessenberg / R, column-major
   double y[kMaxRestart];                       // least-squares solution
-  // BiCGSTAB scalars (device only): rho, alpha, omega and beta of the current step
+  // BiCGSTAB / TFQMR scalars (device only)
   double bi_rho, bi_alpha, bi_omega, bi_beta;
+  double tf_theta, tf_eta, tf_tau, tf_half;  // TFQMR: theta, eta, tau, half-steps done
+  int32_t tf_stop, pad1;                     // TFQMR: the bound met at the last half-step
 };
 constexpr size_t kCtlHeaderBytes = offsetof(Ctl, scale);
 
@@ -243,13 +245,17 @@ hipError_t launch_apply(mdp_handle* h, int mode, const int32_t* pi, const double
 
 // Richardson step on the ping-pong pair, early-exiting on ctl->done.
 hipError_t launch_richardson_step(mdp_handle* h, const int32_t* pi, double* buf0, double* buf1);
-// BiCGSTAB (bicgstab.hip) on (I - gamma P_pi) x = g_pi in float64.  The
+// BiCGSTAB (krylov.hip) on (I - gamma P_pi) x = g_pi in float64.  The
 // residual r0 sits in basis slot 0 and ctl holds its norm and the tolerance
 // (kRedGmresStart); init sets up the shadow residual and the first direction,
 // step enqueues one iteration (two products).  Slots 0..5 of the float64
 // basis hold r, r^, p, v, s, t.
 hipError_t launch_bicgstab_init(mdp_handle* h);
 hipError_t launch_bicgstab_step(mdp_handle* h, const int32_t* pi, double* x);
+// TFQMR (krylov.hip), same conventions; slots 0..7 hold r^, w, y1, y2, v, d,
+// A y2, A y1.
+hipError_t launch_tfqmr_init(mdp_handle* h, const int32_t* pi);
+hipError_t launch_tfqmr_step(mdp_handle* h, const int32_t* pi, double* x);
 
 // One Arnoldi step j (product + Gram-Schmidt + norm + Givens), early-exiting.
 hipError_t launch_arnoldi_step(mdp_handle* h, Prec prec, const int32_t* pi, int j, int m);

@@ -14,7 +14,7 @@ MDP_E_INVAL, MDP_E_NOMEM, MDP_E_DEVICE, MDP_E_NUMERIC, MDP_E_STATE, MDP_E_NOTSUP
 STATUS_NAMES = {0: "MDP_OK", 1: "MDP_W_MAXITER", -1: "MDP_E_INVAL", -2: "MDP_E_NOMEM",
                 -3: "MDP_E_DEVICE", -4: "MDP_E_NUMERIC", -5: "MDP_E_STATE", -6: "MDP_E_NOTSUP"}
 MDP_FP64, MDP_MIXED_FP32, MDP_MIXED_FP16 = 0, 1, 2
-MDP_INNER_GMRES, MDP_INNER_RICHARDSON, MDP_INNER_BICGSTAB = 0, 1, 2
+MDP_INNER_GMRES, MDP_INNER_RICHARDSON, MDP_INNER_BICGSTAB, MDP_INNER_TFQMR = 0, 1, 2, 3
 MDP_BUILD_FP32, MDP_BUILD_FP16 = 1, 2
 MDP_MINIMIZE_COST, MDP_MAXIMIZE_REWARD = 0, 1
 
