@@ -151,6 +151,26 @@ mdp_status mdp_create(int64_t S, int32_t A, const int64_t* row_ptr, const int32_
                       const double* val, const double* cost, double gamma,
                       const mdp_create_opts* opt, mdp_t* out);
 
+/* Rows of an MDP produced on demand, e.g. by a simulator (the paper builds
+ * MDPs from offline data or from online simulation, section
+ * "Implementation").  The function fills the rows of states [s_begin, s_end):
+ * row i = (s - s_begin) * A + a holds len[i] <= k_max entries in
+ * col[i * k_max + j], val[i * k_max + j] (j < len[i], columns increasing) and
+ * the cost (or, with MDP_MAXIMIZE_REWARD, the reward) cost[i].  It returns 0,
+ * or nonzero to abort the creation.  It is called from several host threads
+ * at once, on disjoint state ranges. */
+typedef int32_t (*mdp_rows_fn)(void* user, int64_t s_begin, int64_t s_end, int32_t k_max,
+                               int32_t* col, double* val, int32_t* len, double* cost);
+
+/* Create a handle from a row function: host threads (up to 16) call fn on
+ * ranges of states, the rows are packed into CSR, validated as by mdp_create
+ * when opt->validate is set, and copied to the device.  Host memory peaks at
+ * about (S*A*k_max + nnz) * 12 bytes (the padded rows and the packed CSR).
+ * MDP_E_INVAL when fn returns nonzero or a row is longer than k_max; other
+ * errors as mdp_create. */
+mdp_status mdp_create_from_rows(int64_t S, int32_t A, int32_t k_max, mdp_rows_fn fn, void* user,
+                                double gamma, const mdp_create_opts* opt, mdp_t* out);
+
 /* One fused Bellman sweep in float64 (greedy step of policy iteration):
  *   Tv[s] = min_a g(s,a) + gamma * sum_j P[(s,a),j] v[j],
  *   policy[s] = the lowest action attaining the minimum,

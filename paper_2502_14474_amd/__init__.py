@@ -14,7 +14,7 @@ from .native import (MDP_FP64, MDP_MIXED_FP32, MDP_MIXED_FP16, MDP_INNER_GMRES, 
                      MDP_BUILD_FP32, MDP_BUILD_FP16, MDP_OK,
                      MDP_W_MAXITER, MDPError)
 
-__all__ = ["mdp_create", "mdp_bellman", "mdp_policy_apply", "mdp_policy_eval", "mdp_solve",
+__all__ = ["mdp_create", "mdp_create_from_rows", "mdp_bellman", "mdp_policy_apply", "mdp_policy_eval", "mdp_solve",
            "mdp_solve_batch", "Server",
            "mdp_destroy", "mdp_info", "mdp_autotune", "mdp_profile", "mdp_profile_read",
            "mdp_last_error", "MDP", "MDPError"]
@@ -66,6 +66,37 @@ def mdp_create(S, A, row_ptr, col, val, cost, gamma, stream=None, device=-1, val
                                 _ptr(col, np.int32, nnz, "col"), _ptr(val, np.float64, nnz, "val"),
                                 _ptr(cost, np.float64, S * A, "cost"), float(gamma), C.byref(o),
                                 C.byref(h)))
+    return h
+
+
+def mdp_create_from_rows(S, A, k_max, fn, gamma, stream=None, device=-1, validate=True,
+                         low_precision=0, lanes_per_row=0, col_blocks=-1, objective=0):
+    """Create a handle from a row function (mdp_create_from_rows in the C
+    ABI).  fn(s_begin, s_end, col, val, length, cost) fills, for the states
+    [s_begin, s_end), numpy views shaped (rows, k_max) for col (int32) and val
+    (float64) and (rows,) for length (int32) and cost (float64), where rows =
+    (s_end - s_begin) * A; it is called from several threads at once."""
+    lib = native.load()
+    o = native.CreateOpts()
+    lib.mdp_default_create_opts(C.byref(o))
+    o.stream, o.device, o.validate = stream, device, 1 if validate else 0
+    o.low_precision, o.lanes_per_row = low_precision, lanes_per_row
+    o.col_blocks, o.objective = col_blocks, objective
+
+    def cb(user, s0, s1, k, colp, valp, lenp, costp):
+        try:
+            n = int(s1 - s0) * A
+            fn(int(s0), int(s1), np.ctypeslib.as_array(colp, shape=(n, k)),
+               np.ctypeslib.as_array(valp, shape=(n, k)), np.ctypeslib.as_array(lenp, shape=(n,)),
+               np.ctypeslib.as_array(costp, shape=(n,)))
+            return 0
+        except Exception:  # reported to the library as a failed range
+            return 1
+
+    cfn = native.ROWS_FN(cb)
+    h = C.c_void_p()
+    native.check(lib.mdp_create_from_rows(int(S), int(A), int(k_max), cfn, None, float(gamma),
+                                          C.byref(o), C.byref(h)))
     return h
 
 

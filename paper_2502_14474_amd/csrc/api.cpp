@@ -698,6 +698,80 @@ mdp_status mdp_create(int64_t S, int32_t A, const int64_t* row_ptr, const int32_
   return MDP_OK;
 }
 
+mdp_status mdp_create_from_rows(int64_t S, int32_t A, int32_t k_max, mdp_rows_fn fn, void* user,
+                                double gamma, const mdp_create_opts* opt, mdp_t* out) {
+  clear_error();
+  if (!out) return fail(MDP_E_INVAL, "out is NULL");
+  *out = nullptr;
+  if (!fn) return fail(MDP_E_INVAL, "row function is NULL");
+  if (S < 1 || A < 1) return fail(MDP_E_INVAL, "S and A must be at least 1");
+  if (k_max < 1) return fail(MDP_E_INVAL, "k_max must be at least 1");
+  const int64_t rows = S * A;
+  if (rows >= (int64_t{1} << 31) - 1) return fail(MDP_E_NOTSUP, "S*A must be below 2^31");
+  const unsigned nt = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+  // ranges of about 2^20 padded entries, handed out to the threads in turn
+  const int64_t chunk = std::max<int64_t>(1, (int64_t{1} << 20) / (static_cast<int64_t>(A) * k_max));
+  const int64_t n_chunks = (S + chunk - 1) / chunk;
+  std::vector<int32_t> pcol, len(rows);
+  std::vector<double> pval, cost(rows);
+  try {
+    pcol.resize(static_cast<size_t>(rows) * k_max);
+    pval.resize(static_cast<size_t>(rows) * k_max);
+  } catch (const std::bad_alloc&) {
+    return fail(MDP_E_NOMEM, "host memory for the padded rows");
+  }
+  std::atomic<int64_t> next{0};
+  std::atomic<int> failed{0};
+  auto fill = [&]() {
+    for (;;) {
+      const int64_t c = next.fetch_add(1);
+      if (c >= n_chunks || failed.load()) return;
+      const int64_t s0 = c * chunk, s1 = std::min(S, s0 + chunk), r0 = s0 * A;
+      if (fn(user, s0, s1, k_max, pcol.data() + r0 * k_max, pval.data() + r0 * k_max, len.data() + r0,
+             cost.data() + r0) != 0)
+        failed.store(1);
+    }
+  };
+  {
+    std::vector<std::thread> ts;
+    for (unsigned t = 0; t < nt; ++t) ts.emplace_back(fill);
+    for (auto& t : ts) t.join();
+  }
+  if (failed.load()) return fail(MDP_E_INVAL, "the row function reported a failure");
+  std::vector<int64_t> rp(rows + 1);
+  rp[0] = 0;
+  for (int64_t r = 0; r < rows; ++r) {
+    if (len[r] < 0 || len[r] > k_max)
+      return fail(MDP_E_INVAL, "row " + std::to_string(r) + " has " + std::to_string(len[r]) +
+                                   " entries (k_max " + std::to_string(k_max) + ")");
+    rp[r + 1] = rp[r] + len[r];
+  }
+  const int64_t nnz = rp[rows];
+  if (nnz >= (int64_t{1} << 31)) return fail(MDP_E_NOTSUP, "nnz must be below 2^31");
+  std::vector<int32_t> col;
+  std::vector<double> val;
+  try {
+    col.resize(nnz);
+    val.resize(nnz);
+  } catch (const std::bad_alloc&) {
+    return fail(MDP_E_NOMEM, "host memory for the packed rows");
+  }
+  {
+    std::vector<std::thread> ts;
+    for (unsigned t = 0; t < nt; ++t)
+      ts.emplace_back([&, t]() {
+        for (int64_t r = t; r < rows; r += nt) {
+          std::memcpy(col.data() + rp[r], pcol.data() + r * k_max, len[r] * sizeof(int32_t));
+          std::memcpy(val.data() + rp[r], pval.data() + r * k_max, len[r] * sizeof(double));
+        }
+      });
+    for (auto& t : ts) t.join();
+  }
+  std::vector<int32_t>().swap(pcol);
+  std::vector<double>().swap(pval);
+  return mdp_create(S, A, rp.data(), col.data(), val.data(), cost.data(), gamma, opt, out);
+}
+
 mdp_status mdp_info(mdp_t h, int64_t* S, int32_t* A, int64_t* nnz, int32_t* lanes,
                     int64_t* device_bytes) {
   clear_error();

@@ -71,8 +71,15 @@ class RequestStats(C.Structure):
 
 
 # name -> (restype, argtypes); the exported symbols of include/mdp.h
+# int32_t (*)(void* user, int64_t s_begin, int64_t s_end, int32_t k_max, int32_t* col,
+#            double* val, int32_t* len, double* cost)
+ROWS_FN = C.CFUNCTYPE(C.c_int32, C.c_void_p, C.c_int64, C.c_int64, C.c_int32, C.POINTER(C.c_int32),
+                      C.POINTER(C.c_double), C.POINTER(C.c_int32), C.POINTER(C.c_double))
+
 SIGNATURES = {
     "mdp_default_create_opts": (None, [C.POINTER(CreateOpts)]),
+    "mdp_create_from_rows": (C.c_int, [C.c_int64, C.c_int32, C.c_int32, ROWS_FN, C.c_void_p, C.c_double,
+                                       C.POINTER(CreateOpts), C.POINTER(C.c_void_p)]),
     "mdp_default_eval_opts": (None, [C.POINTER(EvalOpts)]),
     "mdp_default_solve_opts": (None, [C.POINTER(SolveOpts)]),
     "mdp_create": (C.c_int, [C.c_int64, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p,

@@ -116,3 +116,35 @@ def test_valid_create_without_gpu_reports_device_error():
     st, msg, h = _create(S, A, rp, col, val, cost, gamma)
     assert st in (native.MDP_E_DEVICE, native.MDP_E_NOMEM), (st, msg)
     assert not h.value
+
+
+def _rows_from(inst, k_max):
+    def fn(s0, s1, col, val, length, cost):
+        r0, r1 = s0 * inst.A, s1 * inst.A
+        for i, r in enumerate(range(r0, r1)):
+            a, b = inst.row_ptr[r], inst.row_ptr[r + 1]
+            col[i, :b - a] = inst.col[a:b]
+            val[i, :b - a] = inst.val[a:b]
+            length[i] = b - a
+            cost[i] = inst.cost[r]
+    return fn
+
+
+def test_create_from_rows_reports_row_function_failures():
+    """A failing row function or a row longer than k_max is refused on the
+    host, before any device work."""
+    import paper_2502_14474_amd as m
+    inst = config1(S=50, seed=1)
+
+    def broken(s0, s1, col, val, length, cost):
+        raise RuntimeError("simulator failed")
+    with pytest.raises(m.MDPError) as ei:
+        m.mdp_create_from_rows(inst.S, inst.A, 10, broken, inst.gamma)
+    assert ei.value.status == native.MDP_E_INVAL and "row function" in str(ei.value)
+
+    def too_long(s0, s1, col, val, length, cost):
+        _rows_from(inst, 10)(s0, s1, col, val, length, cost)
+        length[0] = 11
+    with pytest.raises(m.MDPError) as ei:
+        m.mdp_create_from_rows(inst.S, inst.A, 10, too_long, inst.gamma)
+    assert ei.value.status == native.MDP_E_INVAL and "k_max" in str(ei.value)
