@@ -633,21 +633,56 @@ mdp_status mdp_create(int64_t S, int32_t A, const int64_t* row_ptr, const int32_
   CHK(dev_alloc(h, &h->col, nnz));
   CHK(dev_alloc(h, &h->val, nnz));
   CHK(dev_alloc(h, &h->cost, rows));
-  if (dev_in) {
-    int64_t* tmp = nullptr;
-    CHK(hipMalloc(reinterpret_cast<void**>(&tmp), (rows + 1) * sizeof(int64_t)));
-    CHK(hipMemcpyAsync(tmp, row_ptr, (rows + 1) * sizeof(int64_t), hipMemcpyDefault, h->stream));
-    CHK(launch_i64_to_i32(h->stream, tmp, h->row_ptr, rows + 1));
-    CHK(hipStreamSynchronize(h->stream));
-    CHK(hipFree(tmp));
-  } else {
-    std::vector<int32_t> rp32(rows + 1);
+  // Rows are stored in the tile-by-tile, action-major order of row_of():
+  // the natural arrays go to scratch buffers and one kernel moves them.
+  const bool permute = A > 1 && sweep_tile_states(A) > 1;
+  {
+    std::vector<int32_t> rp32(rows + 1), rpn(permute ? rows + 1 : 0);
     for (int64_t r = 0; r <= rows; ++r) rp32[r] = static_cast<int32_t>(rp_host[r]);
-    CHK(hipMemcpy(h->row_ptr, rp32.data(), (rows + 1) * sizeof(int32_t), hipMemcpyHostToDevice));
+    if (permute) {
+      rpn[0] = 0;
+      for (int64_t r = 0; r < rows; ++r) {
+        const int64_t s = state_of_row(r, A, S);
+        const int T = sweep_tile_states(A);
+        const int64_t t0 = (s / T) * T;
+        const int64_t n = std::min<int64_t>(T, S - t0);
+        const int64_t ro = s * A + (r - t0 * A) / n;
+        rpn[r + 1] = rpn[r] + (rp32[ro + 1] - rp32[ro]);
+      }
+    }
+    if (!permute) {
+      CHK(hipMemcpy(h->row_ptr, rp32.data(), (rows + 1) * sizeof(int32_t), hipMemcpyHostToDevice));
+      CHK(hipMemcpyAsync(h->col, col, nnz * sizeof(int32_t), hipMemcpyDefault, h->stream));
+      CHK(hipMemcpyAsync(h->val, val, nnz * sizeof(double), hipMemcpyDefault, h->stream));
+      CHK(hipMemcpyAsync(h->cost, cost, rows * sizeof(double), hipMemcpyDefault, h->stream));
+    } else {
+      CHK(hipMemcpy(h->row_ptr, rpn.data(), (rows + 1) * sizeof(int32_t), hipMemcpyHostToDevice));
+      int32_t *rp_old = nullptr, *col_old = nullptr;
+      double *val_old = nullptr, *cost_old = nullptr;
+      auto free_old = [&]() {
+        if (rp_old) (void)hipFree(rp_old);
+        if (col_old) (void)hipFree(col_old);
+        if (val_old) (void)hipFree(val_old);
+        if (cost_old) (void)hipFree(cost_old);
+      };
+      hipError_t e = hipMalloc(reinterpret_cast<void**>(&rp_old), (rows + 1) * sizeof(int32_t));
+      if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&col_old), nnz * sizeof(int32_t));
+      if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&val_old), nnz * sizeof(double));
+      if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&cost_old), rows * sizeof(double));
+      if (e == hipSuccess)
+        e = hipMemcpyAsync(rp_old, rp32.data(), (rows + 1) * sizeof(int32_t), hipMemcpyHostToDevice, h->stream);
+      if (e == hipSuccess) e = hipMemcpyAsync(col_old, col, nnz * sizeof(int32_t), hipMemcpyDefault, h->stream);
+      if (e == hipSuccess) e = hipMemcpyAsync(val_old, val, nnz * sizeof(double), hipMemcpyDefault, h->stream);
+      if (e == hipSuccess) e = hipMemcpyAsync(cost_old, cost, rows * sizeof(double), hipMemcpyDefault, h->stream);
+      if (e == hipSuccess)
+        e = launch_permute_rows(h->stream, S, A, rp_old, col_old, val_old, cost_old, h->row_ptr, h->col,
+                                h->val, h->cost);
+      if (e == hipSuccess) e = hipStreamSynchronize(h->stream);  // the host vectors and scratch go away
+      free_old();
+      CHK(e);
+    }
+    if (!permute) CHK(hipStreamSynchronize(h->stream));
   }
-  CHK(hipMemcpyAsync(h->col, col, nnz * sizeof(int32_t), hipMemcpyDefault, h->stream));
-  CHK(hipMemcpyAsync(h->val, val, nnz * sizeof(double), hipMemcpyDefault, h->stream));
-  CHK(hipMemcpyAsync(h->cost, cost, rows * sizeof(double), hipMemcpyDefault, h->stream));
   h->maximize = o.objective == MDP_MAXIMIZE_REWARD;
   if (h->maximize) CHK(launch_negate(h->stream, h->cost, rows));  // rewards -> costs
   CHK(dev_alloc(h, &h->v, S));

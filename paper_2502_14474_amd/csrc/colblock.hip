@@ -30,7 +30,7 @@ namespace {
 
 // cnt[b][r] for every row; *far += entries outside the row's own slice;
 // *bad = 1 when a row is not supported.
-__global__ __launch_bounds__(kBlock) void k_cb_count(int64_t rows, int A, const int* __restrict__ rp,
+__global__ __launch_bounds__(kBlock) void k_cb_count(int64_t S, int64_t rows, int A, const int* __restrict__ rp,
                                                      const int* __restrict__ col, int slice,
                                                      uint8_t* __restrict__ cnt,
                                                      unsigned long long* __restrict__ far,
@@ -39,7 +39,7 @@ __global__ __launch_bounds__(kBlock) void k_cb_count(int64_t rows, int A, const 
   unsigned long long f = 0;
   int b_bad = 0;
   if (r < rows) {
-    const int own = static_cast<int>((r / A) / slice);
+    const int own = static_cast<int>(state_of_row(r, A, S) / slice);
     int cur = -1, run = 0;
     for (int e = rp[r]; e < rp[r + 1]; ++e) {
       const int b = col[e] / slice;
@@ -187,7 +187,7 @@ __global__ __launch_bounds__(kBlock) void k_bellman_cb(
     if (i >= nrows) continue;
     const double total = FIRST ? sum[k] : prev[k] + sum[k];
     if (LAST) {
-      q[i] = fma(gamma, total, cost[row0 + i]);
+      q[(i % ns) * A + i / ns] = fma(gamma, total, cost[row0 + i]);  // stored row -> (state, action)
     } else {
       acc[row0 + i] = total;
     }
@@ -282,7 +282,7 @@ hipError_t build_colblocks(mdp_handle* h, int blocks, bool require, bool* built,
   auto* far = static_cast<unsigned long long*>(scratch);
   int* bad = reinterpret_cast<int*>(static_cast<char*>(scratch) + 8);
   k_cb_count<<<static_cast<unsigned>((rows + kBlock - 1) / kBlock), kBlock, 0, h->stream>>>(
-      rows, h->A, h->row_ptr, h->col, slice, cnt, far, bad);
+      h->S, rows, h->A, h->row_ptr, h->col, slice, cnt, far, bad);
   CB_CHK(hipGetLastError());
   unsigned long long far_h = 0;
   int bad_h = 0;

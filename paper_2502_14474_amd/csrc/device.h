@@ -416,15 +416,16 @@ __device__ __forceinline__ void bellman_tile(
       },
       col, val, v, S, cost, corr,
       [&](int idx, AT pv, double gc, XT) {
-        if ((threadIdx.x % L) == 0) q[idx] = fma(gam, pv, static_cast<AT>(gc));
+        // stored row idx of the tile is action idx / ns of state idx % ns
+        if ((threadIdx.x % L) == 0) q[(idx % ns) * A + idx / ns] = fma(gam, pv, static_cast<AT>(gc));
       });
   __syncthreads();
   sweep_finish<AT, XT, RT>(s0, ns, A, q, v, Tv, pi, r0, partials, tile);
 }
 
 // Stage the selected rows of kApplyTile states: thread t loads pi(s0+t) and
-// the two row offsets of row s*A + pi(s) (all independent loads).
-__device__ __forceinline__ void stage_policy_rows(int64_t s0, int ns, int A, RowIndex rix,
+// the two row offsets of the stored row of (s, pi(s)) (all independent loads).
+__device__ __forceinline__ void stage_policy_rows(int64_t S, int64_t s0, int ns, int A, RowIndex rix,
                                                   const int* __restrict__ pi, int* st_l,
                                                   int* en_l, int* rw_l) {
   constexpr int KP = (kApplyTile + kBlock - 1) / kBlock;
@@ -437,7 +438,7 @@ __device__ __forceinline__ void stage_policy_rows(int64_t s0, int ns, int A, Row
 #pragma unroll
   for (int k = 0; k < KP; ++k) {
     const int t = threadIdx.x + k * kBlock;
-    const int r = static_cast<int>((s0 + (t < ns ? t : 0)) * A + pv[k]);
+    const int r = static_cast<int>(row_of(s0 + (t < ns ? t : 0), pv[k], A, S));
     pv[k] = r;
     if (rix.kfix > 0) {
       a[k] = r * rix.kfix;
@@ -477,7 +478,7 @@ __device__ __forceinline__ void apply_tile(
   const int64_t s0 = static_cast<int64_t>(tile) * kApplyTile;
   const int ns = static_cast<int>(min<int64_t>(kApplyTile, S - s0));
   const AT gam = static_cast<AT>(gamma);
-  stage_policy_rows(s0, ns, A, rix, pi, st_l, en_l, rw_l);
+  stage_policy_rows(S, s0, ns, A, rix, pi, st_l, en_l, rw_l);
   double dmax = 0.0, dsum = 0.0;
 
   pipelined_rows<L, U, VT, XT, AT, CORR, MODE != kApplyOp, true>(
@@ -541,7 +542,7 @@ __device__ __forceinline__ void arnoldi_apply_tile(
   const BT* __restrict__ xj = Ub + static_cast<int64_t>(j) * ldu;
   BT* __restrict__ w = Ub + static_cast<int64_t>(j + 1) * ldu;
   const double cj = ctl->scale[j];
-  stage_policy_rows(s0, ns, A, rix, pi, st_l, en_l, rw_l);
+  stage_policy_rows(S, s0, ns, A, rix, pi, st_l, en_l, rw_l);
 
   pipelined_rows<L, U, VT, BT, AT, CORR, false, true>(
       ns,

@@ -183,7 +183,34 @@ constexpr int kSweepRows = MDP_SWEEP_ROWS;
 constexpr int64_t kColSliceBytes = int64_t{4} << 20;
 constexpr int64_t kColBlockMinStates = int64_t{1} << 21;
 constexpr int kMaxColBlocks = 64;
-inline int sweep_tile_states(int A) { return A >= kSweepRows ? 1 : kSweepRows / A; }
+__host__ __device__ inline int sweep_tile_states(int A) { return A >= kSweepRows ? 1 : kSweepRows / A; }
+
+// Row order of P on the device.  States are grouped in sweep tiles of
+// T = sweep_tile_states(A) states; a tile's rows are contiguous and, inside
+// the tile, action-major: (s, a) is row t0*A + a*n + (s - t0), where t0 is the
+// tile's first state and n its number of states.  A policy that picks the
+// same action for neighbouring states then selects neighbouring rows, so the
+// policy products read fewer partly used lines; the sweep still streams every
+// row once.
+__host__ __device__ inline int64_t row_of(int64_t s, int a, int A, int64_t S) {
+  const int T = sweep_tile_states(A);
+  const int64_t t0 = (s / T) * T;
+  const int64_t n = (S - t0) < T ? (S - t0) : T;
+  return t0 * A + a * n + (s - t0);
+}
+// The state of a stored row.
+__host__ __device__ inline int64_t state_of_row(int64_t r, int A, int64_t S) {
+  const int T = sweep_tile_states(A);
+  const int64_t t0 = (r / (static_cast<int64_t>(T) * A)) * T;
+  const int64_t n = (S - t0) < T ? (S - t0) : T;
+  return t0 + (r - t0 * A) % n;
+}
+
+// Copy natural-order rows (s*A + a) into the stored order (vecops.hip).
+hipError_t launch_permute_rows(hipStream_t st, int64_t S, int A, const int32_t* rp_old,
+                               const int32_t* col_old, const double* val_old,
+                               const double* cost_old, const int32_t* rp_new, int32_t* col_new,
+                               double* val_new, double* cost_new);
 size_t partials_doubles(int64_t S, int A, int m);
 
 // Host helpers shared by the single and the batched drivers (api.cpp).
