@@ -5,14 +5,16 @@
  * sections): an infinite-horizon discounted MDP with finite state space
  * {0..S-1}, finite action space {0..A-1}, stage costs g(s,a), discount
  * gamma in [0,1) and transition probabilities P[(s,a), s'].  The solver
- * minimises the expected discounted cumulative cost.  It uses inexact policy
- * iteration: a greedy improvement step (one Bellman sweep) alternates with an
- * approximate policy evaluation whose level of inexactness and inner solver
- * (restarted GMRES or Richardson) the caller selects.
+ * minimises the expected discounted cumulative cost (or, on request,
+ * maximises the expected discounted cumulative reward).  It uses inexact
+ * policy iteration: a greedy improvement step (one Bellman sweep) alternates
+ * with an approximate policy evaluation whose level of inexactness and inner
+ * solver (restarted GMRES, Richardson, BiCGSTAB or TFQMR) the caller selects.
  *
  * Layout of an MDP handed to mdp_create ("Implementation" section: an MDP is
  * created from offline data):
- *   - rows r = s*A + a (state-major), S*A rows in total;
+ *   - rows r = s*A + a (state-major), S*A rows in total (this is the input
+ *     order only: the library copies rows into an order of its own);
  *   - row_ptr: int64[S*A+1], CSR row offsets, row_ptr[0] = 0, nondecreasing,
  *     every row non-empty, row_ptr[S*A] = nnz;
  *   - col: int32[nnz], column (successor state) indices in [0,S);

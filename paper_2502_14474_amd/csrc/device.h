@@ -461,7 +461,7 @@ __device__ __forceinline__ void stage_policy_rows(int64_t S, int64_t s0, int ns,
 }
 
 // ----------------------------------------------------------------------------
-// K2/K3/K10: products with P_pi, gathering rows s*A + pi(s)
+// K2/K3/K10: products with P_pi, gathering the stored rows of (s, pi(s))
 // ----------------------------------------------------------------------------
 // MODE kApplyOp : y = x - gamma P_pi x
 // MODE kApplyT  : y = g_pi + gamma P_pi x, partials (max|y - x|, sum (y-x)^2)
