@@ -7,6 +7,7 @@
 #include <cstring>
 #include <limits>
 #include <memory>
+#include <mutex>
 #include <thread>
 #include <vector>
 
@@ -47,6 +48,43 @@ template <typename T>
 void dev_free(T*& p) {
   if (p) (void)hipFree(p);
   p = nullptr;
+}
+
+// Staging memory for uploads at create time comes from a stream-ordered pool
+// that the library creates once per device and keeps until the process ends.
+// hipFree waits for the whole device, which would hold a create (a server
+// admission) behind the solves running beside it; the pool frees in stream
+// order and keeps up to kStagingKeepBytes cached between creates.
+constexpr uint64_t kStagingKeepBytes = uint64_t{2} << 30;
+
+hipError_t staging_alloc(int dev, hipStream_t st, size_t bytes, char** out) {
+  static std::mutex mu;
+  static std::vector<hipMemPool_t> pools;
+  hipMemPool_t pool = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(mu);
+    if (pools.size() <= static_cast<size_t>(dev)) pools.resize(dev + 1, nullptr);
+    if (!pools[dev]) {
+      hipMemPoolProps props;
+      std::memset(&props, 0, sizeof(props));
+      props.allocType = hipMemAllocationTypePinned;
+      props.handleTypes = hipMemHandleTypeNone;
+      props.location.type = hipMemLocationTypeDevice;
+      props.location.id = dev;
+      hipMemPool_t p = nullptr;
+      hipError_t e = hipMemPoolCreate(&p, &props);
+      if (e != hipSuccess) return e;
+      uint64_t keep = kStagingKeepBytes;
+      e = hipMemPoolSetAttribute(p, hipMemPoolAttrReleaseThreshold, &keep);
+      if (e != hipSuccess) {
+        (void)hipMemPoolDestroy(p);
+        return e;
+      }
+      pools[dev] = p;
+    }
+    pool = pools[dev];
+  }
+  return hipMallocFromPoolAsync(reinterpret_cast<void**>(out), std::max<size_t>(bytes, 1), pool, st);
 }
 
 // Copy a caller policy to device memory and check its range.
@@ -634,54 +672,42 @@ mdp_status mdp_create(int64_t S, int32_t A, const int64_t* row_ptr, const int32_
   CHK(dev_alloc(h, &h->val, nnz));
   CHK(dev_alloc(h, &h->cost, rows));
   // Rows are stored in the tile-by-tile, action-major order of row_of():
-  // the natural arrays go to scratch buffers and one kernel moves them.
+  // the natural arrays go to a staging block and one kernel moves them.
   const bool permute = A > 1 && sweep_tile_states(A) > 1;
   {
-    std::vector<int32_t> rp32(rows + 1), rpn(permute ? rows + 1 : 0);
+    std::vector<int32_t> rp32(rows + 1);
     for (int64_t r = 0; r <= rows; ++r) rp32[r] = static_cast<int32_t>(rp_host[r]);
-    if (permute) {
-      rpn[0] = 0;
-      for (int64_t r = 0; r < rows; ++r) {
-        const int64_t s = state_of_row(r, A, S);
-        const int T = sweep_tile_states(A);
-        const int64_t t0 = (s / T) * T;
-        const int64_t n = std::min<int64_t>(T, S - t0);
-        const int64_t ro = s * A + (r - t0 * A) / n;
-        rpn[r + 1] = rpn[r] + (rp32[ro + 1] - rp32[ro]);
-      }
-    }
     if (!permute) {
-      CHK(hipMemcpy(h->row_ptr, rp32.data(), (rows + 1) * sizeof(int32_t), hipMemcpyHostToDevice));
+      CHK(hipMemcpyAsync(h->row_ptr, rp32.data(), (rows + 1) * sizeof(int32_t), hipMemcpyHostToDevice,
+                         h->stream));
       CHK(hipMemcpyAsync(h->col, col, nnz * sizeof(int32_t), hipMemcpyDefault, h->stream));
       CHK(hipMemcpyAsync(h->val, val, nnz * sizeof(double), hipMemcpyDefault, h->stream));
       CHK(hipMemcpyAsync(h->cost, cost, rows * sizeof(double), hipMemcpyDefault, h->stream));
     } else {
-      CHK(hipMemcpy(h->row_ptr, rpn.data(), (rows + 1) * sizeof(int32_t), hipMemcpyHostToDevice));
-      int32_t *rp_old = nullptr, *col_old = nullptr;
-      double *val_old = nullptr, *cost_old = nullptr;
-      auto free_old = [&]() {
-        if (rp_old) (void)hipFree(rp_old);
-        if (col_old) (void)hipFree(col_old);
-        if (val_old) (void)hipFree(val_old);
-        if (cost_old) (void)hipFree(cost_old);
-      };
-      hipError_t e = hipMalloc(reinterpret_cast<void**>(&rp_old), (rows + 1) * sizeof(int32_t));
-      if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&col_old), nnz * sizeof(int32_t));
-      if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&val_old), nnz * sizeof(double));
-      if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&cost_old), rows * sizeof(double));
-      if (e == hipSuccess)
-        e = hipMemcpyAsync(rp_old, rp32.data(), (rows + 1) * sizeof(int32_t), hipMemcpyHostToDevice, h->stream);
+      auto up = [](size_t b) { return (b + 255) / 256 * 256; };
+      const size_t o_val = up(nnz * sizeof(int32_t));
+      const size_t o_cost = o_val + up(nnz * sizeof(double));
+      const size_t o_rp = o_cost + up(rows * sizeof(double));
+      const size_t bytes = o_rp + (rows + 1) * sizeof(int32_t);
+      char* stage = nullptr;
+      CHK(staging_alloc(h->device, h->stream, bytes, &stage));
+      auto* col_old = reinterpret_cast<int32_t*>(stage);
+      auto* val_old = reinterpret_cast<double*>(stage + o_val);
+      auto* cost_old = reinterpret_cast<double*>(stage + o_cost);
+      auto* rp_old = reinterpret_cast<int32_t*>(stage + o_rp);
+      hipError_t e = hipMemcpyAsync(rp_old, rp32.data(), (rows + 1) * sizeof(int32_t), hipMemcpyHostToDevice,
+                                    h->stream);
       if (e == hipSuccess) e = hipMemcpyAsync(col_old, col, nnz * sizeof(int32_t), hipMemcpyDefault, h->stream);
       if (e == hipSuccess) e = hipMemcpyAsync(val_old, val, nnz * sizeof(double), hipMemcpyDefault, h->stream);
       if (e == hipSuccess) e = hipMemcpyAsync(cost_old, cost, rows * sizeof(double), hipMemcpyDefault, h->stream);
       if (e == hipSuccess)
         e = launch_permute_rows(h->stream, S, A, rp_old, col_old, val_old, cost_old, h->row_ptr, h->col,
                                 h->val, h->cost);
-      if (e == hipSuccess) e = hipStreamSynchronize(h->stream);  // the host vectors and scratch go away
-      free_old();
+      const hipError_t ef = hipFreeAsync(stage, h->stream);  // after the kernel, in stream order
+      if (e == hipSuccess) e = ef;
       CHK(e);
     }
-    if (!permute) CHK(hipStreamSynchronize(h->stream));
+    CHK(hipStreamSynchronize(h->stream));  // the host vectors go away
   }
   h->maximize = o.objective == MDP_MAXIMIZE_REWARD;
   if (h->maximize) CHK(launch_negate(h->stream, h->cost, rows));  // rewards -> costs

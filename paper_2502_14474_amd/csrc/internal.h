@@ -206,10 +206,11 @@ __host__ __device__ inline int64_t state_of_row(int64_t r, int A, int64_t S) {
   return t0 + (r - t0 * A) % n;
 }
 
-// Copy natural-order rows (s*A + a) into the stored order (vecops.hip).
+// Copy natural-order rows (s*A + a) into the stored order and write the
+// stored row offsets rp_new[0..S*A] (vecops.hip).
 hipError_t launch_permute_rows(hipStream_t st, int64_t S, int A, const int32_t* rp_old,
                                const int32_t* col_old, const double* val_old,
-                               const double* cost_old, const int32_t* rp_new, int32_t* col_new,
+                               const double* cost_old, int32_t* rp_new, int32_t* col_new,
                                double* val_new, double* cost_new);
 size_t partials_doubles(int64_t S, int A, int m);
 

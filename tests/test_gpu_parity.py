@@ -100,6 +100,25 @@ def test_policy_apply_matches_oracle(name):
     assert np.max(np.abs(ones - (1 - inst.gamma))) <= 64 * EPS
 
 
+@pytest.mark.parametrize("S,A,density", [(700, 3, 0.3), (1000, 8, 0.02), (5, 512, 0.5), (3, 1024, 0.7),
+                                           (2, 1025, 0.7), (130, 7, 0.9)])
+def test_stored_row_order_shapes(S, A, density):
+    # Rows are copied into tiles of floor(1024/A) states, action-major inside a
+    # tile; these shapes cover full and ragged last tiles, tiles of 1023 and
+    # 1024 rows, one-state tiles, and rows longer than the copy's lane groups.
+    inst = random_dense_mdp(S, A, 0.9, seed=S + A, density=density)
+    rng = np.random.default_rng(S)
+    pi = rng.integers(0, A, S).astype(np.int32)
+    x = rng.standard_normal(S)
+    Ppi, gpi = oracle.policy_system(inst, pi)
+    k = np.diff(Ppi.indptr).astype(np.float64)
+    bnd = 2.0 * (k + 2) * EPS * (np.abs(x) + np.abs(gpi) + inst.gamma * np.max(np.abs(x)))
+    with _mdp(inst) as h:
+        _check_bellman(inst, h, x)
+        y1 = h.policy_apply(pi, x, mode=1)
+    assert np.all(np.abs(y1 - (gpi + inst.gamma * (Ppi @ x))) <= bnd)
+
+
 def test_policy_apply_rejects_bad_policy():
     import paper_2502_14474_amd as m
     inst = config1(S=50, seed=3)
