@@ -74,6 +74,15 @@ enum { MDP_MINIMIZE_COST = 0, MDP_MAXIMIZE_REWARD = 1 };
  * 1993; stops on its residual bound tau * sqrt(m + 1)). */
 enum { MDP_INNER_GMRES = 0, MDP_INNER_RICHARDSON = 1, MDP_INNER_BICGSTAB = 2, MDP_INNER_TFQMR = 3 };
 
+/* mdp_create_opts.validate.  row_ptr is checked on the host in every mode, before
+ * any kernel reads a row.  MDP_VALIDATE_NONE leaves the entries and costs
+ * unchecked; MDP_VALIDATE_HOST checks them on host threads (copying device inputs
+ * to the host first); MDP_VALIDATE_DEVICE checks them in a kernel over the
+ * uploaded copy, which spares the host a pass over the data.  The two checking
+ * modes reject the same inputs with the same messages: the row-sum test adds a
+ * row's entries in order on either side. */
+enum { MDP_VALIDATE_NONE = 0, MDP_VALIDATE_HOST = 1, MDP_VALIDATE_DEVICE = 2 };
+
 /* Bits of mdp_create_opts.low_precision: which reduced-precision copies of P to build. */
 enum { MDP_BUILD_FP32 = 1, MDP_BUILD_FP16 = 2 };
 
@@ -81,7 +90,7 @@ typedef struct {
   size_t struct_size;     /* sizeof(mdp_create_opts) */
   void* stream;           /* hipStream_t to run on; NULL: the handle creates its own stream */
   int32_t device;         /* HIP device ordinal; -1: the current device */
-  int32_t validate;       /* nonzero: check the MDP data (see the layout above) */
+  int32_t validate;       /* MDP_VALIDATE_*: check the MDP data (see the layout above) */
   int32_t low_precision;  /* MDP_BUILD_* bits */
   int32_t lanes_per_row;  /* 0: chosen from the mean row length; else 1,2,4,...,64 */
   int32_t col_blocks;     /* column-blocked copy of P for the float64 sweep: -1 (default)

@@ -11,6 +11,7 @@ import numpy as np
 from . import native
 from .native import (MDP_FP64, MDP_MIXED_FP32, MDP_MIXED_FP16, MDP_INNER_GMRES,  # noqa: F401
                      MDP_INNER_RICHARDSON, MDP_INNER_BICGSTAB, MDP_INNER_TFQMR, MDP_MINIMIZE_COST, MDP_MAXIMIZE_REWARD,
+                     MDP_VALIDATE_NONE, MDP_VALIDATE_HOST, MDP_VALIDATE_DEVICE,
                      MDP_BUILD_FP32, MDP_BUILD_FP16, MDP_OK,
                      MDP_W_MAXITER, MDPError)
 
@@ -45,11 +46,21 @@ def mdp_last_error():
     return native.load().mdp_last_error().decode()
 
 
+def _validate_mode(validate):
+    """True/False, or one of "host", "device", "none" (MDP_VALIDATE_*)."""
+    modes = {True: native.MDP_VALIDATE_HOST, False: native.MDP_VALIDATE_NONE,
+             "host": native.MDP_VALIDATE_HOST, "device": native.MDP_VALIDATE_DEVICE,
+             "none": native.MDP_VALIDATE_NONE}
+    if validate not in modes:
+        raise ValueError(f"validate must be True, False, 'host', 'device' or 'none', not {validate!r}")
+    return modes[validate]
+
+
 def mdp_create(S, A, row_ptr, col, val, cost, gamma, stream=None, device=-1, validate=True,
                low_precision=0, lanes_per_row=0, col_blocks=-1, objective=0):
     """objective: native.MDP_MINIMIZE_COST (cost holds costs) or
     native.MDP_MAXIMIZE_REWARD (cost holds rewards; values come back in
-    reward terms)."""
+    reward terms).  validate: see _validate_mode."""
     lib = native.load()
     o = native.CreateOpts()
     lib.mdp_default_create_opts(C.byref(o))
@@ -57,7 +68,7 @@ def mdp_create(S, A, row_ptr, col, val, cost, gamma, stream=None, device=-1, val
     o.objective = objective
     o.stream = stream
     o.device = device
-    o.validate = 1 if validate else 0
+    o.validate = _validate_mode(validate)
     o.low_precision = low_precision
     o.lanes_per_row = lanes_per_row
     h = C.c_void_p()
@@ -79,7 +90,7 @@ def mdp_create_from_rows(S, A, k_max, fn, gamma, stream=None, device=-1, validat
     lib = native.load()
     o = native.CreateOpts()
     lib.mdp_default_create_opts(C.byref(o))
-    o.stream, o.device, o.validate = stream, device, 1 if validate else 0
+    o.stream, o.device, o.validate = stream, device, _validate_mode(validate)
     o.low_precision, o.lanes_per_row = low_precision, lanes_per_row
     o.col_blocks, o.objective = col_blocks, objective
 

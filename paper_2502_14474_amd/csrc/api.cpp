@@ -16,6 +16,181 @@
 
 namespace mdp {
 
+std::shared_mutex& alloc_lock() {
+  static std::shared_mutex mu;
+  return mu;
+}
+
+hipError_t lib_malloc(void** p, size_t bytes) {
+  std::shared_lock<std::shared_mutex> g(alloc_lock());
+  return hipMalloc(p, bytes);
+}
+
+void lib_free(void* p) {
+  if (!p) return;
+  std::shared_lock<std::shared_mutex> g(alloc_lock());
+  (void)hipFree(p);
+}
+
+hipError_t lib_host_malloc(void** p, size_t bytes) {
+  std::shared_lock<std::shared_mutex> g(alloc_lock());
+  return hipHostMalloc(p, bytes, hipHostMallocDefault);
+}
+
+void lib_host_free(void* p) {
+  if (!p) return;
+  std::shared_lock<std::shared_mutex> g(alloc_lock());
+  (void)hipHostFree(p);
+}
+
+// Device memory of handles, and staging memory at create time, come from a
+// stream-ordered pool that the library creates once per device and keeps
+// until the process ends.  hipFree waits for the whole device, so a server
+// retiring a request would wait for the solves running beside it, and each
+// unmapping is slow; the pool frees in stream order and keeps freed memory for
+// the next handle, up to a release threshold of kPoolKeepBytes plus what live
+// servers reserve (their HBM budgets).
+constexpr uint64_t kPoolKeepBytes = uint64_t{2} << 30;
+
+namespace {
+struct DevicePool {
+  hipMemPool_t pool = nullptr;
+  uint64_t reserved = 0;
+};
+std::mutex g_pool_mu;
+std::vector<DevicePool> g_pools;
+
+hipError_t pool_locked(int dev, DevicePool** out) {
+  if (dev < 0) return hipErrorInvalidDevice;
+  if (g_pools.size() <= static_cast<size_t>(dev)) g_pools.resize(dev + 1);
+  DevicePool& d = g_pools[dev];
+  if (!d.pool) {
+    hipMemPoolProps props;
+    std::memset(&props, 0, sizeof(props));
+    props.allocType = hipMemAllocationTypePinned;
+    props.handleTypes = hipMemHandleTypeNone;
+    props.location.type = hipMemLocationTypeDevice;
+    props.location.id = dev;
+    hipMemPool_t p = nullptr;
+    hipError_t e = hipMemPoolCreate(&p, &props);
+    if (e != hipSuccess) return e;
+    uint64_t keep = kPoolKeepBytes;
+    e = hipMemPoolSetAttribute(p, hipMemPoolAttrReleaseThreshold, &keep);
+    if (e != hipSuccess) {
+      (void)hipMemPoolDestroy(p);
+      return e;
+    }
+    d.pool = p;
+  }
+  *out = &d;
+  return hipSuccess;
+}
+}  // namespace
+
+hipError_t device_pool(int dev, hipMemPool_t* out) {
+  std::lock_guard<std::mutex> lk(g_pool_mu);
+  DevicePool* d = nullptr;
+  hipError_t e = pool_locked(dev, &d);
+  if (e == hipSuccess) *out = d->pool;
+  return e;
+}
+
+hipError_t pool_reserve(int dev, int64_t delta) {
+  std::lock_guard<std::mutex> lk(g_pool_mu);
+  DevicePool* d = nullptr;
+  hipError_t e = pool_locked(dev, &d);
+  if (e != hipSuccess) return e;
+  d->reserved = static_cast<uint64_t>(std::max<int64_t>(0, static_cast<int64_t>(d->reserved) + delta));
+  uint64_t keep = kPoolKeepBytes + d->reserved;
+  e = hipMemPoolSetAttribute(d->pool, hipMemPoolAttrReleaseThreshold, &keep);
+  if (e == hipSuccess && delta < 0) e = hipMemPoolTrimTo(d->pool, static_cast<size_t>(keep));
+  return e;
+}
+
+hipError_t handle_alloc(mdp_handle* h, void** p, size_t bytes) {
+  hipMemPool_t pool = nullptr;
+  hipError_t e = device_pool(h->device, &pool);
+  if (e != hipSuccess) return e;
+  {
+    std::shared_lock<std::shared_mutex> g(alloc_lock());
+    e = hipMallocFromPoolAsync(p, std::max<size_t>(bytes, 1), pool, h->stream);
+  }
+  // after this, the memory may be used from any stream
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (e == hipSuccess && (reinterpret_cast<uintptr_t>(*p) & 255) != 0) {
+    handle_free(h, *p);
+    *p = nullptr;
+    e = hipErrorInvalidValue;  // the kernels assume 256-byte aligned arrays
+  }
+  return e;
+}
+
+void handle_free(mdp_handle* h, void* p) {
+  if (!p) return;
+  std::shared_lock<std::shared_mutex> g(alloc_lock());
+  (void)hipFreeAsync(p, h->stream);
+}
+
+// Streams of handles are recycled per device, and the pinned host mirrors of
+// their control blocks come from slabs kept until the process ends: stream
+// creation and destruction cost a few hundred microseconds each, and
+// hipHostFree waits for the device, which would hold a server's retirement
+// behind the solves running beside it.
+constexpr size_t kMaxCachedStreams = 64;
+constexpr int kCtlSlab = 256;
+
+namespace {
+std::mutex g_recycle_mu;
+std::vector<std::vector<hipStream_t>> g_streams;
+std::vector<Ctl*> g_ctl_free;
+}  // namespace
+
+hipError_t stream_take(int dev, hipStream_t* out) {
+  {
+    std::lock_guard<std::mutex> lk(g_recycle_mu);
+    if (dev >= 0 && static_cast<size_t>(dev) < g_streams.size() && !g_streams[dev].empty()) {
+      *out = g_streams[dev].back();
+      g_streams[dev].pop_back();
+      return hipSuccess;
+    }
+  }
+  std::shared_lock<std::shared_mutex> g(alloc_lock());
+  return hipStreamCreateWithFlags(out, hipStreamNonBlocking);
+}
+
+void stream_give(int dev, hipStream_t st) {
+  {
+    std::lock_guard<std::mutex> lk(g_recycle_mu);
+    if (dev >= 0) {
+      if (g_streams.size() <= static_cast<size_t>(dev)) g_streams.resize(dev + 1);
+      if (g_streams[dev].size() < kMaxCachedStreams) {
+        g_streams[dev].push_back(st);
+        return;
+      }
+    }
+  }
+  std::shared_lock<std::shared_mutex> g(alloc_lock());
+  (void)hipStreamDestroy(st);
+}
+
+Ctl* ctl_slot_take() {
+  std::lock_guard<std::mutex> lk(g_recycle_mu);
+  if (g_ctl_free.empty()) {
+    void* slab = nullptr;
+    if (lib_host_malloc(&slab, sizeof(Ctl) * kCtlSlab) != hipSuccess) return nullptr;
+    for (int i = kCtlSlab - 1; i >= 0; --i) g_ctl_free.push_back(static_cast<Ctl*>(slab) + i);
+  }
+  Ctl* c = g_ctl_free.back();
+  g_ctl_free.pop_back();
+  return c;
+}
+
+void ctl_slot_give(Ctl* c) {
+  if (!c) return;
+  std::lock_guard<std::mutex> lk(g_recycle_mu);
+  g_ctl_free.push_back(c);
+}
+
 namespace {
 thread_local std::string g_err;
 
@@ -39,52 +214,28 @@ double now_ms() {
 template <typename T>
 hipError_t dev_alloc(mdp_handle* h, T** p, size_t n) {
   const size_t bytes = std::max<size_t>(1, n) * sizeof(T);
-  hipError_t e = hipMalloc(reinterpret_cast<void**>(p), bytes);
+  hipError_t e = handle_alloc(h, reinterpret_cast<void**>(p), bytes);
   if (e == hipSuccess) h->device_bytes += static_cast<int64_t>(bytes);
   return e;
 }
 
 template <typename T>
-void dev_free(T*& p) {
-  if (p) (void)hipFree(p);
+void dev_free(mdp_handle* h, T*& p) {
+  handle_free(h, p);
   p = nullptr;
 }
 
-// Staging memory for uploads at create time comes from a stream-ordered pool
-// that the library creates once per device and keeps until the process ends.
-// hipFree waits for the whole device, which would hold a create (a server
-// admission) behind the solves running beside it; the pool frees in stream
-// order and keeps up to kStagingKeepBytes cached between creates.
-constexpr uint64_t kStagingKeepBytes = uint64_t{2} << 30;
-
 hipError_t staging_alloc(int dev, hipStream_t st, size_t bytes, char** out) {
-  static std::mutex mu;
-  static std::vector<hipMemPool_t> pools;
   hipMemPool_t pool = nullptr;
-  {
-    std::lock_guard<std::mutex> lk(mu);
-    if (pools.size() <= static_cast<size_t>(dev)) pools.resize(dev + 1, nullptr);
-    if (!pools[dev]) {
-      hipMemPoolProps props;
-      std::memset(&props, 0, sizeof(props));
-      props.allocType = hipMemAllocationTypePinned;
-      props.handleTypes = hipMemHandleTypeNone;
-      props.location.type = hipMemLocationTypeDevice;
-      props.location.id = dev;
-      hipMemPool_t p = nullptr;
-      hipError_t e = hipMemPoolCreate(&p, &props);
-      if (e != hipSuccess) return e;
-      uint64_t keep = kStagingKeepBytes;
-      e = hipMemPoolSetAttribute(p, hipMemPoolAttrReleaseThreshold, &keep);
-      if (e != hipSuccess) {
-        (void)hipMemPoolDestroy(p);
-        return e;
-      }
-      pools[dev] = p;
-    }
-    pool = pools[dev];
-  }
+  hipError_t e = device_pool(dev, &pool);
+  if (e != hipSuccess) return e;
+  std::shared_lock<std::shared_mutex> g(alloc_lock());
   return hipMallocFromPoolAsync(reinterpret_cast<void**>(out), std::max<size_t>(bytes, 1), pool, st);
+}
+
+hipError_t staging_free(char* p, hipStream_t st) {
+  std::shared_lock<std::shared_mutex> g(alloc_lock());
+  return hipFreeAsync(p, st);
 }
 
 // Copy a caller policy to device memory and check its range.
@@ -297,19 +448,35 @@ bool stats_ok(const mdp_stats* st) { return !st || st->struct_size >= sizeof(mdp
 
 }  // namespace
 
-// ---- validation on host arrays ----------------------------------------------
-mdp_status validate_host(int64_t S, int32_t A, const int64_t* rp, const int32_t* col,
-                         const double* val, const double* cost) {
+// ---- validation -------------------------------------------------------------
+// Structure of row_ptr; checked in every mode, since kernels index rows by it.
+mdp_status validate_row_ptr(int64_t S, int32_t A, const int64_t* rp) {
   const int64_t rows = S * A;
   if (rp[0] != 0) return fail(MDP_E_INVAL, "row_ptr[0] must be 0");
   for (int64_t r = 0; r < rows; ++r)
     if (rp[r + 1] <= rp[r])
       return fail(MDP_E_INVAL, "row_ptr must increase (row " + std::to_string(r) +
                                    " of state " + std::to_string(r / A) + " is empty or decreasing)");
-  const int64_t nnz = rp[rows];
-  if (nnz >= (int64_t{1} << 31)) return fail(MDP_E_NOTSUP, "nnz must be below 2^31");
+  if (rp[rows] >= (int64_t{1} << 31)) return fail(MDP_E_NOTSUP, "nnz must be below 2^31");
+  return MDP_OK;
+}
+
+// The first failure of the entry checks, as a message; shared by the host and
+// device checks so that both report alike.  why: 1 column, 2 probability, 3 sum.
+mdp_status entry_failure(int64_t cost_row, int64_t entry_row, int why) {
+  if (cost_row >= 0) return fail(MDP_E_INVAL, "non-finite cost at row " + std::to_string(cost_row));
+  const char* w = why == 1 ? "column index outside [0,S)"
+                  : why == 2 ? "negative or non-finite probability"
+                             : "row does not sum to 1";
+  return fail(MDP_E_INVAL, std::string(w) + " in row " + std::to_string(entry_row));
+}
+
+// Entries and costs on host arrays (row_ptr already checked).
+mdp_status validate_entries_host(int64_t S, int32_t A, const int64_t* rp, const int32_t* col,
+                                 const double* val, const double* cost) {
+  const int64_t rows = S * A;
   for (int64_t r = 0; r < rows; ++r)
-    if (!std::isfinite(cost[r])) return fail(MDP_E_INVAL, "non-finite cost at row " + std::to_string(r));
+    if (!std::isfinite(cost[r])) return entry_failure(r, -1, 0);
   const unsigned nt = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
   std::vector<int64_t> bad(nt, -1);
   std::vector<int> why(nt, 0);
@@ -330,14 +497,15 @@ mdp_status validate_host(int64_t S, int32_t A, const int64_t* rp, const int32_t*
     });
   }
   for (auto& x : th) x.join();
-  for (unsigned t = 0; t < nt; ++t) {
-    if (bad[t] < 0) continue;
-    const char* w = why[t] == 1 ? "column index outside [0,S)"
-                    : why[t] == 2 ? "negative or non-finite probability"
-                                  : "row does not sum to 1";
-    return fail(MDP_E_INVAL, std::string(w) + " in row " + std::to_string(bad[t]));
-  }
+  for (unsigned t = 0; t < nt; ++t)
+    if (bad[t] >= 0) return entry_failure(-1, bad[t], why[t]);
   return MDP_OK;
+}
+
+mdp_status validate_host(int64_t S, int32_t A, const int64_t* rp, const int32_t* col,
+                         const double* val, const double* cost) {
+  MDP_TRY(validate_row_ptr(S, A, rp));
+  return validate_entries_host(S, A, rp, col, val, cost);
 }
 
 bool is_device_ptr(const void* p) {
@@ -371,12 +539,12 @@ mdp_status ctl_wait(mdp_handle* h) {
 mdp_status ensure_basis(mdp_handle* h, Prec prec, int m) {
   if (prec == kF64) {
     if (h->basis_m64 >= m) return MDP_OK;
-    dev_free(h->U64);
+    dev_free(h, h->U64);
     MDP_HIP(dev_alloc(h, &h->U64, static_cast<size_t>(m + 1) * h->ldu));
     h->basis_m64 = m;
   } else {
     if (h->basis_m32 >= m) return MDP_OK;
-    dev_free(h->U32);
+    dev_free(h, h->U32);
     MDP_HIP(dev_alloc(h, &h->U32, static_cast<size_t>(m + 1) * h->ldu));
     h->basis_m32 = m;
   }
@@ -537,37 +705,48 @@ void mdp_default_solve_opts(mdp_solve_opts* o) {
 mdp_status mdp_destroy(mdp_t h) {
   if (!h) return MDP_OK;
   if (h->stream) (void)hipStreamSynchronize(h->stream);
-  dev_free(h->row_ptr);
-  dev_free(h->col);
-  dev_free(h->val);
-  dev_free(h->cost);
-  dev_free(h->val32);
-  dev_free(h->val16);
-  dev_free(h->corr16);
-  dev_free(h->cost32);
-  dev_free(h->cb_col);
-  dev_free(h->cb_val);
-  dev_free(h->cb_rel);
-  dev_free(h->cb_off);
-  dev_free(h->cb_acc);
-  dev_free(h->v);
-  dev_free(h->Tv);
-  dev_free(h->x2);
-  dev_free(h->io);
-  dev_free(h->pi);
-  dev_free(h->pi_io);
-  dev_free(h->v32);
-  dev_free(h->x32a);
-  dev_free(h->x32b);
-  dev_free(h->U64);
-  dev_free(h->U32);
-  dev_free(h->part.buf);
-  dev_free(h->ctl);
-  if (h->ctl_host) (void)hipHostFree(h->ctl_host);
-  if (h->ctl_event) (void)hipEventDestroy(h->ctl_event);
+  dev_free(h, h->row_ptr);
+  dev_free(h, h->col);
+  dev_free(h, h->val);
+  dev_free(h, h->cost);
+  dev_free(h, h->val32);
+  dev_free(h, h->val16);
+  dev_free(h, h->corr16);
+  dev_free(h, h->cost32);
+  dev_free(h, h->cb_col);
+  dev_free(h, h->cb_val);
+  dev_free(h, h->cb_rel);
+  dev_free(h, h->cb_off);
+  dev_free(h, h->cb_acc);
+  dev_free(h, h->v);
+  dev_free(h, h->Tv);
+  dev_free(h, h->x2);
+  dev_free(h, h->io);
+  dev_free(h, h->pi);
+  dev_free(h, h->pi_io);
+  dev_free(h, h->v32);
+  dev_free(h, h->x32a);
+  dev_free(h, h->x32b);
+  dev_free(h, h->U64);
+  dev_free(h, h->U32);
+  dev_free(h, h->part.buf);
+  dev_free(h, h->ctl);
+  ctl_slot_give(h->ctl_host);
   prof_resolve(h);
-  for (auto e : h->prof_pool) (void)hipEventDestroy(e);
-  if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
+  {
+    std::shared_lock<std::shared_mutex> g(alloc_lock());
+    if (h->ctl_event) (void)hipEventDestroy(h->ctl_event);
+    for (auto e : h->prof_pool) (void)hipEventDestroy(e);
+  }
+  if (h->own_stream && h->stream) {
+    // idle once the frees queued on it have run; the next handle may reuse it
+    if (hipStreamSynchronize(h->stream) == hipSuccess) {
+      stream_give(h->device, h->stream);
+    } else {
+      std::shared_lock<std::shared_mutex> g(alloc_lock());
+      (void)hipStreamDestroy(h->stream);
+    }
+  }
   delete h;
   return MDP_OK;
 }
@@ -597,6 +776,8 @@ mdp_status mdp_create(int64_t S, int32_t A, const int64_t* row_ptr, const int32_
     return fail(MDP_E_INVAL, "unknown low_precision bits");
   if (o.objective != MDP_MINIMIZE_COST && o.objective != MDP_MAXIMIZE_REWARD)
     return fail(MDP_E_INVAL, "unknown objective");
+  if (o.validate < MDP_VALIDATE_NONE || o.validate > MDP_VALIDATE_DEVICE)
+    return fail(MDP_E_INVAL, "validate must be MDP_VALIDATE_NONE, _HOST or _DEVICE");
   if (o.col_blocks < -1 || o.col_blocks > kMaxColBlocks)
     return fail(MDP_E_INVAL, "col_blocks must be -1, 0 or 1.." + std::to_string(kMaxColBlocks));
   const int64_t rows = S * A;
@@ -615,16 +796,17 @@ mdp_status mdp_create(int64_t S, int32_t A, const int64_t* row_ptr, const int32_
   nnz = rp_host[rows];
   if (nnz < rows) return fail(MDP_E_INVAL, "row_ptr[S*A] smaller than the number of rows");
   if (nnz >= (int64_t{1} << 31)) return fail(MDP_E_NOTSUP, "nnz must be below 2^31");
-  if (o.validate) {
+  MDP_TRY(validate_row_ptr(S, A, rp_host));
+  if (o.validate == MDP_VALIDATE_HOST) {
     if (dev_in) {
       std::vector<int32_t> c(nnz);
       std::vector<double> v(nnz), g(rows);
       MDP_HIP(hipMemcpy(c.data(), col, nnz * sizeof(int32_t), hipMemcpyDefault));
       MDP_HIP(hipMemcpy(v.data(), val, nnz * sizeof(double), hipMemcpyDefault));
       MDP_HIP(hipMemcpy(g.data(), cost, rows * sizeof(double), hipMemcpyDefault));
-      MDP_TRY(validate_host(S, A, rp_host, c.data(), v.data(), g.data()));
+      MDP_TRY(validate_entries_host(S, A, rp_host, c.data(), v.data(), g.data()));
     } else {
-      MDP_TRY(validate_host(S, A, rp_host, col, val, cost));
+      MDP_TRY(validate_entries_host(S, A, rp_host, col, val, cost));
     }
   }
 
@@ -663,7 +845,7 @@ mdp_status mdp_create(int64_t S, int32_t A, const int64_t* row_ptr, const int32_
   if (o.stream) {
     h->stream = static_cast<hipStream_t>(o.stream);
   } else {
-    CHK(hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking));
+    CHK(stream_take(h->device, &h->stream));
     h->own_stream = true;
   }
   h->ldu = (S + 255) / 256 * 256;
@@ -673,41 +855,63 @@ mdp_status mdp_create(int64_t S, int32_t A, const int64_t* row_ptr, const int32_
   CHK(dev_alloc(h, &h->cost, rows));
   // Rows are stored in the tile-by-tile, action-major order of row_of():
   // the natural arrays go to a staging block and one kernel moves them.
+  // Device validation reads the natural arrays before they move.
   const bool permute = A > 1 && sweep_tile_states(A) > 1;
   {
     std::vector<int32_t> rp32(rows + 1);
     for (int64_t r = 0; r <= rows; ++r) rp32[r] = static_cast<int32_t>(rp_host[r]);
-    if (!permute) {
-      CHK(hipMemcpyAsync(h->row_ptr, rp32.data(), (rows + 1) * sizeof(int32_t), hipMemcpyHostToDevice,
-                         h->stream));
-      CHK(hipMemcpyAsync(h->col, col, nnz * sizeof(int32_t), hipMemcpyDefault, h->stream));
-      CHK(hipMemcpyAsync(h->val, val, nnz * sizeof(double), hipMemcpyDefault, h->stream));
-      CHK(hipMemcpyAsync(h->cost, cost, rows * sizeof(double), hipMemcpyDefault, h->stream));
-    } else {
-      auto up = [](size_t b) { return (b + 255) / 256 * 256; };
-      const size_t o_val = up(nnz * sizeof(int32_t));
-      const size_t o_cost = o_val + up(nnz * sizeof(double));
-      const size_t o_rp = o_cost + up(rows * sizeof(double));
-      const size_t bytes = o_rp + (rows + 1) * sizeof(int32_t);
-      char* stage = nullptr;
-      CHK(staging_alloc(h->device, h->stream, bytes, &stage));
-      auto* col_old = reinterpret_cast<int32_t*>(stage);
-      auto* val_old = reinterpret_cast<double*>(stage + o_val);
-      auto* cost_old = reinterpret_cast<double*>(stage + o_cost);
-      auto* rp_old = reinterpret_cast<int32_t*>(stage + o_rp);
-      hipError_t e = hipMemcpyAsync(rp_old, rp32.data(), (rows + 1) * sizeof(int32_t), hipMemcpyHostToDevice,
-                                    h->stream);
-      if (e == hipSuccess) e = hipMemcpyAsync(col_old, col, nnz * sizeof(int32_t), hipMemcpyDefault, h->stream);
-      if (e == hipSuccess) e = hipMemcpyAsync(val_old, val, nnz * sizeof(double), hipMemcpyDefault, h->stream);
-      if (e == hipSuccess) e = hipMemcpyAsync(cost_old, cost, rows * sizeof(double), hipMemcpyDefault, h->stream);
+    // staging: [verdicts | natural col | val | cost | row_ptr]; natural
+    // arrays only when the rows are permuted
+    auto up = [](size_t b) { return (b + 255) / 256 * 256; };
+    const bool on_dev = o.validate == MDP_VALIDATE_DEVICE;
+    const int vblocks = on_dev ? validate_blocks(rows) : 0;
+    const size_t o_col = up(static_cast<size_t>(vblocks) * 3 * sizeof(int64_t));
+    const size_t o_val = o_col + up(nnz * sizeof(int32_t));
+    const size_t o_cost = o_val + up(nnz * sizeof(double));
+    const size_t o_rp = o_cost + up(rows * sizeof(double));
+    const size_t bytes = permute ? o_rp + (rows + 1) * sizeof(int32_t) : o_col;
+    char* stage = nullptr;
+    if (bytes > 0) CHK(staging_alloc(h->device, h->stream, bytes, &stage));
+    int32_t* rp_nat = permute ? reinterpret_cast<int32_t*>(stage + o_rp) : h->row_ptr;
+    int32_t* col_nat = permute ? reinterpret_cast<int32_t*>(stage + o_col) : h->col;
+    double* val_nat = permute ? reinterpret_cast<double*>(stage + o_val) : h->val;
+    double* cost_nat = permute ? reinterpret_cast<double*>(stage + o_cost) : h->cost;
+    std::vector<int64_t> verdict(static_cast<size_t>(vblocks) * 3);
+    hipError_t e = hipMemcpyAsync(rp_nat, rp32.data(), (rows + 1) * sizeof(int32_t), hipMemcpyHostToDevice,
+                                  h->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(col_nat, col, nnz * sizeof(int32_t), hipMemcpyDefault, h->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(val_nat, val, nnz * sizeof(double), hipMemcpyDefault, h->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(cost_nat, cost, rows * sizeof(double), hipMemcpyDefault, h->stream);
+    if (e == hipSuccess && on_dev) {
+      auto* vd = reinterpret_cast<int64_t*>(stage);
+      e = launch_validate(h->stream, S, rows, rp_nat, col_nat, val_nat, cost_nat, vd, vblocks);
       if (e == hipSuccess)
-        e = launch_permute_rows(h->stream, S, A, rp_old, col_old, val_old, cost_old, h->row_ptr, h->col,
-                                h->val, h->cost);
-      const hipError_t ef = hipFreeAsync(stage, h->stream);  // after the kernel, in stream order
-      if (e == hipSuccess) e = ef;
-      CHK(e);
+        e = hipMemcpyAsync(verdict.data(), vd, verdict.size() * sizeof(int64_t), hipMemcpyDeviceToHost,
+                           h->stream);
     }
-    CHK(hipStreamSynchronize(h->stream));  // the host vectors go away
+    // moving rows is safe before the verdict: row_ptr was checked on the host
+    if (e == hipSuccess && permute)
+      e = launch_permute_rows(h->stream, S, A, rp_nat, col_nat, val_nat, cost_nat, h->row_ptr, h->col,
+                              h->val, h->cost);
+    if (stage) {
+      const hipError_t ef = staging_free(stage, h->stream);  // after the kernels, in stream order
+      if (e == hipSuccess) e = ef;
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);  // the host vectors go away
+    CHK(e);
+    if (on_dev) {
+      int64_t cost_row = -1, entry_row = -1;
+      int why = 0;
+      for (int b = 0; b < vblocks; ++b) {
+        const int64_t* q = &verdict[static_cast<size_t>(b) * 3];
+        if (q[0] >= 0 && (cost_row < 0 || q[0] < cost_row)) cost_row = q[0];
+        if (q[1] >= 0 && (entry_row < 0 || q[1] < entry_row)) {
+          entry_row = q[1];
+          why = static_cast<int>(q[2]);
+        }
+      }
+      if (cost_row >= 0 || entry_row >= 0) return bail(entry_failure(cost_row, entry_row, why));
+    }
   }
   h->maximize = o.objective == MDP_MAXIMIZE_REWARD;
   if (h->maximize) CHK(launch_negate(h->stream, h->cost, rows));  // rewards -> costs
@@ -720,8 +924,16 @@ mdp_status mdp_create(int64_t S, int32_t A, const int64_t* row_ptr, const int32_
   h->part.cap = partials_doubles(S, A, kMaxRestart);
   CHK(dev_alloc(h, &h->part.buf, h->part.cap));
   CHK(dev_alloc(h, &h->ctl, 1));
-  CHK(hipHostMalloc(reinterpret_cast<void**>(&h->ctl_host), sizeof(Ctl), hipHostMallocDefault));
-  CHK(hipEventCreateWithFlags(&h->ctl_event, hipEventDisableTiming));
+  h->ctl_host = ctl_slot_take();
+  if (!h->ctl_host) CHK(hipErrorOutOfMemory);
+  {
+    hipError_t e = hipSuccess;
+    {
+      std::shared_lock<std::shared_mutex> g(alloc_lock());
+      e = hipEventCreateWithFlags(&h->ctl_event, hipEventDisableTiming);
+    }
+    CHK(e);
+  }
   std::memset(h->ctl_host, 0, sizeof(Ctl));
   CHK(hipMemsetAsync(h->ctl, 0, sizeof(Ctl), h->stream));
   if (o.low_precision & MDP_BUILD_FP32) {

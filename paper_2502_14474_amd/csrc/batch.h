@@ -95,10 +95,6 @@ class BatchEngine {
   hipStream_t stream = nullptr;
   Prec prec = kF64;
   bool use_graphs = true;
-  // Held exclusively while a graph is captured: threads that allocate or
-  // free device or pinned memory take it shared, since such calls from
-  // another thread can invalidate a capture in progress.
-  std::shared_mutex* capture_lock = nullptr;
   std::vector<BatchItem*> items;
 
   ~BatchEngine();

@@ -257,12 +257,12 @@ void BatchEngine::release() {
     for (auto& e : g.second.exec) (void)hipGraphExecDestroy(e);
   }
   graphs.clear();
-  if (descs_d) (void)hipFree(descs_d);
-  if (lists_d) (void)hipFree(lists_d);
-  if (hdr_d) (void)hipFree(hdr_d);
-  if (hdr_h) (void)hipHostFree(hdr_h);
-  if (lists_h) (void)hipHostFree(lists_h);
-  if (descs_h) (void)hipHostFree(descs_h);
+  lib_free(descs_d);
+  lib_free(lists_d);
+  lib_free(hdr_d);
+  lib_host_free(hdr_h);
+  lib_host_free(lists_h);
+  lib_host_free(descs_h);
   descs_h = nullptr;
   descs_d = nullptr;
   lists_d = nullptr;
@@ -277,14 +277,12 @@ mdp_status BatchEngine::reserve(int n) {
   release();
   cap = std::max(n, 16);
   const size_t list_bytes = WorkList::bytes(cap);
-  MDP_HIP(hipMalloc(reinterpret_cast<void**>(&descs_d), sizeof(BDesc) * cap));
-  MDP_HIP(hipMalloc(reinterpret_cast<void**>(&lists_d), list_bytes * kNumLists));
-  MDP_HIP(hipMalloc(reinterpret_cast<void**>(&hdr_d), sizeof(Ctl) * cap));
-  MDP_HIP(hipHostMalloc(reinterpret_cast<void**>(&hdr_h), sizeof(Ctl) * cap, hipHostMallocDefault));
-  MDP_HIP(hipHostMalloc(reinterpret_cast<void**>(&lists_h), list_bytes * kNumLists,
-                        hipHostMallocDefault));
-  MDP_HIP(hipHostMalloc(reinterpret_cast<void**>(&descs_h), sizeof(BDesc) * cap,
-                        hipHostMallocDefault));
+  MDP_HIP(lib_malloc(reinterpret_cast<void**>(&descs_d), sizeof(BDesc) * cap));
+  MDP_HIP(lib_malloc(reinterpret_cast<void**>(&lists_d), list_bytes * kNumLists));
+  MDP_HIP(lib_malloc(reinterpret_cast<void**>(&hdr_d), sizeof(Ctl) * cap));
+  MDP_HIP(lib_host_malloc(reinterpret_cast<void**>(&hdr_h), sizeof(Ctl) * cap));
+  MDP_HIP(lib_host_malloc(reinterpret_cast<void**>(&lists_h), list_bytes * kNumLists));
+  MDP_HIP(lib_host_malloc(reinterpret_cast<void**>(&descs_h), sizeof(BDesc) * cap));
   std::memset(descs_h, 0, sizeof(BDesc) * cap);
   return MDP_OK;
 }
@@ -533,8 +531,7 @@ mdp_status BatchEngine::cycle_phase(const mdp_solve_opts& o, std::vector<int>& g
   GraphKey key{static_cast<int>(prec), lanes, m, se};
   auto git = graphs.find(key);
   if (use_graphs && git == graphs.end()) {
-    std::unique_lock<std::shared_mutex> cap_guard;
-    if (capture_lock) cap_guard = std::unique_lock<std::shared_mutex>(*capture_lock);
+    std::unique_lock<std::shared_mutex> cap_guard(alloc_lock());
     ChunkGraphs cg;
     for (int j0 = 0; j0 < m; j0 += se) {
       hipGraph_t g;

@@ -257,15 +257,15 @@ hipError_t build_colblocks(mdp_handle* h, int blocks, bool require, bool* built,
   double* acc = nullptr;
   auto done = [&](hipError_t r) {
     (void)hipStreamSynchronize(h->stream);
-    if (scratch) (void)hipFree(scratch);
-    if (tsum) (void)hipFree(tsum);
-    if (cnt) (void)hipFree(cnt);
+    if (scratch) handle_free(h, scratch);
+    if (tsum) handle_free(h, tsum);
+    if (cnt) handle_free(h, cnt);
     if (!*built) {
-      if (off) (void)hipFree(off);
-      if (rel) (void)hipFree(rel);
-      if (cb_col) (void)hipFree(cb_col);
-      if (cb_val) (void)hipFree(cb_val);
-      if (acc) (void)hipFree(acc);
+      if (off) handle_free(h, off);
+      if (rel) handle_free(h, rel);
+      if (cb_col) handle_free(h, cb_col);
+      if (cb_val) handle_free(h, cb_val);
+      if (acc) handle_free(h, acc);
     }
     return r;
   };
@@ -275,8 +275,8 @@ hipError_t build_colblocks(mdp_handle* h, int blocks, bool require, bool* built,
     if ((e = (call)) != hipSuccess) return done(e); \
   } while (0)
   const size_t cnt_bytes = static_cast<size_t>(blocks) * rows;
-  CB_CHK(hipMalloc(reinterpret_cast<void**>(&cnt), cnt_bytes));
-  CB_CHK(hipMalloc(&scratch, 16));
+  CB_CHK(handle_alloc(h, reinterpret_cast<void**>(&cnt), cnt_bytes));
+  CB_CHK(handle_alloc(h, &scratch, 16));
   CB_CHK(hipMemsetAsync(cnt, 0, cnt_bytes, h->stream));
   CB_CHK(hipMemsetAsync(scratch, 0, 16, h->stream));
   auto* far = static_cast<unsigned long long*>(scratch);
@@ -293,7 +293,7 @@ hipError_t build_colblocks(mdp_handle* h, int blocks, bool require, bool* built,
   if (bad_h || (!require && *far_frac < 0.5)) return done(hipSuccess);
 
   const size_t nt = static_cast<size_t>(blocks) * ntiles;
-  CB_CHK(hipMalloc(reinterpret_cast<void**>(&tsum), nt * sizeof(int)));
+  CB_CHK(handle_alloc(h, reinterpret_cast<void**>(&tsum), nt * sizeof(int)));
   k_cb_tile_sums<<<dim3(ntiles, blocks), kBlock, 0, h->stream>>>(rows, tile_rows, ntiles, cnt, tsum);
   CB_CHK(hipGetLastError());
   std::vector<int> ts_h(nt), off_h(static_cast<size_t>(blocks) * (ntiles + 1));
@@ -310,12 +310,12 @@ hipError_t build_colblocks(mdp_handle* h, int blocks, bool require, bool* built,
     off_h[static_cast<size_t>(b) * (ntiles + 1) + ntiles] = static_cast<int>(run);
   }
   if (run != h->nnz) return done(hipErrorInvalidValue);
-  CB_CHK(hipMalloc(reinterpret_cast<void**>(&off), off_h.size() * sizeof(int)));
+  CB_CHK(handle_alloc(h, reinterpret_cast<void**>(&off), off_h.size() * sizeof(int)));
   CB_CHK(hipMemcpyAsync(off, off_h.data(), off_h.size() * sizeof(int), hipMemcpyHostToDevice, h->stream));
-  CB_CHK(hipMalloc(reinterpret_cast<void**>(&rel), cnt_bytes * sizeof(uint16_t)));
-  CB_CHK(hipMalloc(reinterpret_cast<void**>(&cb_col), h->nnz * sizeof(int)));
-  CB_CHK(hipMalloc(reinterpret_cast<void**>(&cb_val), h->nnz * sizeof(double)));
-  CB_CHK(hipMalloc(reinterpret_cast<void**>(&acc), rows * sizeof(double)));
+  CB_CHK(handle_alloc(h, reinterpret_cast<void**>(&rel), cnt_bytes * sizeof(uint16_t)));
+  CB_CHK(handle_alloc(h, reinterpret_cast<void**>(&cb_col), h->nnz * sizeof(int)));
+  CB_CHK(handle_alloc(h, reinterpret_cast<void**>(&cb_val), h->nnz * sizeof(double)));
+  CB_CHK(handle_alloc(h, reinterpret_cast<void**>(&acc), rows * sizeof(double)));
   k_cb_scatter<<<ntiles, kBlock, 0, h->stream>>>(rows, tile_rows, ntiles, blocks, slice, h->row_ptr,
                                                  h->col, h->val, cnt, off, cb_col, cb_val, rel);
   CB_CHK(hipGetLastError());

@@ -5,6 +5,7 @@
 #include <hip/hip_fp16.h>
 
 #include <atomic>
+#include <shared_mutex>
 #include <vector>
 #include <cstdint>
 #include <string>
@@ -206,6 +207,27 @@ __host__ __device__ inline int64_t state_of_row(int64_t r, int A, int64_t S) {
   return t0 + (r - t0 * A) % n;
 }
 
+// Allocation and release of device memory, pinned host memory, streams and
+// events go through these wrappers (api.cpp), which hold the library's
+// allocation lock in shared mode.  Graph capture in the batched solver holds
+// it exclusively: such calls from another thread (hipFree waits for the whole
+// device) would break a capture in progress.
+std::shared_mutex& alloc_lock();
+// Handle memory (api.cpp): from the library's per-device stream-ordered pool,
+// allocated and freed on the handle's stream; an allocation is usable from any
+// stream once handle_alloc returns.  A free is ordered after the work queued on
+// the handle's stream, so work on other streams that touches the memory must
+// be finished first.  pool_reserve raises (or, negative, lowers and trims) the
+// bytes the pool keeps cached.
+hipError_t handle_alloc(mdp_handle* h, void** p, size_t bytes);
+void handle_free(mdp_handle* h, void* p);
+hipError_t device_pool(int dev, hipMemPool_t* out);
+hipError_t pool_reserve(int dev, int64_t delta);
+hipError_t lib_malloc(void** p, size_t bytes);
+void lib_free(void* p);
+hipError_t lib_host_malloc(void** p, size_t bytes);
+void lib_host_free(void* p);
+
 // Copy natural-order rows (s*A + a) into the stored order and write the
 // stored row offsets rp_new[0..S*A] (vecops.hip).
 hipError_t launch_permute_rows(hipStream_t st, int64_t S, int A, const int32_t* rp_old,
@@ -216,6 +238,18 @@ size_t partials_doubles(int64_t S, int A, int m);
 
 // Host helpers shared by the single and the batched drivers (api.cpp).
 bool is_device_ptr(const void* p);
+// Validation (api.cpp): row_ptr structure; entries and costs on the host;
+// both.  entry_failure turns a verdict into the shared message.
+mdp_status validate_row_ptr(int64_t S, int32_t A, const int64_t* rp);
+mdp_status validate_entries_host(int64_t S, int32_t A, const int64_t* rp, const int32_t* col,
+                                 const double* val, const double* cost);
+mdp_status entry_failure(int64_t cost_row, int64_t entry_row, int why);
+// Entry checks on the device (vecops.hip): workgroup b writes out[3b..3b+2] =
+// lowest row with a non-finite cost, lowest row with a bad entry or row sum,
+// and that row's reason (1 column, 2 probability, 3 sum); -1 for none.
+int validate_blocks(int64_t rows);
+hipError_t launch_validate(hipStream_t st, int64_t S, int64_t rows, const int32_t* rp, const int32_t* col,
+                           const double* val, const double* cost, int64_t* out, int blocks);
 mdp_status validate_host(int64_t S, int32_t A, const int64_t* rp, const int32_t* col,
                          const double* val, const double* cost);
 mdp_status sync_ctl(mdp_handle* h);

@@ -81,7 +81,6 @@ struct mdp_server {
   int device = 0;
   hipStream_t stream = nullptr;
   std::mutex mu;
-  std::shared_mutex alloc_mu;  // see BatchEngine::capture_lock
   std::condition_variable cv_admit, cv_work, cv_reap, cv_done;
   std::deque<mdp::Request*> queue;     // submitted, not yet admitted
   std::vector<mdp::Request*> ready;    // admitted, joining at the next round
@@ -213,15 +212,14 @@ mdp_status mdp_server::admit_one(Request* r) {
   mdp_default_create_opts(&co);
   co.stream = nullptr;  // the handle's own stream: admission overlaps the rounds
   co.device = device;
-  co.validate = 0;      // validated at submission
+  // copied requests were validated at submission; lent arrays are checked
+  // here, on the device, over the uploaded copy
+  co.validate = r->borrowed ? MDP_VALIDATE_DEVICE : MDP_VALIDATE_NONE;
   mdp_handle* h = nullptr;
   const int64_t* rp = r->borrowed ? r->b_row_ptr : r->row_ptr.data();
   const int32_t* cl = r->borrowed ? r->b_col : r->col.data();
   const double* vl = r->borrowed ? r->b_val : r->val.data();
   const double* cs = r->borrowed ? r->b_cost : r->cost.data();
-  // validation runs here, off the caller's thread
-  if (r->borrowed) MDP_TRY(validate_host(r->S, r->A, rp, cl, vl, cs));
-  std::shared_lock<std::shared_mutex> alloc_guard(alloc_mu);
   MDP_TRY(mdp_create(r->S, r->A, rp, cl, vl, cs, r->gamma, &co, &h));
   r->h = h;
   const Prec prec = prec_of(opts.solve.precision);
@@ -257,7 +255,6 @@ mdp_status mdp_server::admit_one(Request* r) {
 }
 
 void mdp_server::retire(Request* r) {
-  std::shared_lock<std::shared_mutex> alloc_guard(alloc_mu);
   mdp_handle* h = r->h;
   const BatchItem& it = r->item;
   r->v.resize(h->S);
@@ -329,16 +326,28 @@ mdp_status mdp_server_create(const mdp_server_opts* opt, mdp_server_t* out) {
   }
   if (o.stream) {
     s->stream = static_cast<hipStream_t>(o.stream);
-  } else if (hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking) != hipSuccess) {
-    delete s;
-    return fail(MDP_E_DEVICE, "stream creation failed");
+  } else {
+    hipError_t e = hipSuccess;
+    {
+      std::shared_lock<std::shared_mutex> g(alloc_lock());
+      e = hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking);
+    }
+    if (e != hipSuccess) {
+      delete s;
+      return fail(MDP_E_DEVICE, "stream creation failed");
+    }
   }
   s->eng.stream = s->stream;
   s->eng.prec = prec_of(o.solve.precision);
-  s->eng.capture_lock = &s->alloc_mu;
   mdp_status st = s->eng.reserve(o.max_batch);
+  // memory of retired requests stays in the device pool for later admissions
+  if (st >= 0 && pool_reserve(s->device, o.hbm_budget_bytes) != hipSuccess)
+    st = fail(MDP_E_DEVICE, "device memory pool set-up failed");
   if (st < 0) {
-    if (!o.stream) (void)hipStreamDestroy(s->stream);
+    if (!o.stream) {
+      std::shared_lock<std::shared_mutex> g(alloc_lock());
+      (void)hipStreamDestroy(s->stream);
+    }
     delete s;
     return st;
   }
@@ -479,7 +488,11 @@ mdp_status mdp_server_destroy(mdp_server_t s) {
   for (auto& kv : s->all)
     if (kv.second->h) mdp_destroy(kv.second->h);
   s->eng.release();
-  if (!s->opts.stream && s->stream) (void)hipStreamDestroy(s->stream);
+  (void)pool_reserve(s->device, -s->opts.hbm_budget_bytes);
+  if (!s->opts.stream && s->stream) {
+    std::shared_lock<std::shared_mutex> g(alloc_lock());
+    (void)hipStreamDestroy(s->stream);
+  }
   delete s;
   return MDP_OK;
 }

@@ -60,6 +60,61 @@ __global__ __launch_bounds__(kBlock) void k_permute_rows(int64_t S, int A, const
   }
 }
 
+// Entry checks in natural row order, one thread per row (grid-stride, so a
+// thread's rows increase and its first failure is its lowest).  The row sum
+// adds the entries in order, as the host check does.
+__global__ __launch_bounds__(kBlock) void k_validate(int64_t S, int64_t rows, const int32_t* __restrict__ rp,
+                                                     const int32_t* __restrict__ col,
+                                                     const double* __restrict__ val,
+                                                     const double* __restrict__ cost,
+                                                     int64_t* __restrict__ out) {
+  constexpr int64_t kNone = INT64_MAX;
+  __shared__ int64_t s_cost[kBlock], s_row[kBlock];
+  __shared__ int s_why[kBlock];
+  int64_t bad_cost = kNone, bad_row = kNone;
+  int why = 0;
+  for (int64_t r = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; r < rows;
+       r += static_cast<int64_t>(gridDim.x) * kBlock) {
+    if (bad_cost == kNone && !isfinite(cost[r])) bad_cost = r;
+    if (bad_row != kNone) continue;
+    const int b = rp[r], e_end = rp[r + 1];
+    double sum = 0.0;
+    int w = 0;
+    for (int e = b; e < e_end; ++e) {
+      const int c = col[e];
+      const double x = val[e];
+      if (c < 0 || c >= S) { w = 1; break; }
+      if (!(x >= 0.0) || !isfinite(x)) { w = 2; break; }
+      sum += x;
+    }
+    if (w == 0 && fabs(sum - 1.0) > 1e-12 * fmax(1.0, static_cast<double>(e_end - b))) w = 3;
+    if (w != 0) {
+      bad_row = r;
+      why = w;
+    }
+  }
+  s_cost[threadIdx.x] = bad_cost;
+  s_row[threadIdx.x] = bad_row;
+  s_why[threadIdx.x] = why;
+  __syncthreads();
+  for (int h = kBlock / 2; h > 0; h >>= 1) {
+    if (threadIdx.x < h) {
+      const int o = threadIdx.x + h;
+      if (s_cost[o] < s_cost[threadIdx.x]) s_cost[threadIdx.x] = s_cost[o];
+      if (s_row[o] < s_row[threadIdx.x]) {
+        s_row[threadIdx.x] = s_row[o];
+        s_why[threadIdx.x] = s_why[o];
+      }
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    out[3 * blockIdx.x + 0] = s_cost[0] == kNone ? -1 : s_cost[0];
+    out[3 * blockIdx.x + 1] = s_row[0] == kNone ? -1 : s_row[0];
+    out[3 * blockIdx.x + 2] = s_why[0];
+  }
+}
+
 }  // namespace
 
 hipError_t launch_permute_rows(hipStream_t st, int64_t S, int A, const int32_t* rp_old,
@@ -71,6 +126,17 @@ hipError_t launch_permute_rows(hipStream_t st, int64_t S, int A, const int32_t* 
   const int64_t g = std::min<int64_t>(65536, (S + T - 1) / T);
   k_permute_rows<<<static_cast<unsigned>(g), kBlock, 0, st>>>(S, A, rp_old, col_old, val_old, cost_old,
                                                               rp_new, col_new, val_new, cost_new);
+  return hipGetLastError();
+}
+
+int validate_blocks(int64_t rows) {
+  return static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(1024, (rows + kBlock - 1) / kBlock)));
+}
+
+hipError_t launch_validate(hipStream_t st, int64_t S, int64_t rows, const int32_t* rp, const int32_t* col,
+                           const double* val, const double* cost, int64_t* out, int blocks) {
+  if (blocks != validate_blocks(rows)) return hipErrorInvalidValue;
+  k_validate<<<blocks, kBlock, 0, st>>>(S, rows, rp, col, val, cost, out);
   return hipGetLastError();
 }
 

@@ -17,6 +17,7 @@ MDP_FP64, MDP_MIXED_FP32, MDP_MIXED_FP16 = 0, 1, 2
 MDP_INNER_GMRES, MDP_INNER_RICHARDSON, MDP_INNER_BICGSTAB, MDP_INNER_TFQMR = 0, 1, 2, 3
 MDP_BUILD_FP32, MDP_BUILD_FP16 = 1, 2
 MDP_MINIMIZE_COST, MDP_MAXIMIZE_REWARD = 0, 1
+MDP_VALIDATE_NONE, MDP_VALIDATE_HOST, MDP_VALIDATE_DEVICE = 0, 1, 2
 
 
 class CreateOpts(C.Structure):

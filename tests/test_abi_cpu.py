@@ -84,8 +84,20 @@ def test_validation_rejects_bad_mdp(mutate, expect):
     assert not h.value
 
 
+@pytest.mark.parametrize("mode", [0, 2])
+def test_row_ptr_checked_on_host_in_every_validation_mode(mode):
+    # row_ptr decides which memory the kernels touch, so its structure is
+    # checked on the host even when entries are unchecked or checked on the device
+    S, A, rp, col, val, cost, gamma = _small()
+    rp[4] = rp[3]
+    st, msg, h = _create(S, A, rp, col, val, cost, gamma, validate=mode)
+    assert st == native.MDP_E_INVAL and "row_ptr" in msg and not h.value
+
+
 def test_bad_options_rejected():
     S, A, rp, col, val, cost, gamma = _small()
+    st, msg, _ = _create(S, A, rp, col, val, cost, gamma, validate=3)
+    assert st == native.MDP_E_INVAL and "validate" in msg
     st, msg, _ = _create(S, A, rp, col, val, cost, gamma, lanes_per_row=12)
     assert st == native.MDP_E_INVAL and "lanes_per_row" in msg
     st, msg, _ = _create(S, A, rp, col, val, cost, gamma, low_precision=8)

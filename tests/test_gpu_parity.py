@@ -119,6 +119,69 @@ def test_stored_row_order_shapes(S, A, density):
     assert np.all(np.abs(y1 - (gpi + inst.gamma * (Ppi @ x))) <= bnd)
 
 
+def _create_status(inst, validate):
+    import ctypes as C
+    from paper_2502_14474_amd import native
+    lib = native.load()
+    o = native.CreateOpts()
+    lib.mdp_default_create_opts(C.byref(o))
+    o.validate = validate
+    h = C.c_void_p()
+    st = lib.mdp_create(inst.S, inst.A, inst.row_ptr.ctypes.data, inst.col.ctypes.data, inst.val.ctypes.data,
+                        inst.cost.ctypes.data, inst.gamma, C.byref(o), C.byref(h))
+    msg = lib.mdp_last_error().decode()
+    if h.value:
+        lib.mdp_destroy(h)
+    return st, msg
+
+
+def _mutated(inst, edits):
+    bad = MDPInstance(inst.S, inst.A, inst.row_ptr.copy(), inst.col.copy(), inst.val.copy(), inst.cost.copy(),
+                      inst.gamma, name=inst.name)
+    for arr, idx, value in edits:
+        getattr(bad, arr)[idx] = value(getattr(bad, arr)[idx]) if callable(value) else value
+    return bad
+
+
+VALIDATION_CASES = {
+    "col_high": [("col", 3, 10 ** 6)],
+    "col_negative": [("col", 3, -1)],
+    "val_negative": [("val", 7, -0.01)],
+    "val_nan": [("val", 7, np.nan)],
+    "val_inf": [("val", 7, np.inf)],
+    "row_sum": [("val", 7, lambda x: x + 1e-6)],
+    "cost_inf": [("cost", 5, np.inf)],
+    "cost_beats_entry": [("val", 2, -1.0), ("cost", 900, np.nan)],
+    "lowest_row_wins": [("val", -3, -1.0), ("col", 40, -5), ("val", 1000, lambda x: x * 2)],
+    "tail_only": [("val", -1, lambda x: x + 1e-3)],
+}
+
+
+@pytest.mark.parametrize("case", sorted(VALIDATION_CASES))
+@pytest.mark.parametrize("A", [1, 3, 8])
+def test_device_validation_matches_host(case, A):
+    # rows > 1024 * 256 for A = 8, so the device check runs grid-stride over
+    # several rows per thread; A = 1 keeps the natural row order
+    inst = config1(S=40000, A=A, k=6, seed=4)
+    bad = _mutated(inst, VALIDATION_CASES[case])
+    st_h, msg_h = _create_status(bad, 1)
+    st_d, msg_d = _create_status(bad, 2)
+    print(f"[case] {case} A={A}: {msg_h}", flush=True)
+    assert st_h == -1 and st_d == -1
+    assert msg_d == msg_h
+
+
+def test_device_validation_accepts_valid_mdp():
+    import paper_2502_14474_amd as m
+    inst = config2(S=20000, A=8, seed=2)
+    v = np.random.default_rng(0).standard_normal(inst.S)
+    with _mdp(inst, validate="host") as h1, _mdp(inst, validate="device") as h2:
+        a, b = h1.bellman(v), h2.bellman(v)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]) and a[2] == b[2]
+    with pytest.raises(ValueError):
+        m.MDP.from_instance(inst, validate="sometimes")
+
+
 def test_policy_apply_rejects_bad_policy():
     import paper_2502_14474_amd as m
     inst = config1(S=50, seed=3)
