@@ -79,8 +79,9 @@ enum { MDP_INNER_GMRES = 0, MDP_INNER_RICHARDSON = 1, MDP_INNER_BICGSTAB = 2, MD
  * unchecked; MDP_VALIDATE_HOST checks them on host threads (copying device inputs
  * to the host first); MDP_VALIDATE_DEVICE checks them in a kernel over the
  * uploaded copy, which spares the host a pass over the data.  The two checking
- * modes reject the same inputs with the same messages: the row-sum test adds a
- * row's entries in order on either side. */
+ * modes reject the same inputs with the same messages: both form a row's sum in
+ * one fixed order (eight interleaved partial sums, each in entry order,
+ * combined as ((p0+p4)+(p2+p6)) + ((p1+p5)+(p3+p7))). */
 enum { MDP_VALIDATE_NONE = 0, MDP_VALIDATE_HOST = 1, MDP_VALIDATE_DEVICE = 2 };
 
 /* Bits of mdp_create_opts.low_precision: which reduced-precision copies of P to build. */
@@ -241,9 +242,9 @@ typedef struct {
   int64_t hbm_budget_bytes;  /* admission limit on resident device bytes (default 64 GiB) */
   int32_t device;            /* HIP device; -1: the current device */
   int32_t max_batch;         /* most MDPs resident at once (default 256) */
-  int32_t admit_threads;     /* threads copying new MDPs to the device (default 2: uploads
-                                from more threads contend for the copy engines) */
-  int32_t retire_threads;    /* threads copying results out and freeing (default 2) */
+  int32_t admit_threads;     /* threads copying new MDPs to the device (default 4: while one
+                                waits for its upload, the others queue theirs) */
+  int32_t retire_threads;    /* threads copying results out and freeing (default 4) */
   mdp_solve_opts solve;      /* GMRES only; default precision MDP_MIXED_FP32 */
 } mdp_server_opts;
 

@@ -309,7 +309,7 @@ class Server:
     """Continuous-batching solve server (mdp_server_* in include/mdp.h)."""
 
     def __init__(self, hbm_budget_bytes=64 << 30, max_batch=256, device=-1, stream=None,
-                 admit_threads=2, retire_threads=2, **solve_opts):
+                 admit_threads=4, retire_threads=4, **solve_opts):
         lib = native.load()
         o = native.ServerOpts()
         lib.mdp_default_server_opts(C.byref(o))

@@ -485,12 +485,15 @@ mdp_status validate_entries_host(int64_t S, int32_t A, const int64_t* rp, const 
     th.emplace_back([&, t]() {
       const int64_t r0 = rows * t / nt, r1 = rows * (t + 1) / nt;
       for (int64_t r = r0; r < r1; ++r) {
-        double sum = 0.0;
+        // the library's row-sum order: eight interleaved partials, combined
+        // as ((p0+p4)+(p2+p6)) + ((p1+p5)+(p3+p7)), as the device check does
+        double p[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
         for (int64_t e = rp[r]; e < rp[r + 1]; ++e) {
           if (col[e] < 0 || col[e] >= S) { bad[t] = r; why[t] = 1; return; }
           if (!(val[e] >= 0.0) || !std::isfinite(val[e])) { bad[t] = r; why[t] = 2; return; }
-          sum += val[e];
+          p[(e - rp[r]) % 8] += val[e];
         }
+        const double sum = ((p[0] + p[4]) + (p[2] + p[6])) + ((p[1] + p[5]) + (p[3] + p[7]));
         const double len = static_cast<double>(rp[r + 1] - rp[r]);
         if (std::fabs(sum - 1.0) > 1e-12 * std::max(1.0, len)) { bad[t] = r; why[t] = 3; return; }
       }

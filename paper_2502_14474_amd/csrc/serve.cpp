@@ -288,8 +288,8 @@ void mdp_default_server_opts(mdp_server_opts* o) {
   o->stream = nullptr;
   o->hbm_budget_bytes = int64_t{64} << 30;
   o->max_batch = 256;
-  o->admit_threads = 2;
-  o->retire_threads = 2;
+  o->admit_threads = 4;
+  o->retire_threads = 4;
   mdp_default_solve_opts(&o->solve);
   o->solve.precision = MDP_MIXED_FP32;
 }

@@ -60,34 +60,57 @@ __global__ __launch_bounds__(kBlock) void k_permute_rows(int64_t S, int A, const
   }
 }
 
-// Entry checks in natural row order, one thread per row (grid-stride, so a
-// thread's rows increase and its first failure is its lowest).  The row sum
-// adds the entries in order, as the host check does.
+// Entry checks in natural row order, 8 lanes per row (grid-stride over rows,
+// so each group's rows increase and its first failure is its lowest).  A
+// row's failure is its lowest failing entry.  The row sum is the library's
+// fixed order: lane l adds entries l, l+8, ... in order, then the eight
+// partials combine as ((p0+p4)+(p2+p6)) + ((p1+p5)+(p3+p7)), which the xor
+// butterfly below computes on every lane (addition commutes exactly); the
+// host check forms the same sum.
 __global__ __launch_bounds__(kBlock) void k_validate(int64_t S, int64_t rows, const int32_t* __restrict__ rp,
                                                      const int32_t* __restrict__ col,
                                                      const double* __restrict__ val,
                                                      const double* __restrict__ cost,
                                                      int64_t* __restrict__ out) {
+  constexpr int G = 8;
   constexpr int64_t kNone = INT64_MAX;
   __shared__ int64_t s_cost[kBlock], s_row[kBlock];
   __shared__ int s_why[kBlock];
+  const int lane = threadIdx.x % G;
   int64_t bad_cost = kNone, bad_row = kNone;
   int why = 0;
-  for (int64_t r = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; r < rows;
-       r += static_cast<int64_t>(gridDim.x) * kBlock) {
-    if (bad_cost == kNone && !isfinite(cost[r])) bad_cost = r;
-    if (bad_row != kNone) continue;
+  const int64_t gstride = static_cast<int64_t>(gridDim.x) * (kBlock / G);
+  for (int64_t r = (static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x) / G; r < rows; r += gstride) {
+    if (lane == 0 && bad_cost == kNone && !isfinite(cost[r])) bad_cost = r;
+    if (bad_row != kNone) continue;  // uniform within the group
     const int b = rp[r], e_end = rp[r + 1];
-    double sum = 0.0;
-    int w = 0;
-    for (int e = b; e < e_end; ++e) {
-      const int c = col[e];
-      const double x = val[e];
-      if (c < 0 || c >= S) { w = 1; break; }
-      if (!(x >= 0.0) || !isfinite(x)) { w = 2; break; }
-      sum += x;
+    int first = INT_MAX, w = 0;
+    double part = 0.0;
+    for (int j = b + lane; j < e_end; j += G) {
+      const int c = col[j];
+      const double x = val[j];
+      if (first != INT_MAX) continue;
+      if (c < 0 || c >= S) {
+        first = j;
+        w = 1;
+      } else if (!(x >= 0.0) || !isfinite(x)) {
+        first = j;
+        w = 2;
+      } else {
+        part += x;
+      }
     }
-    if (w == 0 && fabs(sum - 1.0) > 1e-12 * fmax(1.0, static_cast<double>(e_end - b))) w = 3;
+#pragma unroll
+    for (int off = G / 2; off > 0; off >>= 1) {
+      const int of = __shfl_xor(first, off, G);
+      const int ow = __shfl_xor(w, off, G);
+      if (of < first) {
+        first = of;
+        w = ow;
+      }
+      part = part + __shfl_xor(part, off, G);
+    }
+    if (first == INT_MAX && fabs(part - 1.0) > 1e-12 * fmax(1.0, static_cast<double>(e_end - b))) w = 3;
     if (w != 0) {
       bad_row = r;
       why = w;
@@ -130,7 +153,8 @@ hipError_t launch_permute_rows(hipStream_t st, int64_t S, int A, const int32_t* 
 }
 
 int validate_blocks(int64_t rows) {
-  return static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(1024, (rows + kBlock - 1) / kBlock)));
+  constexpr int64_t kRowsPerBlock = kBlock / 8;
+  return static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(2048, (rows + kRowsPerBlock - 1) / kRowsPerBlock)));
 }
 
 hipError_t launch_validate(hipStream_t st, int64_t S, int64_t rows, const int32_t* rp, const int32_t* col,
