@@ -370,6 +370,43 @@ def test_device_pointer_round_trip():
     assert np.array_equal(pi.cpu().numpy(), ref["pi"])
 
 
+@pytest.mark.parametrize("mode", ["host", "device"])
+def test_validation_of_device_pointer_inputs(mode):
+    """Device inputs: the host check copies them back, the device check reads
+    the uploaded copy; both reject a bad probability with the message the host
+    check gives for the same arrays in host memory."""
+    import torch
+    import paper_2502_14474_amd as m
+    bad = _mutated(config1(S=3000, A=6, k=7, seed=8), [("val", 1234, -0.25)])
+    with pytest.raises(m.MDPError) as ref:
+        m.mdp_create(bad.S, bad.A, bad.row_ptr, bad.col, bad.val, bad.cost, bad.gamma, validate="host")
+    dev = torch.device("cuda:0")
+    t = lambda a: torch.from_numpy(a).to(dev)  # noqa: E731
+    with pytest.raises(m.MDPError) as e:
+        m.mdp_create(bad.S, bad.A, t(bad.row_ptr), t(bad.col), t(bad.val), t(bad.cost), bad.gamma,
+                     validate=mode)
+    assert e.value.status == m.native.MDP_E_INVAL and str(e.value) == str(ref.value)
+
+
+def test_reused_device_memory_gives_fresh_results():
+    """Handle memory is recycled through the library's pool: a handle created
+    where a larger, different one lived must compute exactly what a handle of
+    the same MDP computed before it (no state leaks from freed memory)."""
+    import paper_2502_14474_amd as m
+    small = config2(S=20000, A=8, seed=3)
+    v = np.random.default_rng(2).standard_normal(small.S)
+    with _mdp(small) as h:
+        ref = h.bellman(v), h.solve(alpha=1e-2)
+    for seed in (4, 5):
+        big = config2(S=60000, A=8, seed=seed)
+        with _mdp(big, low_precision=m.MDP_BUILD_FP32) as hb:
+            hb.solve(alpha=1e-2, precision=m.MDP_MIXED_FP32)
+        with _mdp(small) as h:
+            got = h.bellman(v), h.solve(alpha=1e-2)
+        assert all(np.array_equal(a, b) for a, b in zip(got[0][:2], ref[0][:2])) and got[0][2] == ref[0][2]
+        assert np.array_equal(got[1][0], ref[1][0]) and np.array_equal(got[1][1], ref[1][1])
+
+
 def test_autotune_remembers_width_per_class(tmp_path, monkeypatch):
     """The autotuner picks one of the candidate widths, stores it under the
     handle's class key and a later handle of that class starts from it; the
