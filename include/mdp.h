@@ -54,7 +54,7 @@ typedef enum {
   MDP_E_DEVICE = -3,   /* a HIP runtime call failed (also: no GPU present) */
   MDP_E_NUMERIC = -4,  /* NaN or Inf met in a residual */
   MDP_E_STATE = -5,    /* handle busy with another call */
-  MDP_E_NOTSUP = -6    /* valid request this build does not support */
+  MDP_E_NOTSUP = -6    /* valid request the library does not support */
 } mdp_status;
 
 /* Arithmetic of the sweeps and of the inner solver. */
