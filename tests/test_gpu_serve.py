@@ -85,3 +85,42 @@ def test_server_borrowed_invalid_request_fails_at_wait():
         assert e.value.status == m.native.MDP_E_INVAL
         v, pi, st = srv.wait(good)
         assert st["status"] == 0
+
+
+def test_server_beside_threads_that_create_and_destroy_handles():
+    """Handles created, solved and destroyed on other host threads while a
+    server captures graphs and admits and retires requests: every result equals
+    the same solve alone (allocation, stream and control-slot recycling and the
+    capture lock are shared across the library)."""
+    import threading
+
+    import paper_2502_14474_amd as m
+    insts = _requests()[:6]
+    ref = [_alone(i, 1) for i in insts]
+    side = [config2(S=5000 + 700 * t, A=4, seed=20 + t) for t in range(3)]
+    side_ref = [_alone(i, 0) for i in side]
+    errors = []
+
+    def churn(t):
+        try:
+            for _ in range(4):
+                v, pi, st = _alone(side[t], 0)
+                if not (np.array_equal(v, side_ref[t][0]) and np.array_equal(pi, side_ref[t][1])):
+                    errors.append(f"thread {t}: result differs")
+        except Exception as e:  # reported below
+            errors.append(f"thread {t}: {e}")
+
+    print(f"[case] server beside 3 churning threads, {len(insts)} requests", flush=True)
+    with m.Server(precision=1, alpha=1e-2, max_batch=3) as srv:
+        threads = [threading.Thread(target=churn, args=(t,)) for t in range(3)]
+        for th in threads:
+            th.start()
+        ids = [srv.submit(inst, borrow=(k % 2 == 0)) for k, inst in enumerate(insts * 2)]
+        outs = [srv.wait(i) for i in ids]
+        for th in threads:
+            th.join(timeout=90)
+        assert not any(th.is_alive() for th in threads)
+    assert not errors, errors
+    for k, (v, pi, st) in enumerate(outs):
+        vr, pir, _ = ref[k % len(insts)]
+        assert st["status"] == 0 and np.array_equal(v, vr) and np.array_equal(pi, pir), k
