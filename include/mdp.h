@@ -133,7 +133,15 @@ typedef struct {
   double rtol_cert;       /* if > 0, also require ||T v - v||_inf <= rtol_cert*(1-gamma)*||T v||_inf */
   int64_t max_outer;      /* cap on Bellman sweeps (default 1000) */
   int64_t max_inner;      /* cap on inner steps per evaluation (default 10000) */
+  int32_t launch;         /* batched solves and the server: how a GMRES cycle's Arnoldi steps
+                             reach the GPU.  MDP_LAUNCH_GRAPHS (and MDP_LAUNCH_AUTO, the
+                             default) replays HIP graphs captured once per configuration, with
+                             fixed persistent grids; MDP_LAUNCH_DIRECT launches each kernel with
+                             a grid sized to the round's work.  Both give bitwise the same
+                             results.  mdp_solve ignores it. */
 } mdp_solve_opts;
+
+enum { MDP_LAUNCH_AUTO = 0, MDP_LAUNCH_GRAPHS = 1, MDP_LAUNCH_DIRECT = 2 };
 
 typedef struct {
   size_t struct_size;     /* sizeof(mdp_stats) */
@@ -216,7 +224,9 @@ mdp_status mdp_solve(mdp_t h, const double* v0, double* v, int32_t* policy,
  * together.  Each round advances every unfinished MDP by one phase (a Bellman
  * sweep, or one GMRES cycle with its restart) in persistent kernels that walk
  * a table of (MDP, tile) work items; the cycle's Arnoldi steps are replayed
- * from captured HIP graphs.  Every MDP gets bitwise the same v, policy and
+ * from captured HIP graphs (see mdp_solve_opts.launch).  The engine and its
+ * graphs are kept per device between calls, so only the first call of a
+ * configuration captures.  Every MDP gets bitwise the same v, policy and
  * statistics as mdp_solve would give it alone (same kernels bodies, tiling,
  * reduction order and decisions).  v0 may be NULL (all zero) or hold n
  * pointers (each NULL or double[S_i]); v[i] (double[S_i]) and policy[i]

@@ -12,6 +12,7 @@ from . import native
 from .native import (MDP_FP64, MDP_MIXED_FP32, MDP_MIXED_FP16, MDP_INNER_GMRES,  # noqa: F401
                      MDP_INNER_RICHARDSON, MDP_INNER_BICGSTAB, MDP_INNER_TFQMR, MDP_MINIMIZE_COST, MDP_MAXIMIZE_REWARD,
                      MDP_VALIDATE_NONE, MDP_VALIDATE_HOST, MDP_VALIDATE_DEVICE,
+                     MDP_LAUNCH_AUTO, MDP_LAUNCH_GRAPHS, MDP_LAUNCH_DIRECT,
                      MDP_BUILD_FP32, MDP_BUILD_FP16, MDP_OK,
                      MDP_W_MAXITER, MDPError)
 
@@ -215,11 +216,12 @@ def mdp_solve(h, v, policy, v0=None, inner=MDP_INNER_GMRES, restart=30, precisio
 
 
 def _solve_opts(lib, inner=MDP_INNER_GMRES, restart=30, precision=MDP_FP64, alpha=1e-4, atol=1e-8,
-                rtol_cert=0.0, max_outer=1000, max_inner=10000, sync_every=0):
+                rtol_cert=0.0, max_outer=1000, max_inner=10000, sync_every=0, launch=0):
     o = native.SolveOpts()
     lib.mdp_default_solve_opts(C.byref(o))
     o.inner, o.restart, o.precision, o.alpha, o.atol = inner, restart, precision, alpha, atol
     o.rtol_cert, o.max_outer, o.max_inner, o.sync_every = rtol_cert, max_outer, max_inner, sync_every
+    o.launch = launch
     return o
 
 

@@ -8,6 +8,7 @@
 #include <limits>
 #include <memory>
 #include <mutex>
+#include <new>
 #include <thread>
 #include <vector>
 
@@ -189,6 +190,38 @@ void ctl_slot_give(Ctl* c) {
   if (!c) return;
   std::lock_guard<std::mutex> lk(g_recycle_mu);
   g_ctl_free.push_back(c);
+}
+
+// Engines of mdp_solve_batch are kept per device between calls, so that the
+// HIP graphs they capture are replayed by later calls of the same
+// configuration.  A call leases an idle engine (or makes one) and hands it
+// back; concurrent calls lease different engines.  Engines stay until the
+// process ends; each holds its work tables and at most 64 graph sets.
+namespace {
+std::mutex g_engine_mu;
+std::vector<std::vector<std::unique_ptr<BatchEngine>>> g_engines;
+}  // namespace
+
+EngineLease::EngineLease(int dev) : dev(dev) {
+  std::lock_guard<std::mutex> lk(g_engine_mu);
+  if (dev >= 0 && static_cast<size_t>(dev) < g_engines.size() && !g_engines[dev].empty()) {
+    eng = g_engines[dev].back().release();
+    g_engines[dev].pop_back();
+  } else {
+    eng = new (std::nothrow) BatchEngine();
+  }
+}
+
+EngineLease::~EngineLease() {
+  if (!eng) return;
+  eng->items.clear();
+  std::lock_guard<std::mutex> lk(g_engine_mu);
+  if (dev < 0) {
+    delete eng;
+    return;
+  }
+  if (g_engines.size() <= static_cast<size_t>(dev)) g_engines.resize(dev + 1);
+  g_engines[dev].emplace_back(eng);
 }
 
 namespace {
@@ -703,6 +736,7 @@ void mdp_default_solve_opts(mdp_solve_opts* o) {
   o->rtol_cert = 0.0;
   o->max_outer = 1000;
   o->max_inner = 10000;
+  o->launch = MDP_LAUNCH_AUTO;
 }
 
 mdp_status mdp_destroy(mdp_t h) {
@@ -1322,6 +1356,7 @@ mdp_status mdp_solve_batch(mdp_t* handles, int32_t n, const double* const* v0, d
     o = *opt;
   }
   if (o.inner != MDP_INNER_GMRES) return fail(MDP_E_NOTSUP, "batched solves use GMRES");
+  if (o.launch < MDP_LAUNCH_AUTO || o.launch > MDP_LAUNCH_DIRECT) return fail(MDP_E_INVAL, "unknown launch mode");
   if (o.restart < 1 || o.restart > kMaxRestart) return fail(MDP_E_INVAL, "restart must lie in [1,64]");
   if (o.precision < MDP_FP64 || o.precision > MDP_MIXED_FP16) return fail(MDP_E_INVAL, "unknown precision");
   if (!(o.alpha > 0.0 && o.alpha < 1.0)) return fail(MDP_E_INVAL, "alpha must lie in (0,1)");
@@ -1355,9 +1390,13 @@ mdp_status mdp_solve_batch(mdp_t* handles, int32_t n, const double* const* v0, d
     it.prev_lowp_res = std::numeric_limits<double>::infinity();
     it.lowp_sweep = prec != kF64;
   }
-  BatchEngine eng;
+  EngineLease lease(handles[0]->device);
+  if (!lease.eng) return fail(MDP_E_NOMEM, "batched engine allocation failed");
+  BatchEngine& eng = *lease.eng;
   eng.stream = handles[0]->stream;
   eng.prec = prec;
+  eng.use_graphs = o.launch != MDP_LAUNCH_DIRECT;
+  eng.items.clear();
   MDP_TRY(eng.reserve(n));
   for (auto& it : items) eng.items.push_back(&it);
   for (;;) {

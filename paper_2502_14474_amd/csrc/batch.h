@@ -124,4 +124,14 @@ class BatchEngine {
   mdp_status cycle_phase(const mdp_solve_opts& o, std::vector<int>& gm);
 };
 
+// A batched engine leased from the library's per-device cache (api.cpp).
+struct EngineLease {
+  explicit EngineLease(int dev);
+  ~EngineLease();
+  EngineLease(const EngineLease&) = delete;
+  EngineLease& operator=(const EngineLease&) = delete;
+  int dev;
+  BatchEngine* eng = nullptr;
+};
+
 }  // namespace mdp

@@ -308,6 +308,8 @@ mdp_status mdp_server_create(const mdp_server_opts* opt, mdp_server_t* out) {
       o.admit_threads < 1 || o.admit_threads > 64 || o.retire_threads < 1 || o.retire_threads > 64)
     return fail(MDP_E_INVAL, "bad server limits");
   if (o.solve.inner != MDP_INNER_GMRES) return fail(MDP_E_NOTSUP, "the server uses GMRES");
+  if (o.solve.launch < MDP_LAUNCH_AUTO || o.solve.launch > MDP_LAUNCH_DIRECT)
+    return fail(MDP_E_INVAL, "unknown launch mode");
   if (o.solve.restart < 1 || o.solve.restart > kMaxRestart) return fail(MDP_E_INVAL, "restart must lie in [1,64]");
   if (o.solve.precision < MDP_FP64 || o.solve.precision > MDP_MIXED_FP16) return fail(MDP_E_INVAL, "unknown precision");
   if (!(o.solve.alpha > 0.0 && o.solve.alpha < 1.0) || !(o.solve.atol > 0.0))
@@ -339,6 +341,7 @@ mdp_status mdp_server_create(const mdp_server_opts* opt, mdp_server_t* out) {
   }
   s->eng.stream = s->stream;
   s->eng.prec = prec_of(o.solve.precision);
+  s->eng.use_graphs = o.solve.launch != MDP_LAUNCH_DIRECT;
   mdp_status st = s->eng.reserve(o.max_batch);
   // memory of retired requests stays in the device pool for later admissions
   if (st >= 0 && pool_reserve(s->device, o.hbm_budget_bytes) != hipSuccess)

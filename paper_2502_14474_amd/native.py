@@ -18,6 +18,7 @@ MDP_INNER_GMRES, MDP_INNER_RICHARDSON, MDP_INNER_BICGSTAB, MDP_INNER_TFQMR = 0, 
 MDP_BUILD_FP32, MDP_BUILD_FP16 = 1, 2
 MDP_MINIMIZE_COST, MDP_MAXIMIZE_REWARD = 0, 1
 MDP_VALIDATE_NONE, MDP_VALIDATE_HOST, MDP_VALIDATE_DEVICE = 0, 1, 2
+MDP_LAUNCH_AUTO, MDP_LAUNCH_GRAPHS, MDP_LAUNCH_DIRECT = 0, 1, 2
 
 
 class CreateOpts(C.Structure):
@@ -36,7 +37,7 @@ class SolveOpts(C.Structure):
     _fields_ = [("struct_size", C.c_size_t), ("inner", C.c_int32), ("restart", C.c_int32),
                 ("precision", C.c_int32), ("sync_every", C.c_int32), ("alpha", C.c_double),
                 ("atol", C.c_double), ("rtol_cert", C.c_double), ("max_outer", C.c_int64),
-                ("max_inner", C.c_int64)]
+                ("max_inner", C.c_int64), ("launch", C.c_int32)]
 
 
 class Stats(C.Structure):

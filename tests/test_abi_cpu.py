@@ -106,6 +106,17 @@ def test_bad_options_rejected():
     assert st == native.MDP_E_NOTSUP
 
 
+def test_server_rejects_unknown_launch_mode():
+    lib = native.load()
+    o = native.ServerOpts()
+    lib.mdp_default_server_opts(C.byref(o))
+    assert o.solve.launch == native.MDP_LAUNCH_AUTO
+    o.solve.launch = 5
+    srv = C.c_void_p()
+    assert lib.mdp_server_create(C.byref(o), C.byref(srv)) == native.MDP_E_INVAL
+    assert "launch" in lib.mdp_last_error().decode() and not srv.value
+
+
 def test_null_handle_calls_fail_cleanly():
     lib = native.load()
     res = C.c_double()

@@ -18,11 +18,12 @@ def _mix():
     return insts
 
 
-@pytest.mark.parametrize("precision", [0, 1])
-def test_batch_bitwise_equals_alone(precision):
+@pytest.mark.parametrize("precision,launch", [(0, 1), (1, 1), (0, 2), (1, 2)])
+def test_batch_bitwise_equals_alone(precision, launch):
+    # launch 1: Arnoldi steps replayed from captured HIP graphs; 2: direct launches
     import paper_2502_14474_amd as m
     insts = _mix()
-    print(f"[case] batch of {len(insts)} MDPs precision={precision}", flush=True)
+    print(f"[case] batch of {len(insts)} MDPs precision={precision} launch={launch}", flush=True)
     handles = [m.mdp_create(i.S, i.A, i.row_ptr, i.col, i.val, i.cost, i.gamma,
                             low_precision=1 if precision else 0) for i in insts]
     try:
@@ -35,11 +36,18 @@ def test_batch_bitwise_equals_alone(precision):
         vs = [np.empty(i.S) for i in insts]
         pis = [np.empty(i.S, np.int32) for i in insts]
         status, sts = m.mdp_solve_batch(handles, vs, pis, precision=precision, alpha=1e-2,
-                                        max_inner=20000)
+                                        max_inner=20000, launch=launch)
+        # a second call leases the cached engine and replays its graphs
+        vs2 = [np.empty(i.S) for i in insts]
+        pis2 = [np.empty(i.S, np.int32) for i in insts]
+        status2, _ = m.mdp_solve_batch(handles, vs2, pis2, precision=precision, alpha=1e-2,
+                                       max_inner=20000, launch=launch)
     finally:
         for h in handles:
             m.mdp_destroy(h)
-    assert status == 0
+    assert status == 0 and status2 == 0
+    assert all(np.array_equal(a, b) for a, b in zip(vs, vs2))
+    assert all(np.array_equal(a, b) for a, b in zip(pis, pis2))
     for k, (inst, (v, pi, st)) in enumerate(zip(insts, alone)):
         assert st["status"] == 0
         assert np.array_equal(vs[k], v), (k, inst.name, np.max(np.abs(vs[k] - v)))

@@ -23,13 +23,14 @@ def _alone(inst, precision):
         return h.solve(precision=precision, alpha=1e-2)
 
 
-@pytest.mark.parametrize("precision", [1, 0])
-def test_server_results_equal_alone_with_staggered_arrivals(precision):
+@pytest.mark.parametrize("precision,launch", [(1, 0), (0, 0), (1, 2)])
+def test_server_results_equal_alone_with_staggered_arrivals(precision, launch):
+    # launch 0: the default (graph replays); 2: direct launches
     import paper_2502_14474_amd as m
     insts = _requests()
-    print(f"[case] server precision={precision} with {len(insts)} requests", flush=True)
+    print(f"[case] server precision={precision} launch={launch} with {len(insts)} requests", flush=True)
     ref = [_alone(i, precision) for i in insts]
-    with m.Server(precision=precision, alpha=1e-2, max_batch=4) as srv:
+    with m.Server(precision=precision, alpha=1e-2, max_batch=4, launch=launch) as srv:
         ids = []
         for k, inst in enumerate(insts):
             ids.append(srv.submit(inst, borrow=(k % 2 == 1)))
