@@ -71,8 +71,10 @@ struct GraphKey {
   int prec;
   std::vector<int> lanes;
   int m, se;
+  int g_apply, g_upd, g_small;  // the captured grids (powers of two, capped)
   bool operator<(const GraphKey& o) const {
-    return std::tie(prec, lanes, m, se) < std::tie(o.prec, o.lanes, o.m, o.se);
+    return std::tie(prec, lanes, m, se, g_apply, g_upd, g_small) <
+           std::tie(o.prec, o.lanes, o.m, o.se, o.g_apply, o.g_upd, o.g_small);
   }
 };
 struct ChunkGraphs {
@@ -118,7 +120,7 @@ class BatchEngine {
   int build_list(int slot, const std::vector<int>& idx, int kind);
   mdp_status upload(int nitems, int nlists);
   mdp_status headers(int slot, int n);
-  hipError_t enqueue_steps(const std::vector<int>& lanes, int j0, int j1, int m, bool fixed,
+  hipError_t enqueue_steps(const std::vector<int>& lanes, int j0, int j1, int m, const GraphKey* fixed,
                            int tiles_apply_max, int tiles_upd, int n_items);
   mdp_status sweep_phase(const mdp_solve_opts& o, std::vector<int>& need);
   mdp_status cycle_phase(const mdp_solve_opts& o, std::vector<int>& gm);

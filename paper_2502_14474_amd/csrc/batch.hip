@@ -360,27 +360,37 @@ mdp_status BatchEngine::headers(int slot, int n) {
 
 static int persistent_grid(int total) { return std::max(1, std::min(total, 2048)); }
 
-// Fixed grids of the captured Arnoldi steps (graph replays keep their launch
-// shapes): enough workgroups for 4 per CU on the big kernels, few on the
-// per-MDP reductions so that idle workgroups cost little in small batches.
+// Grids of the captured Arnoldi steps (graph replays keep their launch
+// shapes, and the kernels walk their work lists grid-stride): the round's work
+// rounded up to a power of two, capped at 4 workgroups per CU on the big
+// kernels and fewer on the per-MDP reductions.  The grids are part of the
+// graph key, so a smaller batch replays graphs with smaller grids.
 constexpr int kGraphGridBig = 1024;
 constexpr int kGraphGridReduce = 512;
 constexpr int kGraphGridSmall = 64;
 
+static int pow2_grid(int work, int cap) {
+  int g = 1;
+  while (g < work && g < cap) g <<= 1;
+  return g;
+}
+
 // Arnoldi steps [j0, j1) of the current cycle for the lanes classes `cls`.
 hipError_t BatchEngine::enqueue_steps(const std::vector<int>& cls_lanes, int j0, int j1, int m,
-                                      bool fixed, int tiles_apply_max, int tiles_upd,
+                                      const GraphKey* fixed, int tiles_apply_max, int tiles_upd,
                                       int n_items) {
-  // Graph replays keep their launch shapes, so captured steps use fixed
-  // persistent grids and read every count from the work lists.
+  // Captured steps take the key's grids and read every count from the work
+  // lists; direct launches size each grid to the work.
   auto grid = [&](int work, int fixed_size) { return fixed ? fixed_size : persistent_grid(work); };
+  const int g_apply = fixed ? fixed->g_apply : 0, g_upd = fixed ? fixed->g_upd : 0;
+  const int g_small = fixed ? fixed->g_small : 0;
   for (int j = j0; j < j1; ++j) {
     for (size_t c = 0; c < cls_lanes.size(); ++c) {
       const int L = cls_lanes[c];
       hipError_t e = with_lanes_b(L, [&](auto Lc) -> hipError_t {
         constexpr int LL = decltype(Lc)::value;
         constexpr int UU = rows_in_flight_b<LL>();
-        const int g = grid(tiles_apply_max, kGraphGridBig);
+        const int g = grid(tiles_apply_max, g_apply);
         if (prec == kF64)
           kb_arnoldi_apply<LL, UU, kF64><<<g, kBlock, 0, stream>>>(descs_d, list_d(kListApply0 + c), j);
         else if (prec == kF32)
@@ -392,12 +402,12 @@ hipError_t BatchEngine::enqueue_steps(const std::vector<int>& cls_lanes, int j0,
       if (e != hipSuccess) return e;
     }
     kb_reduce_dots<<<grid(n_items * (j + 1), kGraphGridReduce), kBlock, 0, stream>>>(descs_d, list_d(kListGm), j);
-    const int gu = grid(tiles_upd, kGraphGridBig);
+    const int gu = grid(tiles_upd, g_upd);
     if (prec == kF64)
       kb_arnoldi_update<double><<<gu, kBlock, 0, stream>>>(descs_d, list_d(kListGmUpd), j);
     else
       kb_arnoldi_update<float><<<gu, kBlock, 0, stream>>>(descs_d, list_d(kListGmUpd), j);
-    kb_norm_givens<<<grid(n_items, kGraphGridSmall), kBlock, 0, stream>>>(descs_d, list_d(kListGm), j, m);
+    kb_norm_givens<<<grid(n_items, g_small), kBlock, 0, stream>>>(descs_d, list_d(kListGm), j, m);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
@@ -528,7 +538,8 @@ mdp_status BatchEngine::cycle_phase(const mdp_solve_opts& o, std::vector<int>& g
   // The Arnoldi steps come from HIP graphs captured once per configuration
   // (precision, lane classes, m, chunk length, grid sizes) and replayed each
   // round; the work lists they read are refreshed before every replay.
-  GraphKey key{static_cast<int>(prec), lanes, m, se};
+  GraphKey key{static_cast<int>(prec), lanes, m, se, pow2_grid(tiles_apply_max, kGraphGridBig),
+               pow2_grid(tiles_upd, kGraphGridBig), pow2_grid(n, kGraphGridSmall)};
   auto git = graphs.find(key);
   if (use_graphs && git == graphs.end()) {
     std::unique_lock<std::shared_mutex> cap_guard(alloc_lock());
@@ -536,7 +547,7 @@ mdp_status BatchEngine::cycle_phase(const mdp_solve_opts& o, std::vector<int>& g
     for (int j0 = 0; j0 < m; j0 += se) {
       hipGraph_t g;
       MDP_HIP(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
-      hipError_t e = enqueue_steps(lanes, j0, std::min(m, j0 + se), m, true, tiles_apply_max,
+      hipError_t e = enqueue_steps(lanes, j0, std::min(m, j0 + se), m, &key, tiles_apply_max,
                                    tiles_upd, n);
       hipGraph_t gout = nullptr;
       hipError_t e2 = hipStreamEndCapture(stream, &gout);
@@ -562,7 +573,7 @@ mdp_status BatchEngine::cycle_phase(const mdp_solve_opts& o, std::vector<int>& g
     if (use_graphs) {
       MDP_HIP(hipGraphLaunch(git->second.exec[chunk], stream));
     } else {
-      MDP_HIP(enqueue_steps(lanes, j0, std::min(m, j0 + se), m, false, tiles_apply_max, tiles_upd,
+      MDP_HIP(enqueue_steps(lanes, j0, std::min(m, j0 + se), m, nullptr, tiles_apply_max, tiles_upd,
                             n));
     }
     MDP_TRY(headers(kListGm, n));
