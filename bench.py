@@ -55,7 +55,10 @@ def make_instance(args):
     if args.config == 1:
         return config1(seed=args.seed)
     if args.config == 2:
-        return config2(S=args.S or 1_000_000, seed=args.seed)
+        inst = config2(S=args.S or 1_000_000, n_band=16 - args.n_jump, n_jump=args.n_jump, seed=args.seed)
+        if args.n_jump != 2:  # another workload: its own name, so no stored counters apply
+            inst.name = f"band-dirichlet1-{args.n_jump}-jumps"
+        return inst
     if args.config == 3:
         side = args.S or 2000
         return config3(H=side, W=side, seed=args.seed)
@@ -264,6 +267,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", type=int, default=2)
     ap.add_argument("--S", type=int, default=0)
+    ap.add_argument("--n-jump", type=int, default=2,
+                    help="config 2: long jumps per row (of 16 entries); 0 gives the band-only "
+                         "twin used to separate the cost of the long-jump gathers")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--restart", type=int, default=30)
     ap.add_argument("--alpha", type=float, default=1e-2)
