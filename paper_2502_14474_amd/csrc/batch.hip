@@ -275,14 +275,19 @@ void BatchEngine::release() {
 mdp_status BatchEngine::reserve(int n) {
   if (n <= cap) return MDP_OK;
   release();
-  cap = std::max(n, 16);
-  const size_t list_bytes = WorkList::bytes(cap);
-  MDP_HIP(lib_malloc(reinterpret_cast<void**>(&descs_d), sizeof(BDesc) * cap));
-  MDP_HIP(lib_malloc(reinterpret_cast<void**>(&lists_d), list_bytes * kNumLists));
-  MDP_HIP(lib_malloc(reinterpret_cast<void**>(&hdr_d), sizeof(Ctl) * cap));
-  MDP_HIP(lib_host_malloc(reinterpret_cast<void**>(&hdr_h), sizeof(Ctl) * cap));
-  MDP_HIP(lib_host_malloc(reinterpret_cast<void**>(&lists_h), list_bytes * kNumLists));
-  MDP_HIP(lib_host_malloc(reinterpret_cast<void**>(&descs_h), sizeof(BDesc) * cap));
+  const int want = std::max(n, 16);
+  const size_t list_bytes = WorkList::bytes(want);
+  hipError_t e = lib_malloc(reinterpret_cast<void**>(&descs_d), sizeof(BDesc) * want);
+  if (e == hipSuccess) e = lib_malloc(reinterpret_cast<void**>(&lists_d), list_bytes * kNumLists);
+  if (e == hipSuccess) e = lib_malloc(reinterpret_cast<void**>(&hdr_d), sizeof(Ctl) * want);
+  if (e == hipSuccess) e = lib_host_malloc(reinterpret_cast<void**>(&hdr_h), sizeof(Ctl) * want);
+  if (e == hipSuccess) e = lib_host_malloc(reinterpret_cast<void**>(&lists_h), list_bytes * kNumLists);
+  if (e == hipSuccess) e = lib_host_malloc(reinterpret_cast<void**>(&descs_h), sizeof(BDesc) * want);
+  if (e != hipSuccess) {
+    release();  // all or nothing: cap stays 0, so a later call allocates again
+    MDP_HIP(e);
+  }
+  cap = want;
   std::memset(descs_h, 0, sizeof(BDesc) * cap);
   return MDP_OK;
 }
