@@ -41,6 +41,13 @@ def test_version_and_defaults():
     c = native.CreateOpts()
     lib.mdp_default_create_opts(C.byref(c))
     assert c.validate == 1 and c.device == -1
+    # the binding's structs have the C layout's size (the library fills struct_size)
+    assert c.struct_size == C.sizeof(native.CreateOpts)
+    so = native.ServerOpts()
+    lib.mdp_default_server_opts(C.byref(so))
+    assert so.struct_size == C.sizeof(native.ServerOpts)
+    assert so.solve.struct_size == C.sizeof(native.SolveOpts) and so.solve.precision == 1
+    assert so.admit_threads == 4 and so.retire_threads == 4 and so.max_batch == 256
 
 
 def _create(S, A, rp, col, val, cost, gamma, **kw):
