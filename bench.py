@@ -173,9 +173,10 @@ def serving_leg(args, m):
     return out
 
 
-def rows_leg(args, m, h, inst, v, pi):
+def rows_leg(args, m, h, inst, v, pi, stream):
     """Times the path's other steps on the solved MDP: the policy product on
-    its own (20 launches at the greedy policy of the solution), solves with
+    its own (20 launches at the greedy policy of the solution, warm and after a
+    1 GiB cache scrub each), the sweep after a scrub, solves with
     Richardson, BiCGSTAB and TFQMR inner iterations, and the per-kernel
     breakdown of one float64 GMRES solve.  Rates use the library's
     algorithmic byte counts."""
@@ -200,6 +201,32 @@ def rows_leg(args, m, h, inst, v, pi):
     torch.cuda.synchronize()
     rows["policy_product"] = summary(m.mdp_profile_read(h))["policy_apply"]
     m.mdp_profile(h, False)
+
+    # Cold: a 1 GiB copy on the handle's stream before each launch, so none of
+    # the kernel's working set is left in the 256 MB Infinity Cache (the warm
+    # numbers above and in the solve can be served partly from it).
+    scrub_a = torch.zeros(1 << 27, dtype=torch.float64, device=v.device)
+    scrub_b = torch.empty_like(scrub_a)
+    Tv = torch.empty_like(v)
+    p_tmp = torch.empty_like(pi)
+    m.mdp_profile(h, kinds=["policy_apply", "bellman"])
+    for _ in range(20):
+        with torch.cuda.stream(stream):
+            scrub_b.copy_(scrub_a)
+        m.mdp_policy_apply(h, pi, v, y, 0)
+        with torch.cuda.stream(stream):
+            scrub_b.copy_(scrub_a)
+        m.mdp_bellman(h, v, Tv, p_tmp)
+    torch.cuda.synchronize()
+    raw = m.mdp_profile_read(h)
+    m.mdp_profile(h, False)
+    cold = summary(raw)
+    prof_bytes = {k: d["bytes"] / d["launches"] for k, d in raw.items() if d["launches"]}
+    for k, name in (("policy_apply", "policy_product_cold"), ("bellman", "bellman_cold")):
+        if k in cold:
+            cold[k]["working_set_mb"] = prof_bytes.get(k, 0.0) / 1e6
+            rows[name] = cold[k]
+    del scrub_a, scrub_b
 
     if inst.gamma <= 0.99:
         w = torch.zeros_like(v)
@@ -253,6 +280,10 @@ def rows_leg(args, m, h, inst, v, pi):
     torch.cuda.synchronize()
     rows["gmres_solve_kernels"] = summary(m.mdp_profile_read(h))
     m.mdp_profile(h, False)
+    pc, bc = rows.get("policy_product_cold", {}), rows.get("bellman_cold", {})
+    log(f"[bench] cold (after a 1 GiB scrub): policy product {pc.get('avg_us', float('nan')):.1f} us "
+        f"(working set {pc.get('working_set_mb', float('nan')):.0f} MB), sweep {bc.get('avg_us', float('nan')):.1f} us "
+        f"(working set {bc.get('working_set_mb', float('nan')):.0f} MB)")
     log(f"[bench] rows: policy product {rows['policy_product']['avg_us']:.1f} us, "
         f"richardson {rows.get('richardson_solve', {}).get('ms', float('nan')):.1f} ms, "
         f"bicgstab {rows['bicgstab_solve']['ms']:.1f} ms ({rows['bicgstab_solve']['inner']} its), "
@@ -335,6 +366,7 @@ def main():
                      stream=stream.cuda_stream, device=0, lanes_per_row=args.lanes,
                      low_precision=0 if args.no_mixed else (
                          m.MDP_BUILD_FP32 if args.mixed == "fp32" else m.MDP_BUILD_FP16))
+    create_s = time.time() - t  # host validation, upload and low-precision copies; not in `value`
     if args.autotune:
         t1 = time.time()
         lanes = m.mdp_autotune(h)
@@ -401,7 +433,7 @@ def main():
     sweep_gbs = sprof["bytes"] / sprof["launches"] / (sweep_avg_ms * 1e-3) / 1e9
 
     # ---- the other rows of the path, each on its own ----------------------------
-    rows = None if args.no_rows else rows_leg(args, m, h, inst, v, pi)
+    rows = None if args.no_rows else rows_leg(args, m, h, inst, v, pi, stream)
 
     # ---- mixed precision --------------------------------------------------------
     mixed = None
@@ -455,6 +487,7 @@ def main():
                      "bytes_per_launch": kernels[dom]["bytes_per_launch"],
                      "avg_us": kernels[dom]["avg_us"]},
         "cpu_baseline": cpu,
+        "create_s": create_s,
         "bellman_sweeps_per_s": args.sweeps / (ts1 - ts0),
         "bellman_kernel": {"avg_us": 1e3 * sweep_avg_ms, "gbs": sweep_gbs,
                            "frac": sweep_gbs / HBM_PEAK_GBS,
