@@ -588,8 +588,8 @@ mdp_status ensure_basis(mdp_handle* h, Prec prec, int m) {
 }
 
 mdp_status ensure_lowp(mdp_handle* h, Prec prec) {
-  if (prec == kF32 && !h->val32) {
-    MDP_HIP(dev_alloc(h, &h->val32, h->nnz));
+  if (prec == kF32 && !h->cv32) {
+    MDP_HIP(dev_alloc(h, &h->cv32, 2 * h->nnz));
     MDP_HIP(launch_build_lowp(h, MDP_BUILD_FP32));
   }
   if (prec == kF16 && !h->val16) {
@@ -746,7 +746,7 @@ mdp_status mdp_destroy(mdp_t h) {
   dev_free(h, h->col);
   dev_free(h, h->val);
   dev_free(h, h->cost);
-  dev_free(h, h->val32);
+  dev_free(h, h->cv32);
   dev_free(h, h->val16);
   dev_free(h, h->corr16);
   dev_free(h, h->cost32);

@@ -21,7 +21,7 @@ struct BDesc {
   const int* row_ptr;
   const int* col;
   const double* val;
-  const float* val32;
+  const float* cv32;  // packed float32 copy (see mdp_handle::cv32)
   const __half* val16;
   const double* corr16;
   const double* cost;

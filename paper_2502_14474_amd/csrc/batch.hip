@@ -83,7 +83,8 @@ __global__ __launch_bounds__(kBlock) void kb_bellman(const BDesc* __restrict__ d
                                                           D.pi, GM ? D.U64 : nullptr, part, tl,
                                                           lds_d);
     } else if (PREC == kF32) {
-      bellman_tile<L, U, float, float, false, float>(D.S, D.A, ts, RowIndex{D.row_ptr, D.kfix}, D.col, D.val32,
+      bellman_tile<L, U, float, float, false, float>(D.S, D.A, ts, RowIndex{D.row_ptr, D.kfix},
+                                                     reinterpret_cast<const int*>(D.cv32), D.cv32,
                                                      nullptr, D.cost, D.v32, D.gamma, nullptr,
                                                      D.pi, D.U32, part, tl, lds_d);
     } else {
@@ -139,7 +140,8 @@ __global__ __launch_bounds__(kBlock) void kb_arnoldi_apply(const BDesc* __restri
                                                       D.pi, D.U64, D.ldu, j, D.gamma, D.ctl,
                                                       D.part, tl, D.nb_apply);
     else if (PREC == kF32)
-      arnoldi_apply_tile<L, U, float, float, false>(D.S, D.A, RowIndex{D.row_ptr, D.kfix}, D.col, D.val32, nullptr,
+      arnoldi_apply_tile<L, U, float, float, false>(D.S, D.A, RowIndex{D.row_ptr, D.kfix},
+                                                    reinterpret_cast<const int*>(D.cv32), D.cv32, nullptr,
                                                     D.pi, D.U32, D.ldu, j, D.gamma, D.ctl, D.part,
                                                     tl, D.nb_apply);
     else
@@ -310,7 +312,7 @@ void BatchEngine::fill_desc(int i) {
   D.kfix = h->kfix;
   D.col = h->col;
   D.val = h->val;
-  D.val32 = h->val32;
+  D.cv32 = h->cv32;
   D.val16 = h->val16;
   D.corr16 = h->corr16;
   D.cost = h->cost;

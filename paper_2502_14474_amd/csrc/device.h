@@ -22,6 +22,7 @@
 #include "internal.h"
 
 #include <cmath>
+#include <type_traits>
 
 namespace mdp {
 
@@ -188,6 +189,11 @@ __device__ __forceinline__ void pipelined_rows(int n, RangeF range, const int* _
                                                const double* __restrict__ cost,
                                                const double* __restrict__ corr, SinkF sink) {
   constexpr int G = kBlock / L;
+  // The float32 copy is packed per row (columns, then values, in one run of
+  // words), so that a selected row of 16 entries is one 128-byte line: `col`
+  // and `val` then point at the same array, and entry e of the row [st, en)
+  // has its column at word st + e and its value at word en + e.
+  constexpr bool PACKED = std::is_same<VT, float>::value;
   const Gather<XT> gx(x, nx);
   constexpr int STEP = G * U;
   const int g = threadIdx.x / L, lane = threadIdx.x % L;
@@ -214,8 +220,8 @@ __device__ __forceinline__ void pipelined_rows(int n, RangeF range, const int* _
       const int e = st[u] + lane;
       const bool ok = e < en[u];
       const int es = ok ? e : 0;
-      const int craw = ld_col(col + es);
-      const AT praw = static_cast<AT>(ld_val(val + es));
+      const int craw = ld_col(col + (PACKED ? st[u] : 0) + es);
+      const AT praw = static_cast<AT>(ld_val(val + (PACKED ? en[u] : 0) + es));
       c[u] = ok ? craw : -1;
       p[u] = ok ? praw : AT(0);
       if (NEEDCOST) gc[u] = cost[ri[u]];
@@ -255,8 +261,8 @@ __device__ __forceinline__ void pipelined_rows(int n, RangeF range, const int* _
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       for (int e = cst[u] + lane + L; e < cen[u]; e += L) {
-        const AT xv = static_cast<AT>(gx(ld_col(col + e)));
-        acc[u] = fma(static_cast<AT>(ld_val(val + e)), xv, acc[u]);
+        const AT xv = static_cast<AT>(gx(ld_col(col + (PACKED ? cst[u] : 0) + e)));
+        acc[u] = fma(static_cast<AT>(ld_val(val + (PACKED ? cen[u] : 0) + e)), xv, acc[u]);
         if (CORR) xs[u] += xv;
       }
     }

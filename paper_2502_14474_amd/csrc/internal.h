@@ -90,7 +90,9 @@ struct mdp_handle {
   int32_t* col = nullptr;
   double* val = nullptr;
   double* cost = nullptr;
-  float* val32 = nullptr;       // float32 copy
+  float* cv32 = nullptr;        // float32 copy, packed per row: the row's int32 columns, then its
+                                // float32 values (2*nnz words; entry e of the row [st, en) has its
+                                // column at word st + e and its value at word en + e)
   __half* val16 = nullptr;      // float16 copy
   double* corr16 = nullptr;     // per-row correction 1 - sum fp16(p)
   float* cost32 = nullptr;      // float32 costs

@@ -137,6 +137,25 @@ __global__ __launch_bounds__(kBlock) void k_to_f32(const double* __restrict__ a,
     b[i] = static_cast<float>(a[i]);
 }
 
+// The packed float32 copy: groups of 8 lanes per row copy its columns to
+// words [2 st, st + en) and its values, rounded to float32, to [st + en, 2 en).
+__global__ __launch_bounds__(kBlock) void k_pack_f32(int64_t rows, const int* __restrict__ row_ptr, int kfix,
+                                                    const int* __restrict__ col, const double* __restrict__ val,
+                                                    float* __restrict__ cv) {
+  constexpr int G = 8;
+  int* __restrict__ cvi = reinterpret_cast<int*>(cv);
+  const int l = threadIdx.x % G;
+  for (int64_t r = (static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x) / G; r < rows;
+       r += static_cast<int64_t>(gridDim.x) * (kBlock / G)) {
+    const int st = kfix > 0 ? static_cast<int>(r) * kfix : row_ptr[r];
+    const int en = kfix > 0 ? st + kfix : row_ptr[r + 1];
+    for (int e = st + l; e < en; e += G) {
+      cvi[st + e] = col[e];
+      cv[en + e] = static_cast<float>(val[e]);
+    }
+  }
+}
+
 // One thread per row: float16 values (round to nearest even) and the row
 // correction c_r = 1 - sum_j double(fp16(p_rj)) summed in entry order.
 __global__ __launch_bounds__(kBlock) void k_to_f16_rows(int64_t rows,
@@ -263,7 +282,7 @@ hipError_t launch_bellman(mdp_handle* h, Prec prec, const void* v, double* Tv, i
       const size_t lds = static_cast<size_t>(ts) * h->A * sizeof(double) +
                          (static_cast<size_t>(ts) * h->A + 1) * sizeof(int);
       k_bellman<L, U, float, float, false, float><<<nb, kBlock, lds, h->stream>>>(
-          h->S, h->A, ts, h->row_ptr, h->kfix, h->col, h->val32, nullptr, h->cost,
+          h->S, h->A, ts, h->row_ptr, h->kfix, reinterpret_cast<const int*>(h->cv32), h->cv32, nullptr, h->cost,
           static_cast<const float*>(v), h->gamma, Tv, pi, static_cast<float*>(r0), part);
     } else {
       const size_t lds = static_cast<size_t>(ts) * h->A * sizeof(double) +
@@ -347,7 +366,8 @@ hipError_t launch_arnoldi_step(mdp_handle* h, Prec prec, const int32_t* pi, int 
           h->ctl, h->part.buf);
     else if (prec == kF32)
       k_arnoldi_apply<L, U, float, float, false><<<nb, kBlock, 0, h->stream>>>(
-          h->S, h->A, h->row_ptr, h->kfix, h->col, h->val32, nullptr, pi, h->U32, h->ldu, j, h->gamma,
+          h->S, h->A, h->row_ptr, h->kfix, reinterpret_cast<const int*>(h->cv32), h->cv32, nullptr, pi, h->U32,
+          h->ldu, j, h->gamma,
           h->ctl, h->part.buf);
     else
       k_arnoldi_apply<L, U, __half, float, true><<<nb, kBlock, 0, h->stream>>>(
@@ -410,7 +430,8 @@ hipError_t launch_rich_begin(mdp_handle* h, double tol, int cur, int steps) {
 
 hipError_t launch_build_lowp(mdp_handle* h, int which) {
   if (which & MDP_BUILD_FP32) {
-    k_to_f32<<<grid_stride(h->nnz), kBlock, 0, h->stream>>>(h->val, h->val32, h->nnz);
+    k_pack_f32<<<grid_stride(h->rows), kBlock, 0, h->stream>>>(h->rows, h->row_ptr, h->kfix, h->col, h->val,
+                                                                h->cv32);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }

@@ -68,7 +68,7 @@ static int64_t footprint_of(int64_t S, int32_t A, int64_t nnz, const mdp_solve_o
   int64_t b = nnz * 12 + (rows + 1) * 4 + rows * 8;          // CSR + costs
   b += S * (8 * 4 + 4 * 2);                                   // v, Tv, x2, io, pi, pi_io
   b += static_cast<int64_t>(o.restart + 1) * ldu * (mixed ? 4 : 8);
-  if (o.precision == MDP_MIXED_FP32) b += nnz * 4 + S * 4;
+  if (o.precision == MDP_MIXED_FP32) b += nnz * 8 + S * 4;  // packed columns + float32 values
   if (o.precision == MDP_MIXED_FP16) b += nnz * 2 + rows * 8 + S * 4;
   b += static_cast<int64_t>(partials_doubles(S, A, kMaxRestart)) * 8 + sizeof(Ctl);
   return b;
