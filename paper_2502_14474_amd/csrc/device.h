@@ -220,8 +220,15 @@ __device__ __forceinline__ void pipelined_rows(int n, RangeF range, const int* _
       const int e = st[u] + lane;
       const bool ok = e < en[u];
       const int es = ok ? e : 0;
-      const int craw = ld_col(col + (PACKED ? st[u] : 0) + es);
-      const AT praw = static_cast<AT>(ld_val(val + (PACKED ? en[u] : 0) + es));
+      int craw;
+      AT praw;
+      if constexpr (PACKED) {  // word indices reach 2*nnz: formed in 64 bits
+        craw = ld_col(col + (static_cast<int64_t>(st[u]) + es));
+        praw = static_cast<AT>(ld_val(val + (static_cast<int64_t>(en[u]) + es)));
+      } else {
+        craw = ld_col(col + es);
+        praw = static_cast<AT>(ld_val(val + es));
+      }
       c[u] = ok ? craw : -1;
       p[u] = ok ? praw : AT(0);
       if (NEEDCOST) gc[u] = cost[ri[u]];
@@ -261,8 +268,10 @@ __device__ __forceinline__ void pipelined_rows(int n, RangeF range, const int* _
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       for (int e = cst[u] + lane + L; e < cen[u]; e += L) {
-        const AT xv = static_cast<AT>(gx(ld_col(col + (PACKED ? cst[u] : 0) + e)));
-        acc[u] = fma(static_cast<AT>(ld_val(val + (PACKED ? cen[u] : 0) + e)), xv, acc[u]);
+        const int64_t co = PACKED ? static_cast<int64_t>(cst[u]) + e : e;
+        const int64_t vo = PACKED ? static_cast<int64_t>(cen[u]) + e : e;
+        const AT xv = static_cast<AT>(gx(ld_col(col + co)));
+        acc[u] = fma(static_cast<AT>(ld_val(val + vo)), xv, acc[u]);
         if (CORR) xs[u] += xv;
       }
     }

@@ -138,7 +138,8 @@ __global__ __launch_bounds__(kBlock) void k_to_f32(const double* __restrict__ a,
 }
 
 // The packed float32 copy: groups of 8 lanes per row copy its columns to
-// words [2 st, st + en) and its values, rounded to float32, to [st + en, 2 en).
+// words [2 st, st + en) and its values, rounded to float32, to [st + en, 2 en)
+// (word indices up to 2*nnz, so they are formed in 64 bits).
 __global__ __launch_bounds__(kBlock) void k_pack_f32(int64_t rows, const int* __restrict__ row_ptr, int kfix,
                                                     const int* __restrict__ col, const double* __restrict__ val,
                                                     float* __restrict__ cv) {
@@ -149,9 +150,10 @@ __global__ __launch_bounds__(kBlock) void k_pack_f32(int64_t rows, const int* __
        r += static_cast<int64_t>(gridDim.x) * (kBlock / G)) {
     const int st = kfix > 0 ? static_cast<int>(r) * kfix : row_ptr[r];
     const int en = kfix > 0 ? st + kfix : row_ptr[r + 1];
+    // word indices reach 2*nnz, beyond int32 once nnz >= 2^30: 64-bit sums
     for (int e = st + l; e < en; e += G) {
-      cvi[st + e] = col[e];
-      cv[en + e] = static_cast<float>(val[e]);
+      cvi[static_cast<int64_t>(st) + e] = col[e];
+      cv[static_cast<int64_t>(en) + e] = static_cast<float>(val[e]);
     }
   }
 }

@@ -148,3 +148,18 @@ def test_config4_full_mixed_fp16(c4):
         v, pi, st = h.solve(alpha=1e-2, precision=m.MDP_MIXED_FP16, rtol_cert=1e-9)
     assert st["status"] == 0, st
     _certify(inst, v, 1e-8, "config4 mixed fp16")
+
+
+def test_config4_full_mixed_fp32_packed_copy(c4):
+    """The packed float32 copy holds 2*nnz = 3.07e9 words here, past the
+    int32 range: its build and its row loads form word indices in 64 bits.
+    The mixed solve reaches the target and its sweep at the solution agrees
+    with the float64 handle's."""
+    import paper_2502_14474_amd as m
+    inst = c4
+    assert 2 * inst.nnz > 2 ** 31
+    print("[case] config 4 mixed fp32 with the packed copy", flush=True)
+    with m.MDP.from_instance(inst, validate=False, low_precision=m.MDP_BUILD_FP32) as h:
+        v, pi, st = h.solve(alpha=1e-2, precision=m.MDP_MIXED_FP32, rtol_cert=1e-9)
+    assert st["status"] == 0, st
+    _certify(inst, v, 1e-8, "config4 mixed fp32")
