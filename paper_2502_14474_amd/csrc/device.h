@@ -222,9 +222,12 @@ __device__ __forceinline__ void pipelined_rows(int n, RangeF range, const int* _
       const int es = ok ? e : 0;
       int craw;
       AT praw;
-      if constexpr (PACKED) {  // word indices reach 2*nnz: formed in 64 bits
-        craw = ld_col(col + (static_cast<int64_t>(st[u]) + es));
-        praw = static_cast<AT>(ld_val(val + (static_cast<int64_t>(en[u]) + es)));
+      if constexpr (PACKED) {
+        // word indices reach 2*nnz: formed in 64 bits.  Idle lanes read word 0,
+        // one address for all of them, as the unpacked arrays' idle lanes read
+        // entry 0 (an address inside each row would cost a line per row).
+        craw = ld_col(col + (ok ? static_cast<int64_t>(st[u]) + e : int64_t{0}));
+        praw = static_cast<AT>(ld_val(val + (ok ? static_cast<int64_t>(en[u]) + e : int64_t{0})));
       } else {
         craw = ld_col(col + es);
         praw = static_cast<AT>(ld_val(val + es));
