@@ -91,9 +91,12 @@ typedef struct {
   size_t struct_size;     /* sizeof(mdp_create_opts) */
   void* stream;           /* hipStream_t to run on; NULL: the handle creates its own stream */
   int32_t device;         /* HIP device ordinal; -1: the current device */
-  int32_t validate;       /* MDP_VALIDATE_*: check the MDP data (see the layout above) */
-  int32_t low_precision;  /* MDP_BUILD_* bits */
-  int32_t lanes_per_row;  /* 0: chosen from the mean row length; else 1,2,4,...,64 */
+  int32_t validate;       /* MDP_VALIDATE_* (default MDP_VALIDATE_HOST): check the MDP data */
+  int32_t low_precision;  /* MDP_BUILD_* bits (also built on first use by a mixed solve); the
+                             float32 copy is packed per row, the float16 copy carries a float64
+                             per-row correction */
+  int32_t lanes_per_row;  /* 0: from the autotuner's cache, else from the mean row length;
+                             otherwise a power of two in [2, 64] */
   int32_t col_blocks;     /* column-blocked copy of P for the float64 sweep: -1 (default)
                              builds one when S >= 2^21 and at least half of the entries lie
                              outside their row's column slice (slices of 4 MB of v);
