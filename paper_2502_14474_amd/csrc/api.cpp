@@ -742,6 +742,14 @@ void mdp_default_solve_opts(mdp_solve_opts* o) {
 mdp_status mdp_destroy(mdp_t h) {
   if (!h) return MDP_OK;
   if (h->stream) (void)hipStreamSynchronize(h->stream);
+  if (h->arena) {  // the arrays inside it go with it
+    dev_free(h, h->arena);
+    h->row_ptr = h->col = nullptr;
+    h->val = h->cost = h->v = h->Tv = h->x2 = h->io = nullptr;
+    h->pi = h->pi_io = nullptr;
+    h->part.buf = nullptr;
+    h->ctl = nullptr;
+  }
   dev_free(h, h->row_ptr);
   dev_free(h, h->col);
   dev_free(h, h->val);
@@ -886,10 +894,40 @@ mdp_status mdp_create(int64_t S, int32_t A, const int64_t* row_ptr, const int32_
     h->own_stream = true;
   }
   h->ldu = (S + 255) / 256 * 256;
-  CHK(dev_alloc(h, &h->row_ptr, rows + 1));
-  CHK(dev_alloc(h, &h->col, nnz));
-  CHK(dev_alloc(h, &h->val, nnz));
-  CHK(dev_alloc(h, &h->cost, rows));
+  // One allocation holds the CSR arrays, the S-vectors, the partials and the
+  // control block: one pool call and one stream sync per create, one free.
+  h->part.cap = partials_doubles(S, A, kMaxRestart);
+  {
+    auto up = [](size_t b) { return (b + 255) / 256 * 256; };
+    const size_t sz[] = {static_cast<size_t>(rows + 1) * sizeof(int32_t), static_cast<size_t>(nnz) * sizeof(int32_t),
+                         static_cast<size_t>(nnz) * sizeof(double),       static_cast<size_t>(rows) * sizeof(double),
+                         static_cast<size_t>(S) * sizeof(double),         static_cast<size_t>(S) * sizeof(double),
+                         static_cast<size_t>(S) * sizeof(double),         static_cast<size_t>(S) * sizeof(double),
+                         static_cast<size_t>(S) * sizeof(int32_t),        static_cast<size_t>(S) * sizeof(int32_t),
+                         h->part.cap * sizeof(double),                    sizeof(Ctl)};
+    size_t total = 0;
+    for (size_t b : sz) total += up(b);
+    CHK(dev_alloc(h, &h->arena, total));
+    char* at = h->arena;
+    int k = 0;
+    auto take = [&]() {
+      char* q = at;
+      at += up(sz[k++]);
+      return q;
+    };
+    h->row_ptr = reinterpret_cast<int32_t*>(take());
+    h->col = reinterpret_cast<int32_t*>(take());
+    h->val = reinterpret_cast<double*>(take());
+    h->cost = reinterpret_cast<double*>(take());
+    h->v = reinterpret_cast<double*>(take());
+    h->Tv = reinterpret_cast<double*>(take());
+    h->x2 = reinterpret_cast<double*>(take());
+    h->io = reinterpret_cast<double*>(take());
+    h->pi = reinterpret_cast<int32_t*>(take());
+    h->pi_io = reinterpret_cast<int32_t*>(take());
+    h->part.buf = reinterpret_cast<double*>(take());
+    h->ctl = reinterpret_cast<Ctl*>(take());
+  }
   // Rows are stored in the tile-by-tile, action-major order of row_of():
   // the natural arrays go to a staging block and one kernel moves them.
   // Device validation reads the natural arrays before they move.
@@ -952,15 +990,6 @@ mdp_status mdp_create(int64_t S, int32_t A, const int64_t* row_ptr, const int32_
   }
   h->maximize = o.objective == MDP_MAXIMIZE_REWARD;
   if (h->maximize) CHK(launch_negate(h->stream, h->cost, rows));  // rewards -> costs
-  CHK(dev_alloc(h, &h->v, S));
-  CHK(dev_alloc(h, &h->Tv, S));
-  CHK(dev_alloc(h, &h->x2, S));
-  CHK(dev_alloc(h, &h->io, S));
-  CHK(dev_alloc(h, &h->pi, S));
-  CHK(dev_alloc(h, &h->pi_io, S));
-  h->part.cap = partials_doubles(S, A, kMaxRestart);
-  CHK(dev_alloc(h, &h->part.buf, h->part.cap));
-  CHK(dev_alloc(h, &h->ctl, 1));
   h->ctl_host = ctl_slot_take();
   if (!h->ctl_host) CHK(hipErrorOutOfMemory);
   {

@@ -90,6 +90,8 @@ struct mdp_handle {
   int32_t* col = nullptr;
   double* val = nullptr;
   double* cost = nullptr;
+  char* arena = nullptr;        // one allocation holding row_ptr, col, val, cost, the S-vectors,
+                                // the partials and the control block
   float* cv32 = nullptr;        // float32 copy, packed per row: the row's int32 columns, then its
                                 // float32 values (2*nnz words; entry e of the row [st, en) has its
                                 // column at word st + e and its value at word en + e)
