@@ -103,6 +103,7 @@ hipError_t pool_reserve(int dev, int64_t delta) {
   if (e != hipSuccess) return e;
   d->reserved = static_cast<uint64_t>(std::max<int64_t>(0, static_cast<int64_t>(d->reserved) + delta));
   uint64_t keep = kPoolKeepBytes + d->reserved;
+  std::shared_lock<std::shared_mutex> g(alloc_lock());  // trimming releases memory
   e = hipMemPoolSetAttribute(d->pool, hipMemPoolAttrReleaseThreshold, &keep);
   if (e == hipSuccess && delta < 0) e = hipMemPoolTrimTo(d->pool, static_cast<size_t>(keep));
   return e;
