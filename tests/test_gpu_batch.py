@@ -89,3 +89,38 @@ def test_batch_rejects_bad_input():
             m.mdp_solve_batch([h], [v], [pi], inner=1)
     finally:
         m.mdp_destroy(h)
+
+
+def test_concurrent_batches_lease_separate_engines():
+    """Two host threads run batched solves at once (each leases its own cached
+    engine); both give bitwise what the same batch gives alone."""
+    import threading
+
+    import paper_2502_14474_amd as m
+    groups = [[config1(S=600, seed=s) for s in range(3)], [config2(S=5000, A=4, seed=s) for s in range(3)]]
+    handles = [[m.mdp_create(i.S, i.A, i.row_ptr, i.col, i.val, i.cost, i.gamma) for i in g] for g in groups]
+    try:
+        def run(k, out):
+            vs = [np.empty(i.S) for i in groups[k]]
+            pis = [np.empty(i.S, np.int32) for i in groups[k]]
+            status, _ = m.mdp_solve_batch(handles[k], vs, pis, alpha=1e-2)
+            out[k] = (status, vs, pis)
+
+        alone = {}
+        for k in range(2):
+            run(k, alone)
+        together = {}
+        threads = [threading.Thread(target=run, args=(k, together)) for k in range(2)]
+        for t in threads:
+            t.start()
+        for t in threads:
+            t.join(timeout=60)
+        assert not any(t.is_alive() for t in threads)
+    finally:
+        for g in handles:
+            for h in g:
+                m.mdp_destroy(h)
+    for k in range(2):
+        assert alone[k][0] == 0 and together[k][0] == 0
+        assert all(np.array_equal(a, b) for a, b in zip(alone[k][1], together[k][1]))
+        assert all(np.array_equal(a, b) for a, b in zip(alone[k][2], together[k][2]))
