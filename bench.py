@@ -96,6 +96,7 @@ def cpu_baseline(args, full_inst):
     scale = full_inst.nnz / twin.nnz
     est = dt * scale
     return {"value": 1.0 / est, "unit": "solves/s", "cores": 1, "kind": "oracle",
+            "host_cores_available": len(os.sched_getaffinity(0)),
             "sample": (f"oracle exact policy iteration on a {S_s}-state twin of the workload "
                        f"(same generator, A, k, gamma): {dt:.2f} s, {r['iters']} improvement "
                        f"steps, scaled x{scale:.1f} by nonzeros to {est:.1f} s per full solve; "
