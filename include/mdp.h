@@ -166,10 +166,14 @@ void mdp_default_create_opts(mdp_create_opts* o);
 void mdp_default_eval_opts(mdp_eval_opts* o);
 void mdp_default_solve_opts(mdp_solve_opts* o);
 
-/* Create a handle: copy the MDP (layout above) to the device, optionally
- * validate it, and build the requested reduced-precision copies of P.
- * opt may be NULL (defaults).  nnz must be below 2^31.  On success *out owns
- * all device memory of the MDP. */
+/* Create a handle from offline data (the paper's "Implementation" section
+ * builds an MDP from offline data or from online simulation): copy the MDP
+ * (layout above) to the device, optionally validate it, and build the
+ * requested reduced-precision copies of P.  opt may be NULL (defaults).
+ * Size limits (MDP_E_NOTSUP beyond them, checked before any array is read
+ * past row_ptr[S*A]): A <= 4096, S*A < 2^31 - 1, S < 2^29 (the kernels form
+ * 32-bit byte offsets into float64 vectors) and nnz <= 2^31 - 4096.  On
+ * success *out owns all device memory of the MDP. */
 mdp_status mdp_create(int64_t S, int32_t A, const int64_t* row_ptr, const int32_t* col,
                       const double* val, const double* cost, double gamma,
                       const mdp_create_opts* opt, mdp_t* out);
@@ -194,7 +198,9 @@ typedef int32_t (*mdp_rows_fn)(void* user, int64_t s_begin, int64_t s_end, int32
 mdp_status mdp_create_from_rows(int64_t S, int32_t A, int32_t k_max, mdp_rows_fn fn, void* user,
                                 double gamma, const mdp_create_opts* opt, mdp_t* out);
 
-/* One fused Bellman sweep in float64 (greedy step of policy iteration):
+/* One fused Bellman sweep in float64: the greedy (policy improvement) step of
+ * policy iteration, section "Problem Setting and Solution Methods", applied to
+ * the minimisation of discounted cost stated in the "Summary":
  *   Tv[s] = min_a g(s,a) + gamma * sum_j P[(s,a),j] v[j],
  *   policy[s] = the lowest action attaining the minimum,
  *   *res_inf = max_s |Tv[s] - v[s]|.
@@ -202,29 +208,37 @@ mdp_status mdp_create_from_rows(int64_t S, int32_t A, int32_t k_max, mdp_rows_fn
 mdp_status mdp_bellman(mdp_t h, const double* v, double* Tv, int32_t* policy, double* res_inf);
 
 /* Product with the transition matrix of a policy, gathering rows s*A+policy[s]
- * of P without forming P_pi (policy evaluation operator):
+ * of P without forming P_pi: the operator of the linear system that policy
+ * evaluation solves (section "Problem Setting and Solution Methods"):
  *   mode 0: y = x - gamma * P_pi x         ((I - gamma P_pi) x)
  *   mode 1: y = g_pi + gamma * P_pi x      (T_pi x)
  * policy: int32[S] with entries in [0,A) (else MDP_E_INVAL); x, y: double[S]. */
 mdp_status mdp_policy_apply(mdp_t h, const int32_t* policy, const double* x, double* y,
                             int32_t mode);
 
-/* Approximate policy evaluation: solve (I - gamma P_pi) v = g_pi starting from
- * v0 (NULL: zero) with the inner solver and tolerance of opt (NULL: defaults).
+/* Approximate policy evaluation (section "Problem Setting and Solution
+ * Methods": the inexact evaluation step of iPI, with a caller-chosen inner
+ * iterative solver and level of inexactness): solve (I - gamma P_pi) v = g_pi
+ * starting from v0 (NULL: zero) with the inner solver and tolerance of opt
+ * (NULL: defaults).
  * v: double[S] output.  stats may be NULL.  Returns MDP_W_MAXITER when the
  * tolerance was not met within max_iter steps. */
 mdp_status mdp_policy_eval(mdp_t h, const int32_t* policy, const double* v0, double* v,
                            const mdp_eval_opts* opt, mdp_stats* stats);
 
-/* Inexact policy iteration from v0 (NULL: zero).  Stops at the first sweep
+/* Inexact policy iteration (section "Problem Setting and Solution Methods":
+ * greedy steps alternating with approximate evaluations; value iteration and
+ * modified policy iteration are the special cases of Richardson inner solves
+ * with one or a fixed number of steps) from v0 (NULL: zero).  Stops at the first sweep
  * with ||T v_k - v_k||_inf <= atol (and the certified relative test if
  * rtol_cert > 0); returns v = v_k and policy = the greedy policy of v_k.
  * Returns MDP_W_MAXITER with the last iterate after max_outer sweeps. */
 mdp_status mdp_solve(mdp_t h, const double* v0, double* v, int32_t* policy,
                      const mdp_solve_opts* opt, mdp_stats* stats);
 
-/* Batched inexact policy iteration: solve n MDPs (handles on one device)
- * together.  Each round advances every unfinished MDP by one phase (a Bellman
+/* Batched inexact policy iteration (an extension: the paper defines no
+ * batched or served solve; each MDP follows mdp_solve): solve n MDPs (handles
+ * on one device) together.  Each round advances every unfinished MDP by one phase (a Bellman
  * sweep, or one GMRES cycle with its restart) in persistent kernels that walk
  * a table of (MDP, tile) work items; the cycle's Arnoldi steps are replayed
  * from captured HIP graphs (see mdp_solve_opts.launch).  The engine and its
@@ -239,7 +253,8 @@ mdp_status mdp_solve_batch(mdp_t* handles, int32_t n, const double* const* v0, d
                            int32_t* const* policy, const mdp_solve_opts* opt, mdp_stats* stats);
 
 /* ---- serving: continuous batching of solve requests ----------------------
- * A server owns a worker thread on one GPU.  Submitted MDPs wait in a queue;
+ * An extension the paper does not define: requests are solved as by
+ * mdp_solve_batch.  A server owns a worker thread on one GPU.  Submitted MDPs wait in a queue;
  * the worker admits them while the estimated device footprint of the resident
  * set stays within hbm_budget_bytes and at most max_batch are resident, keeps
  * admitted MDPs and their iterates resident, and advances all of them with

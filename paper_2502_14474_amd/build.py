@@ -1,40 +1,66 @@
-"""Build the C-ABI shared library libmdp.so for gfx950 with hipcc (in-tree)."""
+"""Build the C-ABI shared library libmdp.so for gfx950 with hipcc (in-tree).
+
+Each source is compiled to an object of its own (in parallel, under _build/),
+then the objects are linked into libmdp.so."""
 import os
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmdp.so")
-SOURCES = ["kernels.hip", "colblock.hip", "krylov.hip", "vecops.hip", "batch.hip", "api.cpp", "serve.cpp", "tune.cpp"]
+OBJDIR = os.path.join(ROOT, "_build")
+SOURCES = ["kernels.hip", "colblock.hip", "krylov.hip", "vecops.hip", "batch.hip", "api.cpp", "serve.cpp",
+           "tune.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
-    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
     # one rounding per operation: every fused multiply-add is written out
     "-ffp-contract=off",
     # no packed float32 instructions
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wno-unused-command-line-argument",
 ]
+NOISE = ("unknown target feature", "packed-fp32-ops", "warning generated")
+
+
+def _run(cmd):
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    msgs = [ln for ln in (r.stdout + r.stderr).splitlines() if not any(n in ln for n in NOISE)]
+    return r.returncode, msgs
 
 
 def build(verbose=False, out=LIB, defines=()):
-    cmd = [HIPCC] + FLAGS + ["-I", os.path.join(ROOT, "include"), "-I", CSRC]
-    cmd += ["-D" + d for d in defines]
-    cmd += [os.path.join(CSRC, s) for s in SOURCES]
-    tmp = out + ".tmp"
-    cmd += ["-o", tmp]
+    os.makedirs(OBJDIR, exist_ok=True)
+    tag = "" if not defines else "_" + str(abs(hash(tuple(defines))))
+    inc = ["-I", os.path.join(ROOT, "include"), "-I", CSRC] + ["-D" + d for d in defines]
+    jobs = []
+    for s in SOURCES:
+        obj = os.path.join(OBJDIR, os.path.splitext(s)[0] + tag + ".o")
+        jobs.append((s, obj, [HIPCC] + FLAGS + inc + ["-c", os.path.join(CSRC, s), "-o", obj]))
     if verbose:
-        print(" ".join(cmd), flush=True)
-    r = subprocess.run(cmd, capture_output=True, text=True)
-    noise = ("unknown target feature", "packed-fp32-ops", "warning generated")
-    msgs = [ln for ln in (r.stdout + r.stderr).splitlines() if not any(n in ln for n in noise)]
-    if r.returncode != 0:
-        raise RuntimeError("hipcc failed:\n" + "\n".join(msgs))
-    if verbose and msgs:
-        print("\n".join(msgs))
+        for _, _, c in jobs:
+            print(" ".join(c), flush=True)
+    workers = max(1, min(len(jobs), int(os.environ.get("MAX_JOBS", "8"))))
+    with ThreadPoolExecutor(workers) as ex:
+        results = list(ex.map(lambda j: (j[0],) + _run(j[2]), jobs))
+    errors = [f"{s}:\n" + "\n".join(m) for s, rc, m in results if rc != 0]
+    if errors:
+        raise RuntimeError("hipcc failed:\n" + "\n".join(errors))
+    if verbose:
+        for s, _, m in results:
+            if m:
+                print(f"{s}:\n" + "\n".join(m))
+    tmp = out + ".tmp"
+    link = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + [o for _, o, _ in jobs]
+    if verbose:
+        print(" ".join(link), flush=True)
+    rc, msgs = _run(link)
+    if rc != 0:
+        raise RuntimeError("hipcc link failed:\n" + "\n".join(msgs))
     os.replace(tmp, out)
     return out
 

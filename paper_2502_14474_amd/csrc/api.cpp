@@ -483,6 +483,15 @@ bool stats_ok(const mdp_stats* st) { return !st || st->struct_size >= sizeof(mdp
 }  // namespace
 
 // ---- validation -------------------------------------------------------------
+mdp_status check_size_limits(int64_t S, int32_t A, int64_t nnz) {
+  if (A > 4096) return fail(MDP_E_NOTSUP, "A above 4096 is not supported");
+  if (S * static_cast<int64_t>(A) >= (int64_t{1} << 31) - 1)
+    return fail(MDP_E_NOTSUP, "S*A must be below 2^31");
+  if (S > kMaxStates) return fail(MDP_E_NOTSUP, "S must be below 2^29");
+  if (nnz > kMaxNnz) return fail(MDP_E_NOTSUP, "nnz must be at most 2^31 - 4096");
+  return MDP_OK;
+}
+
 // Structure of row_ptr; checked in every mode, since kernels index rows by it.
 mdp_status validate_row_ptr(int64_t S, int32_t A, const int64_t* rp) {
   const int64_t rows = S * A;
@@ -491,8 +500,7 @@ mdp_status validate_row_ptr(int64_t S, int32_t A, const int64_t* rp) {
     if (rp[r + 1] <= rp[r])
       return fail(MDP_E_INVAL, "row_ptr must increase (row " + std::to_string(r) +
                                    " of state " + std::to_string(r / A) + " is empty or decreasing)");
-  if (rp[rows] >= (int64_t{1} << 31)) return fail(MDP_E_NOTSUP, "nnz must be below 2^31");
-  return MDP_OK;
+  return check_size_limits(S, A, rp[rows]);
 }
 
 // The first failure of the entry checks, as a message; shared by the host and
@@ -810,9 +818,7 @@ mdp_status mdp_create(int64_t S, int32_t A, const int64_t* row_ptr, const int32_
     o = *opt;
   }
   if (S < 1 || A < 1) return fail(MDP_E_INVAL, "S and A must be at least 1");
-  if (A > 4096) return fail(MDP_E_NOTSUP, "A above 4096 is not supported");
-  if (S * static_cast<int64_t>(A) >= (int64_t{1} << 31) - 1)
-    return fail(MDP_E_NOTSUP, "S*A must be below 2^31");
+  MDP_TRY(check_size_limits(S, A, -1));
   if (!(gamma >= 0.0 && gamma < 1.0)) return fail(MDP_E_INVAL, "gamma must lie in [0,1)");
   if (!row_ptr || !col || !val || !cost) return fail(MDP_E_INVAL, "NULL MDP array");
   if (o.lanes_per_row != 0 &&
@@ -841,7 +847,7 @@ mdp_status mdp_create(int64_t S, int32_t A, const int64_t* row_ptr, const int32_
   }
   nnz = rp_host[rows];
   if (nnz < rows) return fail(MDP_E_INVAL, "row_ptr[S*A] smaller than the number of rows");
-  if (nnz >= (int64_t{1} << 31)) return fail(MDP_E_NOTSUP, "nnz must be below 2^31");
+  MDP_TRY(check_size_limits(S, A, nnz));
   MDP_TRY(validate_row_ptr(S, A, rp_host));
   if (o.validate == MDP_VALIDATE_HOST) {
     if (dev_in) {
@@ -1046,8 +1052,8 @@ mdp_status mdp_create_from_rows(int64_t S, int32_t A, int32_t k_max, mdp_rows_fn
   if (!fn) return fail(MDP_E_INVAL, "row function is NULL");
   if (S < 1 || A < 1) return fail(MDP_E_INVAL, "S and A must be at least 1");
   if (k_max < 1) return fail(MDP_E_INVAL, "k_max must be at least 1");
+  MDP_TRY(check_size_limits(S, A, -1));
   const int64_t rows = S * A;
-  if (rows >= (int64_t{1} << 31) - 1) return fail(MDP_E_NOTSUP, "S*A must be below 2^31");
   const unsigned nt = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
   // ranges of about 2^20 padded entries, handed out to the threads in turn
   const int64_t chunk = std::max<int64_t>(1, (int64_t{1} << 20) / (static_cast<int64_t>(A) * k_max));
@@ -1087,7 +1093,7 @@ mdp_status mdp_create_from_rows(int64_t S, int32_t A, int32_t k_max, mdp_rows_fn
     rp[r + 1] = rp[r] + len[r];
   }
   const int64_t nnz = rp[rows];
-  if (nnz >= (int64_t{1} << 31)) return fail(MDP_E_NOTSUP, "nnz must be below 2^31");
+  MDP_TRY(check_size_limits(S, A, nnz));
   std::vector<int32_t> col;
   std::vector<double> val;
   try {

@@ -62,18 +62,24 @@ template <typename T>
 struct Gather {
   __amdgpu_buffer_rsrc_t r;
   __device__ __forceinline__ Gather(const T* x, int64_t n)
-      : r(__builtin_amdgcn_make_buffer_rsrc(const_cast<T*>(x), static_cast<short>(0),
-                                            static_cast<int>(n * static_cast<int64_t>(sizeof(T))),
-                                            kRawBufferWord3)) {}
+      : r(__builtin_amdgcn_make_buffer_rsrc(
+            const_cast<T*>(x), static_cast<short>(0),
+            static_cast<int>(static_cast<uint32_t>(n * static_cast<int64_t>(sizeof(T)))), kRawBufferWord3)) {}
   __device__ __forceinline__ T operator()(int c) const;
 };
+// The byte offset is formed in unsigned 32-bit arithmetic: the hardware reads
+// it as unsigned, c = -1 becomes 0xFFFFFFF8 (0xFFFFFFFC), beyond any buffer,
+// and the library admits no vector of 2^29 float64 entries or more
+// (check_size_limits), so every real offset fits.
 template <>
 __device__ __forceinline__ double Gather<double>::operator()(int c) const {
-  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, c * 8, 0, 0));
+  return __builtin_bit_cast(
+      double, __builtin_amdgcn_raw_buffer_load_b64(r, static_cast<int>(static_cast<uint32_t>(c) * 8u), 0, 0));
 }
 template <>
 __device__ __forceinline__ float Gather<float>::operator()(int c) const {
-  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, c * 4, 0, 0));
+  return __builtin_bit_cast(
+      float, __builtin_amdgcn_raw_buffer_load_b32(r, static_cast<int>(static_cast<uint32_t>(c) * 4u), 0, 0));
 }
 
 // Lane exchange inside a row of 16 lanes through the DPP crossbar (no LDS):

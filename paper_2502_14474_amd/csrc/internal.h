@@ -242,6 +242,13 @@ size_t partials_doubles(int64_t S, int A, int m);
 
 // Host helpers shared by the single and the batched drivers (api.cpp).
 bool is_device_ptr(const void* p);
+// Sizes the kernels can index: A <= 4096, S*A < 2^31 - 1, S < 2^29 (gathers
+// form 32-bit byte offsets into float64 vectors) and nnz <= kMaxNnz (row loops
+// step an int32 entry index past a row's end by up to a wavefront).  nnz < 0:
+// not known yet.  MDP_E_NOTSUP with a message otherwise.
+constexpr int64_t kMaxStates = (int64_t{1} << 29) - 1;
+constexpr int64_t kMaxNnz = (int64_t{1} << 31) - 4096;
+mdp_status check_size_limits(int64_t S, int32_t A, int64_t nnz);
 // Validation (api.cpp): row_ptr structure; entries and costs on the host;
 // both.  entry_failure turns a verdict into the shared message.
 mdp_status validate_row_ptr(int64_t S, int32_t A, const int64_t* rp);

@@ -96,7 +96,6 @@ struct mdp_server {
   std::thread worker;
   int reapers_left = 0;
   mdp::BatchEngine eng;
-  std::string fatal;
   int64_t rounds = 0;
 
   void admit_loop();
@@ -167,10 +166,13 @@ void mdp_server::work_loop() {
     lk.lock();
     ++rounds;
     if (st < 0) {
-      fatal = mdp_last_error();
+      // the message goes into each request under the lock, so that the
+      // reapers (which run unlocked) only read what was handed to them
+      const std::string msg = mdp_last_error();
       for (Request* r : resident) {
         r->item.status = st;
         r->item.state = BatchItem::kDone;
+        r->error = msg;
       }
     }
     std::vector<Request*> keep;
@@ -268,7 +270,7 @@ void mdp_server::retire(Request* r) {
   r->st.finish_ms = clock_ms() - t0;  // results are on the host
   r->status = e != hipSuccess ? MDP_E_DEVICE : it.status;
   if (e != hipSuccess) r->error = hipGetErrorString(e);
-  else if (it.status < 0) r->error = fatal.empty() ? "non-finite residual" : fatal;
+  else if (it.status < 0 && r->error.empty()) r->error = "non-finite residual";
   r->st.outer_iters = it.k;
   r->st.inner_iters = it.inner;
   r->st.bellman_sweeps = it.sweeps;
@@ -370,11 +372,11 @@ static mdp_status submit_common(mdp_server_t s, int64_t S, int32_t A, const int6
   if (!s || !request_id) return fail(MDP_E_INVAL, "NULL argument");
   if (S < 1 || A < 1 || !row_ptr || !col || !val || !cost) return fail(MDP_E_INVAL, "bad MDP");
   if (!(gamma >= 0.0 && gamma < 1.0)) return fail(MDP_E_INVAL, "gamma must lie in [0,1)");
-  if (A > 4096 || S * static_cast<int64_t>(A) >= (int64_t{1} << 31) - 1)
-    return fail(MDP_E_NOTSUP, "MDP too large for one request");
+  MDP_TRY(check_size_limits(S, A, -1));
   const int64_t rows = S * A;
   const int64_t nnz = row_ptr[rows];
-  if (nnz < rows || nnz >= (int64_t{1} << 31)) return fail(MDP_E_INVAL, "bad row_ptr");
+  if (nnz < rows) return fail(MDP_E_INVAL, "bad row_ptr");
+  MDP_TRY(check_size_limits(S, A, nnz));
   auto r = std::make_unique<Request>();
   r->S = S;
   r->A = A;

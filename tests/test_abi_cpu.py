@@ -178,3 +178,44 @@ def test_create_from_rows_reports_row_function_failures():
     with pytest.raises(m.MDPError) as ei:
         m.mdp_create_from_rows(inst.S, inst.A, 10, too_long, inst.gamma)
     assert ei.value.status == native.MDP_E_INVAL and "k_max" in str(ei.value)
+
+
+def test_sizes_the_kernels_cannot_index_are_refused():
+    """S >= 2^29 (32-bit byte offsets into float64 vectors) and nnz above
+    2^31 - 4096 (int32 entry loops) are refused on the host before any array
+    past row_ptr[S*A] is read; the small dummy arrays here are never touched."""
+    lib = native.load()
+    dummy_i64 = np.zeros(4, dtype=np.int64)
+    dummy_i32 = np.zeros(4, dtype=np.int32)
+    dummy_f64 = np.zeros(4)
+    h = C.c_void_p()
+    # S = 2^29, A = 1: refused by its state count alone, row_ptr is not read
+    st = lib.mdp_create(1 << 29, 1, dummy_i64.ctypes.data, dummy_i32.ctypes.data,
+                        dummy_f64.ctypes.data, dummy_f64.ctypes.data, 0.9, None, C.byref(h))
+    assert st == native.MDP_E_NOTSUP and "2^29" in lib.mdp_last_error().decode() and not h.value
+    # one state, one action, nnz claimed at 2^31 - 4095: refused from row_ptr[S*A]
+    rp = np.array([0, (1 << 31) - 4095], dtype=np.int64)
+    st = lib.mdp_create(1, 1, rp.ctypes.data, dummy_i32.ctypes.data, dummy_f64.ctypes.data,
+                        dummy_f64.ctypes.data, 0.9, None, C.byref(h))
+    assert st == native.MDP_E_NOTSUP and "2^31 - 4096" in lib.mdp_last_error().decode()
+    # the same limits hold for row functions and for server submissions
+    import paper_2502_14474_amd as m
+    with pytest.raises(m.MDPError) as ei:
+        m.mdp_create_from_rows(1 << 29, 1, 4, lambda *a: None, 0.9)
+    assert ei.value.status == native.MDP_E_NOTSUP
+    o = native.ServerOpts()
+    lib.mdp_default_server_opts(C.byref(o))
+    srv = C.c_void_p()
+    st = lib.mdp_server_create(C.byref(o), C.byref(srv))
+    if st != native.MDP_OK:
+        pytest.skip("no server without a GPU: " + lib.mdp_last_error().decode())
+    try:
+        rid = C.c_int64()
+        st = lib.mdp_server_submit(srv, 1 << 29, 1, dummy_i64.ctypes.data, dummy_i32.ctypes.data,
+                                   dummy_f64.ctypes.data, dummy_f64.ctypes.data, 0.9, C.byref(rid))
+        assert st == native.MDP_E_NOTSUP
+        st = lib.mdp_server_submit(srv, 1, 1, rp.ctypes.data, dummy_i32.ctypes.data,
+                                   dummy_f64.ctypes.data, dummy_f64.ctypes.data, 0.9, C.byref(rid))
+        assert st == native.MDP_E_NOTSUP
+    finally:
+        lib.mdp_server_destroy(srv)
