@@ -207,6 +207,32 @@ mdp_status mdp_create_from_rows(int64_t S, int32_t A, int32_t k_max, mdp_rows_fn
  * v: double[S].  Tv (double[S]), policy (int32[S]) and res_inf may be NULL. */
 mdp_status mdp_bellman(mdp_t h, const double* v, double* Tv, int32_t* policy, double* res_inf);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the sweep of
+ * mdp_bellman on the caller's own device arrays, with no handle and no
+ * allocation.  The per-workgroup partials go to a fixed device array of the
+ * library (2 MiB per GPU, held until the process ends).
+ *   row_ptr int64[S*A+1], col int32[nnz], val double[nnz], cost double[S*A]:
+ *     the MDP in the input layout of mdp_create (rows r = s*A + a), NOT
+ *     validated here (validate it once with mdp_create or on the host);
+ *   v double[S]; Tv double[S], policy int32[S] and res_inf double[1] may each
+ *     be NULL; Tv must not alias v;
+ *   lanes_per_row: 0 (from the mean row length) or a power of two in [2,64];
+ *     with the width of a handle (mdp_info) the results are bitwise those of
+ *     mdp_bellman on that handle;
+ *   stream: hipStream_t (NULL: the null stream).
+ * Every pointer must be device memory of the current device (else
+ * MDP_E_INVAL).  The call only enqueues work on the stream and returns; the
+ * outputs are ready when the stream reaches that point.  It calls no
+ * allocator.  Limits: S*A rows in at most 65536 sweep tiles (about 2^26 rows,
+ * MDP_E_NOTSUP beyond) and the size limits of mdp_create.  All calls on one
+ * GPU share the partials array: calls that overlap in time on one GPU (two
+ * streams, two threads) race and must be serialised by the caller. */
+mdp_status mdp_bellman_noalloc(int64_t S, int32_t A, int64_t nnz, const int64_t* row_ptr,
+                               const int32_t* col, const double* val, const double* cost,
+                               double gamma, const double* v, double* Tv, int32_t* policy,
+                               double* res_inf, int32_t lanes_per_row, void* stream);
+
 /* Product with the transition matrix of a policy, gathering rows s*A+policy[s]
  * of P without forming P_pi: the operator of the linear system that policy
  * evaluation solves (section "Problem Setting and Solution Methods"):

@@ -16,7 +16,7 @@ from .native import (MDP_FP64, MDP_MIXED_FP32, MDP_MIXED_FP16, MDP_INNER_GMRES, 
                      MDP_BUILD_FP32, MDP_BUILD_FP16, MDP_OK,
                      MDP_W_MAXITER, MDPError)
 
-__all__ = ["mdp_create", "mdp_create_from_rows", "mdp_bellman", "mdp_policy_apply", "mdp_policy_eval", "mdp_solve",
+__all__ = ["mdp_create", "mdp_create_from_rows", "mdp_bellman", "mdp_bellman_noalloc", "mdp_policy_apply", "mdp_policy_eval", "mdp_solve",
            "mdp_solve_batch", "Server",
            "mdp_destroy", "mdp_info", "mdp_autotune", "mdp_profile", "mdp_profile_read",
            "mdp_last_error", "MDP", "MDPError"]
@@ -154,6 +154,21 @@ def mdp_bellman(h, v, Tv=None, policy=None):
                                             _ptr(Tv, np.float64, name="Tv"),
                                             _ptr(policy, np.int32, name="policy"), C.byref(res)))
     return res.value
+
+
+def mdp_bellman_noalloc(S, A, nnz, row_ptr, col, val, cost, gamma, v, Tv=None, policy=None,
+                        res_inf=None, lanes_per_row=0, stream=None):
+    """The allocation-free sweep on caller device tensors (mdp_bellman_noalloc):
+    row_ptr int64, col int32, val/cost/v/Tv/res_inf float64, policy int32, all
+    on the current device.  Only enqueues work on `stream` (a raw hipStream_t
+    handle, e.g. torch.cuda.current_stream().cuda_stream; None: the null stream)."""
+    rows = int(S) * int(A)
+    return native.check(native.load().mdp_bellman_noalloc(
+        int(S), int(A), int(nnz), _ptr(row_ptr, np.int64, rows + 1, "row_ptr"),
+        _ptr(col, np.int32, nnz, "col"), _ptr(val, np.float64, nnz, "val"),
+        _ptr(cost, np.float64, rows, "cost"), float(gamma), _ptr(v, np.float64, S, "v"),
+        _ptr(Tv, np.float64, S, "Tv"), _ptr(policy, np.int32, S, "policy"),
+        _ptr(res_inf, np.float64, 1, "res_inf"), int(lanes_per_row), stream))
 
 
 def mdp_policy_apply(h, policy, x, y, mode=0):

@@ -193,6 +193,14 @@ void ctl_slot_give(Ctl* c) {
   g_ctl_free.push_back(c);
 }
 
+// Lanes per CSR row when neither the caller nor the autotuner's cache gives a
+// width: the smallest power of two in [2, 64] that covers the mean row length.
+int default_lanes(double mean_row) {
+  int L = 2;
+  while (L < 64 && L < mean_row) L <<= 1;
+  return L;
+}
+
 // Engines of mdp_solve_batch are kept per device between calls, so that the
 // HIP graphs they capture are replayed by later calls of the same
 // configuration.  A call leases an idle engine (or makes one) and hands it
@@ -311,12 +319,6 @@ mdp_status store(mdp_handle* h, void* dst, const void* src, size_t bytes) {
 mdp_status store_values(mdp_handle* h, double* dst, double* src) {
   if (h->maximize) MDP_HIP(launch_negate(h->stream, src, h->S));
   return store(h, dst, src, h->S * sizeof(double));
-}
-
-int default_lanes(double mean_row) {
-  int L = 2;
-  while (L < 64 && L < mean_row) L <<= 1;
-  return L;
 }
 
 struct InnerResult {

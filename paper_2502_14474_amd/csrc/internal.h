@@ -249,6 +249,8 @@ bool is_device_ptr(const void* p);
 constexpr int64_t kMaxStates = (int64_t{1} << 29) - 1;
 constexpr int64_t kMaxNnz = (int64_t{1} << 31) - 4096;
 mdp_status check_size_limits(int64_t S, int32_t A, int64_t nnz);
+// Default lanes per CSR row for a mean row length (api.cpp).
+int default_lanes(double mean_row);
 // Validation (api.cpp): row_ptr structure; entries and costs on the host;
 // both.  entry_failure turns a verdict into the shared message.
 mdp_status validate_row_ptr(int64_t S, int32_t A, const int64_t* rp);
