@@ -1,10 +1,13 @@
 """Benchmark of the inexact-policy-iteration hot path on one MI355X.
 
-One step = one full mdp_solve (float64 inexact policy iteration with
-GMRES(30) policy evaluation) on the banded-plus-long-jump MDP with S = 10^6
-states, A = 8 actions, 16 nonzeros per row (128M nonzeros), gamma = 0.99, from
-v = 0 to ||T v - v||_inf <= 1e-8.  Inputs are resident in HBM before the timed
-region.  Prints one JSON line.
+One step = one full mdp_solve: float64 inexact policy iteration with GMRES(30)
+policy evaluation, from v = 0 to ||T v - v||_inf <= 1e-8, with the instance
+resident in HBM before the timed region.  The default workload is the largest
+single-GPU configuration: S = 4e6 states, A = 16 actions, 24 uniform-random
+nonzeros per row (1.536G nonzeros), Dirichlet(0.5) probabilities,
+Lognormal(0,1) costs, gamma = 0.995; the mixed-precision solve on the same
+instance is reported beside it.  --config 1..3 select the other single-MDP
+workloads and --config 5 the serving load.  Prints one JSON line.
 """
 import argparse
 import json
@@ -18,8 +21,9 @@ sys.path.insert(0, ROOT)
 METRIC = ("Bellman sweeps/s + HBM GB/s (% peak); solve time to ‖Tv−v‖∞≤1e-8, "
           "FP64 vs mixed")
 HBM_PEAK_GBS = 8000.0
-KERNEL_SOURCES = ("paper_2502_14474_amd/csrc/device.h", "paper_2502_14474_amd/csrc/kernels.hip")
-COUNTERS_FILE = os.path.join(ROOT, "profiles", "counters_config2_fp64.json")
+KERNEL_SOURCES = ("paper_2502_14474_amd/csrc/device.h", "paper_2502_14474_amd/csrc/kernels.hip",
+                  "paper_2502_14474_amd/csrc/colblock.hip")
+COUNTERS_GLOB = os.path.join(ROOT, "profiles", "counters_*.json")
 
 
 def kernel_source_sha():
@@ -33,17 +37,25 @@ def kernel_source_sha():
 
 def counter_traffic(kind, workload):
     """HBM bytes per launch of a kernel class from the committed rocprofv3
-    FETCH_SIZE / WRITE_SIZE runs, or None when they were taken on other
-    kernel sources or another workload."""
-    try:
-        with open(COUNTERS_FILE) as f:
-            d = json.load(f)
-    except (OSError, ValueError):
-        return None
-    if d.get("source_sha") != kernel_source_sha() or d.get("workload") != workload:
-        return None
-    k = d.get("kernels", {}).get(kind)
-    return None if k is None else k.get("traffic_bytes_per_launch")
+    FETCH_SIZE / WRITE_SIZE runs (profiles/counters_*.json), or None when none
+    was taken on this workload with the current kernel sources."""
+    import glob
+    sha = None
+    for path in sorted(glob.glob(COUNTERS_GLOB)):
+        try:
+            with open(path) as f:
+                d = json.load(f)
+        except (OSError, ValueError):
+            continue
+        if d.get("workload") != workload:
+            continue
+        sha = sha or kernel_source_sha()
+        if d.get("source_sha") != sha:
+            continue
+        k = d.get("kernels", {}).get(kind)
+        if k is not None:
+            return k.get("traffic_bytes_per_launch")
+    return None
 
 
 def log(*a):
@@ -77,64 +89,140 @@ def workload_name(inst, args):
             f"evaluation, alpha={args.alpha}, to ||Tv-v||_inf<={args.atol} from v=0")
 
 
-def cpu_baseline(args, full_inst):
-    """The CPU oracle (exact policy iteration, float64, certified GMRES
-    evaluation) on a bounded twin of the workload, scaled to full size by the
-    nonzero count."""
-    from threadpoolctl import threadpool_limits
+ORACLE_RUNS_FILE = os.path.join(ROOT, "profiles", "oracle_full_runs.json")
 
-    import oracle
-    from workloads import config2
-    if args.config != 2:
+
+def oracle_full_run(inst):
+    """The recorded full oracle solve of this exact instance (written by
+    oracle/full_run.py), or None."""
+    try:
+        with open(ORACLE_RUNS_FILE) as f:
+            return json.load(f).get(workload_key(inst))
+    except (OSError, ValueError):
         return None
-    S_s = args.cpu_sample_states
-    twin = config2(S=S_s, seed=args.seed)
-    with threadpool_limits(1):
-        t0 = time.perf_counter()
-        r = oracle.policy_iteration(twin, method="certified")
-        dt = time.perf_counter() - t0
-    scale = full_inst.nnz / twin.nnz
-    est = dt * scale
-    return {"value": 1.0 / est, "unit": "solves/s", "cores": 1, "kind": "oracle",
-            "host_cores_available": len(os.sched_getaffinity(0)),
-            "sample": (f"oracle exact policy iteration on a {S_s}-state twin of the workload "
-                       f"(same generator, A, k, gamma): {dt:.2f} s, {r['iters']} improvement "
-                       f"steps, scaled x{scale:.1f} by nonzeros to {est:.1f} s per full solve; "
-                       f"scipy sparse matvec and numpy on 1 thread"),
-            "seconds_sample": dt}
 
 
-def serving_leg(args, m):
-    """Config-5 style serving load: requests from the seeded stream (S
-    log-uniform in [1e3, 1e6], A in 2..16, nnz/row in 4..32, gamma in
-    {0.9, 0.99, 0.999}), solved in mixed precision with float64 refinement by
-    the continuous-batching server.  A pool of distinct requests is generated
-    up front and cycled.  One server takes every run: after an untimed
-    warm-up pass over the pool, a closed-loop run measures capacity C, then an
-    open-loop Poisson stream at 0.7 C gives the latency percentiles."""
+def blas_threads():
+    from threadpoolctl import threadpool_info
+    n = [d.get("num_threads", 1) for d in threadpool_info() if d.get("user_api") == "blas"]
+    return max(n) if n else 1
+
+
+def cpu_baseline(args, inst):
+    """The CPU oracle (oracle/: plain float64 exact policy iteration) timed on
+    this run's host cores, on the benchmarked instance itself.
+
+    Small workloads (S <= 1e6) run the oracle's whole solve.  Larger ones time
+    the two full-size steps an exact-PI solve repeats: one greedy sweep
+    (oracle.bellman) and one certified policy evaluation
+    (oracle.evaluate_policy) at the first policy; a solve is then priced with
+    the sweep and evaluation counts of the oracle's recorded full run on the
+    same instance (profiles/oracle_full_runs.json).  The CSR conversion is a
+    format copy and is not timed, like the instance generation."""
     import numpy as np
 
-    from workloads import config5_instance, config5_requests
-    reqs = config5_requests(args.serve_pool * 4, seed=args.seed)
-    reqs = [r for r in reqs if r["S"] <= args.serve_max_states][:args.serve_pool]
+    import oracle
+    cores = blas_threads()
+    avail = len(os.sched_getaffinity(0))
+    base = {"unit": "solves/s", "cores": cores, "kind": "oracle", "host_cores_available": avail,
+            "sparse_matvec_threads": 1}
+    if inst.S <= 1_000_000:
+        t0 = time.perf_counter()
+        r = oracle.policy_iteration(inst, method="auto")
+        dt = time.perf_counter() - t0
+        return dict(base, value=1.0 / dt, seconds=dt,
+                    sample=(f"the oracle's whole exact policy iteration on this instance: {dt:.2f} s, "
+                            f"{r['iters']} improvement steps, final residual {r['res']:.1e}; scipy's "
+                            f"sparse matvec runs on 1 thread, BLAS on {cores}"))
+    P = oracle.to_csr(inst)
+    t0 = time.perf_counter()
+    _, pi0, res0 = oracle.bellman(inst, np.zeros(inst.S), P)
+    t_sweep = time.perf_counter() - t0
+    t1 = time.perf_counter()
+    _, true_res = oracle.evaluate_policy(inst, pi0, P, method="certified")
+    t_eval = time.perf_counter() - t1
+    del P
+    steps = {"sweep_s": t_sweep, "evaluation_s": t_eval, "evaluation_true_residual": true_res}
+    rec = oracle_full_run(inst)
+    if rec is None:
+        return dict(base, value=None, steps=steps,
+                    sample=(f"one full-size oracle sweep ({t_sweep:.2f} s) and one certified evaluation "
+                            f"({t_eval:.2f} s); no recorded full oracle run of this instance to count "
+                            f"its steps, so no solve rate"))
+    est = rec["sweeps"] * t_sweep + rec["evaluations"] * t_eval
+    return dict(base, value=1.0 / est, seconds=est, steps=steps, full_run=rec,
+                sample=(f"one full-size oracle sweep ({t_sweep:.2f} s) and one certified policy "
+                        f"evaluation ({t_eval:.2f} s) on this instance, priced at the "
+                        f"{rec['sweeps']} sweeps and {rec['evaluations']} evaluations of the oracle's "
+                        f"recorded full solve of it ({rec['seconds']:.0f} s on {rec['cores']} BLAS "
+                        f"threads): {est:.1f} s per solve"))
+
+
+def serving_requests(args):
+    """The first `serve_pool` requests of the seeded config-5 stream: S
+    log-uniform in [1e3, 1e6], A in 2..16, nnz/row in 4..32 (band plus long
+    jumps), gamma in {0.9, 0.99, 0.999}; the full law, nothing filtered."""
+    from workloads import config5_requests
+    return config5_requests(args.serve_pool, seed=args.seed)
+
+
+def serving_oracle(args, reqs):
+    """The oracle on an S-stratified subsample of the pool: per decade of S
+    (1e3-1e4, 1e4-1e5, 1e5-1e6, each a third of the log-uniform law) the
+    pool's first request, solved by the oracle's exact policy iteration.  A
+    solve costs the strata-weighted mean time."""
+    import oracle
+    from workloads import config5_instance
+    times, picks = [], []
+    for lo in (1e3, 1e4, 1e5):
+        r = next((r for r in reqs if lo <= r["S"] < 10 * lo), None)
+        if r is None:
+            continue
+        inst = config5_instance(r, workers=16)
+        t0 = time.perf_counter()
+        out = oracle.policy_iteration(inst, method="auto" if inst.S <= 2500 else "certified")
+        dt = time.perf_counter() - t0
+        times.append(dt)
+        picks.append(dict(S=r["S"], A=r["A"], k=r["k"], gamma=r["gamma"], nnz=inst.nnz, seconds=dt,
+                          improvement_steps=out["iters"]))
+        log(f"[serve] oracle on S={r['S']} A={r['A']} k={r['k']} gamma={r['gamma']}: {dt:.1f}s")
+    mean = sum(times) / len(times)
+    return {"value": 1.0 / mean, "unit": "solves/s", "cores": blas_threads(), "kind": "oracle",
+            "host_cores_available": len(os.sched_getaffinity(0)), "sparse_matvec_threads": 1,
+            "sample": (f"oracle exact policy iteration on one request per decade of S from the pool "
+                       f"(strata-weighted mean {mean:.1f} s per solve)"), "requests": picks}
+
+
+def serving_bench(args, m):
+    """Config 5: a continuous-batching server under the serving load.
+
+    A pool of distinct requests drawn from the full law is generated before
+    the timed runs (host generation of the whole 10,000-request stream would
+    take most of an hour, at about 70M nonzeros/s).  Submission i sends pool
+    request i mod pool, in stream order.  One server takes every run: an
+    untimed warm-up pass over the pool, a closed-loop run (every request
+    submitted at once) that measures the capacity C, then open-loop Poisson
+    streams at 0.7 C and 0.9 C with the stream's seeded exponential gaps.
+    Mixed float32 with float64 refinement, the server's default."""
+    import numpy as np
+    import torch
+
+    from workloads import MDPInstance, config5_instance, config5_requests
+    reqs = serving_requests(args)
     t = time.time()
-    pool = [config5_instance(r, workers=16) for r in reqs]
-    log(f"[serve] pool of {len(pool)} requests, {sum(p.nnz for p in pool)/1e6:.0f}M nnz, "
-        f"generated in {time.time()-t:.1f}s")
-    n = args.serve_requests
-    pageable = pool
-    if not args.serve_pageable:
-        # the client holds its requests in page-locked host memory, so that the
-        # server's uploads go straight to the copy engines (no staging copy)
-        import torch
-        from workloads import MDPInstance
+    pageable = [config5_instance(r, workers=16) for r in reqs]
+    nnz = np.array([p.nnz for p in pageable])
+    log(f"[serve] pool of {len(pageable)} requests, {nnz.sum()/1e9:.2f}G nnz (median {np.median(nnz)/1e6:.1f}M, "
+        f"max {nnz.max()/1e6:.0f}M), generated in {time.time()-t:.1f}s")
 
-        def pin(a):
-            return torch.from_numpy(a).pin_memory().numpy()
-        pool = [MDPInstance(p.S, p.A, pin(p.row_ptr), pin(p.col), pin(p.val), pin(p.cost), p.gamma,
-                            name=p.name, meta=p.meta) for p in pageable]
+    def pin(a):
+        return torch.from_numpy(a).pin_memory().numpy()
+    pool = [MDPInstance(p.S, p.A, pin(p.row_ptr), pin(p.col), pin(p.val), pin(p.cost), p.gamma,
+                        name=p.name, meta=p.meta) for p in pageable]
+    del pageable
+    n = args.serve_requests or 3 * len(pool)
 
-    def run(srv, gaps, pool=pool, n=n):
+    def run(srv, gaps, n=n):
         ids = []
         t0 = time.perf_counter()
         nxt = t0
@@ -148,30 +236,47 @@ def serving_leg(args, m):
         outs = [srv.wait(r) for r in ids]
         t1 = time.perf_counter()
         lat = np.array([o[2]["finish_ms"] - o[2]["submit_ms"] for o in outs])
-        ok = all(o[2]["status"] == 0 for o in outs)
+        bad = [o[2]["status"] for o in outs if o[2]["status"] != 0]
+        log(f"[serve] run of {n}: {n / (t1 - t0):.1f} solves/s, p50 {np.percentile(lat, 50):.1f} ms, "
+            f"p99 {np.percentile(lat, 99):.1f} ms")
         return dict(solves_per_s=n / (t1 - t0), p50_ms=float(np.percentile(lat, 50)),
-                    p99_ms=float(np.percentile(lat, 99)), ok=ok, wall_s=t1 - t0)
+                    p99_ms=float(np.percentile(lat, 99)), ok=not bad, wall_s=t1 - t0,
+                    residual_max=float(max(o[2]["residual"] for o in outs)))
 
-    # One server serves every run, as a deployed one would.  An untimed
-    # warm-up pass over the distinct requests first fills the library's device
-    # memory pool and stream cache.
     with m.Server(precision=m.MDP_MIXED_FP32, alpha=args.alpha, atol=args.atol,
                   max_batch=args.serve_max_batch) as srv:
-        warm = run(srv, None, pool, len(pool))
-        log(f"[serve] warm-up pass over {len(pool)} requests: {warm['solves_per_s']:.0f} solves/s")
+        warm = run(srv, None, len(pool))
         closed = run(srv, None)
         cap = closed["solves_per_s"]
-        rng_gaps = np.array([r["gap"] for r in config5_requests(n, seed=args.seed + 1)])
-        open70 = run(srv, rng_gaps / (0.7 * cap))
-        log(f"[serve] closed {closed}; open@0.7C {open70}")
-        out = {"requests": n, "pool": len(pool), "pool_nnz": int(sum(p.nnz for p in pool)),
-               "precision": "mixed fp32 + fp64 refinement",
-               "client_memory": "pageable" if args.serve_pageable else "page-locked",
-               "closed_loop": closed, "open_loop_0.7C": open70}
-        if not args.serve_pageable:
-            out["closed_loop_pageable_client"] = run(srv, None, pageable)
-            log(f"[serve] closed, pageable client arrays: {out['closed_loop_pageable_client']}")
-    return out
+        gaps = np.array([r["gap"] for r in config5_requests(n, seed=args.seed)])
+        open70 = run(srv, gaps / (0.7 * cap))
+        open90 = run(srv, gaps / (0.9 * cap))
+        tuned = srv.tuned_widths() if hasattr(srv, "tuned_widths") else None
+    cpu = None if args.no_cpu_baseline else serving_oracle(args, reqs)
+    return {
+        "metric": METRIC,
+        "value": closed["solves_per_s"],
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": n,
+        "warmup": len(pool),
+        "ms_per_step": 1e3 * closed["wall_s"] / n,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": (f"serving load (config 5): {len(pool)} distinct requests from the seeded "
+                                f"stream's law (S log-uniform in [1e3,1e6], A 2..16, 4..32 nnz/row, "
+                                f"gamma in {{0.9,0.99,0.999}}), submitted {n} times in stream order; "
+                                f"mixed float32 + float64 refinement to ||Tv-v||_inf<={args.atol}"),
+                   "pool": len(pool), "pool_nnz": int(nnz.sum()), "pool_max_states": int(max(p.S for p in pool)),
+                   "submissions": n, "alpha": args.alpha},
+        "roofline": None,
+        "cpu_baseline": cpu,
+        "serving": {"warmup_pass": warm, "closed_loop": closed, "open_loop_0.7C": open70,
+                    "open_loop_0.9C": open90, "client_memory": "page-locked", "autotuned_widths": tuned},
+    }
 
 
 def rows_leg(args, m, h, inst, v, pi, stream):
@@ -297,7 +402,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--config", type=int, default=2)
+    ap.add_argument("--config", type=int, default=4)
     ap.add_argument("--S", type=int, default=0)
     ap.add_argument("--n-jump", type=int, default=2,
                     help="config 2: long jumps per row (of 16 entries); 0 gives the band-only "
@@ -315,21 +420,15 @@ def main():
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--mixed", choices=["fp32", "fp16"], default="fp32")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample-states", type=int, default=250_000)
-    ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-rows", action="store_true",
                     help="skip the per-row leg (policy product, Richardson solve, GMRES kernel breakdown)")
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration)")
-    ap.add_argument("--serve-pool", type=int, default=24)
-    ap.add_argument("--serve-max-states", type=int, default=200_000)
-    ap.add_argument("--serve-requests", type=int, default=96)
+    ap.add_argument("--serve-pool", type=int, default=96,
+                    help="config 5: distinct requests generated from the stream's law")
+    ap.add_argument("--serve-requests", type=int, default=0,
+                    help="config 5: submissions per run (0: three times the pool)")
     ap.add_argument("--serve-max-batch", type=int, default=128)
-    ap.add_argument("--serve-only", action="store_true",
-                    help="run only the serving leg and print its results as one JSON line "
-                         "(a profiling aid; not the benchmark line)")
-    ap.add_argument("--serve-pageable", action="store_true",
-                    help="keep the client's request arrays in pageable memory")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported (the "
@@ -354,8 +453,8 @@ def main():
         del a, b
         log("[bench] copy calibration: 3 copies of 1 GiB")
 
-    if args.serve_only:
-        print(json.dumps({"serving": serving_leg(args, m)}), flush=True)
+    if args.config == 5:
+        print(json.dumps(serving_bench(args, m)), flush=True)
         return
 
     t = time.time()
@@ -456,14 +555,11 @@ def main():
                  "rel_diff_vs_fp64": float(np.max(np.abs(vm - v64)) / np.max(np.abs(v64)))}
         log(f"[bench] mixed: {mixed}")
 
-    serve = None
-    if not args.no_serve:
-        serve = serving_leg(args, m)
-
     cpu = None
     if not args.no_cpu_baseline:
+        t = time.time()
         cpu = cpu_baseline(args, inst)
-        log(f"[bench] cpu baseline: {cpu}")
+        log(f"[bench] cpu baseline ({time.time() - t:.0f}s): {cpu}")
 
     m.mdp_destroy(h)
     out = {
@@ -498,11 +594,8 @@ def main():
                   "residual": last["residual"], "history": last.get("history")},
         "mixed": dict(mixed, precision=args.mixed) if mixed else None,
         "rows": rows,
-        "serving": serve,
         "kernels": kernels,
     }
-    if cpu:
-        out["cpu_baseline"].pop("seconds_sample", None)
     print(json.dumps(out), flush=True)
 
 

@@ -31,13 +31,19 @@ def test_band_only_twin_has_its_own_workload_key():
 
 
 def test_stored_counters_apply_only_to_their_sources(tmp_path, monkeypatch):
+    import glob
     import bench
-    with open(bench.COUNTERS_FILE) as f:
+    files = sorted(glob.glob(bench.COUNTERS_GLOB))
+    assert files, "no committed counter summaries"
+    with open(files[0]) as f:
         d = json.load(f)
     assert d["calibration"]["fetch_factor"] > 0 and d["calibration"]["write_factor"] > 0
     # a copy of the counters taken on other kernel sources is ignored
     d["source_sha"] = "0" * 64
-    other = tmp_path / "counters.json"
-    other.write_text(json.dumps(d))
-    monkeypatch.setattr(bench, "COUNTERS_FILE", str(other))
+    (tmp_path / "counters_x.json").write_text(json.dumps(d))
+    monkeypatch.setattr(bench, "COUNTERS_GLOB", str(tmp_path / "counters_*.json"))
     assert bench.counter_traffic("bellman", d["workload"]) is None
+    # the same file with the current sources applies
+    d["source_sha"] = bench.kernel_source_sha()
+    (tmp_path / "counters_x.json").write_text(json.dumps(d))
+    assert bench.counter_traffic("bellman", d["workload"]) == d["kernels"]["bellman"]["traffic_bytes_per_launch"]
