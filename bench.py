@@ -243,15 +243,24 @@ def serving_bench(args, m):
                     p99_ms=float(np.percentile(lat, 99)), ok=not bad, wall_s=t1 - t0,
                     residual_max=float(max(o[2]["residual"] for o in outs)))
 
+    # the server times the lane widths of each new (A, row length) class once,
+    # at the class's first admission; the widths land in this run's own cache
+    import tempfile
+    tune_file = os.path.join(tempfile.mkdtemp(prefix="mdp_tune_"), "tune.json")
+    os.environ["MDP_TUNE_CACHE"] = tune_file
     with m.Server(precision=m.MDP_MIXED_FP32, alpha=args.alpha, atol=args.atol,
-                  max_batch=args.serve_max_batch) as srv:
+                  max_batch=args.serve_max_batch, autotune=not args.no_autotune) as srv:
         warm = run(srv, None, len(pool))
         closed = run(srv, None)
         cap = closed["solves_per_s"]
         gaps = np.array([r["gap"] for r in config5_requests(n, seed=args.seed)])
         open70 = run(srv, gaps / (0.7 * cap))
         open90 = run(srv, gaps / (0.9 * cap))
-        tuned = srv.tuned_widths() if hasattr(srv, "tuned_widths") else None
+    try:
+        with open(tune_file) as f:
+            tuned = json.load(f)
+    except (OSError, ValueError):
+        tuned = {}
     cpu = None if args.no_cpu_baseline else serving_oracle(args, reqs)
     return {
         "metric": METRIC,
@@ -277,6 +286,44 @@ def serving_bench(args, m):
         "serving": {"warmup_pass": warm, "closed_loop": closed, "open_loop_0.7C": open70,
                     "open_loop_0.9C": open90, "client_memory": "page-locked", "autotuned_widths": tuned},
     }
+
+
+def graph_sweep_rate(m, inst, lanes, n=1000, replays=5):
+    """Sweeps/s of value-iteration sweeps v <- T v replayed from one captured
+    HIP graph of n sweeps (the allocation-free sweep, two buffers): what a
+    small MDP reaches once the per-launch host work and syncs are gone."""
+    import numpy as np
+    import torch
+    dev = torch.device("cuda:0")
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)  # noqa: E731
+    rp, col, val, cost = t(inst.row_ptr.astype(np.int64)), t(inst.col), t(inst.val), t(inst.cost)
+    va = torch.zeros(inst.S, dtype=torch.float64, device=dev)
+    vb = torch.zeros_like(va)
+    pol = torch.zeros(inst.S, dtype=torch.int32, device=dev)
+    res = torch.zeros(1, dtype=torch.float64, device=dev)
+    s = torch.cuda.Stream(device=dev)
+
+    def sweeps(count):
+        for _ in range(count // 2):
+            for x, y in ((va, vb), (vb, va)):
+                m.mdp_bellman_noalloc(inst.S, inst.A, inst.nnz, rp, col, val, cost, inst.gamma, x, y, pol, res,
+                                      lanes_per_row=lanes, stream=s.cuda_stream)
+
+    with torch.cuda.stream(s):
+        sweeps(2)  # resolves the scratch address before the capture
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s, capture_error_mode="thread_local"):
+        sweeps(n)
+    g.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(replays):
+        g.replay()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    return {"sweeps_per_s": n * replays / dt, "us_per_sweep": 1e6 * dt / (n * replays), "graph_sweeps": n,
+            "replays": replays, "residual_after": float(res.item())}
 
 
 def rows_leg(args, m, h, inst, v, pi, stream):
@@ -379,6 +426,39 @@ def rows_leg(args, m, h, inst, v, pi, stream):
                            "residual": st["residual"], "kernels": summary(m.mdp_profile_read(h))}
     m.mdp_profile(h, False)
 
+    # GMRES with the polynomial preconditioner sum_{i<d} (gamma P_pi)^i
+    for deg in (2, 4):
+        w.zero_()
+        m.mdp_solve(h, w, p2, restart=args.restart, alpha=args.alpha, atol=args.atol, precond_degree=deg)
+        w.zero_()
+        m.mdp_profile(h, True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st = m.mdp_solve(h, w, p2, restart=args.restart, alpha=args.alpha, atol=args.atol, precond_degree=deg)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        rows[f"gmres_precond{deg}_solve"] = {"ms": 1e3 * (t1 - t0), "status": st["status"],
+                                             "sweeps": st["bellman_sweeps"], "inner": st["inner_iters"],
+                                             "products": st["policy_applies"], "residual": st["residual"],
+                                             "kernels": summary(m.mdp_profile_read(h))}
+        m.mdp_profile(h, False)
+        log(f"[bench] gmres + polynomial preconditioner of degree {deg}: {1e3 * (t1 - t0):.1f} ms, "
+            f"{st['inner_iters']} Arnoldi steps, {st['policy_applies']} products")
+
+    # GMRES with a second Gram-Schmidt pass: its cost, and the loss of
+    # orthogonality the default single pass leaves (the second correction)
+    w.zero_()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st = m.mdp_solve(h, w, p2, restart=args.restart, alpha=args.alpha, atol=args.atol, gs_passes=2)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    rows["gmres_cgs2_solve"] = {"ms": 1e3 * (t1 - t0), "status": st["status"], "sweeps": st["bellman_sweeps"],
+                                "inner": st["inner_iters"], "orth_loss": st["orth_loss"],
+                                "residual": st["residual"]}
+    log(f"[bench] gmres with CGS2: {1e3 * (t1 - t0):.1f} ms, {st['inner_iters']} steps, "
+        f"loss of orthogonality of one pass {st['orth_loss']:.2e}")
+
     w = torch.zeros_like(v)
     p2 = torch.zeros_like(pi)
     m.mdp_profile(h, True)
@@ -429,6 +509,8 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=0,
                     help="config 5: submissions per run (0: three times the pool)")
     ap.add_argument("--serve-max-batch", type=int, default=128)
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="config 5: the server keeps the default lane widths")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported (the "
@@ -532,6 +614,12 @@ def main():
     sweep_avg_ms = sprof["ms"] / sprof["launches"]
     sweep_gbs = sprof["bytes"] / sprof["launches"] / (sweep_avg_ms * 1e-3) / 1e9
 
+    graph_sweeps = None
+    if inst.S <= 100_000:
+        graph_sweeps = graph_sweep_rate(m, inst, info["lanes_per_row"])
+        log(f"[bench] graph-replayed sweeps: {graph_sweeps['sweeps_per_s']:.0f}/s "
+            f"({graph_sweeps['us_per_sweep']:.2f} us each) vs {args.sweeps / (ts1 - ts0):.0f}/s synced")
+
     # ---- the other rows of the path, each on its own ----------------------------
     rows = None if args.no_rows else rows_leg(args, m, h, inst, v, pi, stream)
 
@@ -585,7 +673,9 @@ def main():
                      "avg_us": kernels[dom]["avg_us"]},
         "cpu_baseline": cpu,
         "create_s": create_s,
-        "bellman_sweeps_per_s": args.sweeps / (ts1 - ts0),
+        "bellman_sweeps_per_s": (graph_sweeps["sweeps_per_s"] if graph_sweeps else args.sweeps / (ts1 - ts0)),
+        "bellman_sweeps_per_s_synced": args.sweeps / (ts1 - ts0),
+        "graph_sweeps": graph_sweeps,
         "bellman_kernel": {"avg_us": 1e3 * sweep_avg_ms, "gbs": sweep_gbs,
                            "frac": sweep_gbs / HBM_PEAK_GBS,
                            "bytes_per_launch": sprof["bytes"] / sprof["launches"],

@@ -123,6 +123,20 @@ typedef struct {
   double rtol;            /* stop when ||r|| <= rtol*||r0|| (GMRES, BiCGSTAB: 2-norm of the
                              residual; Richardson: max-norm of successive differences) */
   int64_t max_iter;       /* cap on inner steps (default 10000) */
+  int32_t precond_degree; /* GMRES only: 0 or 1 (default) no preconditioner; d in [2,16]: right
+                             polynomial preconditioner M^-1 = sum_{i<d} (gamma P_pi)^i, the
+                             first d terms of the Neumann series of (I - gamma P_pi)^-1, applied
+                             matrix-free (d - 1 extra products with P_pi per Arnoldi step).
+                             GMRES then works on (I - gamma P_pi) M^-1 = I - (gamma P_pi)^d
+                             and still minimises the true residual.  MDP_E_NOTSUP with the
+                             other inner solvers, batched solves and the server. */
+  int32_t gs_passes;      /* GMRES Gram-Schmidt passes per Arnoldi step: 0 or 1 (default)
+                             classical Gram-Schmidt (CGS), one pass over the basis; 2: CGS2,
+                             which takes the dots of the orthogonalised vector once more and
+                             subtracts them again, and reports the relative size of that
+                             second correction (mdp_stats.orth_loss), the loss of orthogonality
+                             a single pass would have left.  2 is MDP_E_NOTSUP with the other
+                             inner solvers, batched solves and the server. */
 } mdp_eval_opts;
 
 typedef struct {
@@ -142,6 +156,10 @@ typedef struct {
                              fixed persistent grids; MDP_LAUNCH_DIRECT launches each kernel with
                              a grid sized to the round's work.  Both give bitwise the same
                              results.  mdp_solve ignores it. */
+  int32_t precond_degree; /* as in mdp_eval_opts (the paper leaves the inner solver, and so its
+                             preconditioning, to the caller: "Problem Setting and Solution
+                             Methods") */
+  int32_t gs_passes;      /* as in mdp_eval_opts */
 } mdp_solve_opts;
 
 enum { MDP_LAUNCH_AUTO = 0, MDP_LAUNCH_GRAPHS = 1, MDP_LAUNCH_DIRECT = 2 };
@@ -159,6 +177,8 @@ typedef struct {
   double* history;        /* optional caller array receiving ||T v_k - v_k||_inf per sweep */
   int64_t history_cap;    /* its capacity */
   int64_t history_len;    /* entries written */
+  double orth_loss;       /* gs_passes = 2: largest ||second-pass coefficients|| / ||w|| over the
+                             Arnoldi steps of the call (0 otherwise) */
 } mdp_stats;
 
 /* Fill option structs with defaults. */
@@ -197,6 +217,48 @@ typedef int32_t (*mdp_rows_fn)(void* user, int64_t s_begin, int64_t s_end, int32
  * errors as mdp_create. */
 mdp_status mdp_create_from_rows(int64_t S, int32_t A, int32_t k_max, mdp_rows_fn fn, void* user,
                                 double gamma, const mdp_create_opts* opt, mdp_t* out);
+
+/* Rows of an MDP produced on the device by the caller's own kernel, e.g. a
+ * simulator running one thread per state (the paper builds MDPs from online
+ * simulation as well as from offline data, both in parallel, section
+ * "Implementation").  The kernel takes this struct by value as its only
+ * argument, extern "C" __global__ void k(mdp_device_rows_args a), and is
+ * launched with 256 threads per workgroup and ceil((s_end - s_begin) / 256)
+ * workgroups on a 1-D grid; thread blockIdx.x * 256 + threadIdx.x fills state
+ * s = s_begin + that index when s < s_end.  For row i = (s - s_begin) * A + a
+ * it writes len[i] in [1, k_max], col[i * k_max + j] (columns in [0, S),
+ * increasing) and val[i * k_max + j] for j < len[i], and cost[i] (or, with
+ * MDP_MAXIMIZE_REWARD, the reward).  All four arrays are device staging
+ * owned by the library. */
+typedef struct {
+  int64_t S;
+  int32_t A;
+  int32_t k_max;
+  int64_t s_begin, s_end;
+  int32_t* col;
+  double* val;
+  int32_t* len;
+  double* cost;
+  const void* user;  /* the caller's pointer, passed through unchanged */
+} mdp_device_rows_args;
+
+/* Create a handle from a row kernel (a hipFunction_t, e.g. from
+ * mdp_load_kernel or hipModuleGetFunction) on the device of opt (or the
+ * current one): the library launches it into device staging of S*A*k_max
+ * slots (at most 2^34), checks every length, turns the rows into CSR on the
+ * device (a scan of the lengths, then a compaction) and builds the handle from
+ * those device arrays as mdp_create does.  No row is formed on the host.
+ * Validation follows opt->validate; with opt NULL it runs on the device.
+ * MDP_E_INVAL when a length lies outside [1, k_max] or the launch fails; other
+ * errors as mdp_create.  Staging is freed before the call returns. */
+mdp_status mdp_create_from_device_rows(int64_t S, int32_t A, int32_t k_max, void* kernel,
+                                       const void* user, double gamma, const mdp_create_opts* opt,
+                                       mdp_t* out);
+
+/* Load a code object (hipcc --genco, gfx950) and look up the kernel `name`
+ * in it, for mdp_create_from_device_rows.  The module stays loaded until the
+ * process ends.  MDP_E_INVAL when the file or the kernel is missing. */
+mdp_status mdp_load_kernel(const char* code_object_path, const char* name, void** kernel);
 
 /* One fused Bellman sweep in float64: the greedy (policy improvement) step of
  * policy iteration, section "Problem Setting and Solution Methods", applied to
@@ -300,6 +362,12 @@ typedef struct {
                                 waits for its upload, the others queue theirs) */
   int32_t retire_threads;    /* threads copying results out and freeing (default 4) */
   mdp_solve_opts solve;      /* GMRES only; default precision MDP_MIXED_FP32 */
+  int32_t autotune;          /* 1: the first request of a class with no remembered lane width
+                                (see mdp_autotune) is timed at admission and its width stored,
+                                once per class and process; later requests of the class start
+                                from it.  0 (default): widths come from the cache or the mean
+                                row length only.  Results stay those of mdp_solve on a handle
+                                created with the same width. */
 } mdp_server_opts;
 
 typedef struct {

@@ -5,6 +5,7 @@ arguments: numpy arrays are passed as host pointers, torch tensors as host or
 device pointers.  Every step of the computation runs in libmdp.so.
 """
 import ctypes as C
+import os
 
 import numpy as np
 
@@ -16,7 +17,7 @@ from .native import (MDP_FP64, MDP_MIXED_FP32, MDP_MIXED_FP16, MDP_INNER_GMRES, 
                      MDP_BUILD_FP32, MDP_BUILD_FP16, MDP_OK,
                      MDP_W_MAXITER, MDPError)
 
-__all__ = ["mdp_create", "mdp_create_from_rows", "mdp_bellman", "mdp_bellman_noalloc", "mdp_policy_apply", "mdp_policy_eval", "mdp_solve",
+__all__ = ["mdp_create", "mdp_create_from_rows", "mdp_bellman", "mdp_bellman_noalloc", "mdp_create_from_device_rows", "mdp_load_kernel", "mdp_policy_apply", "mdp_policy_eval", "mdp_solve",
            "mdp_solve_batch", "Server",
            "mdp_destroy", "mdp_info", "mdp_autotune", "mdp_profile", "mdp_profile_read",
            "mdp_last_error", "MDP", "MDPError"]
@@ -116,6 +117,30 @@ def mdp_destroy(h):
     return native.check(native.load().mdp_destroy(h))
 
 
+def mdp_load_kernel(path, name):
+    """hipFunction_t of kernel `name` in the code object at `path`."""
+    k = C.c_void_p()
+    native.check(native.load().mdp_load_kernel(os.fsencode(path), name.encode(), C.byref(k)))
+    return k
+
+
+def mdp_create_from_device_rows(S, A, k_max, kernel, user, gamma, stream=None, device=-1,
+                                validate="device", low_precision=0, lanes_per_row=0, col_blocks=-1,
+                                objective=0):
+    """Create a handle from a row kernel run on the device (see
+    mdp_device_rows_args in include/mdp.h).  user: a device pointer (int) or
+    None, passed to the kernel unchanged."""
+    lib = native.load()
+    o = native.CreateOpts()
+    lib.mdp_default_create_opts(C.byref(o))
+    o.col_blocks, o.objective, o.stream, o.device = col_blocks, objective, stream, device
+    o.validate, o.low_precision, o.lanes_per_row = _validate_mode(validate), low_precision, lanes_per_row
+    h = C.c_void_p()
+    native.check(lib.mdp_create_from_device_rows(int(S), int(A), int(k_max), kernel, user, float(gamma),
+                                                 C.byref(o), C.byref(h)))
+    return h
+
+
 def mdp_info(h):
     S, A, nnz, L, b = C.c_int64(), C.c_int32(), C.c_int64(), C.c_int32(), C.c_int64()
     native.check(native.load().mdp_info(h, C.byref(S), C.byref(A), C.byref(nnz), C.byref(L),
@@ -196,12 +221,12 @@ def _stats_dict(st, hist):
 
 
 def mdp_policy_eval(h, policy, v, v0=None, inner=MDP_INNER_GMRES, restart=30, precision=MDP_FP64,
-                    rtol=1e-10, max_iter=10000, sync_every=0):
+                    rtol=1e-10, max_iter=10000, sync_every=0, precond_degree=1, gs_passes=1):
     lib = native.load()
     o = native.EvalOpts()
     lib.mdp_default_eval_opts(C.byref(o))
     o.inner, o.restart, o.precision, o.rtol, o.max_iter = inner, restart, precision, rtol, max_iter
-    o.sync_every = sync_every
+    o.sync_every, o.precond_degree, o.gs_passes = sync_every, precond_degree, gs_passes
     st, hist = _stats()
     status = native.check(lib.mdp_policy_eval(h, _ptr(policy, np.int32, name="policy"),
                                               _ptr(v0, np.float64, name="v0"),
@@ -214,12 +239,13 @@ def mdp_policy_eval(h, policy, v, v0=None, inner=MDP_INNER_GMRES, restart=30, pr
 
 def mdp_solve(h, v, policy, v0=None, inner=MDP_INNER_GMRES, restart=30, precision=MDP_FP64,
               alpha=1e-4, atol=1e-8, rtol_cert=0.0, max_outer=1000, max_inner=10000,
-              sync_every=0, history_cap=1024):
+              sync_every=0, history_cap=1024, precond_degree=1, gs_passes=1):
     lib = native.load()
     o = native.SolveOpts()
     lib.mdp_default_solve_opts(C.byref(o))
     o.inner, o.restart, o.precision, o.alpha, o.atol = inner, restart, precision, alpha, atol
     o.rtol_cert, o.max_outer, o.max_inner, o.sync_every = rtol_cert, max_outer, max_inner, sync_every
+    o.precond_degree, o.gs_passes = precond_degree, gs_passes
     st, hist = _stats(history_cap)
     status = native.check(lib.mdp_solve(h, _ptr(v0, np.float64, name="v0"),
                                         _ptr(v, np.float64, name="v"),
@@ -231,12 +257,13 @@ def mdp_solve(h, v, policy, v0=None, inner=MDP_INNER_GMRES, restart=30, precisio
 
 
 def _solve_opts(lib, inner=MDP_INNER_GMRES, restart=30, precision=MDP_FP64, alpha=1e-4, atol=1e-8,
-                rtol_cert=0.0, max_outer=1000, max_inner=10000, sync_every=0, launch=0):
+                rtol_cert=0.0, max_outer=1000, max_inner=10000, sync_every=0, launch=0, precond_degree=1,
+                gs_passes=1):
     o = native.SolveOpts()
     lib.mdp_default_solve_opts(C.byref(o))
     o.inner, o.restart, o.precision, o.alpha, o.atol = inner, restart, precision, alpha, atol
     o.rtol_cert, o.max_outer, o.max_inner, o.sync_every = rtol_cert, max_outer, max_inner, sync_every
-    o.launch = launch
+    o.launch, o.precond_degree, o.gs_passes = launch, precond_degree, gs_passes
     return o
 
 
@@ -326,12 +353,12 @@ class Server:
     """Continuous-batching solve server (mdp_server_* in include/mdp.h)."""
 
     def __init__(self, hbm_budget_bytes=64 << 30, max_batch=256, device=-1, stream=None,
-                 admit_threads=4, retire_threads=4, **solve_opts):
+                 admit_threads=4, retire_threads=4, autotune=False, **solve_opts):
         lib = native.load()
         o = native.ServerOpts()
         lib.mdp_default_server_opts(C.byref(o))
         o.hbm_budget_bytes, o.max_batch, o.device, o.stream = hbm_budget_bytes, max_batch, device, stream
-        o.admit_threads, o.retire_threads = admit_threads, retire_threads
+        o.admit_threads, o.retire_threads, o.autotune = admit_threads, retire_threads, int(bool(autotune))
         solve_opts.setdefault("precision", MDP_MIXED_FP32)
         o.solve = _solve_opts(lib, **solve_opts)
         self.s = C.c_void_p()

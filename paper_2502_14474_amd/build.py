@@ -13,7 +13,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmdp.so")
 OBJDIR = os.path.join(ROOT, "_build")
 SOURCES = ["kernels.hip", "colblock.hip", "krylov.hip", "vecops.hip", "batch.hip", "api.cpp", "serve.cpp",
-           "tune.cpp", "noalloc.hip"]
+           "tune.cpp", "noalloc.hip", "devrows.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
@@ -63,6 +63,28 @@ def build(verbose=False, out=LIB, defines=()):
         raise RuntimeError("hipcc link failed:\n" + "\n".join(msgs))
     os.replace(tmp, out)
     return out
+
+
+def build_code_objects(verbose=False, directory=os.path.join(ROOT, "tests", "kernels")):
+    """Compile each .hip file of `directory` to a code object (.hsaco, gfx950)
+    beside it: row kernels that tests hand to mdp_create_from_device_rows."""
+    outs = []
+    if not os.path.isdir(directory):
+        return outs
+    for name in sorted(os.listdir(directory)):
+        if not name.endswith(".hip"):
+            continue
+        src = os.path.join(directory, name)
+        out = os.path.splitext(src)[0] + ".hsaco"
+        cmd = [HIPCC, "--genco"] + [f for f in FLAGS if f != "-fPIC"] + ["-I", os.path.join(ROOT, "include"),
+                                                                        src, "-o", out]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        rc, msgs = _run(cmd)
+        if rc != 0:
+            raise RuntimeError(f"hipcc failed on {src}:\n" + "\n".join(msgs))
+        outs.append(out)
+    return outs
 
 
 if __name__ == "__main__":

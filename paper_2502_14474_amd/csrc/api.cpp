@@ -326,6 +326,7 @@ struct InnerResult {
   int64_t applies = 0;
   int64_t refinements = 0;
   double bytes = 0;
+  double orth_loss = 0;
   bool converged = false;
 };
 
@@ -334,7 +335,8 @@ struct InnerResult {
 // run in `prec`; every restart recomputes the residual in float64 from the
 // float64 P, so the mixed-precision variants are iterative refinement.
 mdp_status gmres_inner(mdp_handle* h, Prec prec, const int32_t* pi, double* x, int m,
-                       int64_t max_iter, int sync_every, double alpha, InnerResult* out) {
+                       int64_t max_iter, int sync_every, double alpha, InnerResult* out, int deg = 1,
+                       bool gs2 = false) {
   const Prec bprec = prec == kF64 ? kF64 : kF32;
   const int bb = bprec == kF64 ? 8 : 4;
   for (;;) {
@@ -356,12 +358,12 @@ mdp_status gmres_inner(mdp_handle* h, Prec prec, const int32_t* pi, double* x, i
     bool stale = false;  // steps were queued after the last snapshot
     while (!h->ctl_host->done && j < m) {
       for (int b = 0; b < chunk && j < m; ++b, ++j) {
-        MDP_HIP(launch_arnoldi_step(h, prec, pi, j, m));
+        MDP_HIP(launch_arnoldi_step(h, prec, pi, j, m, deg, gs2));
       }
       const int j_snap = j;
       MDP_TRY(ctl_snapshot(h));
       if (j < m) {
-        MDP_HIP(launch_arnoldi_step(h, prec, pi, j, m));
+        MDP_HIP(launch_arnoldi_step(h, prec, pi, j, m, deg, gs2));
         ++j;
       }
       stale = j > j_snap;
@@ -382,14 +384,26 @@ mdp_status gmres_inner(mdp_handle* h, Prec prec, const int32_t* pi, double* x, i
     if (stale && !h->ctl_host->done) MDP_TRY(sync_ctl(h));
     const int done_j = h->ctl_host->j;
     prof_discard_steps(h, rec0, done_j);
+    // a preconditioned step also makes deg - 1 Horner products (y = b + gamma P_pi x)
+    const double horner_bytes = bytes_apply(h, bval_of(prec), bb, bb) + h->S * (double)bb;
     for (int jj = 0; jj < done_j; ++jj)
-      out->bytes += bytes_arnoldi_apply(h, bval_of(prec), bb, jj) + bytes_arnoldi_update(h, bb, jj);
-    out->applies += done_j;
+      out->bytes += bytes_arnoldi_apply(h, bval_of(prec), bb, jj) + bytes_arnoldi_update(h, bb, jj) +
+                    (deg - 1) * horner_bytes;
+    out->applies += static_cast<int64_t>(done_j) * deg;
     if (done_j > 0) {
-      MDP_HIP(launch_gmres_update_x(h, bprec, x));
-      out->bytes += h->S * (16.0 + done_j * (double)bb);
+      if (deg > 1) {
+        MDP_HIP(launch_precond_update_x(h, prec, pi, x, m, deg));
+        out->applies += deg - 1;
+        out->bytes += h->S * (16.0 + done_j * (double)bb) + (deg - 1) * horner_bytes;
+      } else {
+        MDP_HIP(launch_gmres_update_x(h, bprec, x));
+        out->bytes += h->S * (16.0 + done_j * (double)bb);
+      }
     }
     out->steps = h->ctl_host->steps;
+    out->orth_loss = std::max(out->orth_loss, h->ctl_host->orth_loss);
+    if (gs2)  // the second pass reads the basis and the new vector once more and updates again
+      for (int jj = 0; jj < done_j; ++jj) out->bytes += h->S * (jj + 2.0) * bb + bytes_arnoldi_update(h, bb, jj);
     const double est = h->ctl_host->res_est;
     if (!std::isfinite(est)) return fail(MDP_E_NUMERIC, "non-finite GMRES residual");
     if (h->ctl_host->converged && prec == kF64) {
@@ -732,6 +746,8 @@ void mdp_default_eval_opts(mdp_eval_opts* o) {
   o->sync_every = 0;
   o->rtol = 1e-10;
   o->max_iter = 10000;
+  o->precond_degree = 1;
+  o->gs_passes = 1;
 }
 
 void mdp_default_solve_opts(mdp_solve_opts* o) {
@@ -748,6 +764,8 @@ void mdp_default_solve_opts(mdp_solve_opts* o) {
   o->max_outer = 1000;
   o->max_inner = 10000;
   o->launch = MDP_LAUNCH_AUTO;
+  o->precond_degree = 1;
+  o->gs_passes = 1;
 }
 
 mdp_status mdp_destroy(mdp_t h) {
@@ -1204,6 +1222,14 @@ mdp_status mdp_policy_eval(mdp_t h, const int32_t* policy, const double* v0, dou
   if (o.inner == MDP_INNER_RICHARDSON && o.precision != MDP_FP64)
     return fail(MDP_E_NOTSUP, "Richardson runs in float64 only");
   if (!(o.rtol >= 0.0) || o.max_iter < 0) return fail(MDP_E_INVAL, "bad tolerance or iteration cap");
+  if (o.precond_degree < 0 || o.precond_degree > kMaxPrecondDegree)
+    return fail(MDP_E_INVAL, "precond_degree must lie in [0,16]");
+  const int deg = std::max(1, o.precond_degree);
+  if (deg > 1 && o.inner != MDP_INNER_GMRES)
+    return fail(MDP_E_NOTSUP, "the polynomial preconditioner serves GMRES only");
+  if (o.gs_passes < 0 || o.gs_passes > 2) return fail(MDP_E_INVAL, "gs_passes must be 0, 1 or 2");
+  const bool gs2 = o.gs_passes == 2;
+  if (gs2 && o.inner != MDP_INNER_GMRES) return fail(MDP_E_NOTSUP, "gs_passes = 2 serves GMRES only");
   BusyGuard g(h);
   if (!g.ok) return fail(MDP_E_STATE, "handle is busy");
   stats_begin(stats);
@@ -1222,13 +1248,13 @@ mdp_status mdp_policy_eval(mdp_t h, const int32_t* policy, const double* v0, dou
     rel = h->ctl_host->beta0 > 0 ? h->ctl_host->res_est / h->ctl_host->beta0 : 0.0;
   } else if (o.inner == MDP_INNER_GMRES) {
     const Prec prec = prec_of(o.precision);
-    MDP_TRY(ensure_basis(h, prec == kF64 ? kF64 : kF32, o.restart));
+    MDP_TRY(ensure_basis(h, prec == kF64 ? kF64 : kF32, o.restart + (deg > 1 ? 3 : 0)));
     if (prec != kF64) MDP_TRY(ensure_lowp(h, prec));
     void* slot0 = prec == kF64 ? static_cast<void*>(h->U64) : static_cast<void*>(h->U32);
     MDP_HIP(launch_apply(h, kApplyRes, h->pi, h->v, slot0, prec != kF64, kRedGmresStart, 1, o.rtol,
                          floor_of(prec)));
     ir.applies += 1;
-    MDP_TRY(gmres_inner(h, prec, h->pi, h->v, o.restart, o.max_iter, sync_every, o.rtol, &ir));
+    MDP_TRY(gmres_inner(h, prec, h->pi, h->v, o.restart, o.max_iter, sync_every, o.rtol, &ir, deg, gs2));
     MDP_TRY(sync_ctl(h));
     rel = h->ctl_host->beta0 > 0 ? h->ctl_host->res_est / h->ctl_host->beta0 : 0.0;
     if (ir.converged && prec != kF64)
@@ -1248,6 +1274,7 @@ mdp_status mdp_policy_eval(mdp_t h, const int32_t* policy, const double* v0, dou
     stats->inner_iters = ir.steps;
     stats->policy_applies = ir.applies;
     stats->refinements = ir.refinements;
+    stats->orth_loss = ir.orth_loss;
     stats->residual = rel;
     stats->bytes = ir.bytes;
     stats->time_ms = now_ms() - t0;
@@ -1277,6 +1304,14 @@ mdp_status mdp_solve(mdp_t h, const double* v0, double* v, int32_t* policy,
     return fail(MDP_E_NOTSUP, "Richardson runs in float64 only");
   if (!(o.alpha > 0.0 && o.alpha < 1.0)) return fail(MDP_E_INVAL, "alpha must lie in (0,1)");
   if (!(o.atol > 0.0) || o.max_outer < 0 || o.max_inner < 1) return fail(MDP_E_INVAL, "bad tolerance or caps");
+  if (o.precond_degree < 0 || o.precond_degree > kMaxPrecondDegree)
+    return fail(MDP_E_INVAL, "precond_degree must lie in [0,16]");
+  const int deg = std::max(1, o.precond_degree);
+  if (deg > 1 && o.inner != MDP_INNER_GMRES)
+    return fail(MDP_E_NOTSUP, "the polynomial preconditioner serves GMRES only");
+  if (o.gs_passes < 0 || o.gs_passes > 2) return fail(MDP_E_INVAL, "gs_passes must be 0, 1 or 2");
+  const bool gs2 = o.gs_passes == 2;
+  if (gs2 && o.inner != MDP_INNER_GMRES) return fail(MDP_E_NOTSUP, "gs_passes = 2 serves GMRES only");
   BusyGuard g(h);
   if (!g.ok) return fail(MDP_E_STATE, "handle is busy");
   stats_begin(stats);
@@ -1284,7 +1319,7 @@ mdp_status mdp_solve(mdp_t h, const double* v0, double* v, int32_t* policy,
   const Prec iprec = prec_of(o.precision);
   const bool gm = o.inner == MDP_INNER_GMRES;
   const bool bi = o.inner == MDP_INNER_BICGSTAB || o.inner == MDP_INNER_TFQMR;
-  if (gm) MDP_TRY(ensure_basis(h, iprec == kF64 ? kF64 : kF32, o.restart));
+  if (gm) MDP_TRY(ensure_basis(h, iprec == kF64 ? kF64 : kF32, o.restart + (deg > 1 ? 3 : 0)));
   if (bi) MDP_TRY(ensure_basis(h, kF64, std::max(o.restart, 7)));
   if (iprec != kF64) MDP_TRY(ensure_lowp(h, iprec));
   MDP_TRY(load_vec(h, v0, h->v));
@@ -1294,7 +1329,7 @@ mdp_status mdp_solve(mdp_t h, const double* v0, double* v, int32_t* policy,
   double prev_res = std::numeric_limits<double>::infinity();
   double res = prev_res, tv_max = 0.0;
   int64_t k = 0, sweeps = 0, inner = 0, applies = 0, refinements = 0;
-  double bytes = 0.0;
+  double bytes = 0.0, orth_loss = 0.0;
   bool converged = false;
   // mixed precision: low-precision sweeps until the residual is small relative to |v|;
   // with a column-blocked copy the float64 sweep is the faster one and is used throughout
@@ -1345,7 +1380,7 @@ mdp_status mdp_solve(mdp_t h, const double* v0, double* v, int32_t* policy,
     prev_res = res;
     InnerResult ir;
     if (gm) {
-      MDP_TRY(gmres_inner(h, iprec, h->pi, h->v, o.restart, o.max_inner, sync_every, alpha, &ir));
+      MDP_TRY(gmres_inner(h, iprec, h->pi, h->v, o.restart, o.max_inner, sync_every, alpha, &ir, deg, gs2));
     } else if (bi) {
       MDP_TRY(bicgstab_inner(h, h->pi, h->v, o.max_inner, sync_every, &ir, o.inner == MDP_INNER_TFQMR));
     } else {
@@ -1364,6 +1399,7 @@ mdp_status mdp_solve(mdp_t h, const double* v0, double* v, int32_t* policy,
     applies += ir.applies;
     refinements += ir.refinements;
     bytes += ir.bytes;
+    orth_loss = std::max(orth_loss, ir.orth_loss);
     ++k;
   }
   MDP_TRY(store_values(h, v, h->v));
@@ -1375,6 +1411,7 @@ mdp_status mdp_solve(mdp_t h, const double* v0, double* v, int32_t* policy,
     stats->bellman_sweeps = sweeps;
     stats->policy_applies = applies;
     stats->refinements = refinements;
+    stats->orth_loss = orth_loss;
     stats->residual = res;
     stats->bytes = bytes;
     stats->time_ms = now_ms() - t0;
@@ -1394,6 +1431,8 @@ mdp_status mdp_solve_batch(mdp_t* handles, int32_t n, const double* const* v0, d
     o = *opt;
   }
   if (o.inner != MDP_INNER_GMRES) return fail(MDP_E_NOTSUP, "batched solves use GMRES");
+  if (o.precond_degree > 1) return fail(MDP_E_NOTSUP, "batched solves run without a preconditioner");
+  if (o.gs_passes > 1) return fail(MDP_E_NOTSUP, "batched solves use one Gram-Schmidt pass");
   if (o.launch < MDP_LAUNCH_AUTO || o.launch > MDP_LAUNCH_DIRECT) return fail(MDP_E_INVAL, "unknown launch mode");
   if (o.restart < 1 || o.restart > kMaxRestart) return fail(MDP_E_INVAL, "restart must lie in [1,64]");
   if (o.precision < MDP_FP64 || o.precision > MDP_MIXED_FP16) return fail(MDP_E_INVAL, "unknown precision");

@@ -16,12 +16,12 @@
 // in increasing order and tiles holding more than 65535 entries of one slice
 // are not supported: the copy is then not built.
 //
-// The slices of a row are short (a row's k entries spread over all slices),
-// so one thread takes a whole row segment: it loads the first E entries
-// unconditionally (E about twice the mean segment length) and sums them in
-// CSR order.  A row's sum is the sum of its
-// slice parts in slice order, so the result is deterministic and identical
-// rows give identical sums.
+// The slice parts of a row are short (a row's k entries spread over all
+// slices), so a pass streams each tile's segment as a flat array, every lane
+// taking every kBlock-th entry, and only then assigns the products to rows
+// (through LDS).  A row's sum is the sum of its slice parts in slice order,
+// each part an fma chain in CSR order, so the result is deterministic and
+// identical rows give identical sums.
 #include "device.h"
 
 namespace mdp {
@@ -121,12 +121,23 @@ __global__ __launch_bounds__(kBlock) void k_cb_scatter(int64_t rows, int tile_ro
   }
 }
 
-// One pass of the blocked sweep over slice b for one tile of states; thread
-// i takes rows i, i + kBlock, ... of the tile.  Passes before the last add the
-// slice's part of each row into acc; the last pass forms
-// Q = g + gamma * (acc + part) in LDS and finishes the tile like the plain
-// sweep.
-template <int E, bool FIRST, bool LAST, typename RT>
+// One pass of the blocked sweep over slice b for one tile of states.  The
+// tile's entries in slice b are one contiguous segment; it is streamed in
+// chunks of kCbChunk entries.  Every thread loads entries i, i + kBlock, ...
+// of a chunk (coalesced column and value streams), gathers their v values
+// from the L2-resident slice, and leaves each (value, v) pair in LDS; the next
+// chunk's loads are issued before the pairs are stored, so they stay in
+// flight.  Then thread i carries rows i, i + kBlock, ... of the tile (at most
+// 4) through the chunk: a row's slice part is the fma chain over its entries
+// in CSR order, started from 0, and continues across chunks.  Passes before
+// the last add the part into acc; the last forms Q = g + gamma (acc + part)
+// in LDS and finishes the tile like the plain sweep.
+#ifndef MDP_CB_CHUNK
+#define MDP_CB_CHUNK 1024
+#endif
+constexpr int kCbChunk = MDP_CB_CHUNK;
+
+template <bool FIRST, bool LAST, typename RT>
 __global__ __launch_bounds__(kBlock) void k_bellman_cb(
     int64_t S, int A, int tile_states, int ntiles, int b, const uint16_t* __restrict__ rel,
     const int* __restrict__ off, const int* __restrict__ cb_col, const double* __restrict__ cb_val,
@@ -134,7 +145,9 @@ __global__ __launch_bounds__(kBlock) void k_bellman_cb(
     double* __restrict__ acc, double* __restrict__ Tv, int* __restrict__ pi, RT* __restrict__ r0,
     double4* __restrict__ partials) {
   extern __shared__ double q[];  // LAST: one value per row of the tile
-  constexpr int RPT = 4;         // rows per thread: tiles hold at most 4 * kBlock rows
+  __shared__ double lp[kCbChunk], lx[kCbChunk];
+  constexpr int RPT = 4;  // rows per thread: tiles hold at most 4 * kBlock rows
+  constexpr int EPT = kCbChunk / kBlock;
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
   const int64_t rows = S * A;
   const int64_t s0 = static_cast<int64_t>(tile) * tile_states;
@@ -142,44 +155,65 @@ __global__ __launch_bounds__(kBlock) void k_bellman_cb(
   const int nrows = ns * A;
   const int64_t row0 = s0 * A;
   const int64_t ob = static_cast<int64_t>(b) * (ntiles + 1) + tile;
-  const int base = off[ob], tend = off[ob + 1];
+  const int base = off[ob];
+  const int n = off[ob + 1] - base;
   const uint16_t* __restrict__ rl = rel + static_cast<int64_t>(b) * rows + row0;
+  const int* __restrict__ cc = cb_col + base;
+  const double* __restrict__ cv = cb_val + base;
   const Gather<double> gx(v, S);
   int st[RPT], en[RPT];
-  double prev[RPT];
+  double prev[RPT], sum[RPT];
 #pragma unroll
   for (int k = 0; k < RPT; ++k) {
     const int i = threadIdx.x + k * kBlock;
     const bool valid = i < nrows;
     const int a = rl[valid ? i : 0];
     const int z = rl[i + 1 < nrows ? i + 1 : 0];
-    st[k] = valid ? base + a : 0;
-    en[k] = valid ? (i + 1 < nrows ? base + z : tend) : 0;
-    if (!FIRST) prev[k] = acc[row0 + (valid ? i : 0)];
+    st[k] = valid ? a : 0;
+    en[k] = valid ? (i + 1 < nrows ? z : n) : 0;
+    prev[k] = FIRST ? 0.0 : acc[row0 + (valid ? i : 0)];
+    sum[k] = 0.0;
   }
-  int c[RPT][E];
-  double p[RPT][E];
+  int c[EPT];
+  double p[EPT];
+  // unconditional loads: lanes past the segment read its first entry (an
+  // empty segment is never fetched)
+  auto fetch = [&](int c0) {
 #pragma unroll
-  for (int k = 0; k < RPT; ++k)
-#pragma unroll
-    for (int e = 0; e < E; ++e) {
-      const int idx = st[k] + e;
-      const bool ok = idx < en[k];
-      const int is = ok ? idx : 0;
-      const int cv = ld_col(cb_col + is);
-      const double pv = ld_val(cb_val + is);
-      c[k][e] = ok ? cv : -1;
-      p[k][e] = ok ? pv : 0.0;
+    for (int e = 0; e < EPT; ++e) {
+      const int idx = c0 + threadIdx.x + e * kBlock;
+      const bool ok = idx < n;
+      const int craw = ld_col(cc + (ok ? idx : 0));
+      const double praw = ld_val(cv + (ok ? idx : 0));
+      c[e] = ok ? craw : -1;
+      p[e] = ok ? praw : 0.0;
     }
-  double sum[RPT];
+  };
+  if (n > 0) fetch(0);
+  for (int c0 = 0; c0 < n; c0 += kCbChunk) {
+    double x[EPT], pc[EPT];
 #pragma unroll
-  for (int k = 0; k < RPT; ++k) {
-    double sk = 0.0;
+    for (int e = 0; e < EPT; ++e) {
+      x[e] = gx(c[e]);  // 0 past the segment (c = -1)
+      pc[e] = p[e];
+    }
+    fetch(c0 + kCbChunk < n ? c0 + kCbChunk : c0);
 #pragma unroll
-    for (int e = 0; e < E; ++e) sk = fma(p[k][e], gx(c[k][e]), sk);  // 0 for empty slots
-    for (int idx = st[k] + E; idx < en[k]; ++idx)
-      sk = fma(ld_val(cb_val + idx), gx(ld_col(cb_col + idx)), sk);
-    sum[k] = sk;
+    for (int e = 0; e < EPT; ++e) {
+      lp[threadIdx.x + e * kBlock] = pc[e];
+      lx[threadIdx.x + e * kBlock] = x[e];
+    }
+    __syncthreads();
+    const int c1 = c0 + kCbChunk;
+#pragma unroll
+    for (int k = 0; k < RPT; ++k) {
+      const int lo = st[k] > c0 ? st[k] : c0;
+      const int hi = en[k] < c1 ? en[k] : c1;
+      double sk = sum[k];
+      for (int j = lo; j < hi; ++j) sk = fma(lp[j - c0], lx[j - c0], sk);
+      sum[k] = sk;
+    }
+    __syncthreads();
   }
 #pragma unroll
   for (int k = 0; k < RPT; ++k) {
@@ -198,37 +232,25 @@ __global__ __launch_bounds__(kBlock) void k_bellman_cb(
   }
 }
 
-template <typename F>
-hipError_t with_cb_width(int width, F&& f) {
-  switch (width) {
-    case 2: return f(std::integral_constant<int, 2>{});
-    case 4: return f(std::integral_constant<int, 4>{});
-    default: return f(std::integral_constant<int, 8>{});
-  }
-}
-
 template <typename RT>
 hipError_t cb_passes(mdp_handle* h, const double* v, double* Tv, int32_t* pi, RT* r0,
                      double4* part, int nb) {
   const int ts = sweep_tile_states(h->A);
   const int nblk = h->cb_blocks;
   const size_t lds_last = static_cast<size_t>(ts) * h->A * sizeof(double);
-  return with_cb_width(h->cb_width, [&](auto Ec) -> hipError_t {
-    constexpr int E = decltype(Ec)::value;
 #define MDP_CB_ARGS(B)                                                                     \
   h->S, h->A, ts, nb, (B), h->cb_rel, h->cb_off, h->cb_col, h->cb_val, h->cost, v, h->gamma, \
       h->cb_acc, Tv, pi, r0, part
-    if (nblk == 1) {
-      k_bellman_cb<E, true, true, RT><<<nb, kBlock, lds_last, h->stream>>>(MDP_CB_ARGS(0));
-      return hipGetLastError();
-    }
-    k_bellman_cb<E, true, false, RT><<<nb, kBlock, 0, h->stream>>>(MDP_CB_ARGS(0));
-    for (int b = 1; b + 1 < nblk; ++b)
-      k_bellman_cb<E, false, false, RT><<<nb, kBlock, 0, h->stream>>>(MDP_CB_ARGS(b));
-    k_bellman_cb<E, false, true, RT><<<nb, kBlock, lds_last, h->stream>>>(MDP_CB_ARGS(nblk - 1));
-#undef MDP_CB_ARGS
+  if (nblk == 1) {
+    k_bellman_cb<true, true, RT><<<nb, kBlock, lds_last, h->stream>>>(MDP_CB_ARGS(0));
     return hipGetLastError();
-  });
+  }
+  k_bellman_cb<true, false, RT><<<nb, kBlock, 0, h->stream>>>(MDP_CB_ARGS(0));
+  for (int b = 1; b + 1 < nblk; ++b)
+    k_bellman_cb<false, false, RT><<<nb, kBlock, 0, h->stream>>>(MDP_CB_ARGS(b));
+  k_bellman_cb<false, true, RT><<<nb, kBlock, lds_last, h->stream>>>(MDP_CB_ARGS(nblk - 1));
+#undef MDP_CB_ARGS
+  return hipGetLastError();
 }
 
 }  // namespace
@@ -328,9 +350,6 @@ hipError_t build_colblocks(mdp_handle* h, int blocks, bool require, bool* built,
   h->cb_col = cb_col;
   h->cb_val = cb_val;
   h->cb_acc = acc;
-  const double mean = static_cast<double>(h->nnz) / static_cast<double>(rows) / blocks;
-  // slots loaded per row segment: about twice the mean segment length
-  h->cb_width = mean <= 1.0 ? 2 : (mean <= 2.0 ? 4 : 8);
   h->device_bytes += static_cast<int64_t>(cnt_bytes * sizeof(uint16_t) + off_h.size() * sizeof(int) +
                                           h->nnz * 12 + rows * 8);
   *built = true;

@@ -547,6 +547,43 @@ __device__ __forceinline__ void apply_tile(
 // ctl->scale[i] * U_i.  That lets the normalisation of a new vector ride on the
 // next pass instead of costing a pass of its own.
 
+// One Horner step of the polynomial preconditioner M^-1 = sum_{i<d} (gamma P_pi)^i
+// (a truncated Neumann series of (I - gamma P_pi)^-1):  y = b + gamma P_pi x.
+// d - 1 steps from x = b give M^-1 b.  The tile's b values are staged in LDS
+// with its selected rows, so the sink issues no load of its own.
+template <int L, int U, typename VT, typename XT, bool CORR>
+__device__ __forceinline__ void horner_tile(int64_t S, int A, RowIndex rix, const int* __restrict__ col,
+                                            const VT* __restrict__ val, const double* __restrict__ corr,
+                                            const int* __restrict__ pi, const XT* __restrict__ x,
+                                            const XT* __restrict__ b, double gamma, XT* __restrict__ y,
+                                            int tile) {
+  using AT = typename Acc<XT>::type;
+  __shared__ int st_l[kApplyTile], en_l[kApplyTile], rw_l[kApplyTile];
+  __shared__ XT b_l[kApplyTile];
+  const int64_t s0 = static_cast<int64_t>(tile) * kApplyTile;
+  const int ns = static_cast<int>(min<int64_t>(kApplyTile, S - s0));
+  const AT gam = static_cast<AT>(gamma);
+  for (int t = threadIdx.x; t < ns; t += kBlock) b_l[t] = b[s0 + t];
+  stage_policy_rows(S, s0, ns, A, rix, pi, st_l, en_l, rw_l);  // its barrier publishes b_l
+  pipelined_rows<L, U, VT, XT, AT, CORR, false, false>(
+      ns,
+      [&](int idx, int& st, int& en, int& ri, int& si) {
+        st = st_l[idx];
+        en = en_l[idx];
+        ri = rw_l[idx];
+        si = -1;
+      },
+      col, val, x, S, nullptr, corr,
+      [&](int ss, AT pv, double, XT) {
+        if ((threadIdx.x % L) == 0) y[s0 + ss] = static_cast<XT>(fma(gam, pv, static_cast<AT>(b_l[ss])));
+      });
+}
+
+template <typename BT>
+__device__ __forceinline__ void cgs_dots_tile(const BT* __restrict__ Ub, int64_t ldu, int j, int64_t s0, int ns,
+                                              const double* w_lds, double* __restrict__ partials, int tile,
+                                              int nb);
+
 // K2+K4: w = scale_j * (I - gamma P_pi) U_j stored into U_{j+1}, and the
 // workgroup's partial dot products sum_s U_i[s] w[s], i = 0..j (classical
 // Gram-Schmidt, one pass over the basis).  partials[i * nb + tile].
@@ -555,15 +592,15 @@ __device__ __forceinline__ void arnoldi_apply_tile(
     int64_t S, int A, RowIndex rix, const int* __restrict__ col,
     const VT* __restrict__ val, const double* __restrict__ corr, const int* __restrict__ pi,
     BT* __restrict__ Ub, int64_t ldu, int j, double gamma, const Ctl* __restrict__ ctl,
-    double* __restrict__ partials, int tile, int nb) {
+    double* __restrict__ partials, int tile, int nb, const BT* __restrict__ xin = nullptr) {
   using AT = typename Acc<BT>::type;
   __shared__ double w_lds[kApplyTile];
   __shared__ int st_l[kApplyTile], en_l[kApplyTile], rw_l[kApplyTile];
-  __shared__ double red[kBlock / kWave][8];
   const int64_t s0 = static_cast<int64_t>(tile) * kApplyTile;
   const int ns = static_cast<int>(min<int64_t>(kApplyTile, S - s0));
   const AT gam = static_cast<AT>(gamma);
-  const BT* __restrict__ xj = Ub + static_cast<int64_t>(j) * ldu;
+  // the product's input: U_j, or (polynomial preconditioning) M^-1 U_j
+  const BT* __restrict__ xj = xin ? xin : Ub + static_cast<int64_t>(j) * ldu;
   BT* __restrict__ w = Ub + static_cast<int64_t>(j + 1) * ldu;
   const double cj = ctl->scale[j];
   stage_policy_rows(S, s0, ns, A, rix, pi, st_l, en_l, rw_l);
@@ -586,7 +623,17 @@ __device__ __forceinline__ void arnoldi_apply_tile(
         w_lds[ss] = static_cast<double>(wv);
       });
   __syncthreads();
+  cgs_dots_tile<BT>(Ub, ldu, j, s0, ns, w_lds, partials, tile, nb);
+}
 
+// The classical Gram-Schmidt dots of an Arnoldi tile: the workgroup's partial
+// sum_s U_i[s] w[s] for i = 0..j into partials[i * nb + tile], with the tile's
+// w values (already written to U_{j+1}) in w_lds.  Every thread must call it.
+template <typename BT>
+__device__ __forceinline__ void cgs_dots_tile(const BT* __restrict__ Ub, int64_t ldu, int j, int64_t s0, int ns,
+                                              const double* w_lds, double* __restrict__ partials, int tile,
+                                              int nb) {
+  __shared__ double red[kBlock / kWave][8];
   const int wv_id = threadIdx.x / kWave;
   constexpr int KS = kApplyTile / kBlock;
   for (int i0 = 0; i0 <= j; i0 += 8) {
@@ -641,6 +688,36 @@ __device__ __forceinline__ void reduce_dots_body(const double* __restrict__ part
     const double h = ctl->scale[i] * s;
     ctl->H[i + j * (kMaxRestart + 1)] = h;
     ctl->hc[i] = h * ctl->scale[i];
+  }
+}
+
+// CGS2, second pass: the dots of the once-orthogonalised w = U_{j+1} with
+// U_0..U_j, as in the first pass (same tiles, same order).
+template <typename BT>
+__device__ __forceinline__ void cgs2_dots_tile(int64_t S, const BT* __restrict__ Ub, int64_t ldu, int j,
+                                               double* __restrict__ partials, int tile, int nb) {
+  __shared__ double w_lds[kApplyTile];
+  const int64_t s0 = static_cast<int64_t>(tile) * kApplyTile;
+  const int ns = static_cast<int>(min<int64_t>(kApplyTile, S - s0));
+  const BT* __restrict__ w = Ub + static_cast<int64_t>(j + 1) * ldu;
+  for (int t = threadIdx.x; t < ns; t += kBlock) w_lds[t] = static_cast<double>(w[s0 + t]);
+  __syncthreads();
+  cgs_dots_tile<BT>(Ub, ldu, j, s0, ns, w_lds, partials, tile, nb);
+}
+
+// CGS2, second pass: column i (= blockIdx.x) of the dots; the coefficient h2
+// is added to H[i, j], becomes the next update's coefficient, and its square
+// is kept for the loss-of-orthogonality measure.
+__device__ __forceinline__ void reduce_dots2_body(const double* __restrict__ partials, int nb, int j,
+                                                  Ctl* __restrict__ ctl, int i) {
+  double s = strided_sum(partials + static_cast<int64_t>(i) * nb, nb, 0.0);
+  double mx = 0.0;
+  block_max_sum(mx, s);
+  if (threadIdx.x == 0) {
+    const double h2 = ctl->scale[i] * s;
+    ctl->H[i + j * (kMaxRestart + 1)] += h2;
+    ctl->hc[i] = h2 * ctl->scale[i];
+    ctl->h2sq[i] = h2 * h2;
   }
 }
 
@@ -702,7 +779,7 @@ __device__ __forceinline__ void arnoldi_update_body(int64_t S, BT* __restrict__ 
 // residual estimate and the stop decision.  One workgroup; the back
 // substitution at the end of a cycle runs column by column over the threads.
 __device__ __forceinline__ void norm_givens_body(const double* __restrict__ partials, int nb,
-                                                 int j, int m, Ctl* __restrict__ ctl) {
+                                                 int j, int m, Ctl* __restrict__ ctl, bool gs2 = false) {
   __shared__ int s_done;
   __shared__ double s_t[kMaxRestart];
   __shared__ double s_h[kMaxRestart + 2], s_cs[kMaxRestart], s_sn[kMaxRestart];
@@ -719,6 +796,13 @@ __device__ __forceinline__ void norm_givens_body(const double* __restrict__ part
   block_max_sum(mx, s);  // its barriers also publish the staged values
   if (threadIdx.x == 0) {
     const double hn = sqrt(s);
+    if (gs2) {
+      // size of the second Gram-Schmidt correction relative to the final vector
+      double q = 0.0;
+      for (int i = 0; i <= j; ++i) q += ctl->h2sq[i];
+      const double loss = hn > 0.0 ? sqrt(q) / hn : 0.0;
+      ctl->orth_loss = max_nan(ctl->orth_loss, loss);
+    }
     // size of the column before orthogonalisation, for the breakdown test
     double colnorm2 = hn * hn;
     for (int i = 0; i <= j; ++i) colnorm2 += s_h[i] * s_h[i];

@@ -18,6 +18,7 @@ constexpr int kBlock = 256;       // threads per workgroup (4 wavefronts of 64)
 constexpr int kWave = 64;         // CDNA wavefront width
 constexpr int kNumXcd = 8;        // MI355X: 8 accelerator complex dies, one L2 each
 constexpr int kMaxRestart = 64;   // largest GMRES restart length
+constexpr int kMaxPrecondDegree = 16;  // most terms of the polynomial preconditioner
 #ifndef MDP_APPLY_TILE
 #define MDP_APPLY_TILE 512
 #endif
@@ -42,6 +43,7 @@ struct Ctl {
   double beta0;        // 2-norm of the first residual of the inner solve
   double tol_cycle;    // stop threshold of the current GMRES cycle (>= tol)
   double aux_max;      // last reduced max |Tv| (Bellman sweeps)
+  double orth_loss;    // CGS2: largest ||second-pass coefficients|| / ||w|| of the cycles so far
   int32_t j;           // Arnoldi columns completed in the current cycle
   int32_t done;        // nonzero: kernels of the current batch exit at once
   int32_t converged;   // 1: tolerance met
@@ -57,6 +59,7 @@ struct Ctl {
   double cs[kMaxRestart], sn[kMaxRestart];     // Givens rotations
   double H[(kMaxRestart + 1) * kMaxRestart];   // Hessenberg / R, column-major
   double y[kMaxRestart];                       // least-squares solution
+  double h2sq[kMaxRestart + 1];                // CGS2: squares of the second-pass coefficients
   // BiCGSTAB / TFQMR scalars (device only)
   double bi_rho, bi_alpha, bi_omega, bi_beta;
   double tf_theta, tf_eta, tf_tau, tf_half;  // TFQMR: theta, eta, tau, half-steps done
@@ -105,7 +108,6 @@ struct mdp_handle {
   // so that one pass over slice b gathers only from an L2-sized piece of v.
   int32_t cb_blocks = 0;
   int32_t cb_slice = 0;
-  int32_t cb_width = 4;         // entries per row segment loaded unconditionally
   int32_t* cb_col = nullptr;    // nnz
   double* cb_val = nullptr;     // nnz
   uint16_t* cb_rel = nullptr;   // cb_blocks x rows: row start inside its (slice, tile) segment
@@ -285,6 +287,12 @@ double bytes_arnoldi_update(const mdp_handle* h, int bb, int j);
 std::string tune_key(const mdp_handle* h);
 int tune_lookup(const mdp_handle* h);
 void tune_store(const mdp_handle* h, int lanes);
+// The server tunes each new class once per process: tune_claim is true for the
+// first caller of a class, which tunes and then calls tune_release; later
+// callers of the class wait in tune_wait until the width is stored.
+bool tune_claim(const mdp_handle* h);
+void tune_release(const mdp_handle* h);
+void tune_wait(const mdp_handle* h);
 
 // Profiler hooks: bracket one launch with events when its class is selected.
 void prof_begin(mdp_handle* h, int kind, hipEvent_t* a);
@@ -333,7 +341,18 @@ hipError_t launch_tfqmr_init(mdp_handle* h, const int32_t* pi);
 hipError_t launch_tfqmr_step(mdp_handle* h, const int32_t* pi, double* x);
 
 // One Arnoldi step j (product + Gram-Schmidt + norm + Givens), early-exiting.
-hipError_t launch_arnoldi_step(mdp_handle* h, Prec prec, const int32_t* pi, int j, int m);
+// deg > 1: right polynomial preconditioning, the product runs on
+// M^-1 U_j = sum_{i<deg} (gamma P_pi)^i U_j (deg - 1 Horner steps in basis
+// slots m + 1, m + 2; the basis must hold m + 4 slots).
+// gs2: classical Gram-Schmidt with one re-orthogonalisation pass (CGS2): the
+// updated vector's dots with the basis are taken again, added into the
+// Hessenberg column and subtracted once more; ctl->orth_loss keeps the largest
+// relative size of that second correction.
+hipError_t launch_arnoldi_step(mdp_handle* h, Prec prec, const int32_t* pi, int j, int m, int deg = 1,
+                               bool gs2 = false);
+// End of a cycle with polynomial preconditioning: x += M^-1 (V y) (slots
+// m + 1 .. m + 3).
+hipError_t launch_precond_update_x(mdp_handle* h, Prec prec, const int32_t* pi, double* x, int m, int deg);
 
 // x += V y over the completed columns of the current cycle.
 hipError_t launch_gmres_update_x(mdp_handle* h, Prec prec, double* x);

@@ -44,11 +44,40 @@ __global__ __launch_bounds__(kBlock) void k_arnoldi_apply(
     int64_t S, int A, const int* __restrict__ row_ptr, int kfix, const int* __restrict__ col,
     const VT* __restrict__ val, const double* __restrict__ corr, const int* __restrict__ pi,
     BT* __restrict__ Ub, int64_t ldu, int j, double gamma, const Ctl* __restrict__ ctl,
-    double* __restrict__ partials) {
+    double* __restrict__ partials, const BT* __restrict__ xin) {
   if (ctl->done) return;
   arnoldi_apply_tile<L, U, VT, BT, CORR>(S, A, RowIndex{row_ptr, kfix}, col, val, corr, pi, Ub, ldu, j, gamma,
                                          ctl, partials, xcd_tile(blockIdx.x, gridDim.x),
-                                         gridDim.x);
+                                         gridDim.x, xin);
+}
+
+// Horner step y = b + gamma P_pi x of the polynomial preconditioner; exits at
+// once when ctl is given and the current GMRES cycle is done.
+template <int L, int U, typename VT, typename XT, bool CORR>
+__global__ __launch_bounds__(kBlock) void k_horner(int64_t S, int A, const int* __restrict__ row_ptr, int kfix,
+                                                   const int* __restrict__ col, const VT* __restrict__ val,
+                                                   const double* __restrict__ corr, const int* __restrict__ pi,
+                                                   const XT* __restrict__ x, const XT* __restrict__ b,
+                                                   double gamma, XT* __restrict__ y,
+                                                   const Ctl* __restrict__ ctl) {
+  if (ctl && ctl->done) return;
+  horner_tile<L, U, VT, XT, CORR>(S, A, RowIndex{row_ptr, kfix}, col, val, corr, pi, x, b, gamma, y,
+                                  xcd_tile(blockIdx.x, gridDim.x));
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_zero(T* __restrict__ x, int64_t n) {
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * kBlock)
+    x[i] = T(0);
+}
+
+// x += q (q in the basis precision)
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_add_to(double* __restrict__ x, const T* __restrict__ q, int64_t n) {
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * kBlock)
+    x[i] += static_cast<double>(q[i]);
 }
 
 __global__ __launch_bounds__(kBlock) void k_reduce_dots(const double* __restrict__ partials,
@@ -68,9 +97,22 @@ __global__ __launch_bounds__(kBlock) void k_arnoldi_update(int64_t S, BT* __rest
 
 __global__ __launch_bounds__(kBlock) void k_norm_givens(const double* __restrict__ partials,
                                                         int nb, int j, int m,
+                                                        Ctl* __restrict__ ctl, int gs2) {
+  if (ctl->done) return;
+  norm_givens_body(partials, nb, j, m, ctl, gs2 != 0);
+}
+
+template <typename BT>
+__global__ __launch_bounds__(kBlock) void k_cgs2_dots(int64_t S, const BT* __restrict__ Ub, int64_t ldu, int j,
+                                                     const Ctl* __restrict__ ctl, double* __restrict__ partials) {
+  if (ctl->done) return;
+  cgs2_dots_tile<BT>(S, Ub, ldu, j, partials, xcd_tile(blockIdx.x, gridDim.x), gridDim.x);
+}
+
+__global__ __launch_bounds__(kBlock) void k_reduce_dots2(const double* __restrict__ partials, int nb, int j,
                                                         Ctl* __restrict__ ctl) {
   if (ctl->done) return;
-  norm_givens_body(partials, nb, j, m, ctl);
+  reduce_dots2_body(partials, nb, j, ctl, blockIdx.x);
 }
 
 template <typename BT, typename XT>
@@ -99,6 +141,7 @@ __global__ void k_ctl_reset(Ctl* ctl, double tol) {
     ctl->beta0 = 0.0;
     ctl->tol_cycle = tol;
     ctl->aux_max = 0.0;
+    ctl->orth_loss = 0.0;
     ctl->j = 0;
     ctl->done = 0;
     ctl->converged = 0;
@@ -354,9 +397,64 @@ hipError_t launch_richardson_step(mdp_handle* h, const int32_t* pi, double* buf0
   return reduce_into_ctl(h, nb, kRedRichardson, 0, 0.0, 0.0);
 }
 
-hipError_t launch_arnoldi_step(mdp_handle* h, Prec prec, const int32_t* pi, int j, int m) {
+// y = b + gamma P_pi x in the arithmetic of `prec` (x, b, y: double* for kF64,
+// float* otherwise); ctl may be null (no early exit).
+hipError_t launch_horner(mdp_handle* h, Prec prec, const int32_t* pi, const void* x, const void* b, void* y,
+                         const Ctl* ctl) {
+  const int nb = grid_for(h->S, kApplyTile);
+  Prof pf(h, MDP_K_POLICY_APPLY, bytes_apply(h, bval_of(prec), prec == kF64 ? 8 : 4, prec == kF64 ? 8 : 4) +
+                                     h->S * (prec == kF64 ? 8.0 : 4.0) + (prec == kF16 ? h->S * 8.0 : 0.0));
+  return with_lanes(h->lanes, [&](auto Lc) -> hipError_t {
+    constexpr int L = decltype(Lc)::value;
+    constexpr int U = rows_in_flight<L>();
+    if (prec == kF64)
+      k_horner<L, U, double, double, false><<<nb, kBlock, 0, h->stream>>>(
+          h->S, h->A, h->row_ptr, h->kfix, h->col, h->val, nullptr, pi, static_cast<const double*>(x),
+          static_cast<const double*>(b), h->gamma, static_cast<double*>(y), ctl);
+    else if (prec == kF32)
+      k_horner<L, U, float, float, false><<<nb, kBlock, 0, h->stream>>>(
+          h->S, h->A, h->row_ptr, h->kfix, reinterpret_cast<const int*>(h->cv32), h->cv32, nullptr, pi,
+          static_cast<const float*>(x), static_cast<const float*>(b), h->gamma, static_cast<float*>(y), ctl);
+    else
+      k_horner<L, U, __half, float, true><<<nb, kBlock, 0, h->stream>>>(
+          h->S, h->A, h->row_ptr, h->kfix, h->col, h->val16, h->corr16, pi, static_cast<const float*>(x),
+          static_cast<const float*>(b), h->gamma, static_cast<float*>(y), ctl);
+    return hipGetLastError();
+  });
+}
+
+// Basis slot i of the basis precision of `prec`.
+void* basis_slot(mdp_handle* h, Prec prec, int i) {
+  if (prec == kF64) return h->U64 + static_cast<int64_t>(i) * h->ldu;
+  return h->U32 + static_cast<int64_t>(i) * h->ldu;
+}
+
+// M^-1 u = sum_{i<deg} (gamma P_pi)^i u by deg - 1 Horner steps from u, using
+// the two scratch slots a and b; returns the slot holding the result (u itself
+// when deg <= 1).
+void* precond_apply(mdp_handle* h, Prec prec, const int32_t* pi, void* u, int a, int b, int deg,
+                    const Ctl* ctl, hipError_t* err) {
+  void* cur = u;
+  *err = hipSuccess;
+  for (int k = 1; k < deg && *err == hipSuccess; ++k) {
+    void* nxt = basis_slot(h, prec, (k & 1) ? a : b);
+    *err = launch_horner(h, prec, pi, cur, u, nxt, ctl);
+    cur = nxt;
+  }
+  return cur;
+}
+
+hipError_t launch_arnoldi_step(mdp_handle* h, Prec prec, const int32_t* pi, int j, int m, int deg, bool gs2) {
   const int nb = grid_for(h->S, kApplyTile);
   hipError_t e;
+  const Prec bprec = prec == kF64 ? kF64 : kF32;
+  // polynomial preconditioning (deg > 1): the product runs on q = M^-1 U_j,
+  // built in basis slots m + 1 and m + 2
+  const void* xin = nullptr;
+  if (deg > 1) {
+    xin = precond_apply(h, prec, pi, basis_slot(h, bprec, j), m + 1, m + 2, deg, h->ctl, &e);
+    if (e != hipSuccess) return e;
+  }
   {
     Prof pf(h, MDP_K_ARNOLDI_APPLY, bytes_arnoldi_apply(h, prec == kF64 ? 8 : (prec == kF32 ? 4 : 2), prec == kF64 ? 8 : 4, j) + (prec == kF16 ? h->S * 8.0 : 0.0), j);
     e = with_lanes(h->lanes, [&](auto Lc) -> hipError_t {
@@ -365,16 +463,16 @@ hipError_t launch_arnoldi_step(mdp_handle* h, Prec prec, const int32_t* pi, int 
     if (prec == kF64)
       k_arnoldi_apply<L, U, double, double, false><<<nb, kBlock, 0, h->stream>>>(
           h->S, h->A, h->row_ptr, h->kfix, h->col, h->val, nullptr, pi, h->U64, h->ldu, j, h->gamma,
-          h->ctl, h->part.buf);
+          h->ctl, h->part.buf, static_cast<const double*>(xin));
     else if (prec == kF32)
       k_arnoldi_apply<L, U, float, float, false><<<nb, kBlock, 0, h->stream>>>(
           h->S, h->A, h->row_ptr, h->kfix, reinterpret_cast<const int*>(h->cv32), h->cv32, nullptr, pi, h->U32,
           h->ldu, j, h->gamma,
-          h->ctl, h->part.buf);
+          h->ctl, h->part.buf, static_cast<const float*>(xin));
     else
       k_arnoldi_apply<L, U, __half, float, true><<<nb, kBlock, 0, h->stream>>>(
           h->S, h->A, h->row_ptr, h->kfix, h->col, h->val16, h->corr16, pi, h->U32, h->ldu, j, h->gamma,
-          h->ctl, h->part.buf);
+          h->ctl, h->part.buf, static_cast<const float*>(xin));
     return hipGetLastError();
   });
   }
@@ -395,8 +493,31 @@ hipError_t launch_arnoldi_step(mdp_handle* h, Prec prec, const int32_t* pi, int 
                                                             h->part.buf);
   }
   if ((e = hipGetLastError()) != hipSuccess) return e;
+  if (gs2) {
+    {
+      Prof pf(h, MDP_K_ARNOLDI_UPDATE, h->S * (j + 2.0) * (prec == kF64 ? 8.0 : 4.0), j);
+      if (prec == kF64)
+        k_cgs2_dots<double><<<nb, kBlock, 0, h->stream>>>(h->S, h->U64, h->ldu, j, h->ctl, h->part.buf);
+      else
+        k_cgs2_dots<float><<<nb, kBlock, 0, h->stream>>>(h->S, h->U32, h->ldu, j, h->ctl, h->part.buf);
+    }
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    {
+      Prof pf(h, MDP_K_REDUCE, 0.0, j);
+      k_reduce_dots2<<<j + 1, kBlock, 0, h->stream>>>(h->part.buf, nb, j, h->ctl);
+    }
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    {
+      Prof pf(h, MDP_K_ARNOLDI_UPDATE, bytes_arnoldi_update(h, prec == kF64 ? 8 : 4, j), j);
+      if (prec == kF64)
+        k_arnoldi_update<double><<<nbu, kBlock, 0, h->stream>>>(h->S, h->U64, h->ldu, j, h->ctl, h->part.buf);
+      else
+        k_arnoldi_update<float><<<nbu, kBlock, 0, h->stream>>>(h->S, h->U32, h->ldu, j, h->ctl, h->part.buf);
+    }
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
   Prof pf(h, MDP_K_REDUCE, 0.0, j);
-  k_norm_givens<<<1, kBlock, 0, h->stream>>>(h->part.buf, nbu, j, m, h->ctl);
+  k_norm_givens<<<1, kBlock, 0, h->stream>>>(h->part.buf, nbu, j, m, h->ctl, gs2 ? 1 : 0);
   return hipGetLastError();
 }
 
@@ -409,6 +530,36 @@ hipError_t launch_gmres_update_x(mdp_handle* h, Prec prec, double* x) {
   else
     k_gmres_update_x<float, double><<<nbu, kBlock, 0, h->stream>>>(h->S, x, h->U32, h->ldu,
                                                                     h->ctl);
+  return hipGetLastError();
+}
+
+// End of a preconditioned GMRES cycle: x += M^-1 (V y).  V y goes to basis
+// slot m + 1 (in the basis precision), M^-1 uses slots m + 2 and m + 3.
+hipError_t launch_precond_update_x(mdp_handle* h, Prec prec, const int32_t* pi, double* x, int m, int deg) {
+  const Prec bprec = prec == kF64 ? kF64 : kF32;
+  const int nbu = grid_for(h->S, kUpdTile);
+  void* t = basis_slot(h, bprec, m + 1);
+  hipError_t e;
+  {
+    Prof pf(h, MDP_K_GMRES_UPDATE_X, 0.0);
+    if (bprec == kF64) {
+      k_zero<double><<<grid_stride(h->S), kBlock, 0, h->stream>>>(static_cast<double*>(t), h->S);
+      k_gmres_update_x<double, double><<<nbu, kBlock, 0, h->stream>>>(h->S, static_cast<double*>(t), h->U64,
+                                                                       h->ldu, h->ctl);
+    } else {
+      k_zero<float><<<grid_stride(h->S), kBlock, 0, h->stream>>>(static_cast<float*>(t), h->S);
+      k_gmres_update_x<float, float><<<nbu, kBlock, 0, h->stream>>>(h->S, static_cast<float*>(t), h->U32,
+                                                                     h->ldu, h->ctl);
+    }
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  void* q = precond_apply(h, prec, pi, t, m + 2, m + 3, deg, nullptr, &e);
+  if (e != hipSuccess) return e;
+  Prof pf(h, MDP_K_GMRES_UPDATE_X, 0.0);
+  if (bprec == kF64)
+    k_add_to<double><<<grid_stride(h->S), kBlock, 0, h->stream>>>(x, static_cast<const double*>(q), h->S);
+  else
+    k_add_to<float><<<grid_stride(h->S), kBlock, 0, h->stream>>>(x, static_cast<const float*>(q), h->S);
   return hipGetLastError();
 }
 

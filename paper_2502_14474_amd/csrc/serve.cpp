@@ -224,6 +224,23 @@ mdp_status mdp_server::admit_one(Request* r) {
   const double* cs = r->borrowed ? r->b_cost : r->cost.data();
   MDP_TRY(mdp_create(r->S, r->A, rp, cl, vl, cs, r->gamma, &co, &h));
   r->h = h;
+  // a class seen for the first time: time its lane widths once, on this MDP;
+  // requests of the class admitted meanwhile wait for the stored width, so
+  // that every request of a class runs with the same width
+  if (opts.autotune && tune_lookup(h) == 0) {
+    if (tune_claim(h)) {
+      const mdp_status ts = mdp_autotune(h, nullptr);
+      tune_release(h);
+      if (ts < 0) {
+        mdp_destroy(h);
+        r->h = nullptr;
+        return ts;
+      }
+    } else {
+      tune_wait(h);
+      if (const int L = tune_lookup(h)) h->lanes = L;
+    }
+  }
   const Prec prec = prec_of(opts.solve.precision);
   mdp_status st = ensure_basis(h, prec == kF64 ? kF64 : kF32, opts.solve.restart);
   if (st >= 0 && prec != kF64) st = ensure_lowp(h, prec);
@@ -313,6 +330,8 @@ mdp_status mdp_server_create(const mdp_server_opts* opt, mdp_server_t* out) {
   if (o.solve.launch < MDP_LAUNCH_AUTO || o.solve.launch > MDP_LAUNCH_DIRECT)
     return fail(MDP_E_INVAL, "unknown launch mode");
   if (o.solve.restart < 1 || o.solve.restart > kMaxRestart) return fail(MDP_E_INVAL, "restart must lie in [1,64]");
+  if (o.solve.precond_degree > 1) return fail(MDP_E_NOTSUP, "the server runs without a preconditioner");
+  if (o.solve.gs_passes > 1) return fail(MDP_E_NOTSUP, "the server uses one Gram-Schmidt pass");
   if (o.solve.precision < MDP_FP64 || o.solve.precision > MDP_MIXED_FP16) return fail(MDP_E_INVAL, "unknown precision");
   if (!(o.solve.alpha > 0.0 && o.solve.alpha < 1.0) || !(o.solve.atol > 0.0))
     return fail(MDP_E_INVAL, "bad tolerances");

@@ -16,6 +16,7 @@
 #include <limits>
 #include <map>
 #include <mutex>
+#include <condition_variable>
 #include <sstream>
 #include <string>
 
@@ -130,6 +131,33 @@ int tune_lookup(const mdp_handle* h) {
   if (it == m.end()) return 0;
   const int L = it->second;
   return (L >= 2 && L <= 64 && (L & (L - 1)) == 0) ? L : 0;
+}
+
+namespace {
+std::map<std::string, bool> g_claims;  // class -> tuning finished (claimed classes only)
+std::condition_variable g_claim_cv;
+}  // namespace
+
+bool tune_claim(const mdp_handle* h) {
+  std::lock_guard<std::mutex> g(g_tune_mu);
+  return g_claims.emplace(key_locked(h), false).second;
+}
+
+void tune_release(const mdp_handle* h) {
+  {
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    g_claims[key_locked(h)] = true;
+  }
+  g_claim_cv.notify_all();
+}
+
+void tune_wait(const mdp_handle* h) {
+  std::unique_lock<std::mutex> g(g_tune_mu);
+  const std::string k = key_locked(h);
+  g_claim_cv.wait(g, [&]() {
+    const auto it = g_claims.find(k);
+    return it == g_claims.end() || it->second;
+  });
 }
 
 void tune_store(const mdp_handle* h, int lanes) {

@@ -30,14 +30,15 @@ class CreateOpts(C.Structure):
 class EvalOpts(C.Structure):
     _fields_ = [("struct_size", C.c_size_t), ("inner", C.c_int32), ("restart", C.c_int32),
                 ("precision", C.c_int32), ("sync_every", C.c_int32), ("rtol", C.c_double),
-                ("max_iter", C.c_int64)]
+                ("max_iter", C.c_int64), ("precond_degree", C.c_int32), ("gs_passes", C.c_int32)]
 
 
 class SolveOpts(C.Structure):
     _fields_ = [("struct_size", C.c_size_t), ("inner", C.c_int32), ("restart", C.c_int32),
                 ("precision", C.c_int32), ("sync_every", C.c_int32), ("alpha", C.c_double),
                 ("atol", C.c_double), ("rtol_cert", C.c_double), ("max_outer", C.c_int64),
-                ("max_inner", C.c_int64), ("launch", C.c_int32)]
+                ("max_inner", C.c_int64), ("launch", C.c_int32), ("precond_degree", C.c_int32),
+                ("gs_passes", C.c_int32)]
 
 
 class Stats(C.Structure):
@@ -46,7 +47,7 @@ class Stats(C.Structure):
                 ("policy_applies", C.c_int64), ("refinements", C.c_int64),
                 ("residual", C.c_double), ("time_ms", C.c_double), ("bytes", C.c_double),
                 ("history", C.POINTER(C.c_double)), ("history_cap", C.c_int64),
-                ("history_len", C.c_int64)]
+                ("history_len", C.c_int64), ("orth_loss", C.c_double)]
 
 
 NUM_KERNEL_KINDS = 7
@@ -63,7 +64,7 @@ class ServerOpts(C.Structure):
     _fields_ = [("struct_size", C.c_size_t), ("stream", C.c_void_p),
                 ("hbm_budget_bytes", C.c_int64), ("device", C.c_int32), ("max_batch", C.c_int32),
                 ("admit_threads", C.c_int32), ("retire_threads", C.c_int32),
-                ("solve", SolveOpts)]
+                ("solve", SolveOpts), ("autotune", C.c_int32)]
 
 
 class RequestStats(C.Structure):
@@ -82,6 +83,9 @@ SIGNATURES = {
     "mdp_default_create_opts": (None, [C.POINTER(CreateOpts)]),
     "mdp_create_from_rows": (C.c_int, [C.c_int64, C.c_int32, C.c_int32, ROWS_FN, C.c_void_p, C.c_double,
                                        C.POINTER(CreateOpts), C.POINTER(C.c_void_p)]),
+    "mdp_create_from_device_rows": (C.c_int, [C.c_int64, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p,
+                                              C.c_double, C.POINTER(CreateOpts), C.POINTER(C.c_void_p)]),
+    "mdp_load_kernel": (C.c_int, [C.c_char_p, C.c_char_p, C.POINTER(C.c_void_p)]),
     "mdp_default_eval_opts": (None, [C.POINTER(EvalOpts)]),
     "mdp_default_solve_opts": (None, [C.POINTER(SolveOpts)]),
     "mdp_create": (C.c_int, [C.c_int64, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p,

@@ -471,6 +471,25 @@ def test_colblocked_solve_certified(precision):
     assert rel <= (1e-9 if precision == 0 else 1e-8)
 
 
+@pytest.mark.parametrize("deg", [1, 3])
+@pytest.mark.parametrize("name", ["c2twin_b3", "c4twin_b7", "ragged_b2"])
+def test_colblocked_policy_products_match_exact_solve(name, deg):
+    """float64 GMRES on handles that carry the column-blocked copy (the
+    sweeps run over it, the P_pi products over the plain rows), with and
+    without the polynomial preconditioner, against the oracle's exact policy
+    evaluation."""
+    make, blocks = CB_CASES[name]
+    inst = make()
+    rng = np.random.default_rng(8)
+    pi = rng.integers(0, inst.A, inst.S).astype(np.int32)
+    v_ref, _ = oracle.evaluate_policy(inst, pi)
+    with _mdp(inst, col_blocks=blocks) as h:
+        v, st = h.policy_eval(pi, rtol=1e-13, max_iter=20000, precond_degree=deg)
+    err = np.max(np.abs(v - v_ref)) / np.max(np.abs(v_ref))
+    assert st["status"] == 0, st
+    assert err <= 1e-9, (err, st)
+
+
 def test_colblocks_option_rules():
     """Forced blocks cost device memory, the automatic rule leaves small
     matrices alone, and unsupported rows are refused."""

@@ -125,3 +125,27 @@ def test_server_beside_threads_that_create_and_destroy_handles():
     for k, (v, pi, st) in enumerate(outs):
         vr, pir, _ = ref[k % len(insts)]
         assert st["status"] == 0 and np.array_equal(v, vr) and np.array_equal(pi, pir), k
+
+
+def test_server_autotunes_each_new_class_once(tmp_path, monkeypatch):
+    """autotune=True: the first request of each class times the lane widths at
+    admission and stores the winner; every request of the class then runs
+    with it, so each result equals mdp_solve on a handle created afterwards
+    (which starts from the stored width)."""
+    import json
+    import paper_2502_14474_amd as m
+    cache = tmp_path / "tune.json"
+    monkeypatch.setenv("MDP_TUNE_CACHE", str(cache))
+    insts = [config1(S=3000, A=4, k=10, seed=s) for s in range(3)]  # one class, three requests
+    insts += [config2(S=7000, A=8, seed=3), config4(S=6000, A=6, k=24, seed=4)]
+    print(f"[case] server autotune over {len(insts)} requests", flush=True)
+    with m.Server(precision=1, alpha=1e-2, max_batch=4, autotune=True) as srv:
+        ids = [srv.submit(i) for i in insts]
+        outs = [srv.wait(i) for i in ids]
+    widths = json.loads(cache.read_text())
+    assert len(widths) == 3, widths  # three classes, each stored once
+    assert all(v in (2, 4, 8, 16, 32, 64) for v in widths.values())
+    for k, (inst, (v, pi, st)) in enumerate(zip(insts, outs)):
+        vr, pir, str_ = _alone(inst, 1)
+        assert st["status"] == 0 and str_["status"] == 0
+        assert np.array_equal(v, vr) and np.array_equal(pi, pir), k
