@@ -65,6 +65,26 @@ def build(verbose=False, out=LIB, defines=()):
     return out
 
 
+def build_probes(verbose=False):
+    """Compile the stand-alone probes (paper_2502_14474_amd/probes/*.hip) to
+    executables beside their sources: hardware ceilings the profiles quote."""
+    outs = []
+    d = os.path.join(HERE, "probes")
+    for name in sorted(os.listdir(d)) if os.path.isdir(d) else []:
+        if not name.endswith(".hip"):
+            continue
+        src = os.path.join(d, name)
+        out = os.path.splitext(src)[0]
+        cmd = [HIPCC] + [f for f in FLAGS if f != "-fPIC"] + [src, "-o", out]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        rc, msgs = _run(cmd)
+        if rc != 0:
+            raise RuntimeError(f"hipcc failed on {src}:\n" + "\n".join(msgs))
+        outs.append(out)
+    return outs
+
+
 def build_code_objects(verbose=False, directory=os.path.join(ROOT, "tests", "kernels")):
     """Compile each .hip file of `directory` to a code object (.hsaco, gfx950)
     beside it: row kernels that tests hand to mdp_create_from_device_rows."""

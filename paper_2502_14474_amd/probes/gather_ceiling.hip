@@ -1,0 +1,98 @@
+// Gather-rate probe: throughput of uniformly random 8-byte gathers from
+// tables of several sizes (one XCD's L2, the Infinity Cache, HBM).  A sparse
+// product whose columns are uniform random over a large vector is bound by
+// this rate rather than by its streamed bytes; the probe gives that ceiling.
+// 96 * 2^20 gathers per launch (about the size of a product with P_pi on the 4M-state,
+// 24-entry workload), four independent gathers in flight per thread, indices
+// from the SplitMix64 output mix of the gather number, so that they are
+// uniform and reproducible.
+#include <hip/hip_runtime.h>
+#include <cstdio>
+#include <cstdint>
+#include <vector>
+
+#define CHK(x) do { hipError_t e_ = (x); if (e_ != hipSuccess) { printf("HIP error %s at %d\n", hipGetErrorString(e_), __LINE__); return 1; } } while (0)
+
+__global__ void fill_idx(int* idx, int64_t n, uint32_t table, uint32_t seed) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    uint64_t z = (uint64_t)i * 0x9E3779B97F4A7C15ull + seed;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    idx[i] = (int)(z % table);
+  }
+}
+
+__global__ void fill_x(double* x, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) x[i] = 1.0 + (double)(i & 7);
+}
+
+// every thread: U independent gathers in flight per iteration
+template <int U>
+__global__ __launch_bounds__(256) void gather(const int* __restrict__ idx, const double* __restrict__ x, int64_t n, double* out) {
+  double s = 0.0;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  for (; i + (U - 1) * stride < n; i += U * stride) {
+    int c[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) c[u] = __builtin_nontemporal_load(idx + i + u * stride);
+    double v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) v[u] = x[c[u]];
+#pragma unroll
+    for (int u = 0; u < U; ++u) s += v[u];
+  }
+  for (; i < n; i += stride) s += x[idx[i]];
+  out[blockIdx.x * (int64_t)blockDim.x + threadIdx.x] = s;
+}
+
+// streaming read of the index array alone (the gather-free floor)
+__global__ __launch_bounds__(256) void stream_idx(const int* __restrict__ idx, int64_t n, double* out) {
+  double s = 0.0;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    s += (double)__builtin_nontemporal_load(idx + i);
+  out[blockIdx.x * (int64_t)blockDim.x + threadIdx.x] = s;
+}
+
+int main() {
+  const int64_t n = 96ll << 20;  // 96M gathers (the config-4 policy product)
+  const int grid = 256 * 16;
+  int* idx;
+  double *x, *out;
+  const int64_t max_table = 1ll << 27;  // 1 GiB of doubles
+  CHK(hipMalloc(&idx, n * sizeof(int)));
+  CHK(hipMalloc(&x, max_table * sizeof(double)));
+  CHK(hipMalloc(&out, (int64_t)grid * 256 * sizeof(double)));
+  fill_x<<<4096, 256>>>(x, max_table);
+  CHK(hipGetLastError());
+  hipEvent_t a, b;
+  CHK(hipEventCreate(&a));
+  CHK(hipEventCreate(&b));
+  const int64_t tables[] = {1ll << 19, 1ll << 22, 1ll << 24, 1ll << 25, 1ll << 27};
+  for (int64_t t : tables) {
+    fill_idx<<<4096, 256>>>(idx, n, (uint32_t)t, 12345u);
+    CHK(hipGetLastError());
+    CHK(hipDeviceSynchronize());
+    for (int rep = 0; rep < 2; ++rep) gather<4><<<grid, 256>>>(idx, x, n, out);
+    CHK(hipEventRecord(a));
+    const int reps = 10;
+    for (int rep = 0; rep < reps; ++rep) gather<4><<<grid, 256>>>(idx, x, n, out);
+    CHK(hipEventRecord(b));
+    CHK(hipEventSynchronize(b));
+    float ms;
+    CHK(hipEventElapsedTime(&ms, a, b));
+    ms /= reps;
+    printf("table %8.1f MB: %.3f ms per %lld gathers -> %.1f G gathers/s (index stream %.2f TB/s)\n",
+           t * 8.0 / 1e6, ms, (long long)n, n / (ms * 1e-3) / 1e9, n * 4.0 / (ms * 1e-3) / 1e12);
+    fflush(stdout);
+  }
+  CHK(hipEventRecord(a));
+  for (int rep = 0; rep < 10; ++rep) stream_idx<<<grid, 256>>>(idx, n, out);
+  CHK(hipEventRecord(b));
+  CHK(hipEventSynchronize(b));
+  float ms;
+  CHK(hipEventElapsedTime(&ms, a, b));
+  printf("index stream alone: %.3f ms -> %.2f TB/s\n", ms / 10, n * 4.0 / (ms / 10 * 1e-3) / 1e12);
+  return 0;
+}
