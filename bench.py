@@ -84,9 +84,11 @@ def workload_key(inst):
 
 
 def workload_name(inst, args):
+    pre = (f" with the degree-{args.precond_degree} polynomial preconditioner"
+           if getattr(args, "precond_degree", 1) > 1 else "")
     return (f"{inst.name} MDP (config {args.config}): S={inst.S}, A={inst.A}, nnz={inst.nnz}, "
             f"gamma={inst.gamma}; float64 inexact policy iteration, GMRES({args.restart}) "
-            f"evaluation, alpha={args.alpha}, to ||Tv-v||_inf<={args.atol} from v=0")
+            f"evaluation{pre}, alpha={args.alpha}, to ||Tv-v||_inf<={args.atol} from v=0")
 
 
 ORACLE_RUNS_FILE = os.path.join(ROOT, "profiles", "oracle_full_runs.json")
@@ -167,15 +169,19 @@ def serving_requests(args):
 
 
 def serving_oracle(args, reqs):
-    """The oracle on an S-stratified subsample of the pool: per decade of S
-    (1e3-1e4, 1e4-1e5, 1e5-1e6, each a third of the log-uniform law) the
-    pool's first request, solved by the oracle's exact policy iteration.  A
-    solve costs the strata-weighted mean time."""
+    """The oracle on a stratified subsample of the pool: per decade of S
+    (1e3-1e4, 1e4-1e5, 1e5-1e6, each a third of the log-uniform law) and per
+    discount (0.9, 0.99, 0.999, each a third), the pool's smallest request of
+    that cell (smallest S*A*k, which keeps the oracle's time bounded and so
+    favours the CPU), solved by the oracle's exact policy iteration.  A solve
+    costs the mean over the cells."""
     import oracle
     from workloads import config5_instance
     times, picks = [], []
-    for lo in (1e3, 1e4, 1e5):
-        r = next((r for r in reqs if lo <= r["S"] < 10 * lo), None)
+    cells = [(lo, g) for lo in (1e3, 1e4, 1e5) for g in (0.9, 0.99, 0.999)]
+    for lo, g in cells:
+        cand = [r for r in reqs if lo <= r["S"] < 10 * lo and r["gamma"] == g]
+        r = min(cand, key=lambda r: r["S"] * r["A"] * r["k"]) if cand else None
         if r is None:
             continue
         inst = config5_instance(r, workers=16)
@@ -189,8 +195,8 @@ def serving_oracle(args, reqs):
     mean = sum(times) / len(times)
     return {"value": 1.0 / mean, "unit": "solves/s", "cores": blas_threads(), "kind": "oracle",
             "host_cores_available": len(os.sched_getaffinity(0)), "sparse_matvec_threads": 1,
-            "sample": (f"oracle exact policy iteration on one request per decade of S from the pool "
-                       f"(strata-weighted mean {mean:.1f} s per solve)"), "requests": picks}
+            "sample": (f"oracle exact policy iteration on the smallest pool request of each (decade of S, "
+                       f"gamma) cell, {len(picks)} cells: mean {mean:.2f} s per solve"), "requests": picks}
 
 
 def serving_bench(args, m):
@@ -445,6 +451,25 @@ def rows_leg(args, m, h, inst, v, pi, stream):
         log(f"[bench] gmres + polynomial preconditioner of degree {deg}: {1e3 * (t1 - t0):.1f} ms, "
             f"{st['inner_iters']} Arnoldi steps, {st['policy_applies']} products")
 
+    if not args.no_mixed:
+        # mixed float32 inner solves with the polynomial preconditioner
+        mp = m.MDP_MIXED_FP32 if args.mixed == "fp32" else m.MDP_MIXED_FP16
+        w.zero_()
+        m.mdp_solve(h, w, p2, restart=args.restart, alpha=args.alpha, atol=args.atol, precision=mp,
+                    precond_degree=4)
+        w.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st = m.mdp_solve(h, w, p2, restart=args.restart, alpha=args.alpha, atol=args.atol, precision=mp,
+                         precond_degree=4)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        rows["mixed_precond4_solve"] = {"ms": 1e3 * (t1 - t0), "status": st["status"], "sweeps": st["bellman_sweeps"],
+                                        "inner": st["inner_iters"], "products": st["policy_applies"],
+                                        "refinements": st["refinements"], "residual": st["residual"],
+                                        "precision": args.mixed}
+        log(f"[bench] mixed {args.mixed} + polynomial preconditioner of degree 4: {1e3 * (t1 - t0):.1f} ms")
+
     # GMRES with a second Gram-Schmidt pass: its cost, and the loss of
     # orthogonality the default single pass leaves (the second correction)
     w.zero_()
@@ -493,6 +518,8 @@ def main():
     ap.add_argument("--atol", type=float, default=1e-8)
     ap.add_argument("--sweeps", type=int, default=20)
     ap.add_argument("--lanes", type=int, default=0)
+    ap.add_argument("--precond-degree", type=int, default=1,
+                    help="GMRES polynomial preconditioner sum_{i<d} (gamma P_pi)^i for the timed solves (1: none)")
     ap.add_argument("--profile-every", type=int, default=4,
                     help="time one launch in this many per kernel class inside the timed region")
     ap.add_argument("--autotune", action="store_true",
@@ -560,7 +587,7 @@ def main():
     kw = dict(restart=args.restart, alpha=args.alpha, atol=args.atol)
 
     def solve(prec):
-        return m.mdp_solve(h, v, pi, precision=prec, **kw)
+        return m.mdp_solve(h, v, pi, precision=prec, precond_degree=args.precond_degree, **kw)
 
     for _ in range(args.warmup):
         st = solve(m.MDP_FP64)
@@ -665,6 +692,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": workload_name(inst, args), "S": inst.S, "A": inst.A,
                    "nnz": inst.nnz, "gamma": inst.gamma, "inner": f"gmres({args.restart})",
+                   "precond_degree": args.precond_degree,
                    "alpha": args.alpha, "atol": args.atol, "lanes_per_row": info["lanes_per_row"]},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": counter_traffic(dom, workload_key(inst)),
