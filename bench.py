@@ -242,12 +242,20 @@ def serving_bench(args, m):
         outs = [srv.wait(r) for r in ids]
         t1 = time.perf_counter()
         lat = np.array([o[2]["finish_ms"] - o[2]["submit_ms"] for o in outs])
+        wait = np.array([o[2]["admit_ms"] - o[2]["submit_ms"] for o in outs])
+        size = np.array([pool[i % len(pool)].nnz for i in range(n)])
+        small = size <= np.median(size)
         bad = [o[2]["status"] for o in outs if o[2]["status"] != 0]
         log(f"[serve] run of {n}: {n / (t1 - t0):.1f} solves/s, p50 {np.percentile(lat, 50):.1f} ms, "
-            f"p99 {np.percentile(lat, 99):.1f} ms")
+            f"p99 {np.percentile(lat, 99):.1f} ms; queue wait p50 {np.percentile(wait, 50):.1f} ms; "
+            f"p50 small/large {np.percentile(lat[small], 50):.1f}/{np.percentile(lat[~small], 50):.1f} ms")
         return dict(solves_per_s=n / (t1 - t0), p50_ms=float(np.percentile(lat, 50)),
                     p99_ms=float(np.percentile(lat, 99)), ok=not bad, wall_s=t1 - t0,
-                    residual_max=float(max(o[2]["residual"] for o in outs)))
+                    residual_max=float(max(o[2]["residual"] for o in outs)),
+                    queue_wait_p50_ms=float(np.percentile(wait, 50)),
+                    service_p50_ms=float(np.percentile(lat - wait, 50)),
+                    p50_ms_smaller_half=float(np.percentile(lat[small], 50)),
+                    p50_ms_larger_half=float(np.percentile(lat[~small], 50)))
 
     # the server times the lane widths of each new (A, row length) class once,
     # at the class's first admission; the widths land in this run's own cache
@@ -255,11 +263,17 @@ def serving_bench(args, m):
     tune_file = os.path.join(tempfile.mkdtemp(prefix="mdp_tune_"), "tune.json")
     os.environ["MDP_TUNE_CACHE"] = tune_file
     with m.Server(precision=m.MDP_MIXED_FP32, alpha=args.alpha, atol=args.atol,
-                  max_batch=args.serve_max_batch, autotune=not args.no_autotune) as srv:
+                  max_batch=args.serve_max_batch, autotune=not args.no_autotune,
+                  split_nnz=args.split_nnz,
+                  launch=m.MDP_LAUNCH_DIRECT if args.serve_launch == "direct" else m.MDP_LAUNCH_GRAPHS) as srv:
         warm = run(srv, None, len(pool))
         closed = run(srv, None)
         cap = closed["solves_per_s"]
         gaps = np.array([r["gap"] for r in config5_requests(n, seed=args.seed)])
+        # an untimed open-loop pass first: batches of the sizes spread arrivals
+        # produce (and their captured graphs) are new to the server after the
+        # closed loop
+        warm_open = run(srv, gaps / (0.5 * cap))
         open70 = run(srv, gaps / (0.7 * cap))
         open90 = run(srv, gaps / (0.9 * cap))
     try:
@@ -289,8 +303,10 @@ def serving_bench(args, m):
                    "submissions": n, "alpha": args.alpha},
         "roofline": None,
         "cpu_baseline": cpu,
-        "serving": {"warmup_pass": warm, "closed_loop": closed, "open_loop_0.7C": open70,
-                    "open_loop_0.9C": open90, "client_memory": "page-locked", "autotuned_widths": tuned},
+        "serving": {"warmup_pass": warm, "closed_loop": closed, "open_loop_warmup_0.5C": warm_open,
+                    "open_loop_0.7C": open70,
+                    "open_loop_0.9C": open90, "client_memory": "page-locked", "autotuned_widths": tuned,
+                    "launch": args.serve_launch, "split_nnz": args.split_nnz},
     }
 
 
@@ -538,6 +554,10 @@ def main():
     ap.add_argument("--serve-max-batch", type=int, default=128)
     ap.add_argument("--no-autotune", action="store_true",
                     help="config 5: the server keeps the default lane widths")
+    ap.add_argument("--serve-launch", choices=["graphs", "direct"], default="graphs",
+                    help="config 5: how the server's GMRES cycles reach the GPU")
+    ap.add_argument("--split-nnz", type=int, default=None,
+                    help="config 5: the server's size-class split (0: one worker; default: the library's)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported (the "

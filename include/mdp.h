@@ -99,7 +99,7 @@ typedef struct {
                              otherwise a power of two in [2, 64] */
   int32_t col_blocks;     /* column-blocked copy of P for the float64 sweep: -1 (default)
                              builds one when S >= 2^21 and at least half of the entries lie
-                             outside their row's column slice (slices of 4 MB of v);
+                             outside their row's column slice (slices of 2.75 MB of v);
                              0: never; n >= 1: always, with n slices (MDP_E_NOTSUP if a
                              row holds more than 255 entries of one slice, its columns are
                              not in increasing slice order, or A > 1024).  The blocked
@@ -368,6 +368,11 @@ typedef struct {
                                 from it.  0 (default): widths come from the cache or the mean
                                 row length only.  Results stay those of mdp_solve on a handle
                                 created with the same width. */
+  int64_t split_nnz;         /* size classes: requests of at most split_nnz nonzeros are advanced
+                                by one worker, larger ones by a second worker on its own stream,
+                                so that a small request's rounds do not wait for a large
+                                request's GMRES cycles (default 2^24; 0: one worker for all).
+                                Results do not depend on the class. */
 } mdp_server_opts;
 
 typedef struct {

@@ -42,6 +42,7 @@ struct Request {
   const double* b_cost = nullptr;
   bool borrowed = false;
   int64_t footprint = 0;
+  int lane = 0;  // the worker (size class) that advances it
   // results
   std::vector<double> v;
   std::vector<int32_t> pi;
@@ -76,33 +77,47 @@ static int64_t footprint_of(int64_t S, int32_t A, int64_t nnz, const mdp_solve_o
 
 }  // namespace mdp
 
+// One worker of the server: its own batch engine, stream and resident set.
+// Workers serve size classes (small and large requests), so a small request
+// never waits for a large one's GMRES cycle inside a round.
+struct ServerLane {
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  mdp::BatchEngine eng;
+  std::vector<mdp::Request*> ready;     // admitted, joining at the next round
+  std::vector<mdp::Request*> resident;  // advanced by the rounds
+  std::thread thread;
+  int64_t rounds = 0;
+};
+
 struct mdp_server {
   mdp_server_opts opts{};
   int device = 0;
-  hipStream_t stream = nullptr;
   std::mutex mu;
   std::condition_variable cv_admit, cv_work, cv_reap, cv_done;
   std::deque<mdp::Request*> queue;     // submitted, not yet admitted
-  std::vector<mdp::Request*> ready;    // admitted, joining at the next round
-  std::vector<mdp::Request*> resident; // advanced by the rounds
+  std::vector<std::unique_ptr<ServerLane>> lanes;
   std::deque<mdp::Request*> retiring;  // finished, results being copied out
   std::map<int64_t, std::unique_ptr<mdp::Request>> all;
   int64_t next_id = 1;
   int64_t held_bytes = 0;              // footprint of admitting + resident + retiring
   int admitting = 0;
-  bool stop = false, worker_done = false;
+  bool stop = false;
+  int workers_left = 0;
   double t0 = 0;
   std::vector<std::thread> admitters, reapers;
-  std::thread worker;
   int reapers_left = 0;
-  mdp::BatchEngine eng;
-  int64_t rounds = 0;
 
   void admit_loop();
-  void work_loop();
+  void work_loop(ServerLane* ln);
   void reap_loop();
   mdp_status admit_one(mdp::Request* r);
   void retire(mdp::Request* r);
+  int in_flight() const {
+    int n = admitting;
+    for (const auto& l : lanes) n += static_cast<int>(l->ready.size() + l->resident.size());
+    return n;
+  }
 };
 
 using namespace mdp;
@@ -119,8 +134,7 @@ void mdp_server::admit_loop() {
     cv_admit.wait(lk, [&]() {
       if (stop) return true;
       if (queue.empty()) return false;
-      const int count = admitting + static_cast<int>(ready.size() + resident.size());
-      if (count >= opts.max_batch) return false;
+      if (in_flight() >= opts.max_batch) return false;
       return held_bytes == 0 || held_bytes + queue.front()->footprint <= opts.hbm_budget_bytes;
     });
     if (stop) return;
@@ -142,48 +156,48 @@ void mdp_server::admit_loop() {
       cv_admit.notify_all();
       continue;
     }
-    ready.push_back(r);
+    lanes[r->lane]->ready.push_back(r);
     cv_work.notify_all();
   }
 }
 
-void mdp_server::work_loop() {
+void mdp_server::work_loop(ServerLane* ln) {
   (void)hipSetDevice(device);
   std::unique_lock<std::mutex> lk(mu);
   for (;;) {
-    cv_work.wait(lk, [&]() { return !ready.empty() || !resident.empty() || (stop && admitting == 0); });
-    for (Request* r : ready) resident.push_back(r);
-    ready.clear();
-    if (resident.empty()) {
+    cv_work.wait(lk, [&]() { return !ln->ready.empty() || !ln->resident.empty() || (stop && admitting == 0); });
+    for (Request* r : ln->ready) ln->resident.push_back(r);
+    ln->ready.clear();
+    if (ln->resident.empty()) {
       if (stop && admitting == 0) break;
       continue;
     }
-    // one round over the resident set
-    eng.items.clear();
-    for (Request* r : resident) eng.items.push_back(&r->item);
+    // one round over this worker's resident set
+    ln->eng.items.clear();
+    for (Request* r : ln->resident) ln->eng.items.push_back(&r->item);
     lk.unlock();
-    const mdp_status st = eng.round(opts.solve);
+    const mdp_status st = ln->eng.round(opts.solve);
     lk.lock();
-    ++rounds;
+    ++ln->rounds;
     if (st < 0) {
       // the message goes into each request under the lock, so that the
       // reapers (which run unlocked) only read what was handed to them
       const std::string msg = mdp_last_error();
-      for (Request* r : resident) {
+      for (Request* r : ln->resident) {
         r->item.status = st;
         r->item.state = BatchItem::kDone;
         r->error = msg;
       }
     }
     std::vector<Request*> keep;
-    for (Request* r : resident) {
+    for (Request* r : ln->resident) {
       if (r->item.state == BatchItem::kDone) retiring.push_back(r);
       else keep.push_back(r);
     }
-    resident.swap(keep);
+    ln->resident.swap(keep);
     cv_reap.notify_all();
   }
-  worker_done = true;
+  --workers_left;
   cv_reap.notify_all();
 }
 
@@ -192,8 +206,8 @@ void mdp_server::reap_loop() {
   (void)hipSetDevice(device);
   std::unique_lock<std::mutex> lk(mu);
   for (;;) {
-    cv_reap.wait(lk, [&]() { return !retiring.empty() || worker_done; });
-    if (retiring.empty() && worker_done) {
+    cv_reap.wait(lk, [&]() { return !retiring.empty() || workers_left == 0; });
+    if (retiring.empty() && workers_left == 0) {
       --reapers_left;
       return;
     }
@@ -309,6 +323,7 @@ void mdp_default_server_opts(mdp_server_opts* o) {
   o->max_batch = 256;
   o->admit_threads = 4;
   o->retire_threads = 4;
+  o->split_nnz = int64_t{1} << 24;
   mdp_default_solve_opts(&o->solve);
   o->solve.precision = MDP_MIXED_FP32;
 }
@@ -323,6 +338,7 @@ mdp_status mdp_server_create(const mdp_server_opts* opt, mdp_server_t* out) {
     if (opt->struct_size < sizeof(mdp_server_opts)) return fail(MDP_E_INVAL, "mdp_server_opts.struct_size too small");
     o = *opt;
   }
+  if (o.split_nnz < 0) return fail(MDP_E_INVAL, "split_nnz must be >= 0");
   if (o.max_batch < 1 || o.max_batch > 65536 || o.hbm_budget_bytes <= 0 ||
       o.admit_threads < 1 || o.admit_threads > 64 || o.retire_threads < 1 || o.retire_threads > 64)
     return fail(MDP_E_INVAL, "bad server limits");
@@ -347,37 +363,53 @@ mdp_status mdp_server_create(const mdp_server_opts* opt, mdp_server_t* out) {
     delete s;
     return fail(MDP_E_DEVICE, "no HIP device");
   }
-  if (o.stream) {
-    s->stream = static_cast<hipStream_t>(o.stream);
-  } else {
-    hipError_t e = hipSuccess;
-    {
-      std::shared_lock<std::shared_mutex> g(alloc_lock());
-      e = hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking);
+  // one worker per size class: requests of at most split_nnz nonzeros on the
+  // first, larger ones on the second (split_nnz = 0: a single worker)
+  const int nlanes = o.split_nnz > 0 ? 2 : 1;
+  mdp_status st = MDP_OK;
+  for (int w = 0; w < nlanes && st >= 0; ++w) {
+    auto ln = std::make_unique<ServerLane>();
+    if (w == 0 && o.stream) {
+      ln->stream = static_cast<hipStream_t>(o.stream);
+    } else {
+      hipError_t e = hipSuccess;
+      {
+        std::shared_lock<std::shared_mutex> g(alloc_lock());
+        e = hipStreamCreateWithFlags(&ln->stream, hipStreamNonBlocking);
+      }
+      if (e != hipSuccess) {
+        st = fail(MDP_E_DEVICE, "stream creation failed");
+        break;
+      }
+      ln->own_stream = true;
     }
-    if (e != hipSuccess) {
-      delete s;
-      return fail(MDP_E_DEVICE, "stream creation failed");
-    }
+    ln->eng.stream = ln->stream;
+    ln->eng.prec = prec_of(o.solve.precision);
+    ln->eng.use_graphs = o.solve.launch != MDP_LAUNCH_DIRECT;
+    st = ln->eng.reserve(o.max_batch);
+    s->lanes.push_back(std::move(ln));
   }
-  s->eng.stream = s->stream;
-  s->eng.prec = prec_of(o.solve.precision);
-  s->eng.use_graphs = o.solve.launch != MDP_LAUNCH_DIRECT;
-  mdp_status st = s->eng.reserve(o.max_batch);
   // memory of retired requests stays in the device pool for later admissions
   if (st >= 0 && pool_reserve(s->device, o.hbm_budget_bytes) != hipSuccess)
     st = fail(MDP_E_DEVICE, "device memory pool set-up failed");
   if (st < 0) {
-    if (!o.stream) {
-      std::shared_lock<std::shared_mutex> g(alloc_lock());
-      (void)hipStreamDestroy(s->stream);
+    for (auto& ln : s->lanes) {
+      ln->eng.release();
+      if (ln->own_stream) {
+        std::shared_lock<std::shared_mutex> g(alloc_lock());
+        (void)hipStreamDestroy(ln->stream);
+      }
     }
     delete s;
     return st;
   }
   s->t0 = clock_ms();
   for (int i = 0; i < o.admit_threads; ++i) s->admitters.emplace_back([s]() { s->admit_loop(); });
-  s->worker = std::thread([s]() { s->work_loop(); });
+  s->workers_left = static_cast<int>(s->lanes.size());
+  for (auto& ln : s->lanes) {
+    ServerLane* l = ln.get();
+    l->thread = std::thread([s, l]() { s->work_loop(l); });
+  }
   s->reapers_left = o.retire_threads;
   for (int i = 0; i < o.retire_threads; ++i) s->reapers.emplace_back([s]() { s->reap_loop(); });
   *out = s;
@@ -401,6 +433,7 @@ static mdp_status submit_common(mdp_server_t s, int64_t S, int32_t A, const int6
   r->A = A;
   r->gamma = gamma;
   r->footprint = footprint_of(S, A, nnz, s->opts.solve);
+  r->lane = (s->lanes.size() > 1 && nnz > s->opts.split_nnz) ? 1 : 0;
   if (r->footprint > s->opts.hbm_budget_bytes)
     return fail(MDP_E_NOMEM, "request footprint exceeds the server's HBM budget");
   if (borrow) {
@@ -480,9 +513,14 @@ mdp_status mdp_server_info(mdp_server_t s, int64_t* queued, int64_t* resident,
   if (!s) return fail(MDP_E_INVAL, "NULL server");
   std::lock_guard<std::mutex> g(s->mu);
   if (queued) *queued = static_cast<int64_t>(s->queue.size());
-  if (resident) *resident = static_cast<int64_t>(s->resident.size() + s->ready.size());
+  int64_t res = 0, rnd = 0;
+  for (const auto& ln : s->lanes) {
+    res += static_cast<int64_t>(ln->resident.size() + ln->ready.size());
+    rnd += ln->rounds;
+  }
+  if (resident) *resident = res;
   if (resident_bytes) *resident_bytes = s->held_bytes;
-  if (rounds) *rounds = s->rounds;
+  if (rounds) *rounds = rnd;
   return MDP_OK;
 }
 
@@ -507,16 +545,19 @@ mdp_status mdp_server_destroy(mdp_server_t s) {
     std::lock_guard<std::mutex> g(s->mu);
     s->cv_work.notify_all();
   }
-  if (s->worker.joinable()) s->worker.join();
+  for (auto& ln : s->lanes)
+    if (ln->thread.joinable()) ln->thread.join();
   for (auto& t : s->reapers) t.join();
   for (auto& kv : s->all)
     if (kv.second->h) mdp_destroy(kv.second->h);
-  s->eng.release();
-  (void)pool_reserve(s->device, -s->opts.hbm_budget_bytes);
-  if (!s->opts.stream && s->stream) {
-    std::shared_lock<std::shared_mutex> g(alloc_lock());
-    (void)hipStreamDestroy(s->stream);
+  for (auto& ln : s->lanes) {
+    ln->eng.release();
+    if (ln->own_stream && ln->stream) {
+      std::shared_lock<std::shared_mutex> g(alloc_lock());
+      (void)hipStreamDestroy(ln->stream);
+    }
   }
+  (void)pool_reserve(s->device, -s->opts.hbm_budget_bytes);
   delete s;
   return MDP_OK;
 }

@@ -47,6 +47,34 @@ __global__ __launch_bounds__(256) void gather(const int* __restrict__ idx, const
   out[blockIdx.x * (int64_t)blockDim.x + threadIdx.x] = s;
 }
 
+// The same gathers through a raw buffer resource with the cache-policy bits
+// AUX of the load instruction (gfx950: bit 0 sc0, bit 1 nt, bit 4 sc1): how
+// the line granularity of the path a gather takes changes the rate.
+template <int AUX>
+__global__ __launch_bounds__(256) void gather_policy(const int* __restrict__ idx, const double* __restrict__ x,
+                                                     int64_t nx, int64_t n, double* out) {
+  const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(
+      const_cast<double*>(x), static_cast<short>(0), static_cast<int>(static_cast<uint32_t>(nx * 8)), 0x00020000);
+  constexpr int U = 4;
+  double s = 0.0;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  for (; i + (U - 1) * stride < n; i += U * stride) {
+    int c[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) c[u] = __builtin_nontemporal_load(idx + i + u * stride);
+    double v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      v[u] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(
+                                            r, static_cast<int>(static_cast<uint32_t>(c[u]) * 8u), 0, AUX));
+#pragma unroll
+    for (int u = 0; u < U; ++u) s += v[u];
+  }
+  for (; i < n; i += stride) s += x[idx[i]];
+  out[blockIdx.x * (int64_t)blockDim.x + threadIdx.x] = s;
+}
+
 // streaming read of the index array alone (the gather-free floor)
 __global__ __launch_bounds__(256) void stream_idx(const int* __restrict__ idx, int64_t n, double* out) {
   double s = 0.0;
@@ -86,6 +114,35 @@ int main() {
     printf("table %8.1f MB: %.3f ms per %lld gathers -> %.1f G gathers/s (index stream %.2f TB/s)\n",
            t * 8.0 / 1e6, ms, (long long)n, n / (ms * 1e-3) / 1e9, n * 4.0 / (ms * 1e-3) / 1e12);
     fflush(stdout);
+  }
+  // cache-policy variants of the gathers on a 33.6 MB and a 1 GiB table
+  const int64_t ptables[] = {1ll << 22, 1ll << 27};
+  for (int64_t t : ptables) {
+    fill_idx<<<4096, 256>>>(idx, n, (uint32_t)t, 12345u);
+    CHK(hipGetLastError());
+    CHK(hipDeviceSynchronize());
+    auto run = [&](auto kern, const char* name) -> int {
+      for (int rep = 0; rep < 2; ++rep) kern<<<grid, 256>>>(idx, x, t, n, out);
+      CHK(hipEventRecord(a));
+      for (int rep = 0; rep < 10; ++rep) kern<<<grid, 256>>>(idx, x, t, n, out);
+      CHK(hipEventRecord(b));
+      CHK(hipEventSynchronize(b));
+      float ms;
+      CHK(hipEventElapsedTime(&ms, a, b));
+      ms /= 10;
+      printf("table %8.1f MB, buffer load %-8s: %.3f ms -> %.1f G gathers/s\n", t * 8.0 / 1e6, name, ms,
+             n / (ms * 1e-3) / 1e9);
+      fflush(stdout);
+      return 0;
+    };
+    if (run(gather_policy<0>, "default")) return 1;
+    if (run(gather_policy<1>, "sc0")) return 1;
+    if (run(gather_policy<2>, "nt")) return 1;
+    if (run(gather_policy<3>, "sc0 nt")) return 1;
+    if (run(gather_policy<16>, "sc1")) return 1;
+    if (run(gather_policy<17>, "sc0 sc1")) return 1;
+    if (run(gather_policy<18>, "sc1 nt")) return 1;
+    if (run(gather_policy<19>, "all")) return 1;
   }
   CHK(hipEventRecord(a));
   for (int rep = 0; rep < 10; ++rep) stream_idx<<<grid, 256>>>(idx, n, out);

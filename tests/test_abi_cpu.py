@@ -219,3 +219,46 @@ def test_sizes_the_kernels_cannot_index_are_refused():
         assert st == native.MDP_E_NOTSUP
     finally:
         lib.mdp_server_destroy(srv)
+
+
+def test_new_option_defaults_and_entry_point_checks():
+    """Defaults of the options added for the preconditioner, CGS2, size-classed
+    serving and server autotuning, and the host-side refusals of the
+    allocation-free sweep and of device construction (all before any GPU call)."""
+    lib = native.load()
+    o = native.SolveOpts()
+    lib.mdp_default_solve_opts(C.byref(o))
+    assert o.precond_degree == 1 and o.gs_passes == 1
+    e = native.EvalOpts()
+    lib.mdp_default_eval_opts(C.byref(e))
+    assert e.precond_degree == 1 and e.gs_passes == 1
+    so = native.ServerOpts()
+    lib.mdp_default_server_opts(C.byref(so))
+    assert so.autotune == 0 and so.split_nnz == 1 << 24
+    so.split_nnz = -1
+    srv = C.c_void_p()
+    assert lib.mdp_server_create(C.byref(so), C.byref(srv)) == native.MDP_E_INVAL
+    so.split_nnz = 0
+    so.solve.precond_degree = 2
+    assert lib.mdp_server_create(C.byref(so), C.byref(srv)) == native.MDP_E_NOTSUP
+    so.solve.precond_degree = 1
+    so.solve.gs_passes = 2
+    assert lib.mdp_server_create(C.byref(so), C.byref(srv)) == native.MDP_E_NOTSUP
+    # allocation-free sweep: more sweep tiles than its scratch holds, bad lanes
+    assert lib.mdp_bellman_noalloc(70000 * 1024, 1, 70000 * 1024, None, None, None, None, 0.9, None, None,
+                                   None, None, 0, None) == native.MDP_E_NOTSUP
+    assert lib.mdp_bellman_noalloc(100, 2, 400, None, None, None, None, 0.9, None, None, None, None, 3,
+                                   None) == native.MDP_E_INVAL
+    assert lib.mdp_bellman_noalloc(100, 2, 100, None, None, None, None, 0.9, None, None, None, None, 0,
+                                   None) == native.MDP_E_INVAL  # fewer entries than rows
+    # device construction: argument checks come before any allocation or launch
+    h = C.c_void_p()
+    fake = C.c_void_p(1)
+    assert lib.mdp_create_from_device_rows(100, 2, 4, None, None, 0.9, None, C.byref(h)) == native.MDP_E_INVAL
+    for k_max in (0, 5000):
+        assert lib.mdp_create_from_device_rows(100, 2, k_max, fake, None, 0.9, None, C.byref(h)) == native.MDP_E_INVAL
+    assert lib.mdp_create_from_device_rows(1 << 26, 16, 32, fake, None, 0.9, None,
+                                           C.byref(h)) == native.MDP_E_NOTSUP
+    assert b"2^34" in lib.mdp_last_error()
+    k = C.c_void_p()
+    assert lib.mdp_load_kernel(b"/nonexistent.hsaco", b"k", C.byref(k)) in (native.MDP_E_INVAL, native.MDP_E_DEVICE)

@@ -149,3 +149,29 @@ def test_server_autotunes_each_new_class_once(tmp_path, monkeypatch):
         vr, pir, str_ = _alone(inst, 1)
         assert st["status"] == 0 and str_["status"] == 0
         assert np.array_equal(v, vr) and np.array_equal(pi, pir), k
+
+
+@pytest.mark.parametrize("precision", [1, 0])
+def test_server_size_classes_give_the_alone_results(precision):
+    """Two workers (size classes): requests up to split_nnz nonzeros on one,
+    larger ones on the other, each on its own stream and engine; every result
+    still equals the request solved alone, bit for bit."""
+    import paper_2502_14474_amd as m
+    insts = _requests()
+    split = int(np.median([i.nnz for i in insts]))
+    assert any(i.nnz <= split for i in insts) and any(i.nnz > split for i in insts)
+    print(f"[case] server size classes, split at {split} nonzeros, precision={precision}", flush=True)
+    ref = [_alone(i, precision) for i in insts]
+    with m.Server(precision=precision, alpha=1e-2, max_batch=6, split_nnz=split) as srv:
+        ids = []
+        for k, inst in enumerate(insts):
+            ids.append(srv.submit(inst, borrow=(k % 2 == 0)))
+            if k % 4 == 3:
+                time.sleep(0.005)
+        outs = [srv.wait(i) for i in ids]
+        info = srv.info()
+    assert info["resident"] == 0 and info["queued"] == 0
+    for k, ((v, pi, st), (vr, pir, str_)) in enumerate(zip(outs, ref)):
+        assert st["status"] == 0 and str_["status"] == 0
+        assert np.array_equal(v, vr) and np.array_equal(pi, pir), k
+        assert st["inner_iters"] == str_["inner_iters"]
