@@ -22,7 +22,7 @@ METRIC = ("Bellman sweeps/s + HBM GB/s (% peak); solve time to â€–Tvâˆ’vâ€–âˆžâ‰
           "FP64 vs mixed")
 HBM_PEAK_GBS = 8000.0
 KERNEL_SOURCES = ("paper_2502_14474_amd/csrc/device.h", "paper_2502_14474_amd/csrc/kernels.hip",
-                  "paper_2502_14474_amd/csrc/colblock.hip")
+                  "paper_2502_14474_amd/csrc/colblock.hip", "paper_2502_14474_amd/csrc/internal.h")
 COUNTERS_GLOB = os.path.join(ROOT, "profiles", "counters_*.json")
 
 
@@ -228,7 +228,7 @@ def serving_bench(args, m):
     del pageable
     n = args.serve_requests or 3 * len(pool)
 
-    def run(srv, gaps, n=n):
+    def run(srv, gaps, n=n, tag=""):
         ids = []
         t0 = time.perf_counter()
         nxt = t0
@@ -241,6 +241,14 @@ def serving_bench(args, m):
             ids.append(srv.submit(pool[i % len(pool)], borrow=True))
         outs = [srv.wait(r) for r in ids]
         t1 = time.perf_counter()
+        if args.serve_dump:
+            with open(args.serve_dump, "a") as f:
+                f.write(json.dumps({"run": tag, "requests": [
+                    {"i": i, "nnz": int(pool[i % len(pool)].nnz), "S": int(pool[i % len(pool)].S),
+                     "gamma": pool[i % len(pool)].gamma, "submit_ms": o[2]["submit_ms"],
+                     "admit_ms": o[2]["admit_ms"], "finish_ms": o[2]["finish_ms"],
+                     "sweeps": o[2]["bellman_sweeps"], "inner": o[2]["inner_iters"]}
+                    for i, o in enumerate(outs)]}) + "\n")
         lat = np.array([o[2]["finish_ms"] - o[2]["submit_ms"] for o in outs])
         wait = np.array([o[2]["admit_ms"] - o[2]["submit_ms"] for o in outs])
         size = np.array([pool[i % len(pool)].nnz for i in range(n)])
@@ -265,17 +273,18 @@ def serving_bench(args, m):
     with m.Server(precision=m.MDP_MIXED_FP32, alpha=args.alpha, atol=args.atol,
                   max_batch=args.serve_max_batch, autotune=not args.no_autotune,
                   split_nnz=args.split_nnz,
-                  launch=m.MDP_LAUNCH_DIRECT if args.serve_launch == "direct" else m.MDP_LAUNCH_GRAPHS) as srv:
-        warm = run(srv, None, len(pool))
-        closed = run(srv, None)
+                  launch={"auto": m.MDP_LAUNCH_AUTO, "graphs": m.MDP_LAUNCH_GRAPHS,
+                          "direct": m.MDP_LAUNCH_DIRECT}[args.serve_launch]) as srv:
+        warm = run(srv, None, len(pool), tag="warm")
+        closed = run(srv, None, tag="closed")
         cap = closed["solves_per_s"]
         gaps = np.array([r["gap"] for r in config5_requests(n, seed=args.seed)])
         # an untimed open-loop pass first: batches of the sizes spread arrivals
         # produce (and their captured graphs) are new to the server after the
         # closed loop
-        warm_open = run(srv, gaps / (0.5 * cap))
-        open70 = run(srv, gaps / (0.7 * cap))
-        open90 = run(srv, gaps / (0.9 * cap))
+        warm_open = run(srv, gaps / (0.5 * cap), tag="open0.5")
+        open70 = run(srv, gaps / (0.7 * cap), tag="open0.7")
+        open90 = run(srv, gaps / (0.9 * cap), tag="open0.9")
     try:
         with open(tune_file) as f:
             tuned = json.load(f)
@@ -554,7 +563,9 @@ def main():
     ap.add_argument("--serve-max-batch", type=int, default=128)
     ap.add_argument("--no-autotune", action="store_true",
                     help="config 5: the server keeps the default lane widths")
-    ap.add_argument("--serve-launch", choices=["graphs", "direct"], default="graphs",
+    ap.add_argument("--serve-dump", default=None,
+                    help="config 5: append every request's times, size and iteration counts to this file")
+    ap.add_argument("--serve-launch", choices=["auto", "graphs", "direct"], default="auto",
                     help="config 5: how the server's GMRES cycles reach the GPU")
     ap.add_argument("--split-nnz", type=int, default=None,
                     help="config 5: the server's size-class split (0: one worker; default: the library's)")

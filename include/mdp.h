@@ -151,11 +151,13 @@ typedef struct {
   int64_t max_outer;      /* cap on Bellman sweeps (default 1000) */
   int64_t max_inner;      /* cap on inner steps per evaluation (default 10000) */
   int32_t launch;         /* batched solves and the server: how a GMRES cycle's Arnoldi steps
-                             reach the GPU.  MDP_LAUNCH_GRAPHS (and MDP_LAUNCH_AUTO, the
-                             default) replays HIP graphs captured once per configuration, with
-                             fixed persistent grids; MDP_LAUNCH_DIRECT launches each kernel with
-                             a grid sized to the round's work.  Both give bitwise the same
-                             results.  mdp_solve ignores it. */
+                             reach the GPU.  MDP_LAUNCH_GRAPHS replays HIP graphs captured once
+                             per configuration, with fixed persistent grids; MDP_LAUNCH_DIRECT
+                             launches each kernel with a grid sized to the round's work.
+                             MDP_LAUNCH_AUTO (the default) means graphs for mdp_solve_batch and
+                             direct launches for the server, whose batches change with every
+                             arrival.  Both give bitwise the same results.  mdp_solve ignores
+                             it. */
   int32_t precond_degree; /* as in mdp_eval_opts (the paper leaves the inner solver, and so its
                              preconditioning, to the caller: "Problem Setting and Solution
                              Methods") */

@@ -385,7 +385,10 @@ mdp_status mdp_server_create(const mdp_server_opts* opt, mdp_server_t* out) {
     }
     ln->eng.stream = ln->stream;
     ln->eng.prec = prec_of(o.solve.precision);
-    ln->eng.use_graphs = o.solve.launch != MDP_LAUNCH_DIRECT;
+    // a server's batches change with every arrival, so new graph keys (and
+    // captures, which hold the allocation lock against admissions) keep
+    // coming: it launches directly unless graphs are asked for
+    ln->eng.use_graphs = o.solve.launch == MDP_LAUNCH_GRAPHS;
     st = ln->eng.reserve(o.max_batch);
     s->lanes.push_back(std::move(ln));
   }

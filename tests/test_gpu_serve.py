@@ -23,9 +23,9 @@ def _alone(inst, precision):
         return h.solve(precision=precision, alpha=1e-2)
 
 
-@pytest.mark.parametrize("precision,launch", [(1, 0), (0, 0), (1, 2)])
+@pytest.mark.parametrize("precision,launch", [(1, 0), (0, 0), (1, 1), (1, 2)])
 def test_server_results_equal_alone_with_staggered_arrivals(precision, launch):
-    # launch 0: the default (graph replays); 2: direct launches
+    # launch 0: the default (direct launches for a server); 1: graph replays; 2: direct launches
     import paper_2502_14474_amd as m
     insts = _requests()
     print(f"[case] server precision={precision} launch={launch} with {len(insts)} requests", flush=True)
