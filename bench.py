@@ -271,6 +271,7 @@ def serving_bench(args, m):
     tune_file = os.path.join(tempfile.mkdtemp(prefix="mdp_tune_"), "tune.json")
     os.environ["MDP_TUNE_CACHE"] = tune_file
     with m.Server(precision=m.MDP_MIXED_FP32, alpha=args.alpha, atol=args.atol,
+                  hbm_budget_bytes=int(args.serve_budget_gib * (1 << 30)),
                   max_batch=args.serve_max_batch, autotune=not args.no_autotune,
                   split_nnz=args.split_nnz,
                   launch={"auto": m.MDP_LAUNCH_AUTO, "graphs": m.MDP_LAUNCH_GRAPHS,
@@ -309,7 +310,8 @@ def serving_bench(args, m):
                                 f"gamma in {{0.9,0.99,0.999}}), submitted {n} times in stream order; "
                                 f"mixed float32 + float64 refinement to ||Tv-v||_inf<={args.atol}"),
                    "pool": len(pool), "pool_nnz": int(nnz.sum()), "pool_max_states": int(max(p.S for p in pool)),
-                   "submissions": n, "alpha": args.alpha},
+                   "submissions": n, "alpha": args.alpha, "hbm_budget_gib": args.serve_budget_gib,
+                   "max_batch": args.serve_max_batch},
         "roofline": None,
         "cpu_baseline": cpu,
         "serving": {"warmup_pass": warm, "closed_loop": closed, "open_loop_warmup_0.5C": warm_open,
@@ -561,6 +563,8 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=0,
                     help="config 5: submissions per run (0: three times the pool)")
     ap.add_argument("--serve-max-batch", type=int, default=128)
+    ap.add_argument("--serve-budget-gib", type=float, default=192.0,
+                    help="config 5: the server's HBM budget (of the 288 GB on the GPU)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="config 5: the server keeps the default lane widths")
     ap.add_argument("--serve-dump", default=None,

@@ -344,9 +344,11 @@ mdp_status mdp_solve_batch(mdp_t* handles, int32_t n, const double* const* v0, d
 
 /* ---- serving: continuous batching of solve requests ----------------------
  * An extension the paper does not define: requests are solved as by
- * mdp_solve_batch.  A server owns a worker thread on one GPU.  Submitted MDPs wait in a queue;
- * the worker admits them while the estimated device footprint of the resident
- * set stays within hbm_budget_bytes and at most max_batch are resident, keeps
+ * mdp_solve_batch.  A server owns worker threads on one GPU.  Submitted MDPs wait in a queue;
+ * the server admits them in order while the estimated device footprint of the resident
+ * set stays within hbm_budget_bytes and at most max_batch are resident (when the
+ * request at the head does not fit, later ones that fit may pass it, up to 64
+ * times, after which it waits for room), keeps
  * admitted MDPs and their iterates resident, and advances all of them with
  * the batched engine (see mdp_solve_batch), one round at a time.  Requests
  * that arrive while others run join at the next round; finished ones leave,

@@ -43,6 +43,7 @@ struct Request {
   bool borrowed = false;
   int64_t footprint = 0;
   int lane = 0;  // the worker (size class) that advances it
+  int passed = 0;  // times a later request was admitted ahead of it
   // results
   std::vector<double> v;
   std::vector<int32_t> pi;
@@ -130,16 +131,27 @@ using namespace mdp;
 void mdp_server::admit_loop() {
   (void)hipSetDevice(device);
   std::unique_lock<std::mutex> lk(mu);
+  // The queue is served in order, except that while the request at its head
+  // does not fit the budget, later requests that fit may pass it, at most
+  // kMaxPasses times (then the head waits for room): a large request does not
+  // hold up the small ones behind it, and is not starved by them either.
+  constexpr int kMaxPasses = 64;
+  auto pick = [&]() -> std::deque<Request*>::iterator {
+    if (queue.empty() || in_flight() >= opts.max_batch) return queue.end();
+    auto fits = [&](const Request* r) { return held_bytes == 0 || held_bytes + r->footprint <= opts.hbm_budget_bytes; };
+    if (fits(queue.front())) return queue.begin();
+    if (queue.front()->passed >= kMaxPasses) return queue.end();
+    for (auto it = std::next(queue.begin()); it != queue.end(); ++it)
+      if (fits(*it)) return it;
+    return queue.end();
+  };
   for (;;) {
-    cv_admit.wait(lk, [&]() {
-      if (stop) return true;
-      if (queue.empty()) return false;
-      if (in_flight() >= opts.max_batch) return false;
-      return held_bytes == 0 || held_bytes + queue.front()->footprint <= opts.hbm_budget_bytes;
-    });
+    std::deque<Request*>::iterator it;
+    cv_admit.wait(lk, [&]() { return stop || (it = pick()) != queue.end(); });
     if (stop) return;
-    Request* r = queue.front();
-    queue.pop_front();
+    Request* r = *it;
+    if (it != queue.begin()) ++queue.front()->passed;
+    queue.erase(it);
     held_bytes += r->footprint;
     ++admitting;
     lk.unlock();

@@ -175,3 +175,22 @@ def test_server_size_classes_give_the_alone_results(precision):
         assert st["status"] == 0 and str_["status"] == 0
         assert np.array_equal(v, vr) and np.array_equal(pi, pir), k
         assert st["inner_iters"] == str_["inner_iters"]
+
+
+def test_server_small_requests_pass_a_large_head_that_does_not_fit():
+    """Budget for one large request plus small ones: a second large request at
+    the head of the queue waits for room while the small ones behind it are
+    admitted; every result still equals the request solved alone."""
+    import paper_2502_14474_amd as m
+    big = [config2(S=200000, A=8, seed=s) for s in (5, 6)]
+    small = [config1(S=3000, seed=s) for s in range(4)]
+    insts = big + small
+    print(f"[case] server head-of-line bypass: 2 large ({big[0].nnz} nnz) + 4 small", flush=True)
+    with m.Server(hbm_budget_bytes=700 << 20, max_batch=8, alpha=1e-2, split_nnz=0) as srv:
+        ids = [srv.submit(i) for i in insts]
+        outs = [srv.wait(i) for i in ids]
+    admit = [o[2]["admit_ms"] for o in outs]
+    assert max(admit[2:]) <= admit[1], admit
+    for inst, (v, pi, st) in zip(insts, outs):
+        vr, pir, _ = _alone(inst, 1)
+        assert st["status"] == 0 and np.array_equal(v, vr) and np.array_equal(pi, pir)
