@@ -273,7 +273,7 @@ def serving_bench(args, m):
     with m.Server(precision=m.MDP_MIXED_FP32, alpha=args.alpha, atol=args.atol,
                   hbm_budget_bytes=int(args.serve_budget_gib * (1 << 30)),
                   max_batch=args.serve_max_batch, autotune=not args.no_autotune,
-                  split_nnz=args.split_nnz,
+                  split_nnz=args.split_nnz, trace_path=args.serve_trace,
                   launch={"auto": m.MDP_LAUNCH_AUTO, "graphs": m.MDP_LAUNCH_GRAPHS,
                           "direct": m.MDP_LAUNCH_DIRECT}[args.serve_launch]) as srv:
         warm = run(srv, None, len(pool), tag="warm")
@@ -567,6 +567,8 @@ def main():
                     help="config 5: the server's HBM budget (of the 288 GB on the GPU)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="config 5: the server keeps the default lane widths")
+    ap.add_argument("--serve-trace", default=None,
+                    help="config 5: file for the server's trace of admissions, rounds and retirements")
     ap.add_argument("--serve-dump", default=None,
                     help="config 5: append every request's times, size and iteration counts to this file")
     ap.add_argument("--serve-launch", choices=["auto", "graphs", "direct"], default="auto",

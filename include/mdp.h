@@ -359,7 +359,13 @@ typedef struct mdp_server* mdp_server_t;
 typedef struct {
   size_t struct_size;        /* sizeof(mdp_server_opts) */
   void* stream;              /* hipStream_t for the worker; NULL: its own */
-  int64_t hbm_budget_bytes;  /* admission limit on resident device bytes (default 64 GiB) */
+  int64_t hbm_budget_bytes;  /* admission limit on resident device bytes (default 64 GiB).  The
+                                server reserves the budget plus a quarter (for the staging of
+                                admissions in flight) as one device allocation when it starts,
+                                less when the device has less free memory, and places admitted
+                                MDPs in it, so that admitting and retiring never call the HIP
+                                allocator; what does not fit there comes from the library's
+                                device pool */
   int32_t device;            /* HIP device; -1: the current device */
   int32_t max_batch;         /* most MDPs resident at once (default 256) */
   int32_t admit_threads;     /* threads copying new MDPs to the device (default 4: while one
@@ -377,6 +383,12 @@ typedef struct {
                                 so that a small request's rounds do not wait for a large
                                 request's GMRES cycles (default 2^24; 0: one worker for all).
                                 Results do not depend on the class. */
+  const char* trace_path;    /* non-NULL: the server times each admission (handle created, lane
+                                width known, end; with the bytes in use in the server's
+                                allocation and the free device bytes at its start), each round (sweep phase end,
+                                MDPs advanced, swept and finished) and each retirement, in ms
+                                since its creation, and writes them to this file, one JSON
+                                object a line, when it is destroyed (default NULL: no trace) */
 } mdp_server_opts;
 
 typedef struct {

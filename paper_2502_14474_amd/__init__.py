@@ -353,7 +353,8 @@ class Server:
     """Continuous-batching solve server (mdp_server_* in include/mdp.h)."""
 
     def __init__(self, hbm_budget_bytes=64 << 30, max_batch=256, device=-1, stream=None,
-                 admit_threads=4, retire_threads=4, autotune=False, split_nnz=None, **solve_opts):
+                 admit_threads=4, retire_threads=4, autotune=False, split_nnz=None, trace_path=None,
+                 **solve_opts):
         lib = native.load()
         o = native.ServerOpts()
         lib.mdp_default_server_opts(C.byref(o))
@@ -361,6 +362,8 @@ class Server:
         o.admit_threads, o.retire_threads, o.autotune = admit_threads, retire_threads, int(bool(autotune))
         if split_nnz is not None:
             o.split_nnz = split_nnz
+        if trace_path is not None:
+            o.trace_path = os.fsencode(trace_path)
         solve_opts.setdefault("precision", MDP_MIXED_FP32)
         o.solve = _solve_opts(lib, **solve_opts)
         self.s = C.c_void_p()

@@ -44,19 +44,19 @@ void lib_host_free(void* p) {
   (void)hipHostFree(p);
 }
 
-// Device memory of handles, and staging memory at create time, come from a
-// stream-ordered pool that the library creates once per device and keeps
-// until the process ends.  hipFree waits for the whole device, so a server
-// retiring a request would wait for the solves running beside it, and each
-// unmapping is slow; the pool frees in stream order and keeps freed memory for
-// the next handle, up to a release threshold of kPoolKeepBytes plus what live
-// servers reserve (their HBM budgets).
+// Device memory of handles, and staging memory at create time, come from the
+// handle's arena when it has one (arena.cpp; servers admit into one), else
+// from a stream-ordered pool that the library creates once per device and
+// keeps until the process ends.  hipFree waits for the whole device, so a
+// solve ending beside others would wait for them; the pool frees in stream
+// order.  (The runtime's pool hands most freed memory back at the next
+// synchronisation, whatever its release threshold, so a handle created after
+// others were destroyed usually takes fresh memory from the device.)
 constexpr uint64_t kPoolKeepBytes = uint64_t{2} << 30;
 
 namespace {
 struct DevicePool {
   hipMemPool_t pool = nullptr;
-  uint64_t reserved = 0;
 };
 std::mutex g_pool_mu;
 std::vector<DevicePool> g_pools;
@@ -96,20 +96,11 @@ hipError_t device_pool(int dev, hipMemPool_t* out) {
   return e;
 }
 
-hipError_t pool_reserve(int dev, int64_t delta) {
-  std::lock_guard<std::mutex> lk(g_pool_mu);
-  DevicePool* d = nullptr;
-  hipError_t e = pool_locked(dev, &d);
-  if (e != hipSuccess) return e;
-  d->reserved = static_cast<uint64_t>(std::max<int64_t>(0, static_cast<int64_t>(d->reserved) + delta));
-  uint64_t keep = kPoolKeepBytes + d->reserved;
-  std::shared_lock<std::shared_mutex> g(alloc_lock());  // trimming releases memory
-  e = hipMemPoolSetAttribute(d->pool, hipMemPoolAttrReleaseThreshold, &keep);
-  if (e == hipSuccess && delta < 0) e = hipMemPoolTrimTo(d->pool, static_cast<size_t>(keep));
-  return e;
-}
-
 hipError_t handle_alloc(mdp_handle* h, void** p, size_t bytes) {
+  if (h->dev_arena) {
+    *p = h->dev_arena->alloc(bytes);
+    if (*p) return hipSuccess;  // arena ranges are 256-byte aligned
+  }
   hipMemPool_t pool = nullptr;
   hipError_t e = device_pool(h->device, &pool);
   if (e != hipSuccess) return e;
@@ -129,6 +120,10 @@ hipError_t handle_alloc(mdp_handle* h, void** p, size_t bytes) {
 
 void handle_free(mdp_handle* h, void* p) {
   if (!p) return;
+  if (DeviceArena* a = arena_of(p)) {
+    a->free(p, h->destroying ? nullptr : h->stream);
+    return;
+  }
   std::shared_lock<std::shared_mutex> g(alloc_lock());
   (void)hipFreeAsync(p, h->stream);
 }
@@ -268,6 +263,10 @@ void dev_free(mdp_handle* h, T*& p) {
 }
 
 hipError_t staging_alloc(int dev, hipStream_t st, size_t bytes, char** out) {
+  if (DeviceArena* a = current_arena(); a && a->device() == dev) {
+    *out = static_cast<char*>(a->alloc(bytes));
+    if (*out) return hipSuccess;
+  }
   hipMemPool_t pool = nullptr;
   hipError_t e = device_pool(dev, &pool);
   if (e != hipSuccess) return e;
@@ -276,9 +275,145 @@ hipError_t staging_alloc(int dev, hipStream_t st, size_t bytes, char** out) {
 }
 
 hipError_t staging_free(char* p, hipStream_t st) {
+  if (DeviceArena* a = arena_of(p)) {
+    a->free(p, st);
+    return hipSuccess;
+  }
   std::shared_lock<std::shared_mutex> g(alloc_lock());
   return hipFreeAsync(p, st);
 }
+
+}  // namespace
+
+namespace {
+std::mutex g_stage_mu;
+std::vector<StageBlock> g_stage_free;
+}  // namespace
+
+bool stage_take(StageBlock* b) {
+  {
+    std::lock_guard<std::mutex> lk(g_stage_mu);
+    if (!g_stage_free.empty()) {
+      *b = g_stage_free.back();
+      g_stage_free.pop_back();
+      return true;
+    }
+  }
+  StageBlock n;
+  void* p = nullptr;
+  if (lib_host_malloc(&p, kStageBlockBytes) != hipSuccess) return false;
+  hipError_t e;
+  {
+    std::shared_lock<std::shared_mutex> g(alloc_lock());
+    e = hipEventCreateWithFlags(&n.ev, hipEventDisableTiming);
+  }
+  if (e != hipSuccess) {
+    lib_host_free(p);
+    return false;
+  }
+  n.p = static_cast<char*>(p);
+  *b = n;
+  return true;
+}
+
+void stage_give(const StageBlock& b) {
+  if (!b.p) return;
+  std::lock_guard<std::mutex> lk(g_stage_mu);
+  g_stage_free.push_back(b);
+}
+
+bool host_pageable(const void* p) {
+  if (!p) return false;
+  hipPointerAttribute_t a;
+  std::memset(&a, 0, sizeof(a));
+  if (hipPointerGetAttributes(&a, p) != hipSuccess) {
+    (void)hipGetLastError();
+    return true;
+  }
+  return a.type == hipMemoryTypeUnregistered;
+}
+
+namespace {
+// Two blocks per staged copy, so that the host side of one chunk overlaps the
+// transfer of the other; handed back once the stream has drained them.
+struct StagePair {
+  StageBlock b[2];
+  bool ok = false;
+  StagePair() {
+    ok = stage_take(&b[0]);
+    if (ok && !stage_take(&b[1])) {
+      stage_give(b[0]);
+      b[0] = StageBlock();
+      ok = false;
+    }
+  }
+  ~StagePair() {
+    stage_give(b[0]);
+    stage_give(b[1]);
+  }
+};
+}  // namespace
+
+hipError_t copy_in(void* dst, const void* src, size_t bytes, hipStream_t st) {
+  if (bytes == 0) return hipSuccess;
+  if (!host_pageable(src)) return hipMemcpyAsync(dst, src, bytes, hipMemcpyDefault, st);
+  if (host_pageable(dst)) {  // host to host
+    std::memcpy(dst, src, bytes);
+    return hipSuccess;
+  }
+  StagePair sp;
+  if (!sp.ok) return hipErrorOutOfMemory;
+  hipError_t e = hipSuccess;
+  bool used[2] = {false, false};
+  int k = 0;
+  for (size_t off = 0; off < bytes && e == hipSuccess; off += kStageBlockBytes, k ^= 1) {
+    const size_t c = std::min(kStageBlockBytes, bytes - off);
+    if (used[k]) e = hipEventSynchronize(sp.b[k].ev);  // the block's previous chunk has left
+    if (e != hipSuccess) break;
+    std::memcpy(sp.b[k].p, static_cast<const char*>(src) + off, c);
+    e = hipMemcpyAsync(static_cast<char*>(dst) + off, sp.b[k].p, c, hipMemcpyDefault, st);
+    if (e == hipSuccess) e = hipEventRecord(sp.b[k].ev, st);
+    used[k] = true;
+  }
+  const hipError_t es = hipStreamSynchronize(st);  // the blocks go back idle
+  return e != hipSuccess ? e : es;
+}
+
+hipError_t copy_out(void* dst, const void* src, size_t bytes, hipStream_t st) {
+  if (bytes == 0) return hipSuccess;
+  if (!host_pageable(dst)) return hipMemcpyAsync(dst, src, bytes, hipMemcpyDefault, st);
+  if (host_pageable(src)) {  // host to host
+    std::memcpy(dst, src, bytes);
+    return hipSuccess;
+  }
+  StagePair sp;
+  if (!sp.ok) return hipErrorOutOfMemory;
+  hipError_t e = hipSuccess;
+  size_t prev_off = 0, prev_c = 0;
+  bool pending = false;
+  int k = 0;
+  // chunk i goes into block k while chunk i-1 leaves block k^1 for dst
+  for (size_t off = 0; off < bytes && e == hipSuccess; off += kStageBlockBytes, k ^= 1) {
+    const size_t c = std::min(kStageBlockBytes, bytes - off);
+    e = hipMemcpyAsync(sp.b[k].p, static_cast<const char*>(src) + off, c, hipMemcpyDefault, st);
+    if (e == hipSuccess) e = hipEventRecord(sp.b[k].ev, st);
+    if (e == hipSuccess && pending) {
+      e = hipEventSynchronize(sp.b[k ^ 1].ev);
+      if (e == hipSuccess) std::memcpy(static_cast<char*>(dst) + prev_off, sp.b[k ^ 1].p, prev_c);
+    }
+    pending = e == hipSuccess;
+    prev_off = off;
+    prev_c = c;
+  }
+  if (e == hipSuccess && pending) {
+    e = hipEventSynchronize(sp.b[k ^ 1].ev);
+    if (e == hipSuccess) std::memcpy(static_cast<char*>(dst) + prev_off, sp.b[k ^ 1].p, prev_c);
+  }
+  const hipError_t es = hipStreamSynchronize(st);
+  return e != hipSuccess ? e : es;
+}
+
+namespace {
 
 // Copy a caller policy to device memory and check its range.
 mdp_status load_policy(mdp_handle* h, const int32_t* policy, int32_t* dst) {
@@ -287,7 +422,7 @@ mdp_status load_policy(mdp_handle* h, const int32_t* policy, int32_t* dst) {
     for (int64_t s = 0; s < h->S; ++s)
       if (policy[s] < 0 || policy[s] >= h->A)
         return fail(MDP_E_INVAL, "policy entry outside [0,A) at state " + std::to_string(s));
-    MDP_HIP(hipMemcpyAsync(dst, policy, h->S * sizeof(int32_t), hipMemcpyHostToDevice, h->stream));
+    MDP_HIP(copy_in(dst, policy, h->S * sizeof(int32_t), h->stream));
     return MDP_OK;
   }
   MDP_HIP(hipMemcpyAsync(dst, policy, h->S * sizeof(int32_t), hipMemcpyDeviceToDevice, h->stream));
@@ -301,7 +436,7 @@ mdp_status load_policy(mdp_handle* h, const int32_t* policy, int32_t* dst) {
 
 mdp_status load_vec(mdp_handle* h, const double* src, double* dst) {
   if (src) {
-    MDP_HIP(hipMemcpyAsync(dst, src, h->S * sizeof(double), hipMemcpyDefault, h->stream));
+    MDP_HIP(copy_in(dst, src, h->S * sizeof(double), h->stream));
     if (h->maximize) MDP_HIP(launch_negate(h->stream, dst, h->S));
   } else {
     MDP_HIP(hipMemsetAsync(dst, 0, h->S * sizeof(double), h->stream));
@@ -310,7 +445,7 @@ mdp_status load_vec(mdp_handle* h, const double* src, double* dst) {
 }
 
 mdp_status store(mdp_handle* h, void* dst, const void* src, size_t bytes) {
-  if (dst && dst != src) MDP_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyDefault, h->stream));
+  if (dst && dst != src) MDP_HIP(copy_out(dst, src, bytes, h->stream));
   return MDP_OK;
 }
 
@@ -771,6 +906,7 @@ void mdp_default_solve_opts(mdp_solve_opts* o) {
 mdp_status mdp_destroy(mdp_t h) {
   if (!h) return MDP_OK;
   if (h->stream) (void)hipStreamSynchronize(h->stream);
+  h->destroying = true;
   if (h->arena) {  // the arrays inside it go with it
     dev_free(h, h->arena);
     h->row_ptr = h->col = nullptr;
@@ -862,7 +998,7 @@ mdp_status mdp_create(int64_t S, int32_t A, const int64_t* row_ptr, const int32_
   if (dev_in) {
     // stage through the host for validation
     h_rp.resize(rows + 1);
-    MDP_HIP(hipMemcpy(h_rp.data(), row_ptr, (rows + 1) * sizeof(int64_t), hipMemcpyDefault));
+    MDP_HIP(copy_out(h_rp.data(), row_ptr, (rows + 1) * sizeof(int64_t), static_cast<hipStream_t>(o.stream)));
     rp_host = h_rp.data();
   }
   nnz = rp_host[rows];
@@ -873,9 +1009,10 @@ mdp_status mdp_create(int64_t S, int32_t A, const int64_t* row_ptr, const int32_
     if (dev_in) {
       std::vector<int32_t> c(nnz);
       std::vector<double> v(nnz), g(rows);
-      MDP_HIP(hipMemcpy(c.data(), col, nnz * sizeof(int32_t), hipMemcpyDefault));
-      MDP_HIP(hipMemcpy(v.data(), val, nnz * sizeof(double), hipMemcpyDefault));
-      MDP_HIP(hipMemcpy(g.data(), cost, rows * sizeof(double), hipMemcpyDefault));
+      hipStream_t cs = static_cast<hipStream_t>(o.stream);
+      MDP_HIP(copy_out(c.data(), col, nnz * sizeof(int32_t), cs));
+      MDP_HIP(copy_out(v.data(), val, nnz * sizeof(double), cs));
+      MDP_HIP(copy_out(g.data(), cost, rows * sizeof(double), cs));
       MDP_TRY(validate_entries_host(S, A, rp_host, c.data(), v.data(), g.data()));
     } else {
       MDP_TRY(validate_entries_host(S, A, rp_host, col, val, cost));
@@ -910,6 +1047,7 @@ mdp_status mdp_create(int64_t S, int32_t A, const int64_t* row_ptr, const int32_
   }
   if (o.device >= 0) CHK(hipSetDevice(o.device));
   CHK(hipGetDevice(&h->device));
+  if (DeviceArena* a = current_arena()) h->dev_arena = a->device() == h->device ? a : nullptr;
   if (o.lanes_per_row == 0) {
     const int tuned = tune_lookup(h);  // width measured earlier for this class, if any
     if (tuned) h->lanes = tuned;
@@ -960,36 +1098,40 @@ mdp_status mdp_create(int64_t S, int32_t A, const int64_t* row_ptr, const int32_
   // Device validation reads the natural arrays before they move.
   const bool permute = A > 1 && sweep_tile_states(A) > 1;
   {
-    std::vector<int32_t> rp32(rows + 1);
-    for (int64_t r = 0; r <= rows; ++r) rp32[r] = static_cast<int32_t>(rp_host[r]);
-    // staging: [verdicts | natural col | val | cost | row_ptr]; natural
-    // arrays only when the rows are permuted
+    // staging: [verdicts | natural col | val | cost | int32 row_ptr | int64
+    // row_ptr]; natural arrays only when the rows are permuted, the int64 copy
+    // only when row_ptr is host memory (it is narrowed on the device)
     auto up = [](size_t b) { return (b + 255) / 256 * 256; };
     const bool on_dev = o.validate == MDP_VALIDATE_DEVICE;
+    const bool rp_dev = is_device_ptr(row_ptr);
     const int vblocks = on_dev ? validate_blocks(rows) : 0;
     const size_t o_col = up(static_cast<size_t>(vblocks) * 3 * sizeof(int64_t));
     const size_t o_val = o_col + up(nnz * sizeof(int32_t));
     const size_t o_cost = o_val + up(nnz * sizeof(double));
     const size_t o_rp = o_cost + up(rows * sizeof(double));
-    const size_t bytes = permute ? o_rp + (rows + 1) * sizeof(int32_t) : o_col;
+    const size_t o_rp64 = up(permute ? o_rp + (rows + 1) * sizeof(int32_t) : o_col);
+    const size_t bytes = rp_dev ? (permute ? o_rp + (rows + 1) * sizeof(int32_t) : o_col)
+                                : o_rp64 + (rows + 1) * sizeof(int64_t);
     char* stage = nullptr;
     if (bytes > 0) CHK(staging_alloc(h->device, h->stream, bytes, &stage));
     int32_t* rp_nat = permute ? reinterpret_cast<int32_t*>(stage + o_rp) : h->row_ptr;
     int32_t* col_nat = permute ? reinterpret_cast<int32_t*>(stage + o_col) : h->col;
     double* val_nat = permute ? reinterpret_cast<double*>(stage + o_val) : h->val;
     double* cost_nat = permute ? reinterpret_cast<double*>(stage + o_cost) : h->cost;
-    std::vector<int64_t> verdict(static_cast<size_t>(vblocks) * 3);
-    hipError_t e = hipMemcpyAsync(rp_nat, rp32.data(), (rows + 1) * sizeof(int32_t), hipMemcpyHostToDevice,
-                                  h->stream);
-    if (e == hipSuccess) e = hipMemcpyAsync(col_nat, col, nnz * sizeof(int32_t), hipMemcpyDefault, h->stream);
-    if (e == hipSuccess) e = hipMemcpyAsync(val_nat, val, nnz * sizeof(double), hipMemcpyDefault, h->stream);
-    if (e == hipSuccess) e = hipMemcpyAsync(cost_nat, cost, rows * sizeof(double), hipMemcpyDefault, h->stream);
+    const int64_t* rp64 = rp_dev ? row_ptr : reinterpret_cast<const int64_t*>(stage + o_rp64);
+    StageBlock vb;  // pinned landing place of the verdicts
+    const size_t vbytes = static_cast<size_t>(vblocks) * 3 * sizeof(int64_t);
+    hipError_t e = on_dev && (vbytes > kStageBlockBytes || !stage_take(&vb)) ? hipErrorOutOfMemory : hipSuccess;
+    if (e == hipSuccess && !rp_dev)
+      e = copy_in(stage + o_rp64, row_ptr, (rows + 1) * sizeof(int64_t), h->stream);
+    if (e == hipSuccess) e = launch_narrow_offsets(h->stream, rp64, rp_nat, rows + 1);
+    if (e == hipSuccess) e = copy_in(col_nat, col, nnz * sizeof(int32_t), h->stream);
+    if (e == hipSuccess) e = copy_in(val_nat, val, nnz * sizeof(double), h->stream);
+    if (e == hipSuccess) e = copy_in(cost_nat, cost, rows * sizeof(double), h->stream);
     if (e == hipSuccess && on_dev) {
       auto* vd = reinterpret_cast<int64_t*>(stage);
       e = launch_validate(h->stream, S, rows, rp_nat, col_nat, val_nat, cost_nat, vd, vblocks);
-      if (e == hipSuccess)
-        e = hipMemcpyAsync(verdict.data(), vd, verdict.size() * sizeof(int64_t), hipMemcpyDeviceToHost,
-                           h->stream);
+      if (e == hipSuccess) e = hipMemcpyAsync(vb.p, vd, vbytes, hipMemcpyDeviceToHost, h->stream);
     }
     // moving rows is safe before the verdict: row_ptr was checked on the host
     if (e == hipSuccess && permute)
@@ -999,7 +1141,11 @@ mdp_status mdp_create(int64_t S, int32_t A, const int64_t* row_ptr, const int32_
       const hipError_t ef = staging_free(stage, h->stream);  // after the kernels, in stream order
       if (e == hipSuccess) e = ef;
     }
-    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);  // the host vectors go away
+    const hipError_t es = hipStreamSynchronize(h->stream);  // nothing in flight reads host memory
+    if (e == hipSuccess) e = es;
+    std::vector<int64_t> verdict(vbytes / sizeof(int64_t));
+    if (e == hipSuccess && on_dev) std::memcpy(verdict.data(), vb.p, vbytes);
+    stage_give(vb);
     CHK(e);
     if (on_dev) {
       int64_t cost_row = -1, entry_row = -1;
@@ -1487,8 +1633,8 @@ mdp_status mdp_solve_batch(mdp_t* handles, int32_t n, const double* const* v0, d
     BatchItem& it = items[i];
     mdp_handle* h = it.h;
     if (h->maximize) MDP_HIP(launch_negate(eng.stream, h->v, h->S));
-    MDP_HIP(hipMemcpyAsync(v[i], h->v, h->S * sizeof(double), hipMemcpyDefault, eng.stream));
-    MDP_HIP(hipMemcpyAsync(policy[i], h->pi, h->S * sizeof(int32_t), hipMemcpyDefault, eng.stream));
+    MDP_HIP(copy_out(v[i], h->v, h->S * sizeof(double), eng.stream));
+    MDP_HIP(copy_out(policy[i], h->pi, h->S * sizeof(int32_t), eng.stream));
     if (it.status < 0 && worst >= 0) {
       worst = it.status;
       fail(it.status, "batch item " + std::to_string(i) + " failed with a non-finite residual");

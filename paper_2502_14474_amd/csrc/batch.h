@@ -98,6 +98,10 @@ class BatchEngine {
   Prec prec = kF64;
   bool use_graphs = true;
   std::vector<BatchItem*> items;
+  // the last round: how many items it swept, and when (steady-clock ms) its
+  // sweep phase ended
+  int last_swept = 0;
+  double last_sweep_end_ms = 0;
 
   ~BatchEngine();
   mdp_status reserve(int n);

@@ -17,6 +17,7 @@
 //      met, a float64 residual restart.
 // New MDPs may join between rounds (continuous batching in the server).
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstring>
 #include <limits>
@@ -667,7 +668,10 @@ mdp_status BatchEngine::round(const mdp_solve_opts& o) {
   std::vector<int> need, gm;
   for (size_t i = 0; i < items.size(); ++i)
     if (items[i]->state == BatchItem::kSweep) need.push_back(static_cast<int>(i));
+  last_swept = static_cast<int>(need.size());
   MDP_TRY(sweep_phase(o, need));
+  last_sweep_end_ms = std::chrono::duration<double, std::milli>(
+                          std::chrono::steady_clock::now().time_since_epoch()).count();
   for (size_t i = 0; i < items.size(); ++i)
     if (items[i]->state == BatchItem::kGmres) gm.push_back(static_cast<int>(i));
   MDP_TRY(cycle_phase(o, gm));

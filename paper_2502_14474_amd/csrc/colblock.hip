@@ -308,8 +308,8 @@ hipError_t build_colblocks(mdp_handle* h, int blocks, bool require, bool* built,
   CB_CHK(hipGetLastError());
   unsigned long long far_h = 0;
   int bad_h = 0;
-  CB_CHK(hipMemcpyAsync(&far_h, far, 8, hipMemcpyDeviceToHost, h->stream));
-  CB_CHK(hipMemcpyAsync(&bad_h, bad, 4, hipMemcpyDeviceToHost, h->stream));
+  CB_CHK(copy_out(&far_h, far, 8, h->stream));
+  CB_CHK(copy_out(&bad_h, bad, 4, h->stream));
   CB_CHK(hipStreamSynchronize(h->stream));
   *far_frac = static_cast<double>(far_h) / static_cast<double>(h->nnz);
   if (bad_h || (!require && *far_frac < 0.5)) return done(hipSuccess);
@@ -319,7 +319,7 @@ hipError_t build_colblocks(mdp_handle* h, int blocks, bool require, bool* built,
   k_cb_tile_sums<<<dim3(ntiles, blocks), kBlock, 0, h->stream>>>(rows, tile_rows, ntiles, cnt, tsum);
   CB_CHK(hipGetLastError());
   std::vector<int> ts_h(nt), off_h(static_cast<size_t>(blocks) * (ntiles + 1));
-  CB_CHK(hipMemcpyAsync(ts_h.data(), tsum, nt * sizeof(int), hipMemcpyDeviceToHost, h->stream));
+  CB_CHK(copy_out(ts_h.data(), tsum, nt * sizeof(int), h->stream));
   CB_CHK(hipStreamSynchronize(h->stream));
   int64_t run = 0;
   for (int b = 0; b < blocks; ++b) {
@@ -333,7 +333,7 @@ hipError_t build_colblocks(mdp_handle* h, int blocks, bool require, bool* built,
   }
   if (run != h->nnz) return done(hipErrorInvalidValue);
   CB_CHK(handle_alloc(h, reinterpret_cast<void**>(&off), off_h.size() * sizeof(int)));
-  CB_CHK(hipMemcpyAsync(off, off_h.data(), off_h.size() * sizeof(int), hipMemcpyHostToDevice, h->stream));
+  CB_CHK(copy_in(off, off_h.data(), off_h.size() * sizeof(int), h->stream));
   CB_CHK(handle_alloc(h, reinterpret_cast<void**>(&rel), cnt_bytes * sizeof(uint16_t)));
   CB_CHK(handle_alloc(h, reinterpret_cast<void**>(&cb_col), h->nnz * sizeof(int)));
   CB_CHK(handle_alloc(h, reinterpret_cast<void**>(&cb_val), h->nnz * sizeof(double)));

@@ -145,7 +145,7 @@ extern "C" mdp_status mdp_create_from_device_rows(int64_t S, int32_t A, int32_t 
                                        static_cast<int64_t*>(len64.p), static_cast<unsigned long long*>(bad.p));
   MDP_HIP(hipGetLastError());
   unsigned long long bad_h = 0;
-  MDP_HIP(hipMemcpyAsync(&bad_h, bad.p, sizeof(bad_h), hipMemcpyDeviceToHost, st));
+  MDP_HIP(copy_out(&bad_h, bad.p, sizeof(bad_h), st));
   MDP_HIP(hipStreamSynchronize(st));
   if (bad_h != none)
     return fail(MDP_E_INVAL, "row kernel gave row " + std::to_string(bad_h) + " a length outside [1, k_max]");
@@ -158,7 +158,7 @@ extern "C" mdp_status mdp_create_from_device_rows(int64_t S, int32_t A, int32_t 
   MDP_HIP(hipcub::DeviceScan::InclusiveSum(tmp.p, tbytes, static_cast<const int64_t*>(len64.p), rp1,
                                            static_cast<int>(rows), st));
   int64_t nnz = 0;
-  MDP_HIP(hipMemcpyAsync(&nnz, rp1 + rows - 1, sizeof(nnz), hipMemcpyDeviceToHost, st));
+  MDP_HIP(copy_out(&nnz, rp1 + rows - 1, sizeof(nnz), st));
   MDP_HIP(hipStreamSynchronize(st));
   MDP_TRY(check_size_limits(S, A, nnz));
   MDP_HIP(col.alloc(nnz * sizeof(int32_t)));

@@ -5,7 +5,10 @@
 #include <hip/hip_fp16.h>
 
 #include <atomic>
+#include <map>
+#include <mutex>
 #include <shared_mutex>
+#include <unordered_map>
 #include <vector>
 #include <cstdint>
 #include <string>
@@ -66,6 +69,53 @@ struct Ctl {
   int32_t tf_stop, pad1;                     // TFQMR: the bound met at the last half-step
 };
 constexpr size_t kCtlHeaderBytes = offsetof(Ctl, scale);
+
+// A device arena (arena.cpp): one device allocation carved into handle
+// arrays by the library, so that code admitting and retiring many handles
+// never calls the HIP allocator.  alloc returns nullptr when no free range
+// fits; free returns a range once the work queued on `st` so far has finished
+// (at once for st == nullptr).  Thread-safe.
+class DeviceArena {
+ public:
+  static DeviceArena* create(int dev, size_t bytes);  // nullptr when the memory is not there
+  ~DeviceArena();
+  void* alloc(size_t bytes);
+  void free(void* p, hipStream_t st);
+  bool owns(const void* p) const;
+  size_t size() const { return size_; }
+  int device() const { return dev_; }
+  size_t in_use();
+
+ private:
+  DeviceArena() = default;
+  struct Pending {
+    size_t off;
+    hipEvent_t ev;
+  };
+  int dev_ = 0;
+  char* base_ = nullptr;
+  size_t size_ = 0, in_use_ = 0;
+  std::mutex mu_;
+  std::map<size_t, size_t> free_;             // offset -> length, coalesced
+  std::unordered_map<size_t, size_t> used_;   // offset -> length
+  std::vector<Pending> pending_;              // freed, waiting for their streams
+  std::vector<hipEvent_t> spare_;
+  void release_locked(size_t off);
+  void reap_locked();
+};
+// The arena holding p, if any.
+DeviceArena* arena_of(const void* p);
+// While an ArenaScope lives, handles created on this thread (and the staging
+// of their creation) take their memory from its arena.
+class ArenaScope {
+ public:
+  explicit ArenaScope(DeviceArena* a);
+  ~ArenaScope();
+
+ private:
+  DeviceArena* prev_;
+};
+DeviceArena* current_arena();
 
 struct Partials {
   double* buf;       // device scratch for per-workgroup partial results
@@ -138,6 +188,8 @@ struct mdp_handle {
   hipEvent_t ctl_event = nullptr; // marks the header copy of a snapshot
 
   int64_t device_bytes = 0;
+  mdp::DeviceArena* dev_arena = nullptr;  // where its arrays come from (nullptr: the pool)
+  bool destroying = false;                // its stream is idle: frees return at once
 
   // profiler: one event pair per launch while enabled
   struct ProfRec {
@@ -222,20 +274,43 @@ __host__ __device__ inline int64_t state_of_row(int64_t r, int A, int64_t S) {
 // it exclusively: such calls from another thread (hipFree waits for the whole
 // device) would break a capture in progress.
 std::shared_mutex& alloc_lock();
-// Handle memory (api.cpp): from the library's per-device stream-ordered pool,
+// Handle memory (api.cpp): from the handle's arena when it has one (and the
+// arena has room), else from the library's per-device stream-ordered pool,
 // allocated and freed on the handle's stream; an allocation is usable from any
 // stream once handle_alloc returns.  A free is ordered after the work queued on
 // the handle's stream, so work on other streams that touches the memory must
-// be finished first.  pool_reserve raises (or, negative, lowers and trims) the
-// bytes the pool keeps cached.
+// be finished first.
 hipError_t handle_alloc(mdp_handle* h, void** p, size_t bytes);
 void handle_free(mdp_handle* h, void* p);
 hipError_t device_pool(int dev, hipMemPool_t* out);
-hipError_t pool_reserve(int dev, int64_t delta);
 hipError_t lib_malloc(void** p, size_t bytes);
 void lib_free(void* p);
 hipError_t lib_host_malloc(void** p, size_t bytes);
 void lib_host_free(void* p);
+
+// Copies between the device and host memory (api.cpp).  Memory that HIP
+// knows (device memory, pinned or registered host memory) is copied directly
+// and asynchronously.  Plain pageable host memory is never handed to the
+// runtime: it goes through pinned blocks of the library, in pieces whose host
+// side overlaps the transfer of the previous piece, and the call returns once
+// the copy is complete, so every transfer the library issues is a DMA between
+// the device and memory the runtime knows.
+bool host_pageable(const void* p);
+hipError_t copy_in(void* dst, const void* src, size_t bytes, hipStream_t st);
+hipError_t copy_out(void* dst, const void* src, size_t bytes, hipStream_t st);
+// Pinned host blocks of kStageBlockBytes, with an event each, kept until the
+// process ends: stage_take lends one (false when none can be had), stage_give
+// takes it back once nothing in flight uses it.
+constexpr size_t kStageBlockBytes = size_t{4} << 20;
+struct StageBlock {
+  char* p = nullptr;
+  hipEvent_t ev = nullptr;
+};
+bool stage_take(StageBlock* b);
+void stage_give(const StageBlock& b);
+// dst[i] = src[i] for i < n, 64-bit row offsets narrowed to the stored 32-bit
+// ones (values checked on the host beforehand) (vecops.hip).
+hipError_t launch_narrow_offsets(hipStream_t st, const int64_t* src, int32_t* dst, int64_t n);
 
 // Copy natural-order rows (s*A + a) into the stored order and write the
 // stored row offsets rp_new[0..S*A] (vecops.hip).

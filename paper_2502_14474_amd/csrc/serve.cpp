@@ -13,12 +13,14 @@
 #include <chrono>
 #include <condition_variable>
 #include <cstring>
+#include <cstdio>
 #include <deque>
 #include <limits>
 #include <map>
 #include <memory>
 #include <mutex>
 #include <shared_mutex>
+#include <string>
 #include <thread>
 #include <vector>
 
@@ -61,6 +63,22 @@ static double clock_ms() {
   return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
 }
 
+// One timed event of the server's trace: an admission (t[0] start, t[1]
+// handle created, t[2] lane width known, t[3] end; n[0] nonzeros, n[1]
+// states, n[2] lane width, n[3] bytes in use in the server's arena (without
+// one: held by the device pool) and n[4] free device bytes at the start), a
+// round (t[0] start, t[1] sweep phase done,
+// t[3] end; n[0] MDPs advanced, n[1] of them swept, n[2] finished) or a
+// retirement (t[0] start, t[1] results on the host, t[3] end).  Times are
+// milliseconds since the server's creation.
+struct TraceEvent {
+  char kind = 0;  // 'a', 'r' or 'x'
+  int lane = 0;
+  int64_t id = 0;
+  double t[4] = {0, 0, 0, 0};
+  int64_t n[5] = {0, 0, 0, 0, 0};
+};
+
 // Device bytes a request will hold while resident (CSR, costs, vectors,
 // GMRES basis, reduced-precision copies, partials).
 static int64_t footprint_of(int64_t S, int32_t A, int64_t nnz, const mdp_solve_opts& o) {
@@ -89,6 +107,7 @@ struct ServerLane {
   std::vector<mdp::Request*> resident;  // advanced by the rounds
   std::thread thread;
   int64_t rounds = 0;
+  int index = 0;
 };
 
 struct mdp_server {
@@ -108,6 +127,17 @@ struct mdp_server {
   double t0 = 0;
   std::vector<std::thread> admitters, reapers;
   int reapers_left = 0;
+  mdp::DeviceArena* arena = nullptr;  // where admitted MDPs live (nullptr: the device pool)
+  bool tracing = false;
+  std::string trace_path;
+  std::mutex trace_mu;
+  std::vector<mdp::TraceEvent> trace;
+  double now() const { return mdp::clock_ms() - t0; }
+  void record(const mdp::TraceEvent& e) {
+    std::lock_guard<std::mutex> g(trace_mu);
+    trace.push_back(e);
+  }
+  void write_trace();
 
   void admit_loop();
   void work_loop(ServerLane* ln);
@@ -130,6 +160,7 @@ using namespace mdp;
 // is held at all.
 void mdp_server::admit_loop() {
   (void)hipSetDevice(device);
+  ArenaScope in_arena(arena);
   std::unique_lock<std::mutex> lk(mu);
   // The queue is served in order, except that while the request at its head
   // does not fit the budget, later requests that fit may pass it, at most
@@ -187,6 +218,14 @@ void mdp_server::work_loop(ServerLane* ln) {
     // one round over this worker's resident set
     ln->eng.items.clear();
     for (Request* r : ln->resident) ln->eng.items.push_back(&r->item);
+    TraceEvent ev;
+    if (tracing) {
+      ev.kind = 'r';
+      ev.lane = ln->index;
+      ev.id = ln->rounds;
+      ev.n[0] = static_cast<int64_t>(ln->resident.size());
+      ev.t[0] = now();
+    }
     lk.unlock();
     const mdp_status st = ln->eng.round(opts.solve);
     lk.lock();
@@ -205,6 +244,13 @@ void mdp_server::work_loop(ServerLane* ln) {
     for (Request* r : ln->resident) {
       if (r->item.state == BatchItem::kDone) retiring.push_back(r);
       else keep.push_back(r);
+    }
+    if (tracing) {
+      ev.t[1] = ln->eng.last_sweep_end_ms - t0;
+      ev.t[3] = now();
+      ev.n[1] = ln->eng.last_swept;
+      ev.n[2] = static_cast<int64_t>(ln->resident.size() - keep.size());
+      record(ev);
     }
     ln->resident.swap(keep);
     cv_reap.notify_all();
@@ -236,6 +282,23 @@ void mdp_server::reap_loop() {
 }
 
 mdp_status mdp_server::admit_one(Request* r) {
+  TraceEvent ev;
+  ev.kind = 'a';
+  ev.lane = r->lane;
+  ev.id = r->id;
+  ev.t[0] = now();
+  if (tracing) {
+    hipMemPool_t pool = nullptr;
+    uint64_t held = 0;
+    size_t fr = 0, tot = 0;
+    if (arena)
+      ev.n[3] = static_cast<int64_t>(arena->in_use());
+    else if (device_pool(device, &pool) == hipSuccess &&
+             hipMemPoolGetAttribute(pool, hipMemPoolAttrReservedMemCurrent, &held) == hipSuccess)
+      ev.n[3] = static_cast<int64_t>(held);
+    if (hipMemGetInfo(&fr, &tot) == hipSuccess) ev.n[4] = static_cast<int64_t>(fr);
+    (void)hipGetLastError();
+  }
   mdp_create_opts co;
   mdp_default_create_opts(&co);
   co.stream = nullptr;  // the handle's own stream: admission overlaps the rounds
@@ -250,6 +313,9 @@ mdp_status mdp_server::admit_one(Request* r) {
   const double* cs = r->borrowed ? r->b_cost : r->cost.data();
   MDP_TRY(mdp_create(r->S, r->A, rp, cl, vl, cs, r->gamma, &co, &h));
   r->h = h;
+  ev.t[1] = now();
+  ev.n[0] = h->nnz;
+  ev.n[1] = h->S;
   // a class seen for the first time: time its lane widths once, on this MDP;
   // requests of the class admitted meanwhile wait for the stored width, so
   // that every request of a class runs with the same width
@@ -267,6 +333,8 @@ mdp_status mdp_server::admit_one(Request* r) {
       if (const int L = tune_lookup(h)) h->lanes = L;
     }
   }
+  ev.t[2] = now();
+  ev.n[2] = h->lanes;
   const Prec prec = prec_of(opts.solve.precision);
   mdp_status st = ensure_basis(h, prec == kF64 ? kF64 : kF32, opts.solve.restart);
   if (st >= 0 && prec != kF64) st = ensure_lowp(h, prec);
@@ -296,19 +364,26 @@ mdp_status mdp_server::admit_one(Request* r) {
   it.prev_lowp_res = std::numeric_limits<double>::infinity();
   it.lowp_sweep = prec != kF64;
   r->st.admit_ms = clock_ms() - t0;
+  if (tracing) {
+    ev.t[3] = r->st.admit_ms;
+    record(ev);
+  }
   return MDP_OK;
 }
 
 void mdp_server::retire(Request* r) {
+  TraceEvent ev;
+  ev.kind = 'x';
+  ev.lane = r->lane;
+  ev.id = r->id;
+  ev.t[0] = now();
   mdp_handle* h = r->h;
   const BatchItem& it = r->item;
   r->v.resize(h->S);
   r->pi.resize(h->S);
   // the worker synchronised its stream before handing the request over
-  hipError_t e = hipMemcpyAsync(r->v.data(), h->v, h->S * sizeof(double), hipMemcpyDeviceToHost,
-                                h->stream);
-  if (e == hipSuccess)
-    e = hipMemcpyAsync(r->pi.data(), h->pi, h->S * sizeof(int32_t), hipMemcpyDeviceToHost, h->stream);
+  hipError_t e = copy_out(r->v.data(), h->v, h->S * sizeof(double), h->stream);
+  if (e == hipSuccess) e = copy_out(r->pi.data(), h->pi, h->S * sizeof(int32_t), h->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
   r->st.finish_ms = clock_ms() - t0;  // results are on the host
   r->status = e != hipSuccess ? MDP_E_DEVICE : it.status;
@@ -319,8 +394,26 @@ void mdp_server::retire(Request* r) {
   r->st.bellman_sweeps = it.sweeps;
   r->st.residual = it.res;
   r->st.bytes = it.bytes;
+  ev.t[1] = r->st.finish_ms;
   mdp_destroy(h);
   r->h = nullptr;
+  if (tracing) {
+    ev.t[3] = now();
+    record(ev);
+  }
+}
+
+void mdp_server::write_trace() {
+  FILE* f = std::fopen(trace_path.c_str(), "w");
+  if (!f) return;
+  for (const TraceEvent& e : trace)
+    std::fprintf(f,
+                 "{\"kind\": \"%c\", \"lane\": %d, \"id\": %lld, \"t\": [%.3f, %.3f, %.3f, %.3f], "
+                 "\"n\": [%lld, %lld, %lld, %lld, %lld]}\n",
+                 e.kind, e.lane, static_cast<long long>(e.id), e.t[0], e.t[1], e.t[2], e.t[3],
+                 static_cast<long long>(e.n[0]), static_cast<long long>(e.n[1]), static_cast<long long>(e.n[2]),
+                 static_cast<long long>(e.n[3]), static_cast<long long>(e.n[4]));
+  std::fclose(f);
 }
 
 extern "C" {
@@ -365,6 +458,11 @@ mdp_status mdp_server_create(const mdp_server_opts* opt, mdp_server_t* out) {
     return fail(MDP_E_INVAL, "bad tolerances");
   auto* s = new mdp_server();
   s->opts = o;
+  s->opts.trace_path = nullptr;  // the caller's string is copied, not kept
+  if (o.trace_path) {
+    s->tracing = true;
+    s->trace_path = o.trace_path;
+  }
   if (o.device >= 0) {
     if (hipSetDevice(o.device) != hipSuccess) {
       delete s;
@@ -381,6 +479,7 @@ mdp_status mdp_server_create(const mdp_server_opts* opt, mdp_server_t* out) {
   mdp_status st = MDP_OK;
   for (int w = 0; w < nlanes && st >= 0; ++w) {
     auto ln = std::make_unique<ServerLane>();
+    ln->index = w;
     if (w == 0 && o.stream) {
       ln->stream = static_cast<hipStream_t>(o.stream);
     } else {
@@ -404,9 +503,20 @@ mdp_status mdp_server_create(const mdp_server_opts* opt, mdp_server_t* out) {
     st = ln->eng.reserve(o.max_batch);
     s->lanes.push_back(std::move(ln));
   }
-  // memory of retired requests stays in the device pool for later admissions
-  if (st >= 0 && pool_reserve(s->device, o.hbm_budget_bytes) != hipSuccess)
-    st = fail(MDP_E_DEVICE, "device memory pool set-up failed");
+  // the budget, and room for the staging of admissions in flight, as one
+  // device allocation that admitted MDPs are placed in: admitting and
+  // retiring then never call the HIP allocator.  Without the memory for it
+  // the server takes its handles from the device pool instead.
+  if (st >= 0) {
+    size_t fr = 0, tot = 0;
+    const size_t want = static_cast<size_t>(o.hbm_budget_bytes) + static_cast<size_t>(o.hbm_budget_bytes) / 4;
+    if (hipMemGetInfo(&fr, &tot) == hipSuccess) {
+      const size_t margin = size_t{4} << 30;
+      const size_t can = fr > margin ? fr - margin : 0;
+      s->arena = DeviceArena::create(s->device, std::min(want, can));
+    }
+    (void)hipGetLastError();
+  }
   if (st < 0) {
     for (auto& ln : s->lanes) {
       ln->eng.release();
@@ -572,7 +682,8 @@ mdp_status mdp_server_destroy(mdp_server_t s) {
       (void)hipStreamDestroy(ln->stream);
     }
   }
-  (void)pool_reserve(s->device, -s->opts.hbm_budget_bytes);
+  delete s->arena;
+  if (s->tracing) s->write_trace();
   delete s;
   return MDP_OK;
 }

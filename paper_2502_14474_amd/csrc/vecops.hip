@@ -138,7 +138,21 @@ __global__ __launch_bounds__(kBlock) void k_validate(int64_t S, int64_t rows, co
   }
 }
 
+__global__ __launch_bounds__(kBlock) void k_narrow_offsets(const int64_t* __restrict__ src,
+                                                           int32_t* __restrict__ dst, int64_t n) {
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * kBlock)
+    dst[i] = static_cast<int32_t>(src[i]);
+}
+
 }  // namespace
+
+hipError_t launch_narrow_offsets(hipStream_t st, const int64_t* src, int32_t* dst, int64_t n) {
+  if (n <= 0) return hipSuccess;
+  const int64_t g = std::min<int64_t>(8192, (n + kBlock - 1) / kBlock);
+  k_narrow_offsets<<<static_cast<unsigned>(g), kBlock, 0, st>>>(src, dst, n);
+  return hipGetLastError();
+}
 
 hipError_t launch_permute_rows(hipStream_t st, int64_t S, int A, const int32_t* rp_old,
                                const int32_t* col_old, const double* val_old,

@@ -64,7 +64,8 @@ class ServerOpts(C.Structure):
     _fields_ = [("struct_size", C.c_size_t), ("stream", C.c_void_p),
                 ("hbm_budget_bytes", C.c_int64), ("device", C.c_int32), ("max_batch", C.c_int32),
                 ("admit_threads", C.c_int32), ("retire_threads", C.c_int32),
-                ("solve", SolveOpts), ("autotune", C.c_int32), ("split_nnz", C.c_int64)]
+                ("solve", SolveOpts), ("autotune", C.c_int32), ("split_nnz", C.c_int64),
+                ("trace_path", C.c_char_p)]
 
 
 class RequestStats(C.Structure):
