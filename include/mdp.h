@@ -137,6 +137,12 @@ typedef struct {
                              second correction (mdp_stats.orth_loss), the loss of orthogonality
                              a single pass would have left.  2 is MDP_E_NOTSUP with the other
                              inner solvers, batched solves and the server. */
+  int32_t xcd_products;   /* float64 GMRES on a handle with a column-blocked copy (see
+                             mdp_create_opts.col_blocks): -1 (default) runs the Arnoldi products
+                             on a copy of P_pi cut into column slices, one slice per XCD, formed
+                             once per policy (about S * 8 + nnz(P_pi) * 12 bytes more device
+                             memory); 0 runs them on the CSR rows.  The two differ only in the
+                             rounding of each row's sum. */
 } mdp_eval_opts;
 
 typedef struct {
@@ -162,6 +168,7 @@ typedef struct {
                              preconditioning, to the caller: "Problem Setting and Solution
                              Methods") */
   int32_t gs_passes;      /* as in mdp_eval_opts */
+  int32_t xcd_products;   /* as in mdp_eval_opts (batched solves and the server ignore it) */
 } mdp_solve_opts;
 
 enum { MDP_LAUNCH_AUTO = 0, MDP_LAUNCH_GRAPHS = 1, MDP_LAUNCH_DIRECT = 2 };

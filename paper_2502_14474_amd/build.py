@@ -13,7 +13,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmdp.so")
 OBJDIR = os.path.join(ROOT, "_build")
 SOURCES = ["kernels.hip", "colblock.hip", "krylov.hip", "vecops.hip", "batch.hip", "api.cpp", "serve.cpp",
-           "tune.cpp", "noalloc.hip", "devrows.hip", "arena.cpp"]
+           "tune.cpp", "noalloc.hip", "devrows.hip", "arena.cpp", "xcdprod.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

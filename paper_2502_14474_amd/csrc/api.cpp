@@ -418,6 +418,7 @@ namespace {
 // Copy a caller policy to device memory and check its range.
 mdp_status load_policy(mdp_handle* h, const int32_t* policy, int32_t* dst) {
   if (!policy) return fail(MDP_E_INVAL, "policy is NULL");
+  ++h->pi_gen;  // a policy is written
   if (!is_device_ptr(policy)) {
     for (int64_t s = 0; s < h->S; ++s)
       if (policy[s] < 0 || policy[s] >= h->A)
@@ -471,9 +472,16 @@ struct InnerResult {
 // float64 P, so the mixed-precision variants are iterative refinement.
 mdp_status gmres_inner(mdp_handle* h, Prec prec, const int32_t* pi, double* x, int m,
                        int64_t max_iter, int sync_every, double alpha, InnerResult* out, int deg = 1,
-                       bool gs2 = false) {
+                       bool gs2 = false, int xcd_products = -1) {
   const Prec bprec = prec == kF64 ? kF64 : kF32;
   const int bb = bprec == kF64 ? 8 : 4;
+  // float64 products on a handle with a column-blocked copy: the
+  // XCD-partitioned copy of P_pi for this policy (formed here, once)
+  struct PPGuard {
+    mdp_handle* h;
+    ~PPGuard() { h->pp_ready = false; }
+  } pp_guard{h};
+  if (prec == kF64 && xcd_products != 0 && h->cb_blocks > 0) MDP_HIP(pp_prepare(h, pi));
   for (;;) {
     int j = 0;
     const size_t rec0 = h->prof_pending.size();
@@ -883,6 +891,7 @@ void mdp_default_eval_opts(mdp_eval_opts* o) {
   o->max_iter = 10000;
   o->precond_degree = 1;
   o->gs_passes = 1;
+  o->xcd_products = -1;
 }
 
 void mdp_default_solve_opts(mdp_solve_opts* o) {
@@ -901,6 +910,7 @@ void mdp_default_solve_opts(mdp_solve_opts* o) {
   o->launch = MDP_LAUNCH_AUTO;
   o->precond_degree = 1;
   o->gs_passes = 1;
+  o->xcd_products = -1;
 }
 
 mdp_status mdp_destroy(mdp_t h) {
@@ -941,6 +951,14 @@ mdp_status mdp_destroy(mdp_t h) {
   dev_free(h, h->U32);
   dev_free(h, h->part.buf);
   dev_free(h, h->ctl);
+  dev_free(h, h->pp_col);
+  dev_free(h, h->pp_val);
+  dev_free(h, h->pp_rel);
+  dev_free(h, h->pp_tsum);
+  dev_free(h, h->pp_off);
+  dev_free(h, h->pp_part);
+  dev_free(h, h->pp_stat);
+  dev_free(h, h->pp_tmp);
   ctl_slot_give(h->ctl_host);
   prof_resolve(h);
   {
@@ -1400,7 +1418,8 @@ mdp_status mdp_policy_eval(mdp_t h, const int32_t* policy, const double* v0, dou
     MDP_HIP(launch_apply(h, kApplyRes, h->pi, h->v, slot0, prec != kF64, kRedGmresStart, 1, o.rtol,
                          floor_of(prec)));
     ir.applies += 1;
-    MDP_TRY(gmres_inner(h, prec, h->pi, h->v, o.restart, o.max_iter, sync_every, o.rtol, &ir, deg, gs2));
+    MDP_TRY(gmres_inner(h, prec, h->pi, h->v, o.restart, o.max_iter, sync_every, o.rtol, &ir, deg, gs2,
+                        o.xcd_products));
     MDP_TRY(sync_ctl(h));
     rel = h->ctl_host->beta0 > 0 ? h->ctl_host->res_est / h->ctl_host->beta0 : 0.0;
     if (ir.converged && prec != kF64)
@@ -1526,7 +1545,8 @@ mdp_status mdp_solve(mdp_t h, const double* v0, double* v, int32_t* policy,
     prev_res = res;
     InnerResult ir;
     if (gm) {
-      MDP_TRY(gmres_inner(h, iprec, h->pi, h->v, o.restart, o.max_inner, sync_every, alpha, &ir, deg, gs2));
+      MDP_TRY(gmres_inner(h, iprec, h->pi, h->v, o.restart, o.max_inner, sync_every, alpha, &ir, deg, gs2,
+                          o.xcd_products));
     } else if (bi) {
       MDP_TRY(bicgstab_inner(h, h->pi, h->v, o.max_inner, sync_every, &ir, o.inner == MDP_INNER_TFQMR));
     } else {

@@ -424,6 +424,7 @@ hipError_t BatchEngine::enqueue_steps(const std::vector<int>& cls_lanes, int j0,
 
 mdp_status BatchEngine::sweep_phase(const mdp_solve_opts& o, std::vector<int>& need) {
   // items needing a sweep, grouped by (lanes, sweep precision)
+  for (int i : need) ++items[i]->h->pi_gen;  // their policies are written
   while (!need.empty()) {
     for (int i : need) fill_desc(i);  // tile counts come from the descriptors
     std::map<std::pair<int, int>, std::vector<int>> groups;

@@ -22,6 +22,8 @@
 // (through LDS).  A row's sum is the sum of its slice parts in slice order,
 // each part an fma chain in CSR order, so the result is deterministic and
 // identical rows give identical sums.
+#include <cstdlib>
+
 #include "device.h"
 
 namespace mdp {
@@ -137,18 +139,17 @@ __global__ __launch_bounds__(kBlock) void k_cb_scatter(int64_t rows, int tile_ro
 #endif
 constexpr int kCbChunk = MDP_CB_CHUNK;
 
-template <bool FIRST, bool LAST, typename RT>
-__global__ __launch_bounds__(kBlock) void k_bellman_cb(
-    int64_t S, int A, int tile_states, int ntiles, int b, const uint16_t* __restrict__ rel,
-    const int* __restrict__ off, const int* __restrict__ cb_col, const double* __restrict__ cb_val,
-    const double* __restrict__ cost, const double* __restrict__ v, double gamma,
-    double* __restrict__ acc, double* __restrict__ Tv, int* __restrict__ pi, RT* __restrict__ r0,
-    double4* __restrict__ partials) {
-  extern __shared__ double q[];  // LAST: one value per row of the tile
-  __shared__ double lp[kCbChunk], lx[kCbChunk];
-  constexpr int RPT = 4;  // rows per thread: tiles hold at most 4 * kBlock rows
+constexpr int kCbRpt = 4;  // rows per thread: tiles hold at most 4 * kBlock rows
+
+// The slice-b parts of the rows of one tile: part[k] for row threadIdx.x + k *
+// kBlock (0 for rows past the tile), each the fma chain over the row's entries
+// in slice b in CSR order, started from 0.
+__device__ __forceinline__ void cb_tile_parts(int64_t S, int A, int tile_states, int ntiles, int b, int tile,
+                                              const uint16_t* __restrict__ rel, const int* __restrict__ off,
+                                              const int* __restrict__ cb_col, const double* __restrict__ cb_val,
+                                              const double* __restrict__ v, double* lp, double* lx,
+                                              double (&sum)[kCbRpt]) {
   constexpr int EPT = kCbChunk / kBlock;
-  const int tile = xcd_tile(blockIdx.x, gridDim.x);
   const int64_t rows = S * A;
   const int64_t s0 = static_cast<int64_t>(tile) * tile_states;
   const int ns = static_cast<int>(min<int64_t>(tile_states, S - s0));
@@ -161,17 +162,15 @@ __global__ __launch_bounds__(kBlock) void k_bellman_cb(
   const int* __restrict__ cc = cb_col + base;
   const double* __restrict__ cv = cb_val + base;
   const Gather<double> gx(v, S);
-  int st[RPT], en[RPT];
-  double prev[RPT], sum[RPT];
+  int st[kCbRpt], en[kCbRpt];
 #pragma unroll
-  for (int k = 0; k < RPT; ++k) {
+  for (int k = 0; k < kCbRpt; ++k) {
     const int i = threadIdx.x + k * kBlock;
     const bool valid = i < nrows;
     const int a = rl[valid ? i : 0];
     const int z = rl[i + 1 < nrows ? i + 1 : 0];
     st[k] = valid ? a : 0;
     en[k] = valid ? (i + 1 < nrows ? z : n) : 0;
-    prev[k] = FIRST ? 0.0 : acc[row0 + (valid ? i : 0)];
     sum[k] = 0.0;
   }
   int c[EPT];
@@ -206,7 +205,7 @@ __global__ __launch_bounds__(kBlock) void k_bellman_cb(
     __syncthreads();
     const int c1 = c0 + kCbChunk;
 #pragma unroll
-    for (int k = 0; k < RPT; ++k) {
+    for (int k = 0; k < kCbRpt; ++k) {
       const int lo = st[k] > c0 ? st[k] : c0;
       const int hi = en[k] < c1 ? en[k] : c1;
       double sk = sum[k];
@@ -215,8 +214,32 @@ __global__ __launch_bounds__(kBlock) void k_bellman_cb(
     }
     __syncthreads();
   }
+}
+
+template <bool FIRST, bool LAST, typename RT>
+__global__ __launch_bounds__(kBlock) void k_bellman_cb(
+    int64_t S, int A, int tile_states, int ntiles, int b, const uint16_t* __restrict__ rel,
+    const int* __restrict__ off, const int* __restrict__ cb_col, const double* __restrict__ cb_val,
+    const double* __restrict__ cost, const double* __restrict__ v, double gamma,
+    double* __restrict__ acc, double* __restrict__ Tv, int* __restrict__ pi, RT* __restrict__ r0,
+    double4* __restrict__ partials) {
+  extern __shared__ double q[];  // LAST: one value per row of the tile
+  __shared__ double lp[kCbChunk], lx[kCbChunk];
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  const int64_t s0 = static_cast<int64_t>(tile) * tile_states;
+  const int ns = static_cast<int>(min<int64_t>(tile_states, S - s0));
+  const int nrows = ns * A;
+  const int64_t row0 = s0 * A;
+  double prev[kCbRpt];
 #pragma unroll
-  for (int k = 0; k < RPT; ++k) {
+  for (int k = 0; k < kCbRpt; ++k) {
+    const int i = threadIdx.x + k * kBlock;
+    prev[k] = FIRST ? 0.0 : acc[row0 + (i < nrows ? i : 0)];
+  }
+  double sum[kCbRpt];
+  cb_tile_parts(S, A, tile_states, ntiles, b, tile, rel, off, cb_col, cb_val, v, lp, lx, sum);
+#pragma unroll
+  for (int k = 0; k < kCbRpt; ++k) {
     const int i = threadIdx.x + k * kBlock;
     if (i >= nrows) continue;
     const double total = FIRST ? sum[k] : prev[k] + sum[k];
@@ -232,12 +255,70 @@ __global__ __launch_bounds__(kBlock) void k_bellman_cb(
   }
 }
 
+// All slices of a pass in one launch: workgroup w takes slice pass * 8 + w % 8
+// of tile w / 8, so XCD w % 8 (the dispatcher's choice for workgroup w) keeps
+// only its own slice of v in its L2.  The rows' slice parts go to
+// acc[b * rows + row]; k_bellman_cb_sum then adds them.
+__global__ __launch_bounds__(kBlock) void k_bellman_cb_xcd(
+    int64_t S, int A, int tile_states, int ntiles, int nblk, int pass, const uint16_t* __restrict__ rel,
+    const int* __restrict__ off, const int* __restrict__ cb_col, const double* __restrict__ cb_val,
+    const double* __restrict__ v, double* __restrict__ acc) {
+  __shared__ double lp[kCbChunk], lx[kCbChunk];
+  const int b = pass * kNumXcd + static_cast<int>(blockIdx.x % kNumXcd);
+  const int tile = static_cast<int>(blockIdx.x / kNumXcd);
+  if (b >= nblk || tile >= ntiles) return;  // the same for the whole workgroup
+  const int64_t rows = S * A;
+  const int64_t s0 = static_cast<int64_t>(tile) * tile_states;
+  const int nrows = static_cast<int>(min<int64_t>(tile_states, S - s0)) * A;
+  double sum[kCbRpt];
+  cb_tile_parts(S, A, tile_states, ntiles, b, tile, rel, off, cb_col, cb_val, v, lp, lx, sum);
+  double* __restrict__ out = acc + static_cast<int64_t>(b) * rows + s0 * A;
+#pragma unroll
+  for (int k = 0; k < kCbRpt; ++k) {
+    const int i = threadIdx.x + k * kBlock;
+    if (i < nrows) out[i] = sum[k];
+  }
+}
+
+// A row's sum is its slice parts added in slice order (as the sequential
+// passes carry it), then Q = g + gamma * sum, and the tile is finished like
+// the plain sweep.
+template <typename RT>
+__global__ __launch_bounds__(kBlock) void k_bellman_cb_sum(
+    int64_t S, int A, int tile_states, int nblk, const double* __restrict__ acc, const double* __restrict__ cost,
+    const double* __restrict__ v, double gamma, double* __restrict__ Tv, int* __restrict__ pi,
+    RT* __restrict__ r0, double4* __restrict__ partials) {
+  extern __shared__ double q[];
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  const int64_t rows = S * A;
+  const int64_t s0 = static_cast<int64_t>(tile) * tile_states;
+  const int ns = static_cast<int>(min<int64_t>(tile_states, S - s0));
+  const int nrows = ns * A;
+  const int64_t row0 = s0 * A;
+  for (int i = threadIdx.x; i < nrows; i += kBlock) {
+    double total = acc[row0 + i];
+    for (int b = 1; b < nblk; ++b) total = total + acc[static_cast<int64_t>(b) * rows + row0 + i];
+    q[(i % ns) * A + i / ns] = fma(gamma, total, cost[row0 + i]);
+  }
+  __syncthreads();
+  sweep_finish<double, double, RT>(s0, ns, A, q, v, Tv, pi, r0, partials, tile);
+}
+
 template <typename RT>
 hipError_t cb_passes(mdp_handle* h, const double* v, double* Tv, int32_t* pi, RT* r0,
                      double4* part, int nb) {
   const int ts = sweep_tile_states(h->A);
   const int nblk = h->cb_blocks;
   const size_t lds_last = static_cast<size_t>(ts) * h->A * sizeof(double);
+  if (h->cb_xcd) {
+    const int64_t grid = static_cast<int64_t>(kNumXcd) * nb;
+    for (int p = 0; p * kNumXcd < nblk; ++p)
+      k_bellman_cb_xcd<<<static_cast<unsigned>(grid), kBlock, 0, h->stream>>>(
+          h->S, h->A, ts, nb, nblk, p, h->cb_rel, h->cb_off, h->cb_col, h->cb_val, v, h->cb_acc);
+    k_bellman_cb_sum<RT><<<nb, kBlock, lds_last, h->stream>>>(h->S, h->A, ts, nblk, h->cb_acc, h->cost, v,
+                                                             h->gamma, Tv, pi, r0, part);
+    return hipGetLastError();
+  }
 #define MDP_CB_ARGS(B)                                                                     \
   h->S, h->A, ts, nb, (B), h->cb_rel, h->cb_off, h->cb_col, h->cb_val, h->cost, v, h->gamma, \
       h->cb_acc, Tv, pi, r0, part
@@ -337,7 +418,14 @@ hipError_t build_colblocks(mdp_handle* h, int blocks, bool require, bool* built,
   CB_CHK(handle_alloc(h, reinterpret_cast<void**>(&rel), cnt_bytes * sizeof(uint16_t)));
   CB_CHK(handle_alloc(h, reinterpret_cast<void**>(&cb_col), h->nnz * sizeof(int)));
   CB_CHK(handle_alloc(h, reinterpret_cast<void**>(&cb_val), h->nnz * sizeof(double)));
-  CB_CHK(handle_alloc(h, reinterpret_cast<void**>(&acc), rows * sizeof(double)));
+  // the parts of all slices side by side (one launch for all slices), or
+  // one running sum per row carried from pass to pass
+  // (MDP_CB_PARTS_MAX_BYTES in the environment replaces the limit)
+  int64_t parts_max = kCbXcdMaxBytes;
+  if (const char* env = std::getenv("MDP_CB_PARTS_MAX_BYTES")) parts_max = std::atoll(env);
+  const bool xcd = static_cast<int64_t>(blocks) * rows * static_cast<int64_t>(sizeof(double)) <= parts_max;
+  const int64_t acc_rows = xcd ? static_cast<int64_t>(blocks) * rows : rows;
+  CB_CHK(handle_alloc(h, reinterpret_cast<void**>(&acc), acc_rows * sizeof(double)));
   k_cb_scatter<<<ntiles, kBlock, 0, h->stream>>>(rows, tile_rows, ntiles, blocks, slice, h->row_ptr,
                                                  h->col, h->val, cnt, off, cb_col, cb_val, rel);
   CB_CHK(hipGetLastError());
@@ -350,8 +438,9 @@ hipError_t build_colblocks(mdp_handle* h, int blocks, bool require, bool* built,
   h->cb_col = cb_col;
   h->cb_val = cb_val;
   h->cb_acc = acc;
+  h->cb_xcd = xcd;
   h->device_bytes += static_cast<int64_t>(cnt_bytes * sizeof(uint16_t) + off_h.size() * sizeof(int) +
-                                          h->nnz * 12 + rows * 8);
+                                          h->nnz * 12 + acc_rows * 8);
   *built = true;
   return done(hipSuccess);
 }

@@ -162,7 +162,8 @@ struct mdp_handle {
   double* cb_val = nullptr;     // nnz
   uint16_t* cb_rel = nullptr;   // cb_blocks x rows: row start inside its (slice, tile) segment
   int32_t* cb_off = nullptr;    // cb_blocks x (sweep tiles + 1): first entry of (slice, tile)
-  double* cb_acc = nullptr;     // rows: row sums over the slices done so far
+  double* cb_acc = nullptr;     // cb_xcd: cb_blocks x rows slice parts; else rows: row sums so far
+  bool cb_xcd = false;          // all slices in one launch, one slice per XCD
 
   // float64 vectors
   double* v = nullptr;       // current value iterate
@@ -188,6 +189,27 @@ struct mdp_handle {
   hipEvent_t ctl_event = nullptr; // marks the header copy of a snapshot
 
   int64_t device_bytes = 0;
+
+  // XCD-partitioned copy of P_pi for the float64 Arnoldi products
+  // (xcdprod.hip): pp_state 0 not set up, 1 set up, -1 not possible here.
+  // pi_gen counts the launches that may write a policy; the copy is current
+  // for pp_pi while pp_gen == pi_gen.
+  int pp_state = 0;
+  bool pp_ready = false;  // the products of the running evaluation use the copy
+  int pp_blocks = 0, pp_slice = 0, pp_ntiles = 0;
+  int64_t pp_cap = 0;
+  int* pp_col = nullptr;
+  double* pp_val = nullptr;
+  uint16_t* pp_rel = nullptr;
+  int* pp_tsum = nullptr;
+  int* pp_off = nullptr;
+  double* pp_part = nullptr;
+  unsigned* pp_stat = nullptr;
+  void* pp_tmp = nullptr;
+  size_t pp_tmp_bytes = 0;
+  const int32_t* pp_pi = nullptr;
+  int64_t pp_gen = -1, pi_gen = 0;
+
   mdp::DeviceArena* dev_arena = nullptr;  // where its arrays come from (nullptr: the pool)
   bool destroying = false;                // its stream is idle: frees return at once
 
@@ -243,6 +265,12 @@ constexpr int kSweepRows = MDP_SWEEP_ROWS;
 // 12.0 ms, and 16 of 2 MB, 12.6 ms); built automatically from 2^21 states
 // (16 MB of v) up.
 constexpr int64_t kColSliceBytes = int64_t{11} << 18;
+// Largest buffer of slice parts (cb_blocks x rows float64) for which the
+// blocked sweep runs all slices in one launch, each XCD on its own slice,
+// instead of one pass per slice.  0: never (on the 4M-state workload the
+// one-launch sweep over 8 slices of 4 MB took 12.2 ms, the 12 passes 11.6 ms);
+// MDP_CB_PARTS_MAX_BYTES in the environment replaces it.
+constexpr int64_t kCbXcdMaxBytes = 0;
 constexpr int64_t kColBlockMinStates = int64_t{1} << 21;
 constexpr int kMaxColBlocks = 64;
 __host__ __device__ inline int sweep_tile_states(int A) { return A >= kSweepRows ? 1 : kSweepRows / A; }
@@ -308,6 +336,13 @@ struct StageBlock {
 };
 bool stage_take(StageBlock* b);
 void stage_give(const StageBlock& b);
+// XCD-partitioned P_pi products (xcdprod.hip).  pp_prepare forms the copy
+// for policy pi when it is not current and sets h->pp_ready when the float64
+// Arnoldi products can use it; launch_pp_arnoldi_apply is then the Arnoldi
+// product of step j (input U_j, or xin), with the plain product's outputs.
+hipError_t pp_prepare(mdp_handle* h, const int32_t* pi);
+hipError_t launch_pp_arnoldi_apply(mdp_handle* h, int j, const double* xin, double* partials, int nb);
+
 // dst[i] = src[i] for i < n, 64-bit row offsets narrowed to the stored 32-bit
 // ones (values checked on the host beforehand) (vecops.hip).
 hipError_t launch_narrow_offsets(hipStream_t st, const int64_t* src, int32_t* dst, int64_t n);

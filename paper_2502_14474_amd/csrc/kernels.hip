@@ -295,6 +295,7 @@ size_t partials_doubles(int64_t S, int A, int m) {
 hipError_t launch_bellman(mdp_handle* h, Prec prec, const void* v, double* Tv, int32_t* pi,
                           void* r0, bool r0_f32, int red_mode, int first_cycle, double alpha,
                           double floor_rel) {
+  ++h->pi_gen;  // a policy is written
   const int ts = sweep_tile_states(h->A);
   const int nb = grid_for(h->S, ts);
   auto* part = reinterpret_cast<double4*>(h->part.buf);
@@ -455,7 +456,11 @@ hipError_t launch_arnoldi_step(mdp_handle* h, Prec prec, const int32_t* pi, int 
     xin = precond_apply(h, prec, pi, basis_slot(h, bprec, j), m + 1, m + 2, deg, h->ctl, &e);
     if (e != hipSuccess) return e;
   }
-  {
+  if (prec == kF64 && h->pp_ready && pi == h->pp_pi) {
+    // the XCD-partitioned product on the policy's copy (same outputs)
+    Prof pf(h, MDP_K_ARNOLDI_APPLY, bytes_arnoldi_apply(h, 8, 8, j), j);
+    e = launch_pp_arnoldi_apply(h, j, static_cast<const double*>(xin), h->part.buf, nb);
+  } else {
     Prof pf(h, MDP_K_ARNOLDI_APPLY, bytes_arnoldi_apply(h, prec == kF64 ? 8 : (prec == kF32 ? 4 : 2), prec == kF64 ? 8 : 4, j) + (prec == kF16 ? h->S * 8.0 : 0.0), j);
     e = with_lanes(h->lanes, [&](auto Lc) -> hipError_t {
     constexpr int L = decltype(Lc)::value;

@@ -1,0 +1,389 @@
+// XCD-partitioned P_pi products for large vectors.
+//
+// When x spans many times one XCD's 4 MB L2 and a row's columns fall anywhere
+// in it, each gather of a plain product pulls a line from the Infinity Cache,
+// which serves about 64G gathers/s; gathers that stay inside each XCD's L2 run
+// about three times faster.  The dispatcher hands workgroup w to XCD w % 8,
+// so the product is cut by columns to match: the columns fall into 8 slices
+// (8 P slices in P passes when x is larger than 8 x 4 MB), a copy of P_pi
+// holds each slice's entries tile by tile, and workgroup w streams the
+// entries of slice (w % 8) of tile w / 8, so each XCD's L2 only ever holds its
+// own slice of x.  Every workgroup writes its slice's part of (P_pi x)[s] for
+// the tile's states; a second kernel adds the parts in slice order and
+// finishes the Arnoldi step exactly as the plain product kernel does (new
+// basis vector and the classical Gram-Schmidt dot partials).
+//
+// The copy is formed once per policy: a count kernel (entries of each tile in
+// each slice), a device scan of those counts into segment offsets, and a
+// scatter kernel that walks each selected row once, in CSR order, so inside a
+// slice a state's entries keep their CSR order.  A state's part in a slice is
+// the fma chain over its entries there, started from 0, and the parts are
+// added in slice order: results are deterministic.
+#include <hipcub/hipcub.hpp>
+
+#include <algorithm>
+
+#include "device.h"
+
+namespace mdp {
+
+namespace {
+
+constexpr int kPPTile = 4 * kBlock;                    // states per tile (4 per thread)
+constexpr int kPPMaxBlocks = 16;                       // slices (two passes)
+constexpr int64_t kPPSliceBytes = int64_t{4} << 20;   // x bytes per slice: one XCD's L2
+#ifndef MDP_PP_CHUNK
+#define MDP_PP_CHUNK 1024
+#endif
+constexpr int kPPChunk = MDP_PP_CHUNK;                 // entries staged per step
+static_assert(kPPChunk % kBlock == 0, "chunk of whole rounds");
+
+__device__ __forceinline__ void selected_row(int64_t s, const int* __restrict__ pi, int A, int64_t S, RowIndex rix,
+                                             int* a, int* e) {
+  const int64_t r = row_of(s, pi[s], A, S);
+  if (rix.kfix > 0) {
+    *a = static_cast<int>(r * rix.kfix);
+    *e = *a + rix.kfix;
+  } else {
+    *a = rix.row_ptr[r];
+    *e = rix.row_ptr[r + 1];
+  }
+}
+
+// A tile's selected rows are read two at a time per wavefront: each half of
+// the wavefront (32 lanes) takes one state and reads its row 32 entries at a
+// time (coalesced); ballots over the lanes' slice numbers give the per-slice
+// counts, and lane b of a half keeps the count of slice b.  The loop bounds
+// are uniform over the wavefront (both halves run as many chunks as the
+// longer row), so every ballot sees all 64 lanes.  The next pair's row bounds
+// are loaded before the current pair is worked on.
+constexpr int kPPWaves = kBlock / kWave;
+
+__device__ __forceinline__ uint32_t half_ballot(bool p, int half) {
+  return static_cast<uint32_t>(__ballot(p) >> (32 * half));
+}
+
+// Walk the tile's selected rows in pairs: body(i, a, n) for this half's state
+// i (a = first entry, n = entries; n = 0 past the tile).
+template <typename Body>
+__device__ __forceinline__ void walk_pairs(int64_t S, int A, RowIndex rix, const int* __restrict__ pi, int64_t s0,
+                                           int ns, Body body) {
+  const int half = (threadIdx.x % kWave) / 32, wave = threadIdx.x / kWave;
+  int i = 2 * wave + half;
+  int a = 0, e = 0;
+  if (i < ns) selected_row(s0 + i, pi, A, S, rix, &a, &e);
+  for (int i0 = 2 * wave; i0 < ns; i0 += 2 * kPPWaves) {
+    const int ia = a, na = e - a, ic = i;
+    i += 2 * kPPWaves;
+    a = e = 0;
+    if (i < ns) selected_row(s0 + i, pi, A, S, rix, &a, &e);
+    body(ic, ia, na);
+  }
+}
+
+// Per tile t: rel[b * S + s] = start of state s's entries inside the tile's
+// segment of slice b (exclusive scan of the per-state counts), tsum[b *
+// ntiles + t] = the segment's length; stat[0] = longest segment, stat[1] =
+// longest selected row.  rel is meaningful only when both fit (segments
+// shorter than 65536, rows shorter than 256; checked on the host).
+__global__ __launch_bounds__(kBlock) void k_pp_count(int64_t S, int A, RowIndex rix, const int* __restrict__ col,
+                                                     const int* __restrict__ pi, int slice, int nblk, int ntiles,
+                                                     int* __restrict__ tsum, uint16_t* __restrict__ rel,
+                                                     unsigned* __restrict__ stat) {
+  __shared__ uint8_t c8[kPPMaxBlocks][kPPTile];
+  __shared__ int pos[kPPTile + 1];
+  const int t = blockIdx.x;
+  const int64_t s0 = static_cast<int64_t>(t) * kPPTile;
+  const int ns = static_cast<int>(min<int64_t>(kPPTile, S - s0));
+  const int hl = threadIdx.x % 32, half = (threadIdx.x % kWave) / 32;
+  int longest = 0;
+  walk_pairs(S, A, rix, pi, s0, ns, [&](int i, int a, int n) {
+    longest = max(longest, n);
+    const int nmax = max(n, __shfl_xor(n, 32));
+    int cnt = 0;  // lane hl < nblk: entries of slice hl
+    for (int c0 = 0; c0 < nmax; c0 += 32) {
+      const int b = c0 + hl < n ? col[a + c0 + hl] / slice : -1;
+      for (int bb = 0; bb < nblk; ++bb) {
+        const uint32_t m = half_ballot(b == bb, half);
+        if (hl == bb) cnt += __popc(m);
+      }
+    }
+    if (i < ns && hl < nblk) c8[hl][i] = static_cast<uint8_t>(min(cnt, 255));
+  });
+  double mx = static_cast<double>(longest), sm = 0.0;
+  block_max_sum(mx, sm);  // its barrier also publishes c8
+  if (threadIdx.x == 0) atomicMax(stat + 1, static_cast<unsigned>(mx));
+  for (int b = 0; b < nblk; ++b) {
+    for (int i = threadIdx.x; i < ns; i += kBlock) pos[i] = c8[b][i];
+    __syncthreads();
+    block_exclusive_scan(pos, ns);
+    for (int i = threadIdx.x; i < ns; i += kBlock)
+      rel[static_cast<int64_t>(b) * S + s0 + i] = static_cast<uint16_t>(pos[i]);
+    if (threadIdx.x == 0) {
+      tsum[static_cast<int64_t>(b) * ntiles + t] = pos[ns];
+      atomicMax(stat, static_cast<unsigned>(pos[ns]));
+    }
+    __syncthreads();
+  }
+}
+
+// Scatter the selected rows of tile t into their slice segments.  An entry's
+// place is its segment's start, its state's start there (rel), the entries of
+// its state and slice in earlier chunks of the row, and those before it in
+// its chunk (from the ballot), so each state keeps its CSR order inside every
+// slice.
+__global__ __launch_bounds__(kBlock) void k_pp_scatter(int64_t S, int A, RowIndex rix, const int* __restrict__ col,
+                                                       const double* __restrict__ val, const int* __restrict__ pi,
+                                                       int slice, int nblk, int ntiles, const int* __restrict__ off,
+                                                       const uint16_t* __restrict__ rel, int* __restrict__ pcol,
+                                                       double* __restrict__ pval) {
+  __shared__ int base[kPPMaxBlocks];
+  const int t = blockIdx.x;
+  const int64_t s0 = static_cast<int64_t>(t) * kPPTile;
+  const int ns = static_cast<int>(min<int64_t>(kPPTile, S - s0));
+  const int hl = threadIdx.x % 32, half = (threadIdx.x % kWave) / 32;
+  if (threadIdx.x < nblk) base[threadIdx.x] = off[static_cast<int64_t>(threadIdx.x) * ntiles + t];
+  __syncthreads();
+  walk_pairs(S, A, rix, pi, s0, ns, [&](int i, int a, int n) {
+    const int nmax = max(n, __shfl_xor(n, 32));
+    // lane hl < nblk: the state's first place in slice hl, advanced by the
+    // entries of slice hl placed so far
+    int next = (i < ns && hl < nblk) ? base[hl] + rel[static_cast<int64_t>(hl) * S + s0 + i] : 0;
+    for (int c0 = 0; c0 < nmax; c0 += 32) {
+      const bool valid = c0 + hl < n;
+      const int q = a + c0 + hl;
+      const int c = valid ? col[q] : 0;
+      const double v = valid ? val[q] : 0.0;
+      const int b = valid ? c / slice : -1;
+      uint32_t same = 0;
+      int add = 0;
+      for (int bb = 0; bb < nblk; ++bb) {
+        const uint32_t m = half_ballot(b == bb, half);
+        if (b == bb) same = m;
+        if (hl == bb) add = __popc(m);
+      }
+      const int first = __shfl(next, (threadIdx.x % kWave) - hl + (b < 0 ? 0 : b));
+      if (valid) {
+        const int d = first + __popc(same & ((1u << hl) - 1u));
+        pcol[d] = c;
+        pval[d] = v;
+      }
+      next += add;
+    }
+  });
+}
+
+// Slice parts of P_pi x: workgroup w takes slice pass * 8 + w % 8 of tile w / 8
+// and writes part[b * S + s] for the tile's states.  The segment is streamed in
+// chunks of kPPChunk entries: every thread loads every kBlock-th entry
+// (coalesced), gathers x from the XCD's slice and leaves the (value, x) pair in
+// LDS, with the next chunk's loads issued first; then each thread carries its
+// states (at most 4) through the chunk.  Exits at once when the GMRES cycle is
+// done.
+template <typename XT>
+__global__ __launch_bounds__(kBlock) void k_pp_product(int64_t S, int nblk, int ntiles, int pass,
+                                                       const uint16_t* __restrict__ rel, const int* __restrict__ off,
+                                                       const int* __restrict__ pcol, const double* __restrict__ pval,
+                                                       const XT* __restrict__ x, double* __restrict__ part,
+                                                       const Ctl* __restrict__ ctl) {
+  if (ctl->done) return;
+  __shared__ double lp[kPPChunk], lx[kPPChunk];
+  constexpr int EPT = kPPChunk / kBlock;
+  const int b = pass * kNumXcd + static_cast<int>(blockIdx.x % kNumXcd);
+  const int t = static_cast<int>(blockIdx.x / kNumXcd);
+  if (b >= nblk || t >= ntiles) return;  // the same for the whole workgroup
+  const int64_t s0 = static_cast<int64_t>(t) * kPPTile;
+  const int ns = static_cast<int>(min<int64_t>(kPPTile, S - s0));
+  const int64_t ob = static_cast<int64_t>(b) * ntiles + t;
+  const int seg0 = off[ob];
+  const int n = off[ob + 1] - seg0;
+  const uint16_t* __restrict__ rl = rel + static_cast<int64_t>(b) * S + s0;
+  const int* __restrict__ cc = pcol + seg0;
+  const double* __restrict__ cv = pval + seg0;
+  const Gather<XT> gx(x, S);
+  int st[4], en[4];
+  double sum[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int i = threadIdx.x + k * kBlock;
+    const bool valid = i < ns;
+    const int a = rl[valid ? i : 0];
+    const int z = rl[i + 1 < ns ? i + 1 : 0];
+    st[k] = valid ? a : 0;
+    en[k] = valid ? (i + 1 < ns ? z : n) : 0;
+    sum[k] = 0.0;
+  }
+  int c[EPT];
+  double p[EPT];
+  auto fetch = [&](int c0) {
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {
+      const int idx = c0 + threadIdx.x + e * kBlock;
+      const bool ok = idx < n;
+      const int craw = ld_col(cc + (ok ? idx : 0));
+      const double praw = ld_val(cv + (ok ? idx : 0));
+      c[e] = ok ? craw : -1;
+      p[e] = ok ? praw : 0.0;
+    }
+  };
+  if (n > 0) fetch(0);
+  for (int c0 = 0; c0 < n; c0 += kPPChunk) {
+    double xv[EPT], pc[EPT];
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {
+      xv[e] = static_cast<double>(gx(c[e]));  // 0 past the segment (c = -1)
+      pc[e] = p[e];
+    }
+    fetch(c0 + kPPChunk < n ? c0 + kPPChunk : c0);
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {
+      lp[threadIdx.x + e * kBlock] = pc[e];
+      lx[threadIdx.x + e * kBlock] = xv[e];
+    }
+    __syncthreads();
+    const int c1 = c0 + kPPChunk;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int lo = st[k] > c0 ? st[k] : c0;
+      const int hi = en[k] < c1 ? en[k] : c1;
+      double sk = sum[k];
+      for (int j = lo; j < hi; ++j) sk = fma(lp[j - c0], lx[j - c0], sk);
+      sum[k] = sk;
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int i = threadIdx.x + k * kBlock;
+    if (i < ns) part[static_cast<int64_t>(b) * S + s0 + i] = sum[k];
+  }
+}
+
+// The rest of the Arnoldi step on the parts: (P_pi x)[s] is the sum of the
+// slice parts in slice order, w = scale_j (x - gamma P_pi x) goes to U_{j+1},
+// and the workgroup's dot partials with U_0..U_j go to partials, in the
+// plain product's tiles and layout.
+template <typename BT>
+__global__ __launch_bounds__(kBlock) void k_pp_arnoldi_finish(int64_t S, int nblk, const double* __restrict__ part,
+                                                              BT* __restrict__ Ub, int64_t ldu, int j, double gamma,
+                                                              const Ctl* __restrict__ ctl,
+                                                              double* __restrict__ partials,
+                                                              const BT* __restrict__ xin) {
+  if (ctl->done) return;
+  using AT = typename Acc<BT>::type;
+  __shared__ double w_lds[kApplyTile];
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  const int64_t s0 = static_cast<int64_t>(tile) * kApplyTile;
+  const int ns = static_cast<int>(min<int64_t>(kApplyTile, S - s0));
+  const AT gam = static_cast<AT>(gamma);
+  const BT* __restrict__ xj = xin ? xin : Ub + static_cast<int64_t>(j) * ldu;
+  BT* __restrict__ w = Ub + static_cast<int64_t>(j + 1) * ldu;
+  const double cj = ctl->scale[j];
+  for (int i = threadIdx.x; i < ns; i += kBlock) {
+    const int64_t s = s0 + i;
+    double pv = part[s];
+    for (int b = 1; b < nblk; ++b) pv += part[static_cast<int64_t>(b) * S + s];
+    const AT av = static_cast<AT>(xj[s]) - gam * static_cast<AT>(pv);
+    const BT wv = static_cast<BT>(cj * static_cast<double>(av));
+    w[s] = wv;
+    w_lds[i] = static_cast<double>(wv);
+  }
+  __syncthreads();
+  cgs_dots_tile<BT>(Ub, ldu, j, s0, ns, w_lds, partials, tile, static_cast<int>(gridDim.x));
+}
+
+}  // namespace
+
+// Set up (first call) and form the copy for policy pi; h->pp_ready says
+// whether the partitioned products can run for it.
+hipError_t pp_prepare(mdp_handle* h, const int32_t* pi) {
+  h->pp_ready = false;
+  if (h->pp_state < 0) return hipSuccess;
+  if (h->pp_state > 0 && h->pp_pi == pi && h->pp_gen == h->pi_gen) {
+    h->pp_ready = true;
+    return hipSuccess;
+  }
+  const int64_t S = h->S;
+  if (h->pp_state == 0) {
+    const int64_t passes = (S * static_cast<int64_t>(sizeof(double)) + kNumXcd * kPPSliceBytes - 1) /
+                           (kNumXcd * kPPSliceBytes);
+    const int64_t nblk = kNumXcd * passes;
+    const int64_t ntiles = (S + kPPTile - 1) / kPPTile;
+    if (nblk > kPPMaxBlocks || nblk * ntiles + 1 > (int64_t{1} << 30)) {
+      h->pp_state = -1;
+      return hipSuccess;
+    }
+    h->pp_blocks = static_cast<int>(nblk);
+    h->pp_slice = static_cast<int>((S + nblk - 1) / nblk);
+    h->pp_ntiles = static_cast<int>(ntiles);
+    const int64_t nseg = nblk * ntiles + 1;
+    hipError_t e = handle_alloc(h, reinterpret_cast<void**>(&h->pp_rel), nblk * S * sizeof(uint16_t));
+    if (e == hipSuccess) e = handle_alloc(h, reinterpret_cast<void**>(&h->pp_tsum), nseg * sizeof(int));
+    if (e == hipSuccess) e = handle_alloc(h, reinterpret_cast<void**>(&h->pp_off), nseg * sizeof(int));
+    if (e == hipSuccess) e = handle_alloc(h, reinterpret_cast<void**>(&h->pp_part), nblk * S * sizeof(double));
+    if (e == hipSuccess) e = handle_alloc(h, reinterpret_cast<void**>(&h->pp_stat), 4 * sizeof(unsigned));
+    if (e == hipSuccess)
+      e = hipcub::DeviceScan::ExclusiveSum(nullptr, h->pp_tmp_bytes, h->pp_tsum, h->pp_off,
+                                           static_cast<int>(nseg), h->stream);
+    if (e == hipSuccess) e = handle_alloc(h, &h->pp_tmp, h->pp_tmp_bytes);
+    // the scan's last input stays 0, so its output is the total
+    if (e == hipSuccess) e = hipMemsetAsync(h->pp_tsum + nseg - 1, 0, sizeof(int), h->stream);
+    if (e != hipSuccess) return e;
+    h->device_bytes += static_cast<int64_t>(nblk * S * (sizeof(uint16_t) + sizeof(double)) + 2 * nseg * sizeof(int));
+    h->pp_state = 1;
+  }
+  const int nblk = h->pp_blocks, ntiles = h->pp_ntiles;
+  const int64_t nseg = static_cast<int64_t>(nblk) * ntiles + 1;
+  const RowIndex rix{h->row_ptr, h->kfix};
+  hipError_t e = hipMemsetAsync(h->pp_stat, 0, 2 * sizeof(unsigned), h->stream);
+  if (e != hipSuccess) return e;
+  k_pp_count<<<ntiles, kBlock, 0, h->stream>>>(S, h->A, rix, h->col, pi, h->pp_slice, nblk, ntiles, h->pp_tsum,
+                                               h->pp_rel, h->pp_stat);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  e = hipcub::DeviceScan::ExclusiveSum(h->pp_tmp, h->pp_tmp_bytes, h->pp_tsum, h->pp_off, static_cast<int>(nseg),
+                                       h->stream);
+  if (e != hipSuccess) return e;
+  // largest segment, longest row and the total entries, to the host
+  unsigned stat[2] = {0, 0};
+  int total = 0;
+  if ((e = copy_out(stat, h->pp_stat, sizeof(stat), h->stream)) != hipSuccess) return e;
+  if ((e = copy_out(&total, h->pp_off + nseg - 1, sizeof(int), h->stream)) != hipSuccess) return e;
+  if ((e = hipStreamSynchronize(h->stream)) != hipSuccess) return e;
+  if (stat[0] > 65535u || stat[1] > 255u) return hipSuccess;  // not for this policy: plain products
+  if (total > h->pp_cap) {
+    handle_free(h, h->pp_col);
+    handle_free(h, h->pp_val);
+    h->pp_col = nullptr;
+    h->pp_val = nullptr;
+    h->pp_cap = 0;
+    const int64_t cap = std::min<int64_t>(h->nnz, static_cast<int64_t>(total) + total / 4 + 1024);
+    e = handle_alloc(h, reinterpret_cast<void**>(&h->pp_col), cap * sizeof(int));
+    if (e == hipSuccess) e = handle_alloc(h, reinterpret_cast<void**>(&h->pp_val), cap * sizeof(double));
+    if (e != hipSuccess) return e;
+    h->pp_cap = cap;
+  }
+  k_pp_scatter<<<ntiles, kBlock, 0, h->stream>>>(S, h->A, rix, h->col, h->val, pi, h->pp_slice, nblk, ntiles,
+                                                 h->pp_off, h->pp_rel, h->pp_col, h->pp_val);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  h->pp_pi = pi;
+  h->pp_gen = h->pi_gen;
+  h->pp_ready = true;
+  return hipSuccess;
+}
+
+hipError_t launch_pp_arnoldi_apply(mdp_handle* h, int j, const double* xin, double* partials, int nb) {
+  const double* x = xin ? xin : h->U64 + static_cast<int64_t>(j) * h->ldu;
+  const int passes = h->pp_blocks / kNumXcd;
+  const int64_t grid = static_cast<int64_t>(kNumXcd) * h->pp_ntiles;
+  for (int p = 0; p < passes; ++p) {
+    k_pp_product<double><<<static_cast<unsigned>(grid), kBlock, 0, h->stream>>>(
+        h->S, h->pp_blocks, h->pp_ntiles, p, h->pp_rel, h->pp_off, h->pp_col, h->pp_val, x, h->pp_part, h->ctl);
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  k_pp_arnoldi_finish<double><<<nb, kBlock, 0, h->stream>>>(h->S, h->pp_blocks, h->pp_part, h->U64, h->ldu, j,
+                                                            h->gamma, h->ctl, partials, xin);
+  return hipGetLastError();
+}
+
+}  // namespace mdp

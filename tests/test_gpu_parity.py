@@ -475,7 +475,8 @@ def test_colblocked_solve_certified(precision):
 @pytest.mark.parametrize("name", ["c2twin_b3", "c4twin_b7", "ragged_b2"])
 def test_colblocked_policy_products_match_exact_solve(name, deg):
     """float64 GMRES on handles that carry the column-blocked copy (the
-    sweeps run over it, the P_pi products over the plain rows), with and
+    sweeps run over it, the Arnoldi products over the XCD-partitioned copy of
+    P_pi, the preconditioner's products over the plain rows), with and
     without the polynomial preconditioner, against the oracle's exact policy
     evaluation."""
     make, blocks = CB_CASES[name]

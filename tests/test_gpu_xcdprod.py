@@ -1,0 +1,122 @@
+"""The XCD-partitioned P_pi products of float64 GMRES (xcd_products): on
+handles that carry the column-blocked copy, policy evaluations and solves run
+their Arnoldi products on a copy of P_pi cut into column slices (one per XCD).
+They must match the oracle, match the plain products to rounding, be
+deterministic, and follow policy changes on the same handle."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from workloads import config2, config4, random_dense_mdp
+
+pytestmark = pytest.mark.gpu
+
+CASES = {
+    "c4twin_b7": (lambda: config4(S=12000, A=16, seed=2), 7),
+    "c2twin_b3": (lambda: config2(S=20000, A=8, seed=1), 3),
+    "ragged_b2": (lambda: random_dense_mdp(37, 3, 0.95, seed=5, density=0.3), 2),
+    # 9999 states: no multiple of the 1024-state tiles nor of the 8 slices
+    "tail_b1": (lambda: config4(S=9999, A=3, k=5, seed=4), 1),
+}
+
+
+def _mdp(inst, **kw):
+    import paper_2502_14474_amd as m
+    print(f"[case] {inst.name} S={inst.S} A={inst.A} nnz={inst.nnz} {kw}", flush=True)
+    sys.stdout.flush()
+    return m.MDP.from_instance(inst, **kw)
+
+
+@pytest.mark.parametrize("deg", [1, 3])
+@pytest.mark.parametrize("name", sorted(CASES))
+def test_partitioned_products_match_oracle_and_plain_products(name, deg):
+    make, blocks = CASES[name]
+    inst = make()
+    pi = np.random.default_rng(8).integers(0, inst.A, inst.S).astype(np.int32)
+    v_ref, _ = oracle.evaluate_policy(inst, pi)
+    scale = np.max(np.abs(v_ref))
+    out = {}
+    with _mdp(inst, col_blocks=blocks) as h:
+        for xcd in (-1, 0, -1):
+            v, st = h.policy_eval(pi, rtol=1e-13, max_iter=20000, precond_degree=deg, xcd_products=xcd)
+            assert st["status"] == 0, st
+            assert np.max(np.abs(v - v_ref)) / scale <= 1e-9, (xcd, st)
+            if xcd in out:  # the same copy and policy again: bit for bit
+                assert np.array_equal(v, out[xcd])
+            out[xcd] = v
+    assert np.max(np.abs(out[-1] - out[0])) / scale <= 1e-10
+
+
+def test_partitioned_products_follow_policy_changes():
+    """Evaluations of different policies on one handle, and a solve (whose
+    sweeps change the policy between evaluations) on the same handle."""
+    inst = config4(S=12000, A=16, seed=3)
+    rng = np.random.default_rng(2)
+    p1 = rng.integers(0, inst.A, inst.S).astype(np.int32)
+    p2 = rng.integers(0, inst.A, inst.S).astype(np.int32)
+    with _mdp(inst, col_blocks=4) as h:
+        vs = []
+        for p in (p1, p2, p1):
+            v, st = h.policy_eval(p, rtol=1e-13, max_iter=20000)
+            assert st["status"] == 0, st
+            vs.append(v)
+        v, pi, st = h.solve(alpha=1e-2, rtol_cert=1e-10)
+    for p, vv in zip((p1, p2, p1), vs):
+        ref, _ = oracle.evaluate_policy(inst, p)
+        assert np.max(np.abs(vv - ref)) / np.max(np.abs(ref)) <= 1e-9
+    assert np.array_equal(vs[0], vs[2])
+    assert st["status"] == 0, st
+    ref = oracle.policy_iteration(inst, method="certified")
+    err = np.max(np.abs(v - ref["v"])) / np.max(np.abs(ref["v"]))
+    assert err <= 1e-9, err
+    Q = oracle.q_values(inst, ref["v"])
+    tau = max(1e-9, 2 * inst.gamma * (np.max(np.abs(v - ref["v"])) + 1e-11 * np.max(np.abs(ref["v"]))))
+    pp = oracle.policy_parity(inst, Q, pi, ref["pi"], tau)
+    assert pp["mismatch_outside_band"] == 0 and pp["not_tau_optimal"] == 0, pp
+
+
+def test_partitioned_products_in_two_passes():
+    """A vector of more than 8 x 4 MB: 16 slices, two passes per product.  The
+    oracle's sweep-free check at this size: the partitioned and the plain
+    products give the same evaluation to rounding, and the evaluation solves
+    the policy's linear system (residual checked on the host)."""
+    inst = config4(S=4_300_001, A=2, k=4, seed=6, workers=8)
+    pi = np.random.default_rng(5).integers(0, inst.A, inst.S).astype(np.int32)
+    with _mdp(inst, col_blocks=16) as h:
+        va, sa = h.policy_eval(pi, rtol=1e-12, max_iter=5000, xcd_products=-1)
+        vb, sb = h.policy_eval(pi, rtol=1e-12, max_iter=5000, xcd_products=0)
+    assert sa["status"] == 0 and sb["status"] == 0
+    scale = np.max(np.abs(vb))
+    assert np.max(np.abs(va - vb)) / scale <= 1e-10
+    # v = g_pi + gamma P_pi v, row by row on the host
+    rows = np.arange(inst.S) * inst.A + pi
+    lo, hi = inst.row_ptr[rows], inst.row_ptr[rows + 1]
+    k = hi - lo
+    idx = np.repeat(lo, k) + (np.arange(k.sum()) - np.repeat(np.cumsum(k) - k, k))
+    pv = np.add.reduceat(inst.val[idx] * va[inst.col[idx]], np.cumsum(k) - k)
+    res = va - (inst.cost[rows] + inst.gamma * pv)
+    assert np.max(np.abs(res)) / scale <= 1e-9
+
+
+@pytest.mark.parametrize("blocks", [3, 8])
+def test_blocked_sweep_one_launch_equals_pass_by_pass(blocks, monkeypatch):
+    """The blocked sweep with all slices in one launch (one slice per XCD,
+    parts added afterwards in slice order; enabled by a limit on the parts
+    buffer) against the same sweep run one pass per slice with a running sum
+    (the default): bit for bit, and both against the oracle's sweep."""
+    inst = config4(S=12000, A=16, seed=7)
+    v = 2.0 * np.random.default_rng(6).standard_normal(inst.S)
+    outs = []
+    for limit in (str(1 << 34), None):
+        if limit is None:
+            monkeypatch.delenv("MDP_CB_PARTS_MAX_BYTES", raising=False)
+        else:
+            monkeypatch.setenv("MDP_CB_PARTS_MAX_BYTES", limit)
+        with _mdp(inst, col_blocks=blocks) as h:
+            outs.append(h.bellman(v))
+    (Tv0, pi0, r0), (Tv1, pi1, r1) = outs
+    assert np.array_equal(Tv0, Tv1) and np.array_equal(pi0, pi1) and r0 == r1
+    Q = oracle.q_values(inst, v)
+    assert np.max(np.abs(Tv0 - Q.min(axis=1))) <= 1e-12 * np.max(np.abs(Q))
