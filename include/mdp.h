@@ -137,12 +137,13 @@ typedef struct {
                              second correction (mdp_stats.orth_loss), the loss of orthogonality
                              a single pass would have left.  2 is MDP_E_NOTSUP with the other
                              inner solvers, batched solves and the server. */
-  int32_t xcd_products;   /* float64 GMRES on a handle with a column-blocked copy (see
-                             mdp_create_opts.col_blocks): -1 (default) runs the Arnoldi products
-                             on a copy of P_pi cut into column slices, one slice per XCD, formed
-                             once per policy (about S * 8 + nnz(P_pi) * 12 bytes more device
-                             memory); 0 runs them on the CSR rows.  The two differ only in the
-                             rounding of each row's sum. */
+  int32_t xcd_products;   /* GMRES in float64 or mixed float32 on a handle with a column-blocked
+                             copy (see mdp_create_opts.col_blocks): -1 (default) runs the
+                             Arnoldi products on a copy of P_pi cut into column slices, one
+                             slice per XCD, formed once per policy (about S * 16 + nnz(P_pi) *
+                             12 bytes more device memory), with each row's slice parts summed
+                             in float64; 0 runs them on the CSR rows.  The two differ only in
+                             the rounding of each row's sum. */
 } mdp_eval_opts;
 
 typedef struct {

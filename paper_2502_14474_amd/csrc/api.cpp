@@ -475,13 +475,13 @@ mdp_status gmres_inner(mdp_handle* h, Prec prec, const int32_t* pi, double* x, i
                        bool gs2 = false, int xcd_products = -1) {
   const Prec bprec = prec == kF64 ? kF64 : kF32;
   const int bb = bprec == kF64 ? 8 : 4;
-  // float64 products on a handle with a column-blocked copy: the
-  // XCD-partitioned copy of P_pi for this policy (formed here, once)
+  // float64 and float32 products on a handle with a column-blocked copy:
+  // the XCD-partitioned copy of P_pi for this policy (formed here, once)
   struct PPGuard {
     mdp_handle* h;
     ~PPGuard() { h->pp_ready = false; }
   } pp_guard{h};
-  if (prec == kF64 && xcd_products != 0 && h->cb_blocks > 0) MDP_HIP(pp_prepare(h, pi));
+  if ((prec == kF64 || prec == kF32) && xcd_products != 0 && h->cb_blocks > 0) MDP_HIP(pp_prepare(h, pi));
   for (;;) {
     int j = 0;
     const size_t rec0 = h->prof_pending.size();

@@ -337,11 +337,14 @@ struct StageBlock {
 bool stage_take(StageBlock* b);
 void stage_give(const StageBlock& b);
 // XCD-partitioned P_pi products (xcdprod.hip).  pp_prepare forms the copy
-// for policy pi when it is not current and sets h->pp_ready when the float64
-// Arnoldi products can use it; launch_pp_arnoldi_apply is then the Arnoldi
-// product of step j (input U_j, or xin), with the plain product's outputs.
+// for policy pi when it is not current and sets h->pp_ready when the Arnoldi
+// products can use it; launch_pp_arnoldi_apply is then the Arnoldi product of
+// step j on the float64 or float32 basis (input U_j, or xin), with the plain
+// product's outputs.  The copy keeps float64 values; a float32 basis is
+// gathered in float32 and the slice parts summed in float64.
 hipError_t pp_prepare(mdp_handle* h, const int32_t* pi);
-hipError_t launch_pp_arnoldi_apply(mdp_handle* h, int j, const double* xin, double* partials, int nb);
+hipError_t launch_pp_arnoldi_apply(mdp_handle* h, bool basis_f32, int j, const void* xin, double* partials,
+                                   int nb);
 
 // dst[i] = src[i] for i < n, 64-bit row offsets narrowed to the stored 32-bit
 // ones (values checked on the host beforehand) (vecops.hip).

@@ -456,10 +456,10 @@ hipError_t launch_arnoldi_step(mdp_handle* h, Prec prec, const int32_t* pi, int 
     xin = precond_apply(h, prec, pi, basis_slot(h, bprec, j), m + 1, m + 2, deg, h->ctl, &e);
     if (e != hipSuccess) return e;
   }
-  if (prec == kF64 && h->pp_ready && pi == h->pp_pi) {
+  if ((prec == kF64 || prec == kF32) && h->pp_ready && pi == h->pp_pi) {
     // the XCD-partitioned product on the policy's copy (same outputs)
-    Prof pf(h, MDP_K_ARNOLDI_APPLY, bytes_arnoldi_apply(h, 8, 8, j), j);
-    e = launch_pp_arnoldi_apply(h, j, static_cast<const double*>(xin), h->part.buf, nb);
+    Prof pf(h, MDP_K_ARNOLDI_APPLY, bytes_arnoldi_apply(h, 8, prec == kF64 ? 8 : 4, j), j);
+    e = launch_pp_arnoldi_apply(h, prec == kF32, j, xin, h->part.buf, nb);
   } else {
     Prof pf(h, MDP_K_ARNOLDI_APPLY, bytes_arnoldi_apply(h, prec == kF64 ? 8 : (prec == kF32 ? 4 : 2), prec == kF64 ? 8 : 4, j) + (prec == kF16 ? h->S * 8.0 : 0.0), j);
     e = with_lanes(h->lanes, [&](auto Lc) -> hipError_t {

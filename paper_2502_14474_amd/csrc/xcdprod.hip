@@ -371,19 +371,28 @@ hipError_t pp_prepare(mdp_handle* h, const int32_t* pi) {
   return hipSuccess;
 }
 
-hipError_t launch_pp_arnoldi_apply(mdp_handle* h, int j, const double* xin, double* partials, int nb) {
-  const double* x = xin ? xin : h->U64 + static_cast<int64_t>(j) * h->ldu;
+namespace {
+template <typename BT>
+hipError_t pp_arnoldi_apply(mdp_handle* h, BT* Ub, int j, const BT* xin, double* partials, int nb) {
+  const BT* x = xin ? xin : Ub + static_cast<int64_t>(j) * h->ldu;
   const int passes = h->pp_blocks / kNumXcd;
   const int64_t grid = static_cast<int64_t>(kNumXcd) * h->pp_ntiles;
   for (int p = 0; p < passes; ++p) {
-    k_pp_product<double><<<static_cast<unsigned>(grid), kBlock, 0, h->stream>>>(
+    k_pp_product<BT><<<static_cast<unsigned>(grid), kBlock, 0, h->stream>>>(
         h->S, h->pp_blocks, h->pp_ntiles, p, h->pp_rel, h->pp_off, h->pp_col, h->pp_val, x, h->pp_part, h->ctl);
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  k_pp_arnoldi_finish<double><<<nb, kBlock, 0, h->stream>>>(h->S, h->pp_blocks, h->pp_part, h->U64, h->ldu, j,
-                                                            h->gamma, h->ctl, partials, xin);
+  k_pp_arnoldi_finish<BT><<<nb, kBlock, 0, h->stream>>>(h->S, h->pp_blocks, h->pp_part, Ub, h->ldu, j, h->gamma,
+                                                        h->ctl, partials, xin);
   return hipGetLastError();
+}
+}  // namespace
+
+hipError_t launch_pp_arnoldi_apply(mdp_handle* h, bool basis_f32, int j, const void* xin, double* partials,
+                                   int nb) {
+  if (basis_f32) return pp_arnoldi_apply<float>(h, h->U32, j, static_cast<const float*>(xin), partials, nb);
+  return pp_arnoldi_apply<double>(h, h->U64, j, static_cast<const double*>(xin), partials, nb);
 }
 
 }  // namespace mdp

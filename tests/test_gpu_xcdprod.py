@@ -120,3 +120,25 @@ def test_blocked_sweep_one_launch_equals_pass_by_pass(blocks, monkeypatch):
     assert np.array_equal(Tv0, Tv1) and np.array_equal(pi0, pi1) and r0 == r1
     Q = oracle.q_values(inst, v)
     assert np.max(np.abs(Tv0 - Q.min(axis=1))) <= 1e-12 * np.max(np.abs(Q))
+
+
+@pytest.mark.parametrize("name", ["c4twin_b7", "tail_b1"])
+def test_partitioned_products_in_mixed_solves(name):
+    """Mixed float32 solves (float32 basis gathered from the sliced copy, slice
+    parts summed in float64, float64 refinement) against the oracle, with and
+    without the partitioned products."""
+    import paper_2502_14474_amd as m
+    make, blocks = CASES[name]
+    inst = make()
+    ref = oracle.policy_iteration(inst, method="certified")
+    scale = np.max(np.abs(ref["v"]))
+    Q = oracle.q_values(inst, ref["v"])
+    with _mdp(inst, col_blocks=blocks) as h:
+        for xcd in (-1, 0):
+            v, pi, st = h.solve(alpha=1e-2, precision=m.MDP_MIXED_FP32, rtol_cert=1e-10, xcd_products=xcd)
+            assert st["status"] == 0, (xcd, st)
+            err = np.max(np.abs(v - ref["v"]))
+            assert err / scale <= 1e-9, (xcd, err / scale)
+            tau = max(1e-9, 2 * inst.gamma * (err + 1e-11 * scale))
+            pp = oracle.policy_parity(inst, Q, pi, ref["pi"], tau)
+            assert pp["mismatch_outside_band"] == 0 and pp["not_tau_optimal"] == 0, (xcd, pp)
