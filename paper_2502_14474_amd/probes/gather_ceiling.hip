@@ -75,6 +75,54 @@ __global__ __launch_bounds__(256) void gather_policy(const int* __restrict__ idx
   out[blockIdx.x * (int64_t)blockDim.x + threadIdx.x] = s;
 }
 
+// Slice-aligned indices: element i is read by thread i % T of the grid-stride
+// loop (T = grid * 256), i.e. by workgroup w = (i % T) / 256, and falls in
+// slice f(w) of a table cut into nslices equal slices.  mode 0: f(w) = w % 8 +
+// 8 * ((w / 8) % (nslices / 8)), so the workgroups dispatched to one XCD
+// (w % 8) share that XCD's slices; mode 1: f(w) = (w / 8) % nslices, every
+// XCD sees every slice.
+__global__ void fill_idx_sliced(int* idx, int64_t n, int64_t T, int mode, uint32_t slice_len, int nslices,
+                                uint32_t seed) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t w = (i % T) / 256;
+    uint64_t z = (uint64_t)i * 0x9E3779B97F4A7C15ull + seed;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    const int sl = mode == 0 ? (int)(w % 8) + 8 * (int)((w / 8) % (nslices / 8)) : (int)((w / 8) % nslices);
+    idx[i] = sl * (int)slice_len + (int)(z % slice_len);
+  }
+}
+
+// The traffic of the blocked sweep and of the sliced policy product around
+// each gather: a streamed 4-byte column and 8-byte value per entry, the
+// product accumulated, and one 8-byte partial written per three entries.
+__global__ __launch_bounds__(256) void gather_stream(const int* __restrict__ idx, const double* __restrict__ val,
+                                                     const double* __restrict__ x, int64_t n,
+                                                     double* __restrict__ part) {
+  constexpr int U = 4;
+  double s = 0.0;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  for (; i + (U - 1) * stride < n; i += U * stride) {
+    int c[U];
+    double p[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      c[u] = __builtin_nontemporal_load(idx + i + u * stride);
+      p[u] = __builtin_nontemporal_load(val + i + u * stride);
+    }
+    double v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) v[u] = x[c[u]];
+#pragma unroll
+    for (int u = 0; u < U; ++u) s = fma(p[u], v[u], s);
+    if ((i / stride) % 3 == 0) part[i / 3] = s;
+  }
+  for (; i < n; i += stride) s = fma(val[i], x[idx[i]], s);
+  part[(blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / 3] = s;
+}
+
 // streaming read of the index array alone (the gather-free floor)
 __global__ __launch_bounds__(256) void stream_idx(const int* __restrict__ idx, int64_t n, double* out) {
   double s = 0.0;
@@ -143,6 +191,63 @@ int main() {
     if (run(gather_policy<17>, "sc0 sc1")) return 1;
     if (run(gather_policy<18>, "sc1 nt")) return 1;
     if (run(gather_policy<19>, "all")) return 1;
+  }
+  // slices aligned with the XCDs, on a 33.6 MB table (a 4M-state float64
+  // vector): plain gathers, then with the streamed entries and partials
+  {
+    const int64_t t = 1ll << 22;
+    const int64_t T = (int64_t)grid * 256;
+    double *val, *part;
+    CHK(hipMalloc(&val, n * sizeof(double)));
+    CHK(hipMalloc(&part, (n / 3 + 1) * sizeof(double)));
+    fill_x<<<4096, 256>>>(val, n);
+    CHK(hipGetLastError());
+    struct Case { int mode, nslices; const char* name; };
+    const Case cases[] = {{0, 8, "w%8 -> slice (8 x 4.2 MB)"},
+                          {1, 8, "(w/8)%8 -> slice (8 x 4.2 MB)"},
+                          {0, 16, "w%8 + 8*((w/8)%2) (16 x 2.1 MB)"},
+                          {1, 16, "(w/8)%16 (16 x 2.1 MB)"}};
+    for (const Case& c : cases) {
+      fill_idx_sliced<<<4096, 256>>>(idx, n, T, c.mode, (uint32_t)(t / c.nslices), c.nslices, 12345u);
+      CHK(hipGetLastError());
+      CHK(hipDeviceSynchronize());
+      float ms[2];
+      for (int k = 0; k < 2; ++k) {
+        for (int rep = 0; rep < 2; ++rep) {
+          if (k == 0) gather<4><<<grid, 256>>>(idx, x, n, out);
+          else gather_stream<<<grid, 256>>>(idx, val, x, n, part);
+        }
+        CHK(hipEventRecord(a));
+        for (int rep = 0; rep < 10; ++rep) {
+          if (k == 0) gather<4><<<grid, 256>>>(idx, x, n, out);
+          else gather_stream<<<grid, 256>>>(idx, val, x, n, part);
+        }
+        CHK(hipEventRecord(b));
+        CHK(hipEventSynchronize(b));
+        CHK(hipEventElapsedTime(&ms[k], a, b));
+        ms[k] /= 10;
+      }
+      printf("sliced table 33.6 MB, %-34s gathers %.1f G/s; with streamed entries and partials %.1f G/s\n",
+             c.name, n / (ms[0] * 1e-3) / 1e9, n / (ms[1] * 1e-3) / 1e9);
+      fflush(stdout);
+    }
+    // one 2.8 MB slice for all workgroups (a pass of the blocked sweep)
+    fill_idx<<<4096, 256>>>(idx, n, (uint32_t)((11ll << 18) / 8), 12345u);
+    CHK(hipGetLastError());
+    CHK(hipDeviceSynchronize());
+    for (int rep = 0; rep < 2; ++rep) gather_stream<<<grid, 256>>>(idx, val, x, n, part);
+    CHK(hipEventRecord(a));
+    for (int rep = 0; rep < 10; ++rep) gather_stream<<<grid, 256>>>(idx, val, x, n, part);
+    CHK(hipEventRecord(b));
+    CHK(hipEventSynchronize(b));
+    float ms1;
+    CHK(hipEventElapsedTime(&ms1, a, b));
+    ms1 /= 10;
+    printf("one 2.9 MB table for all workgroups, with streamed entries and partials: %.1f G/s\n",
+           n / (ms1 * 1e-3) / 1e9);
+    fflush(stdout);
+    CHK(hipFree(val));
+    CHK(hipFree(part));
   }
   CHK(hipEventRecord(a));
   for (int rep = 0; rep < 10; ++rep) stream_idx<<<grid, 256>>>(idx, n, out);
