@@ -22,7 +22,8 @@ METRIC = ("Bellman sweeps/s + HBM GB/s (% peak); solve time to â€–Tvâˆ’vâ€–âˆžâ‰
           "FP64 vs mixed")
 HBM_PEAK_GBS = 8000.0
 KERNEL_SOURCES = ("paper_2502_14474_amd/csrc/device.h", "paper_2502_14474_amd/csrc/kernels.hip",
-                  "paper_2502_14474_amd/csrc/colblock.hip", "paper_2502_14474_amd/csrc/internal.h")
+                  "paper_2502_14474_amd/csrc/colblock.hip", "paper_2502_14474_amd/csrc/internal.h",
+                  "paper_2502_14474_amd/csrc/xcdprod.hip")
 COUNTERS_GLOB = os.path.join(ROOT, "profiles", "counters_*.json")
 
 
