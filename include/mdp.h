@@ -137,13 +137,15 @@ typedef struct {
                              second correction (mdp_stats.orth_loss), the loss of orthogonality
                              a single pass would have left.  2 is MDP_E_NOTSUP with the other
                              inner solvers, batched solves and the server. */
-  int32_t xcd_products;   /* GMRES in float64 or mixed float32 on a handle with a column-blocked
-                             copy (see mdp_create_opts.col_blocks): -1 (default) runs the
-                             Arnoldi products on a copy of P_pi cut into column slices, one
-                             slice per XCD, formed once per policy (about S * 16 + nnz(P_pi) *
-                             12 bytes more device memory), with each row's slice parts summed
-                             in float64; 0 runs them on the CSR rows.  The two differ only in
-                             the rounding of each row's sum. */
+  int32_t policy_copy;    /* GMRES in float64 or mixed float32: -1 (default) runs the Arnoldi
+                             products on a copy of P_pi formed once per policy (about S * 16 +
+                             nnz(P_pi) * 12 bytes more device memory), on handles with a
+                             column-blocked copy (see mdp_create_opts.col_blocks) cut into column
+                             slices, one per XCD, and on other handles of at least 2^17 states
+                             with at most 8 entries per row on average stored contiguously; 0
+                             gathers the selected rows through row_ptr
+                             (as every other product does).  The two differ only in the rounding
+                             of each row's sum. */
 } mdp_eval_opts;
 
 typedef struct {
@@ -169,7 +171,7 @@ typedef struct {
                              preconditioning, to the caller: "Problem Setting and Solution
                              Methods") */
   int32_t gs_passes;      /* as in mdp_eval_opts */
-  int32_t xcd_products;   /* as in mdp_eval_opts (batched solves and the server ignore it) */
+  int32_t policy_copy;    /* as in mdp_eval_opts (batched solves and the server ignore it) */
 } mdp_solve_opts;
 
 enum { MDP_LAUNCH_AUTO = 0, MDP_LAUNCH_GRAPHS = 1, MDP_LAUNCH_DIRECT = 2 };

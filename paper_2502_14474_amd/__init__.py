@@ -222,13 +222,13 @@ def _stats_dict(st, hist):
 
 def mdp_policy_eval(h, policy, v, v0=None, inner=MDP_INNER_GMRES, restart=30, precision=MDP_FP64,
                     rtol=1e-10, max_iter=10000, sync_every=0, precond_degree=1, gs_passes=1,
-                    xcd_products=-1):
+                    policy_copy=-1):
     lib = native.load()
     o = native.EvalOpts()
     lib.mdp_default_eval_opts(C.byref(o))
     o.inner, o.restart, o.precision, o.rtol, o.max_iter = inner, restart, precision, rtol, max_iter
     o.sync_every, o.precond_degree, o.gs_passes = sync_every, precond_degree, gs_passes
-    o.xcd_products = xcd_products
+    o.policy_copy = policy_copy
     st, hist = _stats()
     status = native.check(lib.mdp_policy_eval(h, _ptr(policy, np.int32, name="policy"),
                                               _ptr(v0, np.float64, name="v0"),
@@ -241,13 +241,13 @@ def mdp_policy_eval(h, policy, v, v0=None, inner=MDP_INNER_GMRES, restart=30, pr
 
 def mdp_solve(h, v, policy, v0=None, inner=MDP_INNER_GMRES, restart=30, precision=MDP_FP64,
               alpha=1e-4, atol=1e-8, rtol_cert=0.0, max_outer=1000, max_inner=10000,
-              sync_every=0, history_cap=1024, precond_degree=1, gs_passes=1, xcd_products=-1):
+              sync_every=0, history_cap=1024, precond_degree=1, gs_passes=1, policy_copy=-1):
     lib = native.load()
     o = native.SolveOpts()
     lib.mdp_default_solve_opts(C.byref(o))
     o.inner, o.restart, o.precision, o.alpha, o.atol = inner, restart, precision, alpha, atol
     o.rtol_cert, o.max_outer, o.max_inner, o.sync_every = rtol_cert, max_outer, max_inner, sync_every
-    o.precond_degree, o.gs_passes, o.xcd_products = precond_degree, gs_passes, xcd_products
+    o.precond_degree, o.gs_passes, o.policy_copy = precond_degree, gs_passes, policy_copy
     st, hist = _stats(history_cap)
     status = native.check(lib.mdp_solve(h, _ptr(v0, np.float64, name="v0"),
                                         _ptr(v, np.float64, name="v"),
@@ -260,12 +260,12 @@ def mdp_solve(h, v, policy, v0=None, inner=MDP_INNER_GMRES, restart=30, precisio
 
 def _solve_opts(lib, inner=MDP_INNER_GMRES, restart=30, precision=MDP_FP64, alpha=1e-4, atol=1e-8,
                 rtol_cert=0.0, max_outer=1000, max_inner=10000, sync_every=0, launch=0, precond_degree=1,
-                gs_passes=1, xcd_products=-1):
+                gs_passes=1, policy_copy=-1):
     o = native.SolveOpts()
     lib.mdp_default_solve_opts(C.byref(o))
     o.inner, o.restart, o.precision, o.alpha, o.atol = inner, restart, precision, alpha, atol
     o.rtol_cert, o.max_outer, o.max_inner, o.sync_every = rtol_cert, max_outer, max_inner, sync_every
-    o.launch, o.precond_degree, o.gs_passes, o.xcd_products = launch, precond_degree, gs_passes, xcd_products
+    o.launch, o.precond_degree, o.gs_passes, o.policy_copy = launch, precond_degree, gs_passes, policy_copy
     return o
 
 

@@ -472,16 +472,19 @@ struct InnerResult {
 // float64 P, so the mixed-precision variants are iterative refinement.
 mdp_status gmres_inner(mdp_handle* h, Prec prec, const int32_t* pi, double* x, int m,
                        int64_t max_iter, int sync_every, double alpha, InnerResult* out, int deg = 1,
-                       bool gs2 = false, int xcd_products = -1) {
+                       bool gs2 = false, int policy_copy = -1) {
   const Prec bprec = prec == kF64 ? kF64 : kF32;
   const int bb = bprec == kF64 ? 8 : 4;
-  // float64 and float32 products on a handle with a column-blocked copy:
-  // the XCD-partitioned copy of P_pi for this policy (formed here, once)
+  // float64 and float32 products on a large handle: the copy of P_pi for
+  // this policy (formed here, once), cut by XCD when the handle carries a
+  // column-blocked copy, else contiguous when its rows are short
   struct PPGuard {
     mdp_handle* h;
     ~PPGuard() { h->pp_ready = false; }
   } pp_guard{h};
-  if ((prec == kF64 || prec == kF32) && xcd_products != 0 && h->cb_blocks > 0) MDP_HIP(pp_prepare(h, pi));
+  const bool short_rows = h->S >= kPolicyCopyMinStates && h->nnz <= kPolicyCopyMaxRowMean * h->rows;
+  if ((prec == kF64 || prec == kF32) && policy_copy != 0 && (h->cb_blocks > 0 || short_rows))
+    MDP_HIP(pp_prepare(h, pi));
   for (;;) {
     int j = 0;
     const size_t rec0 = h->prof_pending.size();
@@ -891,7 +894,7 @@ void mdp_default_eval_opts(mdp_eval_opts* o) {
   o->max_iter = 10000;
   o->precond_degree = 1;
   o->gs_passes = 1;
-  o->xcd_products = -1;
+  o->policy_copy = -1;
 }
 
 void mdp_default_solve_opts(mdp_solve_opts* o) {
@@ -910,7 +913,7 @@ void mdp_default_solve_opts(mdp_solve_opts* o) {
   o->launch = MDP_LAUNCH_AUTO;
   o->precond_degree = 1;
   o->gs_passes = 1;
-  o->xcd_products = -1;
+  o->policy_copy = -1;
 }
 
 mdp_status mdp_destroy(mdp_t h) {
@@ -1419,7 +1422,7 @@ mdp_status mdp_policy_eval(mdp_t h, const int32_t* policy, const double* v0, dou
                          floor_of(prec)));
     ir.applies += 1;
     MDP_TRY(gmres_inner(h, prec, h->pi, h->v, o.restart, o.max_iter, sync_every, o.rtol, &ir, deg, gs2,
-                        o.xcd_products));
+                        o.policy_copy));
     MDP_TRY(sync_ctl(h));
     rel = h->ctl_host->beta0 > 0 ? h->ctl_host->res_est / h->ctl_host->beta0 : 0.0;
     if (ir.converged && prec != kF64)
@@ -1546,7 +1549,7 @@ mdp_status mdp_solve(mdp_t h, const double* v0, double* v, int32_t* policy,
     InnerResult ir;
     if (gm) {
       MDP_TRY(gmres_inner(h, iprec, h->pi, h->v, o.restart, o.max_inner, sync_every, alpha, &ir, deg, gs2,
-                          o.xcd_products));
+                          o.policy_copy));
     } else if (bi) {
       MDP_TRY(bicgstab_inner(h, h->pi, h->v, o.max_inner, sync_every, &ir, o.inner == MDP_INNER_TFQMR));
     } else {

@@ -343,8 +343,20 @@ void stage_give(const StageBlock& b);
 // product's outputs.  The copy keeps float64 values; a float32 basis is
 // gathered in float32 and the slice parts summed in float64.
 hipError_t pp_prepare(mdp_handle* h, const int32_t* pi);
+// Handles without a column-blocked copy get the contiguous copy when they
+// hold at least kPolicyCopyMinStates states (below, forming it and its host
+// check cost more than they save) and at most kPolicyCopyMaxRowMean entries
+// per row on average.  On the 4M-state maze (4.2 entries per row) its product
+// takes 163 us against 254 us through row_ptr; with 16 entries per row (the
+// 1M-state workload) the row_ptr kernel, 16 lanes per row, is faster (81
+// against 91 us).
+constexpr int64_t kPolicyCopyMinStates = int64_t{1} << 17;
+constexpr int64_t kPolicyCopyMaxRowMean = 8;
 hipError_t launch_pp_arnoldi_apply(mdp_handle* h, bool basis_f32, int j, const void* xin, double* partials,
                                    int nb);
+// One Horner step y = b + gamma P_pi x of the polynomial preconditioner on
+// the copy (float64 or float32 vectors); ctl may be NULL.
+hipError_t launch_pp_horner(mdp_handle* h, bool f32, const void* x, const void* b, void* y, const Ctl* ctl);
 
 // dst[i] = src[i] for i < n, 64-bit row offsets narrowed to the stored 32-bit
 // ones (values checked on the host beforehand) (vecops.hip).

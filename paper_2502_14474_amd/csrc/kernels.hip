@@ -405,6 +405,8 @@ hipError_t launch_horner(mdp_handle* h, Prec prec, const int32_t* pi, const void
   const int nb = grid_for(h->S, kApplyTile);
   Prof pf(h, MDP_K_POLICY_APPLY, bytes_apply(h, bval_of(prec), prec == kF64 ? 8 : 4, prec == kF64 ? 8 : 4) +
                                      h->S * (prec == kF64 ? 8.0 : 4.0) + (prec == kF16 ? h->S * 8.0 : 0.0));
+  if ((prec == kF64 || prec == kF32) && h->pp_ready && pi == h->pp_pi)
+    return launch_pp_horner(h, prec == kF32, x, b, y, ctl);  // on the policy's copy
   return with_lanes(h->lanes, [&](auto Lc) -> hipError_t {
     constexpr int L = decltype(Lc)::value;
     constexpr int U = rows_in_flight<L>();

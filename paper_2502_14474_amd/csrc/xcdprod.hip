@@ -13,6 +13,11 @@
 // finishes the Arnoldi step exactly as the plain product kernel does (new
 // basis vector and the classical Gram-Schmidt dot partials).
 //
+// Where the columns stay near their rows (no column-blocked copy on the
+// handle) the copy has one slice: it is P_pi stored contiguously, tile by
+// tile, and the product streams each tile's rows as one segment, which reads
+// fewer partly used lines than gathering the selected rows through row_ptr.
+//
 // The copy is formed once per policy: a count kernel (entries of each tile in
 // each slice), a device scan of those counts into segment offsets, and a
 // scatter kernel that walks each selected row once, in CSR order, so inside a
@@ -186,11 +191,13 @@ __global__ __launch_bounds__(kBlock) void k_pp_product(int64_t S, int nblk, int 
                                                        const int* __restrict__ pcol, const double* __restrict__ pval,
                                                        const XT* __restrict__ x, double* __restrict__ part,
                                                        const Ctl* __restrict__ ctl) {
-  if (ctl->done) return;
+  if (ctl && ctl->done) return;
   __shared__ double lp[kPPChunk], lx[kPPChunk];
   constexpr int EPT = kPPChunk / kBlock;
-  const int b = pass * kNumXcd + static_cast<int>(blockIdx.x % kNumXcd);
-  const int t = static_cast<int>(blockIdx.x / kNumXcd);
+  // sliced copy: slice pass * 8 + w % 8 of tile w / 8; whole rows: tile w
+  const bool sliced = nblk >= kNumXcd;
+  const int b = sliced ? pass * kNumXcd + static_cast<int>(blockIdx.x % kNumXcd) : 0;
+  const int t = static_cast<int>(sliced ? blockIdx.x / kNumXcd : blockIdx.x);
   if (b >= nblk || t >= ntiles) return;  // the same for the whole workgroup
   const int64_t s0 = static_cast<int64_t>(t) * kPPTile;
   const int ns = static_cast<int>(min<int64_t>(kPPTile, S - s0));
@@ -292,6 +299,24 @@ __global__ __launch_bounds__(kBlock) void k_pp_arnoldi_finish(int64_t S, int nbl
   cgs_dots_tile<BT>(Ub, ldu, j, s0, ns, w_lds, partials, tile, static_cast<int>(gridDim.x));
 }
 
+// One Horner step of the polynomial preconditioner on the parts:
+// y = b + gamma P_pi x, as horner_tile forms it.  Exits at once when ctl is
+// given and the GMRES cycle is done.
+template <typename XT>
+__global__ __launch_bounds__(kBlock) void k_pp_horner_finish(int64_t S, int nblk, const double* __restrict__ part,
+                                                             const XT* __restrict__ b, double gamma,
+                                                             XT* __restrict__ y, const Ctl* __restrict__ ctl) {
+  if (ctl && ctl->done) return;
+  using AT = typename Acc<XT>::type;
+  const AT gam = static_cast<AT>(gamma);
+  for (int64_t s = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; s < S;
+       s += static_cast<int64_t>(gridDim.x) * kBlock) {
+    double pv = part[s];
+    for (int k = 1; k < nblk; ++k) pv += part[static_cast<int64_t>(k) * S + s];
+    y[s] = static_cast<XT>(fma(gam, static_cast<AT>(pv), static_cast<AT>(b[s])));
+  }
+}
+
 }  // namespace
 
 // Set up (first call) and form the copy for policy pi; h->pp_ready says
@@ -305,9 +330,12 @@ hipError_t pp_prepare(mdp_handle* h, const int32_t* pi) {
   }
   const int64_t S = h->S;
   if (h->pp_state == 0) {
+    // slices only where the columns spread over a large vector (the handle
+    // then carries the column-blocked copy); otherwise whole rows, the copy
+    // being P_pi stored contiguously
     const int64_t passes = (S * static_cast<int64_t>(sizeof(double)) + kNumXcd * kPPSliceBytes - 1) /
                            (kNumXcd * kPPSliceBytes);
-    const int64_t nblk = kNumXcd * passes;
+    const int64_t nblk = h->cb_blocks > 0 ? kNumXcd * passes : 1;
     const int64_t ntiles = (S + kPPTile - 1) / kPPTile;
     if (nblk > kPPMaxBlocks || nblk * ntiles + 1 > (int64_t{1} << 30)) {
       h->pp_state = -1;
@@ -372,22 +400,46 @@ hipError_t pp_prepare(mdp_handle* h, const int32_t* pi) {
 }
 
 namespace {
+template <typename XT>
+hipError_t pp_parts(mdp_handle* h, const XT* x, const Ctl* ctl) {
+  const bool sliced = h->pp_blocks >= kNumXcd;
+  const int passes = sliced ? h->pp_blocks / kNumXcd : 1;
+  const int64_t grid = (sliced ? static_cast<int64_t>(kNumXcd) : int64_t{1}) * h->pp_ntiles;
+  for (int p = 0; p < passes; ++p) {
+    k_pp_product<XT><<<static_cast<unsigned>(grid), kBlock, 0, h->stream>>>(
+        h->S, h->pp_blocks, h->pp_ntiles, p, h->pp_rel, h->pp_off, h->pp_col, h->pp_val, x, h->pp_part, ctl);
+  }
+  return hipGetLastError();
+}
+
+template <typename XT>
+hipError_t pp_horner(mdp_handle* h, const XT* x, const XT* b, XT* y, const Ctl* ctl) {
+  hipError_t e = pp_parts<XT>(h, x, ctl);
+  if (e != hipSuccess) return e;
+  const int64_t g = std::min<int64_t>(8192, (h->S + kBlock - 1) / kBlock);
+  k_pp_horner_finish<XT><<<static_cast<unsigned>(g), kBlock, 0, h->stream>>>(h->S, h->pp_blocks, h->pp_part, b,
+                                                                             h->gamma, y, ctl);
+  return hipGetLastError();
+}
+
 template <typename BT>
 hipError_t pp_arnoldi_apply(mdp_handle* h, BT* Ub, int j, const BT* xin, double* partials, int nb) {
   const BT* x = xin ? xin : Ub + static_cast<int64_t>(j) * h->ldu;
-  const int passes = h->pp_blocks / kNumXcd;
-  const int64_t grid = static_cast<int64_t>(kNumXcd) * h->pp_ntiles;
-  for (int p = 0; p < passes; ++p) {
-    k_pp_product<BT><<<static_cast<unsigned>(grid), kBlock, 0, h->stream>>>(
-        h->S, h->pp_blocks, h->pp_ntiles, p, h->pp_rel, h->pp_off, h->pp_col, h->pp_val, x, h->pp_part, h->ctl);
-  }
-  hipError_t e = hipGetLastError();
+  hipError_t e = pp_parts<BT>(h, x, h->ctl);
   if (e != hipSuccess) return e;
   k_pp_arnoldi_finish<BT><<<nb, kBlock, 0, h->stream>>>(h->S, h->pp_blocks, h->pp_part, Ub, h->ldu, j, h->gamma,
                                                         h->ctl, partials, xin);
   return hipGetLastError();
 }
 }  // namespace
+
+hipError_t launch_pp_horner(mdp_handle* h, bool f32, const void* x, const void* b, void* y, const Ctl* ctl) {
+  if (f32)
+    return pp_horner<float>(h, static_cast<const float*>(x), static_cast<const float*>(b), static_cast<float*>(y),
+                            ctl);
+  return pp_horner<double>(h, static_cast<const double*>(x), static_cast<const double*>(b), static_cast<double*>(y),
+                           ctl);
+}
 
 hipError_t launch_pp_arnoldi_apply(mdp_handle* h, bool basis_f32, int j, const void* xin, double* partials,
                                    int nb) {

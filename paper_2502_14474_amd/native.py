@@ -31,7 +31,7 @@ class EvalOpts(C.Structure):
     _fields_ = [("struct_size", C.c_size_t), ("inner", C.c_int32), ("restart", C.c_int32),
                 ("precision", C.c_int32), ("sync_every", C.c_int32), ("rtol", C.c_double),
                 ("max_iter", C.c_int64), ("precond_degree", C.c_int32), ("gs_passes", C.c_int32),
-                ("xcd_products", C.c_int32)]
+                ("policy_copy", C.c_int32)]
 
 
 class SolveOpts(C.Structure):
@@ -39,7 +39,7 @@ class SolveOpts(C.Structure):
                 ("precision", C.c_int32), ("sync_every", C.c_int32), ("alpha", C.c_double),
                 ("atol", C.c_double), ("rtol_cert", C.c_double), ("max_outer", C.c_int64),
                 ("max_inner", C.c_int64), ("launch", C.c_int32), ("precond_degree", C.c_int32),
-                ("gs_passes", C.c_int32), ("xcd_products", C.c_int32)]
+                ("gs_passes", C.c_int32), ("policy_copy", C.c_int32)]
 
 
 class Stats(C.Structure):

@@ -1,15 +1,16 @@
-"""The XCD-partitioned P_pi products of float64 GMRES (xcd_products): on
-handles that carry the column-blocked copy, policy evaluations and solves run
-their Arnoldi products on a copy of P_pi cut into column slices (one per XCD).
-They must match the oracle, match the plain products to rounding, be
-deterministic, and follow policy changes on the same handle."""
+"""The Arnoldi products on a per-policy copy of P_pi (policy_copy): on handles
+that carry the column-blocked copy the copy is cut into column slices (one per
+XCD), on other large handles it is P_pi stored contiguously.  Policy
+evaluations and solves through it must match the oracle, match the products
+through row_ptr to rounding, be deterministic, and follow policy changes on
+the same handle."""
 import sys
 
 import numpy as np
 import pytest
 
 import oracle
-from workloads import config2, config4, random_dense_mdp
+from workloads import config2, config3, config4, random_dense_mdp
 
 pytestmark = pytest.mark.gpu
 
@@ -40,7 +41,7 @@ def test_partitioned_products_match_oracle_and_plain_products(name, deg):
     out = {}
     with _mdp(inst, col_blocks=blocks) as h:
         for xcd in (-1, 0, -1):
-            v, st = h.policy_eval(pi, rtol=1e-13, max_iter=20000, precond_degree=deg, xcd_products=xcd)
+            v, st = h.policy_eval(pi, rtol=1e-13, max_iter=20000, precond_degree=deg, policy_copy=xcd)
             assert st["status"] == 0, st
             assert np.max(np.abs(v - v_ref)) / scale <= 1e-9, (xcd, st)
             if xcd in out:  # the same copy and policy again: bit for bit
@@ -85,8 +86,8 @@ def test_partitioned_products_in_two_passes():
     inst = config4(S=4_300_001, A=2, k=4, seed=6, workers=8)
     pi = np.random.default_rng(5).integers(0, inst.A, inst.S).astype(np.int32)
     with _mdp(inst, col_blocks=16) as h:
-        va, sa = h.policy_eval(pi, rtol=1e-12, max_iter=5000, xcd_products=-1)
-        vb, sb = h.policy_eval(pi, rtol=1e-12, max_iter=5000, xcd_products=0)
+        va, sa = h.policy_eval(pi, rtol=1e-12, max_iter=5000, policy_copy=-1)
+        vb, sb = h.policy_eval(pi, rtol=1e-12, max_iter=5000, policy_copy=0)
     assert sa["status"] == 0 and sb["status"] == 0
     scale = np.max(np.abs(vb))
     assert np.max(np.abs(va - vb)) / scale <= 1e-10
@@ -135,10 +136,70 @@ def test_partitioned_products_in_mixed_solves(name):
     Q = oracle.q_values(inst, ref["v"])
     with _mdp(inst, col_blocks=blocks) as h:
         for xcd in (-1, 0):
-            v, pi, st = h.solve(alpha=1e-2, precision=m.MDP_MIXED_FP32, rtol_cert=1e-10, xcd_products=xcd)
+            v, pi, st = h.solve(alpha=1e-2, precision=m.MDP_MIXED_FP32, rtol_cert=1e-10, policy_copy=xcd)
             assert st["status"] == 0, (xcd, st)
             err = np.max(np.abs(v - ref["v"]))
             assert err / scale <= 1e-9, (xcd, err / scale)
             tau = max(1e-9, 2 * inst.gamma * (err + 1e-11 * scale))
             pp = oracle.policy_parity(inst, Q, pi, ref["pi"], tau)
             assert pp["mismatch_outside_band"] == 0 and pp["not_tau_optimal"] == 0, (xcd, pp)
+
+
+WHOLE = {
+    # no column-blocked copy, at least 2^17 states, short rows: the contiguous copy
+    "c2_140k": lambda: config2(S=140_000, A=2, n_band=4, n_jump=2, seed=3),
+    "maze_370": lambda: config3(H=370, W=370, gamma=0.95, seed=2),
+}
+
+
+def _policy_residual(inst, pi, v):
+    """max |v - (g_pi + gamma P_pi v)| on the host, from the CSR arrays."""
+    rows = np.arange(inst.S) * inst.A + pi
+    lo, hi = inst.row_ptr[rows], inst.row_ptr[rows + 1]
+    k = hi - lo
+    idx = np.repeat(lo, k) + (np.arange(k.sum()) - np.repeat(np.cumsum(k) - k, k))
+    pv = np.add.reduceat(inst.val[idx] * v[inst.col[idx]], np.cumsum(k) - k)
+    return np.max(np.abs(v - (inst.cost[rows] + inst.gamma * pv)))
+
+
+@pytest.mark.parametrize("name", sorted(WHOLE))
+def test_contiguous_policy_copy_solves_the_policy_system(name):
+    """At these sizes the oracle's certified solves take minutes, so the
+    evaluations are checked against the policy's linear system itself (its
+    residual, on the host), the two product paths against each other, and a
+    mixed solve against the Bellman equation (the oracle's Q values)."""
+    import paper_2502_14474_amd as m
+    inst = WHOLE[name]()
+    assert inst.S >= 1 << 17
+    pi = np.random.default_rng(9).integers(0, inst.A, inst.S).astype(np.int32)
+    out = {}
+    with _mdp(inst) as h:
+        for copy in (-1, 0, -1):
+            v, st = h.policy_eval(pi, rtol=1e-13, max_iter=20000, policy_copy=copy)
+            assert st["status"] == 0, st
+            scale = np.max(np.abs(v))
+            assert _policy_residual(inst, pi, v) <= 1e-10 * scale, copy
+            if copy in out:
+                assert np.array_equal(v, out[copy])
+            out[copy] = v
+        v, p, st = h.solve(alpha=1e-2, precision=m.MDP_MIXED_FP32, atol=1e-9, rtol_cert=1e-10)
+    assert np.max(np.abs(out[-1] - out[0])) <= 1e-10 * np.max(np.abs(out[0]))
+    assert st["status"] == 0, st
+    Q = oracle.q_values(inst, v)
+    assert np.max(np.abs(Q.min(axis=1) - v)) <= 2e-9
+    chosen = Q[np.arange(inst.S), p]
+    assert np.all(chosen - Q.min(axis=1) <= 1e-9 * max(1.0, np.max(np.abs(v))))
+
+
+def test_contiguous_policy_copy_in_preconditioned_evaluations():
+    """The polynomial preconditioner's Horner products run on the copy too."""
+    inst = WHOLE["maze_370"]()
+    pi = np.random.default_rng(4).integers(0, inst.A, inst.S).astype(np.int32)
+    out = {}
+    with _mdp(inst) as h:
+        for copy in (-1, 0):
+            v, st = h.policy_eval(pi, rtol=1e-13, max_iter=20000, precond_degree=4, policy_copy=copy)
+            assert st["status"] == 0, st
+            assert _policy_residual(inst, pi, v) <= 1e-10 * np.max(np.abs(v)), copy
+            out[copy] = v
+    assert np.max(np.abs(out[-1] - out[0])) <= 1e-10 * np.max(np.abs(out[0]))
