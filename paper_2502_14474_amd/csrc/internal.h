@@ -357,6 +357,10 @@ hipError_t launch_pp_arnoldi_apply(mdp_handle* h, bool basis_f32, int j, const v
 // One Horner step y = b + gamma P_pi x of the polynomial preconditioner on
 // the copy (float64 or float32 vectors); ctl may be NULL.
 hipError_t launch_pp_horner(mdp_handle* h, bool f32, const void* x, const void* b, void* y, const Ctl* ctl);
+// The float64 residual g_pi - (x - gamma P_pi x) of a GMRES restart on the
+// copy, into y (float64 or float32) with the per-tile (max, sum of squares)
+// partials of the row_ptr kernel (nb tiles of kApplyTile states).
+hipError_t launch_pp_residual(mdp_handle* h, const double* x, void* y, bool y_f32, double4* partials, int nb);
 
 // dst[i] = src[i] for i < n, 64-bit row offsets narrowed to the stored 32-bit
 // ones (values checked on the host beforehand) (vecops.hip).

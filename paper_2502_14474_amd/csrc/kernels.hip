@@ -350,7 +350,10 @@ hipError_t launch_apply(mdp_handle* h, int mode, const int32_t* pi, const double
   const int nb = grid_for(h->S, kApplyTile);
   auto* part = reinterpret_cast<double4*>(h->part.buf);
   hipError_t e;
-  {
+  if (mode == kApplyRes && h->pp_ready && pi == h->pp_pi) {
+    Prof pf(h, MDP_K_POLICY_APPLY, bytes_apply(h, 8, 8, y_f32 ? 4 : 8));
+    e = launch_pp_residual(h, x, y, y_f32, part, nb);  // on the policy's copy
+  } else {
     Prof pf(h, MDP_K_POLICY_APPLY, bytes_apply(h, 8, 8, y_f32 ? 4 : 8));
     e = with_lanes(h->lanes, [&](auto Lc) -> hipError_t {
     constexpr int L = decltype(Lc)::value;

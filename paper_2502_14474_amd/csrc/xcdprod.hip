@@ -317,6 +317,34 @@ __global__ __launch_bounds__(kBlock) void k_pp_horner_finish(int64_t S, int nblk
   }
 }
 
+// The float64 residual r = g_pi - (x - gamma P_pi x) on the parts (a GMRES
+// restart), with each tile's (max |r|, sum r^2) partial, in the tiles and
+// layout of the row_ptr kernel.
+template <typename YT>
+__global__ __launch_bounds__(kBlock) void k_pp_residual_finish(int64_t S, int A, int nblk,
+                                                               const double* __restrict__ part,
+                                                               const double* __restrict__ cost,
+                                                               const int* __restrict__ pi,
+                                                               const double* __restrict__ x, double gamma,
+                                                               YT* __restrict__ y, double4* __restrict__ partials) {
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  const int64_t s0 = static_cast<int64_t>(tile) * kApplyTile;
+  const int ns = static_cast<int>(min<int64_t>(kApplyTile, S - s0));
+  double dmax = 0.0, dsum = 0.0;
+  for (int i = threadIdx.x; i < ns; i += kBlock) {
+    const int64_t s = s0 + i;
+    double pv = part[s];
+    for (int k = 1; k < nblk; ++k) pv += part[static_cast<int64_t>(k) * S + s];
+    const double gc = cost[row_of(s, pi[s], A, S)];
+    const double r = gc - (x[s] - gamma * pv);
+    y[s] = static_cast<YT>(r);
+    dmax = max_nan(dmax, fabs(r));
+    dsum = fma(r, r, dsum);
+  }
+  block_max_sum(dmax, dsum);
+  if (threadIdx.x == 0) partials[tile] = make_double4(dmax, dsum, 0.0, 0.0);
+}
+
 }  // namespace
 
 // Set up (first call) and form the copy for policy pi; h->pp_ready says
@@ -432,6 +460,20 @@ hipError_t pp_arnoldi_apply(mdp_handle* h, BT* Ub, int j, const BT* xin, double*
   return hipGetLastError();
 }
 }  // namespace
+
+hipError_t launch_pp_residual(mdp_handle* h, const double* x, void* y, bool y_f32, double4* partials, int nb) {
+  hipError_t e = pp_parts<double>(h, x, nullptr);
+  if (e != hipSuccess) return e;
+  if (y_f32)
+    k_pp_residual_finish<float><<<nb, kBlock, 0, h->stream>>>(h->S, h->A, h->pp_blocks, h->pp_part, h->cost,
+                                                              h->pp_pi, x, h->gamma, static_cast<float*>(y),
+                                                              partials);
+  else
+    k_pp_residual_finish<double><<<nb, kBlock, 0, h->stream>>>(h->S, h->A, h->pp_blocks, h->pp_part, h->cost,
+                                                               h->pp_pi, x, h->gamma, static_cast<double*>(y),
+                                                               partials);
+  return hipGetLastError();
+}
 
 hipError_t launch_pp_horner(mdp_handle* h, bool f32, const void* x, const void* b, void* y, const Ctl* ctl) {
   if (f32)
