@@ -134,6 +134,12 @@ __global__ __launch_bounds__(kBlock) void k_cb_scatter(int64_t rows, int tile_ro
 // in CSR order, started from 0, and continues across chunks.  Passes before
 // the last add the part into acc; the last forms Q = g + gamma (acc + part)
 // in LDS and finishes the tile like the plain sweep.
+// Nontemporal accesses for the running sums, the slice parts and the row starts: each is touched once per pass, and
+// kept out of the way they leave the L2 to the slice of the gathered vector
+// (on the 4M-state workload: sweep 11.7 -> 11.2 ms, product 809 -> 790 us).
+#ifndef MDP_NT_PARTS
+#define MDP_NT_PARTS 1
+#endif
 #ifndef MDP_CB_CHUNK
 #define MDP_CB_CHUNK 1024
 #endif
@@ -167,8 +173,13 @@ __device__ __forceinline__ void cb_tile_parts(int64_t S, int A, int tile_states,
   for (int k = 0; k < kCbRpt; ++k) {
     const int i = threadIdx.x + k * kBlock;
     const bool valid = i < nrows;
+#if MDP_NT_PARTS
+    const int a = __builtin_nontemporal_load(rl + (valid ? i : 0));
+    const int z = __builtin_nontemporal_load(rl + (i + 1 < nrows ? i + 1 : 0));
+#else
     const int a = rl[valid ? i : 0];
     const int z = rl[i + 1 < nrows ? i + 1 : 0];
+#endif
     st[k] = valid ? a : 0;
     en[k] = valid ? (i + 1 < nrows ? z : n) : 0;
     sum[k] = 0.0;
@@ -234,7 +245,11 @@ __global__ __launch_bounds__(kBlock) void k_bellman_cb(
 #pragma unroll
   for (int k = 0; k < kCbRpt; ++k) {
     const int i = threadIdx.x + k * kBlock;
+#if MDP_NT_PARTS
+    prev[k] = FIRST ? 0.0 : __builtin_nontemporal_load(acc + row0 + (i < nrows ? i : 0));
+#else
     prev[k] = FIRST ? 0.0 : acc[row0 + (i < nrows ? i : 0)];
+#endif
   }
   double sum[kCbRpt];
   cb_tile_parts(S, A, tile_states, ntiles, b, tile, rel, off, cb_col, cb_val, v, lp, lx, sum);
@@ -246,7 +261,11 @@ __global__ __launch_bounds__(kBlock) void k_bellman_cb(
     if (LAST) {
       q[(i % ns) * A + i / ns] = fma(gamma, total, cost[row0 + i]);  // stored row -> (state, action)
     } else {
+#if MDP_NT_PARTS
+      __builtin_nontemporal_store(total, acc + row0 + i);
+#else
       acc[row0 + i] = total;
+#endif
     }
   }
   if (LAST) {
@@ -276,7 +295,11 @@ __global__ __launch_bounds__(kBlock) void k_bellman_cb_xcd(
 #pragma unroll
   for (int k = 0; k < kCbRpt; ++k) {
     const int i = threadIdx.x + k * kBlock;
+#if MDP_NT_PARTS
+    if (i < nrows) __builtin_nontemporal_store(sum[k], out + i);
+#else
     if (i < nrows) out[i] = sum[k];
+#endif
   }
 }
 

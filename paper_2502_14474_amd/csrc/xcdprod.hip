@@ -37,6 +37,12 @@ namespace {
 constexpr int kPPTile = 4 * kBlock;                    // states per tile (4 per thread)
 constexpr int kPPMaxBlocks = 16;                       // slices (two passes)
 constexpr int64_t kPPSliceBytes = int64_t{4} << 20;   // x bytes per slice: one XCD's L2
+// Nontemporal accesses for the slice parts and the state starts: each is touched once per pass, and
+// kept out of the way they leave the L2 to the slice of the gathered vector
+// (on the 4M-state workload: sweep 11.7 -> 11.2 ms, product 809 -> 790 us).
+#ifndef MDP_NT_PARTS
+#define MDP_NT_PARTS 1
+#endif
 #ifndef MDP_PP_CHUNK
 #define MDP_PP_CHUNK 1024
 #endif
@@ -170,7 +176,7 @@ __global__ __launch_bounds__(kBlock) void k_pp_scatter(int64_t S, int A, RowInde
       const int first = __shfl(next, (threadIdx.x % kWave) - hl + (b < 0 ? 0 : b));
       if (valid) {
         const int d = first + __popc(same & ((1u << hl) - 1u));
-        pcol[d] = c;
+        pcol[d] = c;  // plain stores: the L2 gathers the short runs into whole lines
         pval[d] = v;
       }
       next += add;
@@ -214,8 +220,13 @@ __global__ __launch_bounds__(kBlock) void k_pp_product(int64_t S, int nblk, int 
   for (int k = 0; k < 4; ++k) {
     const int i = threadIdx.x + k * kBlock;
     const bool valid = i < ns;
+#if MDP_NT_PARTS
+    const int a = __builtin_nontemporal_load(rl + (valid ? i : 0));
+    const int z = __builtin_nontemporal_load(rl + (i + 1 < ns ? i + 1 : 0));
+#else
     const int a = rl[valid ? i : 0];
     const int z = rl[i + 1 < ns ? i + 1 : 0];
+#endif
     st[k] = valid ? a : 0;
     en[k] = valid ? (i + 1 < ns ? z : n) : 0;
     sum[k] = 0.0;
@@ -262,7 +273,11 @@ __global__ __launch_bounds__(kBlock) void k_pp_product(int64_t S, int nblk, int 
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
     const int i = threadIdx.x + k * kBlock;
+#if MDP_NT_PARTS
+    if (i < ns) __builtin_nontemporal_store(sum[k], part + static_cast<int64_t>(b) * S + s0 + i);
+#else
     if (i < ns) part[static_cast<int64_t>(b) * S + s0 + i] = sum[k];
+#endif
   }
 }
 
