@@ -957,11 +957,9 @@ mdp_status mdp_destroy(mdp_t h) {
   dev_free(h, h->pp_col);
   dev_free(h, h->pp_val);
   dev_free(h, h->pp_rel);
-  dev_free(h, h->pp_tsum);
-  dev_free(h, h->pp_off);
+  dev_free(h, h->pp_seg);
   dev_free(h, h->pp_part);
-  dev_free(h, h->pp_stat);
-  dev_free(h, h->pp_tmp);
+  dev_free(h, h->pp_fill);
   ctl_slot_give(h->ctl_host);
   prof_resolve(h);
   {

@@ -319,8 +319,13 @@ __global__ __launch_bounds__(kBlock) void k_bellman_cb_sum(
   const int nrows = ns * A;
   const int64_t row0 = s0 * A;
   for (int i = threadIdx.x; i < nrows; i += kBlock) {
+#if MDP_NT_PARTS
+    double total = __builtin_nontemporal_load(acc + row0 + i);
+    for (int b = 1; b < nblk; ++b) total = total + __builtin_nontemporal_load(acc + static_cast<int64_t>(b) * rows + row0 + i);
+#else
     double total = acc[row0 + i];
     for (int b = 1; b < nblk; ++b) total = total + acc[static_cast<int64_t>(b) * rows + row0 + i];
+#endif
     q[(i % ns) * A + i / ns] = fma(gamma, total, cost[row0 + i]);
   }
   __syncthreads();

@@ -200,13 +200,10 @@ struct mdp_handle {
   int64_t pp_cap = 0;
   int* pp_col = nullptr;
   double* pp_val = nullptr;
-  uint16_t* pp_rel = nullptr;
-  int* pp_tsum = nullptr;
-  int* pp_off = nullptr;
-  double* pp_part = nullptr;
-  unsigned* pp_stat = nullptr;
-  void* pp_tmp = nullptr;
-  size_t pp_tmp_bytes = 0;
+  uint16_t* pp_rel = nullptr;   // pp_blocks x S: state start inside its tile's segment
+  int2* pp_seg = nullptr;       // pp_blocks x pp_ntiles: (first entry, length) of a segment
+  double* pp_part = nullptr;    // pp_blocks x S: slice parts of a product
+  int* pp_fill = nullptr;       // entries placed so far while the copy is formed
   const int32_t* pp_pi = nullptr;
   int64_t pp_gen = -1, pi_gen = 0;
 

@@ -18,14 +18,13 @@
 // tile, and the product streams each tile's rows as one segment, which reads
 // fewer partly used lines than gathering the selected rows through row_ptr.
 //
-// The copy is formed once per policy: a count kernel (entries of each tile in
-// each slice), a device scan of those counts into segment offsets, and a
-// scatter kernel that walks each selected row once, in CSR order, so inside a
-// slice a state's entries keep their CSR order.  A state's part in a slice is
+// The copy is formed once per policy, with no host round trip: a placing
+// kernel (entries of each state in each slice, each state's start in its
+// tile's segments, the segments placed by atomic adds) and a scatter kernel
+// that walks each selected row once, in CSR order, so inside a slice a
+// state's entries keep their CSR order.  A state's part in a slice is
 // the fma chain over its entries there, started from 0, and the parts are
 // added in slice order: results are deterministic.
-#include <hipcub/hipcub.hpp>
-
 #include <algorithm>
 
 #include "device.h"
@@ -70,6 +69,15 @@ __device__ __forceinline__ void selected_row(int64_t s, const int* __restrict__ 
 // are loaded before the current pair is worked on.
 constexpr int kPPWaves = kBlock / kWave;
 
+// A state's part in slice k (read once).
+__device__ __forceinline__ double ld_part(const double* __restrict__ part, int64_t S, int k, int64_t s) {
+#if MDP_NT_PARTS
+  return __builtin_nontemporal_load(part + static_cast<int64_t>(k) * S + s);
+#else
+  return part[static_cast<int64_t>(k) * S + s];
+#endif
+}
+
 __device__ __forceinline__ uint32_t half_ballot(bool p, int half) {
   return static_cast<uint32_t>(__ballot(p) >> (32 * half));
 }
@@ -92,24 +100,24 @@ __device__ __forceinline__ void walk_pairs(int64_t S, int A, RowIndex rix, const
   }
 }
 
-// Per tile t: rel[b * S + s] = start of state s's entries inside the tile's
-// segment of slice b (exclusive scan of the per-state counts), tsum[b *
-// ntiles + t] = the segment's length; stat[0] = longest segment, stat[1] =
-// longest selected row.  rel is meaningful only when both fit (segments
-// shorter than 65536, rows shorter than 256; checked on the host).
-__global__ __launch_bounds__(kBlock) void k_pp_count(int64_t S, int A, RowIndex rix, const int* __restrict__ col,
+// Forming the copy, first kernel (tile t): per-state slice counts, each
+// state's start inside the tile's segment of each slice (rel[b * S + s]), and
+// one atomic add per slice on *fill that places the segment in the copy
+// (seg[b * ntiles + t] = first entry, length).  Where a segment lands depends
+// on the order of the atomic adds; what it holds does not, nor does any sum.
+// Needs rows of at most 255 entries and at most 65535 entries per segment
+// (guaranteed on the host from the longest row of the MDP).
+__global__ __launch_bounds__(kBlock) void k_pp_place(int64_t S, int A, RowIndex rix, const int* __restrict__ col,
                                                      const int* __restrict__ pi, int slice, int nblk, int ntiles,
-                                                     int* __restrict__ tsum, uint16_t* __restrict__ rel,
-                                                     unsigned* __restrict__ stat) {
+                                                     uint16_t* __restrict__ rel, int2* __restrict__ seg,
+                                                     int* __restrict__ fill) {
   __shared__ uint8_t c8[kPPMaxBlocks][kPPTile];
   __shared__ int pos[kPPTile + 1];
   const int t = blockIdx.x;
   const int64_t s0 = static_cast<int64_t>(t) * kPPTile;
   const int ns = static_cast<int>(min<int64_t>(kPPTile, S - s0));
   const int hl = threadIdx.x % 32, half = (threadIdx.x % kWave) / 32;
-  int longest = 0;
   walk_pairs(S, A, rix, pi, s0, ns, [&](int i, int a, int n) {
-    longest = max(longest, n);
     const int nmax = max(n, __shfl_xor(n, 32));
     int cnt = 0;  // lane hl < nblk: entries of slice hl
     for (int c0 = 0; c0 < nmax; c0 += 32) {
@@ -119,11 +127,9 @@ __global__ __launch_bounds__(kBlock) void k_pp_count(int64_t S, int A, RowIndex 
         if (hl == bb) cnt += __popc(m);
       }
     }
-    if (i < ns && hl < nblk) c8[hl][i] = static_cast<uint8_t>(min(cnt, 255));
+    if (i < ns && hl < nblk) c8[hl][i] = static_cast<uint8_t>(cnt);
   });
-  double mx = static_cast<double>(longest), sm = 0.0;
-  block_max_sum(mx, sm);  // its barrier also publishes c8
-  if (threadIdx.x == 0) atomicMax(stat + 1, static_cast<unsigned>(mx));
+  __syncthreads();
   for (int b = 0; b < nblk; ++b) {
     for (int i = threadIdx.x; i < ns; i += kBlock) pos[i] = c8[b][i];
     __syncthreads();
@@ -131,21 +137,21 @@ __global__ __launch_bounds__(kBlock) void k_pp_count(int64_t S, int A, RowIndex 
     for (int i = threadIdx.x; i < ns; i += kBlock)
       rel[static_cast<int64_t>(b) * S + s0 + i] = static_cast<uint16_t>(pos[i]);
     if (threadIdx.x == 0) {
-      tsum[static_cast<int64_t>(b) * ntiles + t] = pos[ns];
-      atomicMax(stat, static_cast<unsigned>(pos[ns]));
+      const int len = pos[ns];
+      seg[static_cast<int64_t>(b) * ntiles + t] = make_int2(atomicAdd(fill, len), len);
     }
     __syncthreads();
   }
 }
 
-// Scatter the selected rows of tile t into their slice segments.  An entry's
-// place is its segment's start, its state's start there (rel), the entries of
-// its state and slice in earlier chunks of the row, and those before it in
-// its chunk (from the ballot), so each state keeps its CSR order inside every
-// slice.
+// Forming the copy, second kernel: the selected rows of tile t scattered into
+// the tile's segments.  An entry's place is its segment's start, its state's
+// start there (rel), the entries of its state and slice in earlier chunks of
+// the row, and those before it in its chunk (from the ballot), so each state
+// keeps its CSR order inside every slice.
 __global__ __launch_bounds__(kBlock) void k_pp_scatter(int64_t S, int A, RowIndex rix, const int* __restrict__ col,
                                                        const double* __restrict__ val, const int* __restrict__ pi,
-                                                       int slice, int nblk, int ntiles, const int* __restrict__ off,
+                                                       int slice, int nblk, int ntiles, const int2* __restrict__ seg,
                                                        const uint16_t* __restrict__ rel, int* __restrict__ pcol,
                                                        double* __restrict__ pval) {
   __shared__ int base[kPPMaxBlocks];
@@ -153,12 +159,11 @@ __global__ __launch_bounds__(kBlock) void k_pp_scatter(int64_t S, int A, RowInde
   const int64_t s0 = static_cast<int64_t>(t) * kPPTile;
   const int ns = static_cast<int>(min<int64_t>(kPPTile, S - s0));
   const int hl = threadIdx.x % 32, half = (threadIdx.x % kWave) / 32;
-  if (threadIdx.x < nblk) base[threadIdx.x] = off[static_cast<int64_t>(threadIdx.x) * ntiles + t];
+  if (threadIdx.x < nblk) base[threadIdx.x] = seg[static_cast<int64_t>(threadIdx.x) * ntiles + t].x;
   __syncthreads();
   walk_pairs(S, A, rix, pi, s0, ns, [&](int i, int a, int n) {
     const int nmax = max(n, __shfl_xor(n, 32));
-    // lane hl < nblk: the state's first place in slice hl, advanced by the
-    // entries of slice hl placed so far
+    // lane hl < nblk: the state's next place in slice hl
     int next = (i < ns && hl < nblk) ? base[hl] + rel[static_cast<int64_t>(hl) * S + s0 + i] : 0;
     for (int c0 = 0; c0 < nmax; c0 += 32) {
       const bool valid = c0 + hl < n;
@@ -184,6 +189,18 @@ __global__ __launch_bounds__(kBlock) void k_pp_scatter(int64_t S, int A, RowInde
   });
 }
 
+// The longest row of the MDP (stored offsets), into *out.
+__global__ __launch_bounds__(kBlock) void k_longest_row(const int* __restrict__ rp, int64_t rows,
+                                                        unsigned* __restrict__ out) {
+  int m = 0;
+  for (int64_t r = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; r < rows;
+       r += static_cast<int64_t>(gridDim.x) * kBlock)
+    m = max(m, rp[r + 1] - rp[r]);
+  double mx = static_cast<double>(m), sm = 0.0;
+  block_max_sum(mx, sm);
+  if (threadIdx.x == 0) atomicMax(out, static_cast<unsigned>(mx));
+}
+
 // Slice parts of P_pi x: workgroup w takes slice pass * 8 + w % 8 of tile w / 8
 // and writes part[b * S + s] for the tile's states.  The segment is streamed in
 // chunks of kPPChunk entries: every thread loads every kBlock-th entry
@@ -193,7 +210,7 @@ __global__ __launch_bounds__(kBlock) void k_pp_scatter(int64_t S, int A, RowInde
 // done.
 template <typename XT>
 __global__ __launch_bounds__(kBlock) void k_pp_product(int64_t S, int nblk, int ntiles, int pass,
-                                                       const uint16_t* __restrict__ rel, const int* __restrict__ off,
+                                                       const uint16_t* __restrict__ rel, const int2* __restrict__ seg,
                                                        const int* __restrict__ pcol, const double* __restrict__ pval,
                                                        const XT* __restrict__ x, double* __restrict__ part,
                                                        const Ctl* __restrict__ ctl) {
@@ -207,9 +224,9 @@ __global__ __launch_bounds__(kBlock) void k_pp_product(int64_t S, int nblk, int 
   if (b >= nblk || t >= ntiles) return;  // the same for the whole workgroup
   const int64_t s0 = static_cast<int64_t>(t) * kPPTile;
   const int ns = static_cast<int>(min<int64_t>(kPPTile, S - s0));
-  const int64_t ob = static_cast<int64_t>(b) * ntiles + t;
-  const int seg0 = off[ob];
-  const int n = off[ob + 1] - seg0;
+  const int2 sg = seg[static_cast<int64_t>(b) * ntiles + t];
+  const int seg0 = sg.x;
+  const int n = sg.y;
   const uint16_t* __restrict__ rl = rel + static_cast<int64_t>(b) * S + s0;
   const int* __restrict__ cc = pcol + seg0;
   const double* __restrict__ cv = pval + seg0;
@@ -303,8 +320,8 @@ __global__ __launch_bounds__(kBlock) void k_pp_arnoldi_finish(int64_t S, int nbl
   const double cj = ctl->scale[j];
   for (int i = threadIdx.x; i < ns; i += kBlock) {
     const int64_t s = s0 + i;
-    double pv = part[s];
-    for (int b = 1; b < nblk; ++b) pv += part[static_cast<int64_t>(b) * S + s];
+    double pv = ld_part(part, S, 0, s);
+    for (int b = 1; b < nblk; ++b) pv += ld_part(part, S, b, s);
     const AT av = static_cast<AT>(xj[s]) - gam * static_cast<AT>(pv);
     const BT wv = static_cast<BT>(cj * static_cast<double>(av));
     w[s] = wv;
@@ -326,8 +343,8 @@ __global__ __launch_bounds__(kBlock) void k_pp_horner_finish(int64_t S, int nblk
   const AT gam = static_cast<AT>(gamma);
   for (int64_t s = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; s < S;
        s += static_cast<int64_t>(gridDim.x) * kBlock) {
-    double pv = part[s];
-    for (int k = 1; k < nblk; ++k) pv += part[static_cast<int64_t>(k) * S + s];
+    double pv = ld_part(part, S, 0, s);
+    for (int k = 1; k < nblk; ++k) pv += ld_part(part, S, k, s);
     y[s] = static_cast<XT>(fma(gam, static_cast<AT>(pv), static_cast<AT>(b[s])));
   }
 }
@@ -348,8 +365,8 @@ __global__ __launch_bounds__(kBlock) void k_pp_residual_finish(int64_t S, int A,
   double dmax = 0.0, dsum = 0.0;
   for (int i = threadIdx.x; i < ns; i += kBlock) {
     const int64_t s = s0 + i;
-    double pv = part[s];
-    for (int k = 1; k < nblk; ++k) pv += part[static_cast<int64_t>(k) * S + s];
+    double pv = ld_part(part, S, 0, s);
+    for (int k = 1; k < nblk; ++k) pv += ld_part(part, S, k, s);
     const double gc = cost[row_of(s, pi[s], A, S)];
     const double r = gc - (x[s] - gamma * pv);
     y[s] = static_cast<YT>(r);
@@ -380,61 +397,55 @@ hipError_t pp_prepare(mdp_handle* h, const int32_t* pi) {
                            (kNumXcd * kPPSliceBytes);
     const int64_t nblk = h->cb_blocks > 0 ? kNumXcd * passes : 1;
     const int64_t ntiles = (S + kPPTile - 1) / kPPTile;
-    if (nblk > kPPMaxBlocks || nblk * ntiles + 1 > (int64_t{1} << 30)) {
+    if (nblk > kPPMaxBlocks || nblk * ntiles > (int64_t{1} << 30)) {
+      h->pp_state = -1;
+      return hipSuccess;
+    }
+    // the longest row bounds every per-state count (8 bits) and every tile
+    // segment (16 bits), and the copy's size
+    hipError_t e = handle_alloc(h, reinterpret_cast<void**>(&h->pp_fill), 4 * sizeof(int));
+    if (e != hipSuccess) return e;
+    int64_t kmax = h->kfix;
+    if (kmax == 0) {
+      unsigned longest = 0;
+      e = hipMemsetAsync(h->pp_fill, 0, sizeof(unsigned), h->stream);
+      if (e == hipSuccess) {
+        const int64_t g = std::min<int64_t>(4096, (h->rows + kBlock - 1) / kBlock);
+        k_longest_row<<<static_cast<unsigned>(g), kBlock, 0, h->stream>>>(h->row_ptr, h->rows,
+                                                                         reinterpret_cast<unsigned*>(h->pp_fill));
+        e = hipGetLastError();
+      }
+      if (e == hipSuccess) e = copy_out(&longest, h->pp_fill, sizeof(unsigned), h->stream);
+      if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+      if (e != hipSuccess) return e;
+      kmax = longest;
+    }
+    if (kmax > 255 || kmax * kPPTile > 65535) {
       h->pp_state = -1;
       return hipSuccess;
     }
     h->pp_blocks = static_cast<int>(nblk);
     h->pp_slice = static_cast<int>((S + nblk - 1) / nblk);
     h->pp_ntiles = static_cast<int>(ntiles);
-    const int64_t nseg = nblk * ntiles + 1;
-    hipError_t e = handle_alloc(h, reinterpret_cast<void**>(&h->pp_rel), nblk * S * sizeof(uint16_t));
-    if (e == hipSuccess) e = handle_alloc(h, reinterpret_cast<void**>(&h->pp_tsum), nseg * sizeof(int));
-    if (e == hipSuccess) e = handle_alloc(h, reinterpret_cast<void**>(&h->pp_off), nseg * sizeof(int));
+    h->pp_cap = std::min<int64_t>(h->nnz, S * kmax);
+    e = handle_alloc(h, reinterpret_cast<void**>(&h->pp_rel), nblk * S * sizeof(uint16_t));
+    if (e == hipSuccess) e = handle_alloc(h, reinterpret_cast<void**>(&h->pp_seg), nblk * ntiles * sizeof(int2));
     if (e == hipSuccess) e = handle_alloc(h, reinterpret_cast<void**>(&h->pp_part), nblk * S * sizeof(double));
-    if (e == hipSuccess) e = handle_alloc(h, reinterpret_cast<void**>(&h->pp_stat), 4 * sizeof(unsigned));
-    if (e == hipSuccess)
-      e = hipcub::DeviceScan::ExclusiveSum(nullptr, h->pp_tmp_bytes, h->pp_tsum, h->pp_off,
-                                           static_cast<int>(nseg), h->stream);
-    if (e == hipSuccess) e = handle_alloc(h, &h->pp_tmp, h->pp_tmp_bytes);
-    // the scan's last input stays 0, so its output is the total
-    if (e == hipSuccess) e = hipMemsetAsync(h->pp_tsum + nseg - 1, 0, sizeof(int), h->stream);
+    if (e == hipSuccess) e = handle_alloc(h, reinterpret_cast<void**>(&h->pp_col), h->pp_cap * sizeof(int));
+    if (e == hipSuccess) e = handle_alloc(h, reinterpret_cast<void**>(&h->pp_val), h->pp_cap * sizeof(double));
     if (e != hipSuccess) return e;
-    h->device_bytes += static_cast<int64_t>(nblk * S * (sizeof(uint16_t) + sizeof(double)) + 2 * nseg * sizeof(int));
+    h->device_bytes += static_cast<int64_t>(nblk * S * (sizeof(uint16_t) + sizeof(double)) +
+                                            nblk * ntiles * sizeof(int2) + h->pp_cap * 12);
     h->pp_state = 1;
   }
-  const int nblk = h->pp_blocks, ntiles = h->pp_ntiles;
-  const int64_t nseg = static_cast<int64_t>(nblk) * ntiles + 1;
+  // no host round trip: the segments are placed by atomic adds
   const RowIndex rix{h->row_ptr, h->kfix};
-  hipError_t e = hipMemsetAsync(h->pp_stat, 0, 2 * sizeof(unsigned), h->stream);
+  hipError_t e = hipMemsetAsync(h->pp_fill, 0, sizeof(int), h->stream);
   if (e != hipSuccess) return e;
-  k_pp_count<<<ntiles, kBlock, 0, h->stream>>>(S, h->A, rix, h->col, pi, h->pp_slice, nblk, ntiles, h->pp_tsum,
-                                               h->pp_rel, h->pp_stat);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
-  e = hipcub::DeviceScan::ExclusiveSum(h->pp_tmp, h->pp_tmp_bytes, h->pp_tsum, h->pp_off, static_cast<int>(nseg),
-                                       h->stream);
-  if (e != hipSuccess) return e;
-  // largest segment, longest row and the total entries, to the host
-  unsigned stat[2] = {0, 0};
-  int total = 0;
-  if ((e = copy_out(stat, h->pp_stat, sizeof(stat), h->stream)) != hipSuccess) return e;
-  if ((e = copy_out(&total, h->pp_off + nseg - 1, sizeof(int), h->stream)) != hipSuccess) return e;
-  if ((e = hipStreamSynchronize(h->stream)) != hipSuccess) return e;
-  if (stat[0] > 65535u || stat[1] > 255u) return hipSuccess;  // not for this policy: plain products
-  if (total > h->pp_cap) {
-    handle_free(h, h->pp_col);
-    handle_free(h, h->pp_val);
-    h->pp_col = nullptr;
-    h->pp_val = nullptr;
-    h->pp_cap = 0;
-    const int64_t cap = std::min<int64_t>(h->nnz, static_cast<int64_t>(total) + total / 4 + 1024);
-    e = handle_alloc(h, reinterpret_cast<void**>(&h->pp_col), cap * sizeof(int));
-    if (e == hipSuccess) e = handle_alloc(h, reinterpret_cast<void**>(&h->pp_val), cap * sizeof(double));
-    if (e != hipSuccess) return e;
-    h->pp_cap = cap;
-  }
-  k_pp_scatter<<<ntiles, kBlock, 0, h->stream>>>(S, h->A, rix, h->col, h->val, pi, h->pp_slice, nblk, ntiles,
-                                                 h->pp_off, h->pp_rel, h->pp_col, h->pp_val);
+  k_pp_place<<<h->pp_ntiles, kBlock, 0, h->stream>>>(S, h->A, rix, h->col, pi, h->pp_slice, h->pp_blocks,
+                                                     h->pp_ntiles, h->pp_rel, h->pp_seg, h->pp_fill);
+  k_pp_scatter<<<h->pp_ntiles, kBlock, 0, h->stream>>>(S, h->A, rix, h->col, h->val, pi, h->pp_slice, h->pp_blocks,
+                                                       h->pp_ntiles, h->pp_seg, h->pp_rel, h->pp_col, h->pp_val);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   h->pp_pi = pi;
   h->pp_gen = h->pi_gen;
@@ -450,7 +461,7 @@ hipError_t pp_parts(mdp_handle* h, const XT* x, const Ctl* ctl) {
   const int64_t grid = (sliced ? static_cast<int64_t>(kNumXcd) : int64_t{1}) * h->pp_ntiles;
   for (int p = 0; p < passes; ++p) {
     k_pp_product<XT><<<static_cast<unsigned>(grid), kBlock, 0, h->stream>>>(
-        h->S, h->pp_blocks, h->pp_ntiles, p, h->pp_rel, h->pp_off, h->pp_col, h->pp_val, x, h->pp_part, ctl);
+        h->S, h->pp_blocks, h->pp_ntiles, p, h->pp_rel, h->pp_seg, h->pp_col, h->pp_val, x, h->pp_part, ctl);
   }
   return hipGetLastError();
 }
