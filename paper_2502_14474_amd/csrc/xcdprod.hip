@@ -82,21 +82,40 @@ __device__ __forceinline__ uint32_t half_ballot(bool p, int half) {
   return static_cast<uint32_t>(__ballot(p) >> (32 * half));
 }
 
-// Walk the tile's selected rows in pairs: body(i, a, n) for this half's state
-// i (a = first entry, n = entries; n = 0 past the tile).
-template <typename Body>
+// Walk the tile's selected rows in pairs: body(i, a, n, cf, vf) for this
+// half's state i (a = first entry, n = entries; n = 0 past the tile), with the
+// row's first chunk of columns (and, VAL, values) already loaded into cf, vf
+// (lane hl: entry hl, when hl < n).  The wavefronts take pairs in turn, so the
+// workgroup reads neighbouring rows together (giving each wavefront a
+// contiguous quarter of the tile made the scatter 16% slower).  Loads run two
+// pairs ahead for the row bounds and one pair ahead for the first chunk, so
+// they overlap the work on the current pair.
+template <bool VAL, typename Body>
 __device__ __forceinline__ void walk_pairs(int64_t S, int A, RowIndex rix, const int* __restrict__ pi, int64_t s0,
-                                           int ns, Body body) {
-  const int half = (threadIdx.x % kWave) / 32, wave = threadIdx.x / kWave;
-  int i = 2 * wave + half;
+                                           int ns, const int* __restrict__ col, const double* __restrict__ val,
+                                           Body body) {
+  const int half = (threadIdx.x % kWave) / 32, wave = threadIdx.x / kWave, hl = threadIdx.x % 32;
+  constexpr int kStep = 2 * kPPWaves;
+  const int lo = 2 * wave, hi = ns;
+  int i = lo + half;
   int a = 0, e = 0;
-  if (i < ns) selected_row(s0 + i, pi, A, S, rix, &a, &e);
-  for (int i0 = 2 * wave; i0 < ns; i0 += 2 * kPPWaves) {
-    const int ia = a, na = e - a, ic = i;
-    i += 2 * kPPWaves;
-    a = e = 0;
-    if (i < ns) selected_row(s0 + i, pi, A, S, rix, &a, &e);
-    body(ic, ia, na);
+  if (i < hi) selected_row(s0 + i, pi, A, S, rix, &a, &e);
+  int cf = hl < e - a ? col[a + hl] : 0;
+  double vf = VAL && hl < e - a ? val[a + hl] : 0.0;
+  int a1 = 0, e1 = 0;
+  if (i + kStep < hi) selected_row(s0 + i + kStep, pi, A, S, rix, &a1, &e1);
+  for (int i0 = lo; i0 < hi; i0 += kStep) {
+    const int ic = i, ia = a, na = e - a, cc = cf;
+    const double vc = vf;
+    // the next pair's first chunk, and the pair after's bounds
+    i += kStep;
+    a = a1;
+    e = e1;
+    cf = hl < e - a ? col[a + hl] : 0;
+    vf = VAL && hl < e - a ? val[a + hl] : 0.0;
+    a1 = e1 = 0;
+    if (i + kStep < hi) selected_row(s0 + i + kStep, pi, A, S, rix, &a1, &e1);
+    body(ic, ia, na, cc, vc);
   }
 }
 
@@ -117,11 +136,11 @@ __global__ __launch_bounds__(kBlock) void k_pp_place(int64_t S, int A, RowIndex 
   const int64_t s0 = static_cast<int64_t>(t) * kPPTile;
   const int ns = static_cast<int>(min<int64_t>(kPPTile, S - s0));
   const int hl = threadIdx.x % 32, half = (threadIdx.x % kWave) / 32;
-  walk_pairs(S, A, rix, pi, s0, ns, [&](int i, int a, int n) {
+  walk_pairs<false>(S, A, rix, pi, s0, ns, col, nullptr, [&](int i, int a, int n, int cf, double) {
     const int nmax = max(n, __shfl_xor(n, 32));
     int cnt = 0;  // lane hl < nblk: entries of slice hl
     for (int c0 = 0; c0 < nmax; c0 += 32) {
-      const int b = c0 + hl < n ? col[a + c0 + hl] / slice : -1;
+      const int b = c0 + hl < n ? (c0 == 0 ? cf : col[a + c0 + hl]) / slice : -1;
       for (int bb = 0; bb < nblk; ++bb) {
         const uint32_t m = half_ballot(b == bb, half);
         if (hl == bb) cnt += __popc(m);
@@ -161,15 +180,15 @@ __global__ __launch_bounds__(kBlock) void k_pp_scatter(int64_t S, int A, RowInde
   const int hl = threadIdx.x % 32, half = (threadIdx.x % kWave) / 32;
   if (threadIdx.x < nblk) base[threadIdx.x] = seg[static_cast<int64_t>(threadIdx.x) * ntiles + t].x;
   __syncthreads();
-  walk_pairs(S, A, rix, pi, s0, ns, [&](int i, int a, int n) {
+  walk_pairs<true>(S, A, rix, pi, s0, ns, col, val, [&](int i, int a, int n, int cf, double vf) {
     const int nmax = max(n, __shfl_xor(n, 32));
     // lane hl < nblk: the state's next place in slice hl
     int next = (i < ns && hl < nblk) ? base[hl] + rel[static_cast<int64_t>(hl) * S + s0 + i] : 0;
     for (int c0 = 0; c0 < nmax; c0 += 32) {
       const bool valid = c0 + hl < n;
       const int q = a + c0 + hl;
-      const int c = valid ? col[q] : 0;
-      const double v = valid ? val[q] : 0.0;
+      const int c = valid ? (c0 == 0 ? cf : col[q]) : 0;
+      const double v = valid ? (c0 == 0 ? vf : val[q]) : 0.0;
       const int b = valid ? c / slice : -1;
       uint32_t same = 0;
       int add = 0;
