@@ -99,12 +99,16 @@ typedef struct {
                              otherwise a power of two in [2, 64] */
   int32_t col_blocks;     /* column-blocked copy of P for the float64 sweep: -1 (default)
                              builds one when S >= 2^21 and at least half of the entries lie
-                             outside their row's column slice (slices of 2.75 MB of v);
-                             0: never; n >= 1: always, with n slices (MDP_E_NOTSUP if a
+                             outside their row's column slice (slices of 2.75 MB of v); without
+                             one, handles of at least 2^17 states with at most 8 entries per row
+                             on average stream each tile's rows as one segment in the float64
+                             sweep (no copy); 0: never either, every sweep gathers row by row;
+                             n >= 1: always the blocked copy, with n slices (MDP_E_NOTSUP if a
                              row holds more than 255 entries of one slice, its columns are
-                             not in increasing slice order, or A > 1024).  The blocked
-                             sweep takes a row's sum slice by slice, so its rounding
-                             differs from the plain sweep's within the usual bound. */
+                             not in increasing slice order, or A > 1024).  The blocked and
+                             streamed sweeps take a row's sum as one fma chain (per slice), so
+                             their rounding differs from the row-by-row sweep's within the
+                             usual bound. */
   int32_t objective;      /* MDP_MINIMIZE_COST (default): minimise expected discounted cost, as
                              in the paper's problem statement; MDP_MAXIMIZE_REWARD: `cost`
                              holds rewards and every value vector passed in or out (v0, v,

@@ -274,6 +274,91 @@ __global__ __launch_bounds__(kBlock) void k_bellman_cb(
   }
 }
 
+// The float64 sweep streamed tile by tile over the CSR rows themselves, for
+// MDPs with short rows: a tile's rows are contiguous in the stored order, so
+// its entries form one segment, streamed in chunks through LDS as a slice
+// segment is above, and each row's sum is the fma chain over its entries in
+// CSR order (the one-slice blocked sweep, without a copy).  With a few
+// entries per row this leaves no lane of a row group idle.
+template <typename RT>
+__global__ __launch_bounds__(kBlock) void k_bellman_flat(int64_t S, int A, int tile_states,
+                                                         const int* __restrict__ row_ptr, const int* __restrict__ col,
+                                                         const double* __restrict__ val,
+                                                         const double* __restrict__ cost,
+                                                         const double* __restrict__ v, double gamma,
+                                                         double* __restrict__ Tv, int* __restrict__ pi,
+                                                         RT* __restrict__ r0, double4* __restrict__ partials) {
+  extern __shared__ double q[];  // one value per row of the tile
+  __shared__ double lp[kCbChunk], lx[kCbChunk];
+  constexpr int EPT = kCbChunk / kBlock;
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  const int64_t s0 = static_cast<int64_t>(tile) * tile_states;
+  const int ns = static_cast<int>(min<int64_t>(tile_states, S - s0));
+  const int nrows = ns * A;
+  const int64_t row0 = s0 * A;
+  const int base = row_ptr[row0];
+  const int n = row_ptr[row0 + nrows] - base;
+  const int* __restrict__ cc = col + base;
+  const double* __restrict__ cv = val + base;
+  const Gather<double> gx(v, S);
+  int st[kCbRpt], en[kCbRpt];
+  double sum[kCbRpt];
+#pragma unroll
+  for (int k = 0; k < kCbRpt; ++k) {
+    const int i = threadIdx.x + k * kBlock;
+    const bool valid = i < nrows;
+    st[k] = valid ? row_ptr[row0 + i] - base : 0;
+    en[k] = valid ? row_ptr[row0 + i + 1] - base : 0;
+    sum[k] = 0.0;
+  }
+  int c[EPT];
+  double p[EPT];
+  auto fetch = [&](int c0) {
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {
+      const int idx = c0 + threadIdx.x + e * kBlock;
+      const bool ok = idx < n;
+      const int craw = ld_col(cc + (ok ? idx : 0));
+      const double praw = ld_val(cv + (ok ? idx : 0));
+      c[e] = ok ? craw : -1;
+      p[e] = ok ? praw : 0.0;
+    }
+  };
+  if (n > 0) fetch(0);
+  for (int c0 = 0; c0 < n; c0 += kCbChunk) {
+    double x[EPT], pc[EPT];
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {
+      x[e] = gx(c[e]);  // 0 past the segment (c = -1)
+      pc[e] = p[e];
+    }
+    fetch(c0 + kCbChunk < n ? c0 + kCbChunk : c0);
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {
+      lp[threadIdx.x + e * kBlock] = pc[e];
+      lx[threadIdx.x + e * kBlock] = x[e];
+    }
+    __syncthreads();
+    const int c1 = c0 + kCbChunk;
+#pragma unroll
+    for (int k = 0; k < kCbRpt; ++k) {
+      const int lo = st[k] > c0 ? st[k] : c0;
+      const int hi = en[k] < c1 ? en[k] : c1;
+      double sk = sum[k];
+      for (int j = lo; j < hi; ++j) sk = fma(lp[j - c0], lx[j - c0], sk);
+      sum[k] = sk;
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int k = 0; k < kCbRpt; ++k) {
+    const int i = threadIdx.x + k * kBlock;
+    if (i < nrows) q[(i % ns) * A + i / ns] = fma(gamma, sum[k], cost[row0 + i]);  // stored row -> (state, action)
+  }
+  __syncthreads();
+  sweep_finish<double, double, RT>(s0, ns, A, q, v, Tv, pi, r0, partials, tile);
+}
+
 // All slices of a pass in one launch: workgroup w takes slice pass * 8 + w % 8
 // of tile w / 8, so XCD w % 8 (the dispatcher's choice for workgroup w) keeps
 // only its own slice of v in its L2.  The rows' slice parts go to
@@ -363,6 +448,19 @@ hipError_t cb_passes(mdp_handle* h, const double* v, double* Tv, int32_t* pi, RT
 }
 
 }  // namespace
+
+hipError_t launch_bellman_flat(mdp_handle* h, const double* v, double* Tv, int32_t* pi, void* r0, bool r0_f32,
+                               double4* part, int nb) {
+  const int ts = sweep_tile_states(h->A);
+  const size_t lds = static_cast<size_t>(ts) * h->A * sizeof(double);
+  if (r0_f32)
+    k_bellman_flat<float><<<nb, kBlock, lds, h->stream>>>(h->S, h->A, ts, h->row_ptr, h->col, h->val, h->cost, v,
+                                                          h->gamma, Tv, pi, static_cast<float*>(r0), part);
+  else
+    k_bellman_flat<double><<<nb, kBlock, lds, h->stream>>>(h->S, h->A, ts, h->row_ptr, h->col, h->val, h->cost, v,
+                                                           h->gamma, Tv, pi, static_cast<double*>(r0), part);
+  return hipGetLastError();
+}
 
 hipError_t launch_bellman_cb(mdp_handle* h, const double* v, double* Tv, int32_t* pi, void* r0,
                              bool r0_f32, double4* part, int nb) {

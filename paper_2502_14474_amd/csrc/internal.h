@@ -164,6 +164,7 @@ struct mdp_handle {
   int32_t* cb_off = nullptr;    // cb_blocks x (sweep tiles + 1): first entry of (slice, tile)
   double* cb_acc = nullptr;     // cb_xcd: cb_blocks x rows slice parts; else rows: row sums so far
   bool cb_xcd = false;          // all slices in one launch, one slice per XCD
+  bool flat_sweep = false;      // float64 sweeps stream each tile's rows (short rows, no blocked copy)
 
   // float64 vectors
   double* v = nullptr;       // current value iterate
@@ -445,6 +446,10 @@ hipError_t launch_negate(hipStream_t st, double* x, int64_t n);
 hipError_t build_colblocks(mdp_handle* h, int blocks, bool require, bool* built, double* far_frac);
 hipError_t launch_bellman_cb(mdp_handle* h, const double* v, double* Tv, int32_t* pi, void* r0,
                              bool r0_f32, double4* part, int nb);
+// The float64 sweep streamed tile by tile over the CSR rows (colblock.hip),
+// for handles with h->flat_sweep.
+hipError_t launch_bellman_flat(mdp_handle* h, const double* v, double* Tv, int32_t* pi, void* r0, bool r0_f32,
+                               double4* part, int nb);
 
 hipError_t launch_bellman(mdp_handle* h, Prec prec, const void* v, double* Tv, int32_t* pi,
                           void* r0, bool r0_f32, int red_mode, int first_cycle, double alpha,

@@ -308,6 +308,14 @@ hipError_t launch_bellman(mdp_handle* h, Prec prec, const void* v, double* Tv, i
     if (e != hipSuccess) return e;
     return reduce_into_ctl(h, nb, red_mode, first_cycle, alpha, floor_rel);
   }
+  if (prec == kF64 && h->flat_sweep) {
+    {
+      Prof pf(h, MDP_K_BELLMAN, bytes_sweep(h, 8, 8, r0 != nullptr, r0_f32 ? 4 : 8));
+      e = launch_bellman_flat(h, static_cast<const double*>(v), Tv, pi, r0, r0_f32, part, nb);
+    }
+    if (e != hipSuccess) return e;
+    return reduce_into_ctl(h, nb, red_mode, first_cycle, alpha, floor_rel);
+  }
   {
     Prof pf(h, MDP_K_BELLMAN, bytes_sweep(h, prec == kF64 ? 8 : (prec == kF32 ? 4 : 2), prec == kF64 ? 8 : 4, r0 != nullptr, r0_f32 ? 4 : 8) + (prec == kF16 ? h->rows * 8.0 : 0.0));
     e = with_lanes(h->lanes, [&](auto Lc) -> hipError_t {

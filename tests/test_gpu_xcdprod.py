@@ -203,3 +203,23 @@ def test_contiguous_policy_copy_in_preconditioned_evaluations():
             assert _policy_residual(inst, pi, v) <= 1e-10 * np.max(np.abs(v)), copy
             out[copy] = v
     assert np.max(np.abs(out[-1] - out[0])) <= 1e-10 * np.max(np.abs(out[0]))
+
+
+def test_streamed_sweep_on_short_rows():
+    """Handles with short rows (no blocked copy) stream each tile's rows in the
+    float64 sweep: against the oracle's Q values within the rounding bound of
+    two summation orders, bit for bit the one-slice blocked sweep (the same
+    fma chain per row), and against the row-by-row sweep (col_blocks = 0)."""
+    inst = WHOLE["maze_370"]()
+    v = 3.0 * np.random.default_rng(2).standard_normal(inst.S)
+    outs = {}
+    for cb in (-1, 1, 0):
+        with _mdp(inst, col_blocks=cb) as h:
+            outs[cb] = h.bellman(v)
+    Q = oracle.q_values(inst, v)
+    Tv_ref = Q.min(axis=1)
+    bound = 8 * 2.2e-16 * (np.abs(inst.cost).max() + inst.gamma * np.abs(v).max()) * 4
+    for cb, (Tv, pi, r) in outs.items():
+        assert np.max(np.abs(Tv - Tv_ref)) <= bound, cb
+    assert np.array_equal(outs[-1][0], outs[1][0]) and np.array_equal(outs[-1][1], outs[1][1])
+    assert outs[-1][2] == outs[1][2]
