@@ -954,12 +954,7 @@ mdp_status mdp_destroy(mdp_t h) {
   dev_free(h, h->U32);
   dev_free(h, h->part.buf);
   dev_free(h, h->ctl);
-  dev_free(h, h->pp_col);
-  dev_free(h, h->pp_val);
-  dev_free(h, h->pp_rel);
-  dev_free(h, h->pp_seg);
-  dev_free(h, h->pp_part);
-  dev_free(h, h->pp_fill);
+  pp_release(h);
   ctl_slot_give(h->ctl_host);
   prof_resolve(h);
   {

@@ -341,6 +341,8 @@ void stage_give(const StageBlock& b);
 // product's outputs.  The copy keeps float64 values; a float32 basis is
 // gathered in float32 and the slice parts summed in float64.
 hipError_t pp_prepare(mdp_handle* h, const int32_t* pi);
+// Frees the copy's arrays (queued on the handle's stream).
+void pp_release(mdp_handle* h);
 // Handles without a column-blocked copy get the contiguous copy when they
 // hold at least kPolicyCopyMinStates states (below, forming it and its host
 // check cost more than they save) and at most kPolicyCopyMaxRowMean entries

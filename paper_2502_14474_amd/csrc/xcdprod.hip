@@ -400,6 +400,19 @@ __global__ __launch_bounds__(kBlock) void k_pp_residual_finish(int64_t S, int A,
 
 // Set up (first call) and form the copy for policy pi; h->pp_ready says
 // whether the partitioned products can run for it.
+void pp_release(mdp_handle* h) {
+  auto drop = [&](auto*& p) {
+    handle_free(h, p);
+    p = nullptr;
+  };
+  drop(h->pp_col);
+  drop(h->pp_val);
+  drop(h->pp_rel);
+  drop(h->pp_seg);
+  drop(h->pp_part);
+  drop(h->pp_fill);
+}
+
 hipError_t pp_prepare(mdp_handle* h, const int32_t* pi) {
   h->pp_ready = false;
   if (h->pp_state < 0) return hipSuccess;
@@ -423,6 +436,11 @@ hipError_t pp_prepare(mdp_handle* h, const int32_t* pi) {
     // the longest row bounds every per-state count (8 bits) and every tile
     // segment (16 bits), and the copy's size
     hipError_t e = handle_alloc(h, reinterpret_cast<void**>(&h->pp_fill), 4 * sizeof(int));
+    if (e == hipErrorOutOfMemory) {
+      (void)hipGetLastError();
+      h->pp_state = -1;
+      return hipSuccess;
+    }
     if (e != hipSuccess) return e;
     int64_t kmax = h->kfix;
     if (kmax == 0) {
@@ -440,6 +458,7 @@ hipError_t pp_prepare(mdp_handle* h, const int32_t* pi) {
       kmax = longest;
     }
     if (kmax > 255 || kmax * kPPTile > 65535) {
+      pp_release(h);
       h->pp_state = -1;
       return hipSuccess;
     }
@@ -452,6 +471,13 @@ hipError_t pp_prepare(mdp_handle* h, const int32_t* pi) {
     if (e == hipSuccess) e = handle_alloc(h, reinterpret_cast<void**>(&h->pp_part), nblk * S * sizeof(double));
     if (e == hipSuccess) e = handle_alloc(h, reinterpret_cast<void**>(&h->pp_col), h->pp_cap * sizeof(int));
     if (e == hipSuccess) e = handle_alloc(h, reinterpret_cast<void**>(&h->pp_val), h->pp_cap * sizeof(double));
+    if (e == hipErrorOutOfMemory) {
+      // no room for the copy: the products keep gathering through row_ptr
+      (void)hipGetLastError();
+      pp_release(h);
+      h->pp_state = -1;
+      return hipSuccess;
+    }
     if (e != hipSuccess) return e;
     h->device_bytes += static_cast<int64_t>(nblk * S * (sizeof(uint16_t) + sizeof(double)) +
                                             nblk * ntiles * sizeof(int2) + h->pp_cap * 12);
