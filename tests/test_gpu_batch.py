@@ -57,6 +57,41 @@ def test_batch_bitwise_equals_alone(precision, launch):
         assert sts[k]["history"] == st["history"]
 
 
+@pytest.mark.parametrize("precision,launch", [(0, 2), (1, 1)])
+def test_batch_bitwise_equals_alone_many_tiles(precision, launch):
+    """MDPs of more than 256 product tiles (each thread of the dot and norm
+    sums then adds several partials, the last stride ragged) against one of
+    fewer: alone and in the batch the results stay bitwise equal."""
+    import paper_2502_14474_amd as m
+    insts = [config2(S=140000, A=4, seed=11),   # 274 tiles
+             config4(S=300000, A=4, seed=12),   # 586 tiles
+             config2(S=100000, A=4, seed=13)]   # 196 tiles
+    print(f"[case] many-tile batch precision={precision} launch={launch}", flush=True)
+    handles = [m.mdp_create(i.S, i.A, i.row_ptr, i.col, i.val, i.cost, i.gamma,
+                            low_precision=1 if precision else 0) for i in insts]
+    try:
+        alone = []
+        for inst, h in zip(insts, handles):
+            v = np.empty(inst.S)
+            pi = np.empty(inst.S, np.int32)
+            st = m.mdp_solve(h, v, pi, precision=precision, alpha=1e-2, max_inner=20000, policy_copy=0)
+            alone.append((v, pi, st))
+        vs = [np.empty(i.S) for i in insts]
+        pis = [np.empty(i.S, np.int32) for i in insts]
+        status, sts = m.mdp_solve_batch(handles, vs, pis, precision=precision, alpha=1e-2,
+                                        max_inner=20000, launch=launch)
+    finally:
+        for h in handles:
+            m.mdp_destroy(h)
+    assert status == 0
+    for k, (inst, (v, pi, st)) in enumerate(zip(insts, alone)):
+        assert st["status"] == 0
+        assert np.array_equal(vs[k], v), (k, inst.name, np.max(np.abs(vs[k] - v)))
+        assert np.array_equal(pis[k], pi), k
+        assert sts[k]["inner_iters"] == st["inner_iters"]
+        assert sts[k]["history"] == st["history"]
+
+
 def test_batch_matches_oracle():
     import paper_2502_14474_amd as m
     insts = [config1(S=500, seed=s) for s in range(6)] + [config2(S=4000, A=3, seed=9)]
