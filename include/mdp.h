@@ -449,10 +449,13 @@ mdp_status mdp_info(mdp_t h, int64_t* S, int32_t* A, int64_t* nnz, int32_t* lane
                     int64_t* device_bytes);
 
 /* Choose lanes_per_row for this handle by timing candidate widths on the
- * device (one sweep plus four policy products per width); writes the chosen
+ * device (one sweep plus four policy products per width, each width timed in
+ * three rounds and kept at its shortest time, since work sharing the GPU only
+ * lengthens a timing; the width that covers the mean row length is kept
+ * unless another is more than 5% faster); writes the chosen
  * width to *lanes (may be NULL) and remembers it for the handle's class (GPU
  * architecture, action count and mean row length, each rounded up to a power
- * of two) in $MDP_TUNE_CACHE (default $HOME/.cache/mdp_mi355x_tune.json).
+ * of two, and the nonzero count within a factor of 16) in $MDP_TUNE_CACHE (default $HOME/.cache/mdp_mi355x_tune.json).
  * mdp_create with lanes_per_row = 0 starts from a remembered width. */
 mdp_status mdp_autotune(mdp_t h, int32_t* lanes);
 

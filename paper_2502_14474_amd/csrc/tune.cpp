@@ -2,14 +2,16 @@
 // remembers the best width per (GPU architecture, class) in a small JSON file,
 // so that later handles of the same class start from the tuned width.
 //
-// Class key: "A<a>_k<k>": a = the action count rounded up to a power of two,
-// k = the mean row length rounded up to a power of two.  The cache file is
+// Class key: "A<a>_k<k>_n<e>": a = the action count rounded up to a power of
+// two, k = the mean row length rounded up to a power of two, 2^e <= nnz
+// rounded up to a power of two < 2^(e+4) with e a multiple of 4 (the best
+// width of a small, launch-bound MDP says little about a large one).  The cache file is
 // $MDP_TUNE_CACHE, else $HOME/.cache/mdp_mi355x_tune.json; a missing or
 // unreadable file is treated as empty.  The file is read once per process
 // (again whenever the path changes) and rewritten, via a temporary and a
 // rename, by every store; a store that cannot write the file keeps the width
 // for this process only.  The file holds one flat object:
-//   {"gfx950:A8_k16": 16, ...}
+//   {"gfx950:A8_k16_n20": 16, ...}
 #include <cstdio>
 #include <cstdlib>
 #include <fstream>
@@ -115,8 +117,10 @@ const std::map<std::string, int>& cache() {
 
 static std::string key_locked(const mdp_handle* h) {
   const double k = static_cast<double>(h->nnz) / static_cast<double>(h->rows);
+  int e = 0;
+  while (e < 62 && (int64_t{1} << e) < h->nnz) ++e;
   return arch_of(h->device) + ":A" + std::to_string(pow2_ceil(h->A)) + "_k" +
-         std::to_string(pow2_ceil(k));
+         std::to_string(pow2_ceil(k)) + "_n" + std::to_string(e / 4 * 4);
 }
 
 std::string tune_key(const mdp_handle* h) {

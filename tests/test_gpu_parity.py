@@ -426,7 +426,7 @@ def test_autotune_remembers_width_per_class(tmp_path, monkeypatch):
     stored = json.loads(cache.read_text())
     assert len(stored) == 1
     (key, val), = stored.items()
-    assert key.startswith("gfx") and key.endswith(":A8_k16") and val == L
+    assert key.startswith("gfx") and key.endswith(":A8_k16_n20") and val == L  # 2.56M and 640K nonzeros
     with _mdp(config2(S=5000, A=8, seed=4)) as h2:
         assert h2.info()["lanes_per_row"] == L
     with _mdp(config2(S=5000, A=8, seed=4), lanes_per_row=2) as h3:
