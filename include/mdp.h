@@ -141,15 +141,15 @@ typedef struct {
                              second correction (mdp_stats.orth_loss), the loss of orthogonality
                              a single pass would have left.  2 is MDP_E_NOTSUP with the other
                              inner solvers, batched solves and the server. */
-  int32_t policy_copy;    /* GMRES in float64 or mixed float32: -1 (default) runs the Arnoldi
-                             products on a copy of P_pi formed once per policy (about S * 16 +
-                             nnz(P_pi) * 12 bytes more device memory), on handles with a
-                             column-blocked copy (see mdp_create_opts.col_blocks) cut into column
-                             slices, one per XCD, and on other handles of at least 2^17 states
-                             with at most 8 entries per row on average stored contiguously; 0
-                             gathers the selected rows through row_ptr
-                             (as every other product does).  The two differ only in the rounding
-                             of each row's sum. */
+  int32_t policy_copy;    /* GMRES (float64 or mixed float32), BiCGSTAB and TFQMR: -1 (default)
+                             runs the inner solve's products on a copy of P_pi formed once per
+                             policy (about S * 16 + nnz(P_pi) * 12 bytes more device memory), on
+                             handles with a column-blocked copy (see mdp_create_opts.col_blocks)
+                             cut into column slices, one per XCD, and on other handles of at
+                             least 2^17 states with at most 8 entries per row on average stored
+                             contiguously; 0 gathers the selected rows through row_ptr (as every
+                             other product does: sweeps, Richardson, mdp_policy_apply).  The two
+                             differ only in the rounding of each row's sum. */
 } mdp_eval_opts;
 
 typedef struct {

@@ -466,6 +466,21 @@ struct InnerResult {
   bool converged = false;
 };
 
+// Float64 and float32 products of an inner solve on a large handle use the
+// copy of P_pi for its policy (formed at the first inner solve of the
+// policy, kept for the next), cut by XCD when the handle carries a
+// column-blocked copy, else contiguous when its rows are short.  The scope
+// takes the copy out of the products when the inner solve ends.
+struct PolicyCopyScope {
+  mdp_handle* h;
+  ~PolicyCopyScope() { h->pp_ready = false; }
+};
+hipError_t policy_copy_begin(mdp_handle* h, const int32_t* pi, int policy_copy) {
+  const bool short_rows = h->S >= kPolicyCopyMinStates && h->nnz <= kPolicyCopyMaxRowMean * h->rows;
+  if (policy_copy != 0 && (h->cb_blocks > 0 || short_rows)) return pp_prepare(h, pi);
+  return hipSuccess;
+}
+
 // GMRES(m) on (I - gamma P_pi) x = g_pi.  On entry basis slot 0 holds the
 // residual of x and ctl holds a started cycle (kRedGmresStart).  Arnoldi steps
 // run in `prec`; every restart recomputes the residual in float64 from the
@@ -475,16 +490,8 @@ mdp_status gmres_inner(mdp_handle* h, Prec prec, const int32_t* pi, double* x, i
                        bool gs2 = false, int policy_copy = -1) {
   const Prec bprec = prec == kF64 ? kF64 : kF32;
   const int bb = bprec == kF64 ? 8 : 4;
-  // float64 and float32 products on a large handle: the copy of P_pi for
-  // this policy (formed here, once), cut by XCD when the handle carries a
-  // column-blocked copy, else contiguous when its rows are short
-  struct PPGuard {
-    mdp_handle* h;
-    ~PPGuard() { h->pp_ready = false; }
-  } pp_guard{h};
-  const bool short_rows = h->S >= kPolicyCopyMinStates && h->nnz <= kPolicyCopyMaxRowMean * h->rows;
-  if ((prec == kF64 || prec == kF32) && policy_copy != 0 && (h->cb_blocks > 0 || short_rows))
-    MDP_HIP(pp_prepare(h, pi));
+  PolicyCopyScope pp_scope{h};
+  if (prec == kF64 || prec == kF32) MDP_HIP(policy_copy_begin(h, pi, policy_copy));
   for (;;) {
     int j = 0;
     const size_t rec0 = h->prof_pending.size();
@@ -602,7 +609,9 @@ mdp_status richardson_inner(mdp_handle* h, const int32_t* pi, double* buf0, doub
 // tolerance in ctl); stops at ctl->tol, at a breakdown, or after max_iter
 // iterations.
 mdp_status bicgstab_inner(mdp_handle* h, const int32_t* pi, double* x, int64_t max_iter,
-                          int sync_every, InnerResult* out, bool tfqmr = false) {
+                          int sync_every, InnerResult* out, bool tfqmr = false, int policy_copy = -1) {
+  PolicyCopyScope pp_scope{h};
+  MDP_HIP(policy_copy_begin(h, pi, policy_copy));
   if (tfqmr)
     MDP_HIP(launch_tfqmr_init(h, pi));
   else
@@ -1409,7 +1418,8 @@ mdp_status mdp_policy_eval(mdp_t h, const int32_t* policy, const double* v0, dou
     MDP_TRY(ensure_basis(h, kF64, std::max(o.restart, 7)));
     MDP_HIP(launch_apply(h, kApplyRes, h->pi, h->v, h->U64, false, kRedGmresStart, 1, o.rtol, 0.0));
     ir.applies += 1;
-    MDP_TRY(bicgstab_inner(h, h->pi, h->v, o.max_iter, sync_every, &ir, o.inner == MDP_INNER_TFQMR));
+    MDP_TRY(bicgstab_inner(h, h->pi, h->v, o.max_iter, sync_every, &ir, o.inner == MDP_INNER_TFQMR,
+                           o.policy_copy));
     rel = h->ctl_host->beta0 > 0 ? h->ctl_host->res_est / h->ctl_host->beta0 : 0.0;
   } else if (o.inner == MDP_INNER_GMRES) {
     const Prec prec = prec_of(o.precision);
@@ -1549,7 +1559,8 @@ mdp_status mdp_solve(mdp_t h, const double* v0, double* v, int32_t* policy,
       MDP_TRY(gmres_inner(h, iprec, h->pi, h->v, o.restart, o.max_inner, sync_every, alpha, &ir, deg, gs2,
                           o.policy_copy));
     } else if (bi) {
-      MDP_TRY(bicgstab_inner(h, h->pi, h->v, o.max_inner, sync_every, &ir, o.inner == MDP_INNER_TFQMR));
+      MDP_TRY(bicgstab_inner(h, h->pi, h->v, o.max_inner, sync_every, &ir, o.inner == MDP_INNER_TFQMR,
+                             o.policy_copy));
     } else {
       // x1 = T v_k is already in x2; continue T_pi from there
       double* last = h->x2;

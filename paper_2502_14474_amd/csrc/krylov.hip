@@ -403,6 +403,7 @@ hipError_t krylov_product(mdp_handle* h, const int32_t* pi, const double* in, do
   const int64_t S = h->S;
   const int nba = grid_for(S, kApplyTile);
   Prof pf(h, MDP_K_POLICY_APPLY, bytes_apply(h, 8, 8, 8));
+  if (h->pp_ready && pi == h->pp_pi) return launch_pp_op(h, in, out);  // on the policy's copy
 #define MDP_KR_APPLY(LL, UU)                                                              \
   k_bi_apply<LL, UU><<<nba, kBlock, 0, h->stream>>>(S, h->A, h->row_ptr, h->kfix, h->col, h->val, \
                                                      pi, in, h->gamma, out, h->ctl)

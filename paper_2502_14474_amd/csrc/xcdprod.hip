@@ -532,6 +532,16 @@ hipError_t pp_arnoldi_apply(mdp_handle* h, BT* Ub, int j, const BT* xin, double*
 }
 }  // namespace
 
+hipError_t launch_pp_op(mdp_handle* h, const double* x, double* y) {
+  hipError_t e = pp_parts<double>(h, x, h->ctl);
+  if (e != hipSuccess) return e;
+  // y = x + (-gamma) P_pi x: the Horner step with b = x
+  const int64_t g = std::min<int64_t>(8192, (h->S + kBlock - 1) / kBlock);
+  k_pp_horner_finish<double><<<static_cast<unsigned>(g), kBlock, 0, h->stream>>>(h->S, h->pp_blocks, h->pp_part, x,
+                                                                                 -h->gamma, y, h->ctl);
+  return hipGetLastError();
+}
+
 hipError_t launch_pp_residual(mdp_handle* h, const double* x, void* y, bool y_f32, double4* partials, int nb) {
   hipError_t e = pp_parts<double>(h, x, nullptr);
   if (e != hipSuccess) return e;

@@ -205,6 +205,31 @@ def test_contiguous_policy_copy_in_preconditioned_evaluations():
     assert np.max(np.abs(out[-1] - out[0])) <= 1e-10 * np.max(np.abs(out[0]))
 
 
+@pytest.mark.parametrize("inner", [2, 3])  # BiCGSTAB, TFQMR
+@pytest.mark.parametrize("name", ["c4twin_b7", "maze_370"])
+def test_policy_copy_in_short_recurrence_solvers(name, inner):
+    """BiCGSTAB and TFQMR run their products y = x - gamma P_pi x on the copy
+    too (sliced on a column-blocked handle, contiguous on a large short-row
+    one): the evaluation satisfies the policy's system, repeats bit for bit,
+    and agrees with the products through row_ptr to rounding."""
+    if name in CASES:
+        make, blocks = CASES[name]
+        inst, kw = make(), {"col_blocks": blocks}
+    else:
+        inst, kw = WHOLE[name](), {}
+    pi = np.random.default_rng(6).integers(0, inst.A, inst.S).astype(np.int32)
+    out = {}
+    with _mdp(inst, **kw) as h:
+        for copy in (-1, 0, -1):
+            v, st = h.policy_eval(pi, rtol=1e-13, max_iter=20000, inner=inner, policy_copy=copy)
+            assert st["status"] == 0, (copy, st)
+            assert _policy_residual(inst, pi, v) <= 1e-10 * np.max(np.abs(v)), copy
+            if copy in out:
+                assert np.array_equal(v, out[copy])
+            out[copy] = v
+    assert np.max(np.abs(out[-1] - out[0])) <= 1e-10 * np.max(np.abs(out[0]))
+
+
 def test_streamed_sweep_on_short_rows():
     """Handles with short rows (no blocked copy) stream each tile's rows in the
     float64 sweep: against the oracle's Q values within the rounding bound of
