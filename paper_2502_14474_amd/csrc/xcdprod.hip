@@ -87,35 +87,49 @@ __device__ __forceinline__ uint32_t half_ballot(bool p, int half) {
 // row's first chunk of columns (and, VAL, values) already loaded into cf, vf
 // (lane hl: entry hl, when hl < n).  The wavefronts take pairs in turn, so the
 // workgroup reads neighbouring rows together (giving each wavefront a
-// contiguous quarter of the tile made the scatter 16% slower).  Loads run two
-// pairs ahead for the row bounds and one pair ahead for the first chunk, so
-// they overlap the work on the current pair.
+// contiguous quarter of the tile made the scatter 16% slower).  A wavefront
+// works on kPPWalk pairs at a time: their first chunks are loaded together,
+// and the next batch's row bounds before the bodies run, so that the loads of
+// several rows are in flight while one row is worked on (on the 4M-state,
+// 24-column workload: placing 624 -> 578 us, scattering 1127 -> 1041 us per
+// policy; 8 pairs at a time scatter faster there, 972 us, but the maze's
+// scatter then slows from 534 to 743 us).
+#ifndef MDP_PP_WALK
+#define MDP_PP_WALK 4
+#endif
+constexpr int kPPWalk = MDP_PP_WALK;
 template <bool VAL, typename Body>
 __device__ __forceinline__ void walk_pairs(int64_t S, int A, RowIndex rix, const int* __restrict__ pi, int64_t s0,
                                            int ns, const int* __restrict__ col, const double* __restrict__ val,
                                            Body body) {
   const int half = (threadIdx.x % kWave) / 32, wave = threadIdx.x / kWave, hl = threadIdx.x % 32;
   constexpr int kStep = 2 * kPPWaves;
-  const int lo = 2 * wave, hi = ns;
-  int i = lo + half;
-  int a = 0, e = 0;
-  if (i < hi) selected_row(s0 + i, pi, A, S, rix, &a, &e);
-  int cf = hl < e - a ? col[a + hl] : 0;
-  double vf = VAL && hl < e - a ? val[a + hl] : 0.0;
-  int a1 = 0, e1 = 0;
-  if (i + kStep < hi) selected_row(s0 + i + kStep, pi, A, S, rix, &a1, &e1);
-  for (int i0 = lo; i0 < hi; i0 += kStep) {
-    const int ic = i, ia = a, na = e - a, cc = cf;
-    const double vc = vf;
-    // the next pair's first chunk, and the pair after's bounds
-    i += kStep;
-    a = a1;
-    e = e1;
-    cf = hl < e - a ? col[a + hl] : 0;
-    vf = VAL && hl < e - a ? val[a + hl] : 0.0;
-    a1 = e1 = 0;
-    if (i + kStep < hi) selected_row(s0 + i + kStep, pi, A, S, rix, &a1, &e1);
-    body(ic, ia, na, cc, vc);
+  const int lo = 2 * wave;  // the wavefront's first pair (uniform over the wavefront)
+  int a[kPPWalk], e[kPPWalk];
+#pragma unroll
+  for (int d = 0; d < kPPWalk; ++d) {
+    const int i = lo + half + d * kStep;
+    a[d] = e[d] = 0;
+    if (i < ns) selected_row(s0 + i, pi, A, S, rix, &a[d], &e[d]);
+  }
+  for (int ib = lo; ib < ns; ib += kPPWalk * kStep) {
+    int ia[kPPWalk], na[kPPWalk], cf[kPPWalk];
+    double vf[kPPWalk];
+#pragma unroll
+    for (int d = 0; d < kPPWalk; ++d) {
+      ia[d] = a[d];
+      na[d] = e[d] - a[d];
+      cf[d] = hl < na[d] ? col[a[d] + hl] : 0;
+      vf[d] = VAL && hl < na[d] ? val[a[d] + hl] : 0.0;
+    }
+#pragma unroll
+    for (int d = 0; d < kPPWalk; ++d) {
+      const int i = ib + half + (kPPWalk + d) * kStep;
+      a[d] = e[d] = 0;
+      if (i < ns) selected_row(s0 + i, pi, A, S, rix, &a[d], &e[d]);
+    }
+#pragma unroll
+    for (int d = 0; d < kPPWalk; ++d) body(ib + half + d * kStep, ia[d], na[d], cf[d], vf[d]);
   }
 }
 
