@@ -579,7 +579,7 @@ __device__ __forceinline__ void horner_tile(int64_t S, int A, RowIndex rix, cons
       });
 }
 
-template <typename BT>
+template <typename BT, int TILE = kApplyTile>
 __device__ __forceinline__ void cgs_dots_tile(const BT* __restrict__ Ub, int64_t ldu, int j, int64_t s0, int ns,
                                               const double* w_lds, double* __restrict__ partials, int tile,
                                               int nb);
@@ -629,13 +629,13 @@ __device__ __forceinline__ void arnoldi_apply_tile(
 // The classical Gram-Schmidt dots of an Arnoldi tile: the workgroup's partial
 // sum_s U_i[s] w[s] for i = 0..j into partials[i * nb + tile], with the tile's
 // w values (already written to U_{j+1}) in w_lds.  Every thread must call it.
-template <typename BT>
+template <typename BT, int TILE>
 __device__ __forceinline__ void cgs_dots_tile(const BT* __restrict__ Ub, int64_t ldu, int j, int64_t s0, int ns,
                                               const double* w_lds, double* __restrict__ partials, int tile,
                                               int nb) {
   __shared__ double red[kBlock / kWave][8];
   const int wv_id = threadIdx.x / kWave;
-  constexpr int KS = kApplyTile / kBlock;
+  constexpr int KS = TILE / kBlock;
   for (int i0 = 0; i0 <= j; i0 += 8) {
     double a8[8];
 #pragma unroll

@@ -338,7 +338,8 @@ void stage_give(const StageBlock& b);
 // for policy pi when it is not current and sets h->pp_ready when the Arnoldi
 // products can use it; launch_pp_arnoldi_apply is then the Arnoldi product of
 // step j on the float64 or float32 basis (input U_j, or xin), with the plain
-// product's outputs.  The copy keeps float64 values; a float32 basis is
+// product's outputs except that the dot partials come in *nb_dots tiles (the
+// unsliced copy's product and dots run in one launch over its own tiles).  The copy keeps float64 values; a float32 basis is
 // gathered in float32 and the slice parts summed in float64.
 hipError_t pp_prepare(mdp_handle* h, const int32_t* pi);
 // Frees the copy's arrays (queued on the handle's stream).
@@ -353,7 +354,7 @@ void pp_release(mdp_handle* h);
 constexpr int64_t kPolicyCopyMinStates = int64_t{1} << 17;
 constexpr int64_t kPolicyCopyMaxRowMean = 8;
 hipError_t launch_pp_arnoldi_apply(mdp_handle* h, bool basis_f32, int j, const void* xin, double* partials,
-                                   int nb);
+                                   int nb, int* nb_dots);
 // One Horner step y = b + gamma P_pi x of the polynomial preconditioner on
 // the copy (float64 or float32 vectors); ctl may be NULL.
 hipError_t launch_pp_horner(mdp_handle* h, bool f32, const void* x, const void* b, void* y, const Ctl* ctl);

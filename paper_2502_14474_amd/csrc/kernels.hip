@@ -469,10 +469,11 @@ hipError_t launch_arnoldi_step(mdp_handle* h, Prec prec, const int32_t* pi, int 
     xin = precond_apply(h, prec, pi, basis_slot(h, bprec, j), m + 1, m + 2, deg, h->ctl, &e);
     if (e != hipSuccess) return e;
   }
+  int nb_dots = nb;  // tiles of the dot partials
   if ((prec == kF64 || prec == kF32) && h->pp_ready && pi == h->pp_pi) {
     // the XCD-partitioned product on the policy's copy (same outputs)
     Prof pf(h, MDP_K_ARNOLDI_APPLY, bytes_arnoldi_apply(h, 8, prec == kF64 ? 8 : 4, j), j);
-    e = launch_pp_arnoldi_apply(h, prec == kF32, j, xin, h->part.buf, nb);
+    e = launch_pp_arnoldi_apply(h, prec == kF32, j, xin, h->part.buf, nb, &nb_dots);
   } else {
     Prof pf(h, MDP_K_ARNOLDI_APPLY, bytes_arnoldi_apply(h, prec == kF64 ? 8 : (prec == kF32 ? 4 : 2), prec == kF64 ? 8 : 4, j) + (prec == kF16 ? h->S * 8.0 : 0.0), j);
     e = with_lanes(h->lanes, [&](auto Lc) -> hipError_t {
@@ -497,7 +498,7 @@ hipError_t launch_arnoldi_step(mdp_handle* h, Prec prec, const int32_t* pi, int 
   if (e != hipSuccess) return e;
   {
     Prof pf(h, MDP_K_REDUCE, 0.0, j);
-    k_reduce_dots<<<j + 1, kBlock, 0, h->stream>>>(h->part.buf, nb, j, h->ctl);
+    k_reduce_dots<<<j + 1, kBlock, 0, h->stream>>>(h->part.buf, nb_dots, j, h->ctl);
   }
   if ((e = hipGetLastError()) != hipSuccess) return e;
   const int nbu = grid_for(h->S, kUpdTile);

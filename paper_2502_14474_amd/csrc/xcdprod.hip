@@ -241,22 +241,15 @@ __global__ __launch_bounds__(kBlock) void k_longest_row(const int* __restrict__ 
 // LDS, with the next chunk's loads issued first; then each thread carries its
 // states (at most 4) through the chunk.  Exits at once when the GMRES cycle is
 // done.
+// The sums over slice b of tile t (its states s0 + threadIdx.x + k * kBlock,
+// k < 4, into sum[k]; 0 past the tile) of the copy's entries times x.
+// Every thread must call it; lp and lx are the chunk's LDS staging.
 template <typename XT>
-__global__ __launch_bounds__(kBlock) void k_pp_product(int64_t S, int nblk, int ntiles, int pass,
-                                                       const uint16_t* __restrict__ rel, const int2* __restrict__ seg,
-                                                       const int* __restrict__ pcol, const double* __restrict__ pval,
-                                                       const XT* __restrict__ x, double* __restrict__ part,
-                                                       const Ctl* __restrict__ ctl) {
-  if (ctl && ctl->done) return;
-  __shared__ double lp[kPPChunk], lx[kPPChunk];
+__device__ __forceinline__ void pp_tile_sums(int64_t S, int ntiles, int b, int t, int64_t s0, int ns,
+                                             const uint16_t* __restrict__ rel, const int2* __restrict__ seg,
+                                             const int* __restrict__ pcol, const double* __restrict__ pval,
+                                             const XT* __restrict__ x, double* lp, double* lx, double (&sum)[4]) {
   constexpr int EPT = kPPChunk / kBlock;
-  // sliced copy: slice pass * 8 + w % 8 of tile w / 8; whole rows: tile w
-  const bool sliced = nblk >= kNumXcd;
-  const int b = sliced ? pass * kNumXcd + static_cast<int>(blockIdx.x % kNumXcd) : 0;
-  const int t = static_cast<int>(sliced ? blockIdx.x / kNumXcd : blockIdx.x);
-  if (b >= nblk || t >= ntiles) return;  // the same for the whole workgroup
-  const int64_t s0 = static_cast<int64_t>(t) * kPPTile;
-  const int ns = static_cast<int>(min<int64_t>(kPPTile, S - s0));
   const int2 sg = seg[static_cast<int64_t>(b) * ntiles + t];
   const int seg0 = sg.x;
   const int n = sg.y;
@@ -265,7 +258,6 @@ __global__ __launch_bounds__(kBlock) void k_pp_product(int64_t S, int nblk, int 
   const double* __restrict__ cv = pval + seg0;
   const Gather<XT> gx(x, S);
   int st[4], en[4];
-  double sum[4];
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
     const int i = threadIdx.x + k * kBlock;
@@ -320,6 +312,25 @@ __global__ __launch_bounds__(kBlock) void k_pp_product(int64_t S, int nblk, int 
     }
     __syncthreads();
   }
+}
+
+template <typename XT>
+__global__ __launch_bounds__(kBlock) void k_pp_product(int64_t S, int nblk, int ntiles, int pass,
+                                                       const uint16_t* __restrict__ rel, const int2* __restrict__ seg,
+                                                       const int* __restrict__ pcol, const double* __restrict__ pval,
+                                                       const XT* __restrict__ x, double* __restrict__ part,
+                                                       const Ctl* __restrict__ ctl) {
+  if (ctl && ctl->done) return;
+  __shared__ double lp[kPPChunk], lx[kPPChunk];
+  // sliced copy: slice pass * 8 + w % 8 of tile w / 8; whole rows: tile w
+  const bool sliced = nblk >= kNumXcd;
+  const int b = sliced ? pass * kNumXcd + static_cast<int>(blockIdx.x % kNumXcd) : 0;
+  const int t = static_cast<int>(sliced ? blockIdx.x / kNumXcd : blockIdx.x);
+  if (b >= nblk || t >= ntiles) return;  // the same for the whole workgroup
+  const int64_t s0 = static_cast<int64_t>(t) * kPPTile;
+  const int ns = static_cast<int>(min<int64_t>(kPPTile, S - s0));
+  double sum[4];
+  pp_tile_sums<XT>(S, ntiles, b, t, s0, ns, rel, seg, pcol, pval, x, lp, lx, sum);
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
     const int i = threadIdx.x + k * kBlock;
@@ -329,6 +340,68 @@ __global__ __launch_bounds__(kBlock) void k_pp_product(int64_t S, int nblk, int 
     if (i < ns) part[static_cast<int64_t>(b) * S + s0 + i] = sum[k];
 #endif
   }
+}
+
+// The unsliced copy (one slice): the product and its finish in one launch,
+// no parts.  y = b + g P_pi x (a Horner step, or the Krylov product with
+// b = x, g = -gamma), tile w; the same arithmetic as the two-kernel path.
+template <typename XT>
+__global__ __launch_bounds__(kBlock) void k_pp_axpy1(int64_t S, int ntiles, const uint16_t* __restrict__ rel,
+                                                     const int2* __restrict__ seg, const int* __restrict__ pcol,
+                                                     const double* __restrict__ pval, const XT* __restrict__ x,
+                                                     const XT* __restrict__ bv, double g, XT* __restrict__ y,
+                                                     const Ctl* __restrict__ ctl) {
+  if (ctl && ctl->done) return;
+  __shared__ double lp[kPPChunk], lx[kPPChunk];
+  using AT = typename Acc<XT>::type;
+  const int t = static_cast<int>(blockIdx.x);
+  const int64_t s0 = static_cast<int64_t>(t) * kPPTile;
+  const int ns = static_cast<int>(min<int64_t>(kPPTile, S - s0));
+  double sum[4];
+  pp_tile_sums<XT>(S, ntiles, 0, t, s0, ns, rel, seg, pcol, pval, x, lp, lx, sum);
+  const AT gam = static_cast<AT>(g);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int i = threadIdx.x + k * kBlock;
+    if (i < ns) y[s0 + i] = static_cast<XT>(fma(gam, static_cast<AT>(sum[k]), static_cast<AT>(bv[s0 + i])));
+  }
+}
+
+// The unsliced copy: the Arnoldi product of step j and the Gram-Schmidt dot
+// partials of its tile (tiles of kPPTile states, partials[i * ntiles + t]) in
+// one launch; w as k_pp_arnoldi_finish forms it.
+template <typename BT>
+__global__ __launch_bounds__(kBlock) void k_pp_arnoldi1(int64_t S, int ntiles, const uint16_t* __restrict__ rel,
+                                                        const int2* __restrict__ seg, const int* __restrict__ pcol,
+                                                        const double* __restrict__ pval, BT* __restrict__ Ub,
+                                                        int64_t ldu, int j, double gamma, const Ctl* __restrict__ ctl,
+                                                        double* __restrict__ partials, const BT* __restrict__ xin) {
+  if (ctl->done) return;
+  static_assert(kPPChunk >= kPPTile, "the chunk staging doubles as the tile's w");
+  __shared__ double lp[kPPChunk], lx[kPPChunk];
+  using AT = typename Acc<BT>::type;
+  const int t = static_cast<int>(blockIdx.x);
+  const int64_t s0 = static_cast<int64_t>(t) * kPPTile;
+  const int ns = static_cast<int>(min<int64_t>(kPPTile, S - s0));
+  const BT* __restrict__ xj = xin ? xin : Ub + static_cast<int64_t>(j) * ldu;
+  double sum[4];
+  pp_tile_sums<BT>(S, ntiles, 0, t, s0, ns, rel, seg, pcol, pval, xj, lp, lx, sum);
+  const AT gam = static_cast<AT>(gamma);
+  BT* __restrict__ w = Ub + static_cast<int64_t>(j + 1) * ldu;
+  const double cj = ctl->scale[j];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int i = threadIdx.x + k * kBlock;
+    if (i < ns) {
+      const int64_t s = s0 + i;
+      const AT av = static_cast<AT>(xj[s]) - gam * static_cast<AT>(sum[k]);
+      const BT wv = static_cast<BT>(cj * static_cast<double>(av));
+      w[s] = wv;
+      lp[i] = static_cast<double>(wv);  // the staging is free after the last chunk's barrier
+    }
+  }
+  __syncthreads();
+  cgs_dots_tile<BT, kPPTile>(Ub, ldu, j, s0, ns, lp, partials, t, ntiles);
 }
 
 // The rest of the Arnoldi step on the parts: (P_pi x)[s] is the sum of the
@@ -525,18 +598,32 @@ hipError_t pp_parts(mdp_handle* h, const XT* x, const Ctl* ctl) {
   return hipGetLastError();
 }
 
+// y = b + g P_pi x on the copy
 template <typename XT>
-hipError_t pp_horner(mdp_handle* h, const XT* x, const XT* b, XT* y, const Ctl* ctl) {
+hipError_t pp_axpy(mdp_handle* h, const XT* x, const XT* b, double g, XT* y, const Ctl* ctl) {
+  if (h->pp_blocks == 1) {
+    k_pp_axpy1<XT><<<static_cast<unsigned>(h->pp_ntiles), kBlock, 0, h->stream>>>(
+        h->S, h->pp_ntiles, h->pp_rel, h->pp_seg, h->pp_col, h->pp_val, x, b, g, y, ctl);
+    return hipGetLastError();
+  }
   hipError_t e = pp_parts<XT>(h, x, ctl);
   if (e != hipSuccess) return e;
-  const int64_t g = std::min<int64_t>(8192, (h->S + kBlock - 1) / kBlock);
-  k_pp_horner_finish<XT><<<static_cast<unsigned>(g), kBlock, 0, h->stream>>>(h->S, h->pp_blocks, h->pp_part, b,
-                                                                             h->gamma, y, ctl);
+  const int64_t gr = std::min<int64_t>(8192, (h->S + kBlock - 1) / kBlock);
+  k_pp_horner_finish<XT><<<static_cast<unsigned>(gr), kBlock, 0, h->stream>>>(h->S, h->pp_blocks, h->pp_part, b,
+                                                                             g, y, ctl);
   return hipGetLastError();
 }
 
 template <typename BT>
-hipError_t pp_arnoldi_apply(mdp_handle* h, BT* Ub, int j, const BT* xin, double* partials, int nb) {
+hipError_t pp_arnoldi_apply(mdp_handle* h, BT* Ub, int j, const BT* xin, double* partials, int nb, int* nb_dots) {
+  if (h->pp_blocks == 1) {
+    *nb_dots = static_cast<int>(h->pp_ntiles);
+    k_pp_arnoldi1<BT><<<static_cast<unsigned>(h->pp_ntiles), kBlock, 0, h->stream>>>(
+        h->S, h->pp_ntiles, h->pp_rel, h->pp_seg, h->pp_col, h->pp_val, Ub, h->ldu, j, h->gamma, h->ctl, partials,
+        xin);
+    return hipGetLastError();
+  }
+  *nb_dots = nb;
   const BT* x = xin ? xin : Ub + static_cast<int64_t>(j) * h->ldu;
   hipError_t e = pp_parts<BT>(h, x, h->ctl);
   if (e != hipSuccess) return e;
@@ -547,13 +634,7 @@ hipError_t pp_arnoldi_apply(mdp_handle* h, BT* Ub, int j, const BT* xin, double*
 }  // namespace
 
 hipError_t launch_pp_op(mdp_handle* h, const double* x, double* y) {
-  hipError_t e = pp_parts<double>(h, x, h->ctl);
-  if (e != hipSuccess) return e;
-  // y = x + (-gamma) P_pi x: the Horner step with b = x
-  const int64_t g = std::min<int64_t>(8192, (h->S + kBlock - 1) / kBlock);
-  k_pp_horner_finish<double><<<static_cast<unsigned>(g), kBlock, 0, h->stream>>>(h->S, h->pp_blocks, h->pp_part, x,
-                                                                                 -h->gamma, y, h->ctl);
-  return hipGetLastError();
+  return pp_axpy<double>(h, x, x, -h->gamma, y, h->ctl);  // y = x + (-gamma) P_pi x
 }
 
 hipError_t launch_pp_residual(mdp_handle* h, const double* x, void* y, bool y_f32, double4* partials, int nb) {
@@ -572,16 +653,17 @@ hipError_t launch_pp_residual(mdp_handle* h, const double* x, void* y, bool y_f3
 
 hipError_t launch_pp_horner(mdp_handle* h, bool f32, const void* x, const void* b, void* y, const Ctl* ctl) {
   if (f32)
-    return pp_horner<float>(h, static_cast<const float*>(x), static_cast<const float*>(b), static_cast<float*>(y),
-                            ctl);
-  return pp_horner<double>(h, static_cast<const double*>(x), static_cast<const double*>(b), static_cast<double*>(y),
-                           ctl);
+    return pp_axpy<float>(h, static_cast<const float*>(x), static_cast<const float*>(b), h->gamma,
+                          static_cast<float*>(y), ctl);
+  return pp_axpy<double>(h, static_cast<const double*>(x), static_cast<const double*>(b), h->gamma,
+                         static_cast<double*>(y), ctl);
 }
 
 hipError_t launch_pp_arnoldi_apply(mdp_handle* h, bool basis_f32, int j, const void* xin, double* partials,
-                                   int nb) {
-  if (basis_f32) return pp_arnoldi_apply<float>(h, h->U32, j, static_cast<const float*>(xin), partials, nb);
-  return pp_arnoldi_apply<double>(h, h->U64, j, static_cast<const double*>(xin), partials, nb);
+                                   int nb, int* nb_dots) {
+  if (basis_f32)
+    return pp_arnoldi_apply<float>(h, h->U32, j, static_cast<const float*>(xin), partials, nb, nb_dots);
+  return pp_arnoldi_apply<double>(h, h->U64, j, static_cast<const double*>(xin), partials, nb, nb_dots);
 }
 
 }  // namespace mdp
