@@ -107,6 +107,24 @@ def test_config3_full_maze():
     _sampled_bellman_check(inst, Tv, pi, v, rng)
 
 
+@pytest.mark.parametrize("inner,deg", [(2, 1), (0, 4)])  # BiCGSTAB; GMRES with the d = 4 polynomial
+def test_config3_full_maze_other_inner_solvers(inner, deg):
+    """The maze's products on the contiguous copy in one launch each (the
+    Krylov product and the preconditioner's Horner steps): BiCGSTAB, and GMRES
+    preconditioned, certified by the oracle's sweep at full size."""
+    import paper_2502_14474_amd as m
+    inst = config3()
+    _log(f"[case] config3 full, inner={inner} precond_degree={deg}")
+    with m.MDP.from_instance(inst, validate=False) as h:
+        v, pi, st = h.solve(alpha=1e-2, rtol_cert=1e-10, max_inner=20000, inner=inner, precond_degree=deg)
+    assert st["status"] == 0, st
+    _log(f"[case] config3 solve: {st['time_ms']:.1f} ms, sweeps {st['bellman_sweeps']}, inner {st['inner_iters']}")
+    Tv, pi_ref, res = oracle.bellman(inst, v)
+    rel = res / (1.0 - inst.gamma) / np.max(np.abs(Tv))
+    _log(f"[cert] config3 inner={inner}: certified relative error <= {rel:.3e}")
+    assert rel <= 1e-9
+
+
 @pytest.fixture(scope="module")
 def c4():
     t = time.time()
@@ -137,6 +155,16 @@ def test_config4_full_solve_fp64_and_sampled_sweep(c4):
         Tv_gpu, pi_gpu, _ = h.bellman(v)
     _certify(inst, v, 1e-9, "config4 fp64")
     _sampled_bellman_check(inst, Tv_gpu, pi_gpu, v, np.random.default_rng(7))
+
+
+def test_config4_full_bicgstab_on_the_sliced_copy(c4):
+    """BiCGSTAB's products y = x - gamma P_pi x on the XCD-sliced copy at full
+    size, certified by the oracle's streamed sweep."""
+    import paper_2502_14474_amd as m
+    with m.MDP.from_instance(c4, validate=False) as h:
+        v, pi, st = h.solve(alpha=1e-2, rtol_cert=1e-10, inner=2)
+    assert st["status"] == 0, st
+    _certify(c4, v, 1e-9, "config4 bicgstab")
 
 
 def test_config4_full_mixed_fp16(c4):
