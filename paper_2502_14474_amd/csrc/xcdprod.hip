@@ -87,21 +87,24 @@ __device__ __forceinline__ uint32_t half_ballot(bool p, int half) {
 // row's first chunk of columns (and, VAL, values) already loaded into cf, vf
 // (lane hl: entry hl, when hl < n).  The wavefronts take pairs in turn, so the
 // workgroup reads neighbouring rows together (giving each wavefront a
-// contiguous quarter of the tile made the scatter 16% slower).  A wavefront
-// works on kPPWalk pairs at a time: their first chunks are loaded together,
-// and the next batch's row bounds before the bodies run, so that the loads of
-// several rows are in flight while one row is worked on (on the 4M-state,
-// 24-column workload: placing 624 -> 578 us, scattering 1127 -> 1041 us per
-// policy; 8 pairs at a time scatter faster there, 972 us, but the maze's
-// scatter then slows from 534 to 743 us).
+// contiguous quarter of the tile made the scatter 16% slower), kPPWalk pairs
+// at a time, so that the loads of several rows are in flight while one row
+// is worked on.
 #ifndef MDP_PP_WALK
 #define MDP_PP_WALK 4
 #endif
 constexpr int kPPWalk = MDP_PP_WALK;
+
+// Row bounds computed per batch: the batch's first chunks are loaded
+// together and the next batch's bounds before the bodies run.  On the
+// 4M-state, 24-column workload (uniform rows, bounds from the policy entry
+// alone) this took placing 624 -> 578 us and scattering 1127 -> 1041 us per
+// policy against one pair at a time; eight pairs at a time scattered in
+// 972 us there but slowed the maze's scatter from 534 to 743 us.
 template <bool VAL, typename Body>
-__device__ __forceinline__ void walk_pairs(int64_t S, int A, RowIndex rix, const int* __restrict__ pi, int64_t s0,
-                                           int ns, const int* __restrict__ col, const double* __restrict__ val,
-                                           Body body) {
+__device__ __forceinline__ void walk_pairs_direct(int64_t S, int A, RowIndex rix, const int* __restrict__ pi,
+                                                  int64_t s0, int ns, const int* __restrict__ col,
+                                                  const double* __restrict__ val, Body body) {
   const int half = (threadIdx.x % kWave) / 32, wave = threadIdx.x / kWave, hl = threadIdx.x % 32;
   constexpr int kStep = 2 * kPPWaves;
   const int lo = 2 * wave;  // the wavefront's first pair (uniform over the wavefront)
@@ -133,6 +136,72 @@ __device__ __forceinline__ void walk_pairs(int64_t S, int A, RowIndex rix, const
   }
 }
 
+// Row bounds staged in LDS first (every policy entry and row offset of the
+// tile loaded at once), and the next batch's first chunks loaded before the
+// current batch is worked on, so one round trip is in flight behind the
+// work instead of the chain policy -> row offsets -> columns per batch.  On
+// the maze (rows through row_ptr) placing 419 -> 267 us and scattering
+// 534 -> 391 us per policy; on the uniform rows above it was slower (663 and
+// 1080 us: the staging costs the placing kernel occupancy, 5 waves per SIMD
+// instead of 7).
+template <bool VAL, typename Body>
+__device__ __forceinline__ void walk_pairs_staged(int64_t S, int A, RowIndex rix, const int* __restrict__ pi,
+                                                  int64_t s0, int ns, const int* __restrict__ col,
+                                                  const double* __restrict__ val, Body body) {
+  __shared__ int b_lo[kPPTile], b_n[kPPTile];
+#pragma unroll
+  for (int k = 0; k < kPPTile / kBlock; ++k) {
+    const int i = threadIdx.x + k * kBlock;
+    int a = 0, e = 0;
+    if (i < ns) selected_row(s0 + i, pi, A, S, rix, &a, &e);
+    b_lo[i] = a;
+    b_n[i] = e - a;
+  }
+  __syncthreads();
+  const int half = (threadIdx.x % kWave) / 32, wave = threadIdx.x / kWave, hl = threadIdx.x % 32;
+  constexpr int kStep = 2 * kPPWaves;
+  const int lo = 2 * wave;  // the wavefront's first pair (uniform over the wavefront)
+  int cf[kPPWalk];
+  double vf[kPPWalk];
+  auto load = [&](int ib, int (&c)[kPPWalk], double (&v)[kPPWalk]) {
+#pragma unroll
+    for (int d = 0; d < kPPWalk; ++d) {
+      const int i = ib + half + d * kStep;
+      const int a = i < ns ? b_lo[i] : 0, n = i < ns ? b_n[i] : 0;
+      c[d] = hl < n ? col[a + hl] : 0;
+      v[d] = VAL && hl < n ? val[a + hl] : 0.0;
+    }
+  };
+  load(lo, cf, vf);
+  for (int ib = lo; ib < ns; ib += kPPWalk * kStep) {
+    int cn[kPPWalk];
+    double vn[kPPWalk];
+    load(ib + kPPWalk * kStep, cn, vn);
+#pragma unroll
+    for (int d = 0; d < kPPWalk; ++d) {
+      const int i = ib + half + d * kStep;
+      body(i, i < ns ? b_lo[i] : 0, i < ns ? b_n[i] : 0, cf[d], vf[d]);
+    }
+#pragma unroll
+    for (int d = 0; d < kPPWalk; ++d) {
+      cf[d] = cn[d];
+      vf[d] = vn[d];
+    }
+  }
+}
+
+// STAGED: row bounds from LDS (rows through row_ptr); else computed per
+// batch (uniform rows, whose bounds need only the policy entry).
+template <bool VAL, bool STAGED, typename Body>
+__device__ __forceinline__ void walk_pairs(int64_t S, int A, RowIndex rix, const int* __restrict__ pi, int64_t s0,
+                                           int ns, const int* __restrict__ col, const double* __restrict__ val,
+                                           Body body) {
+  if constexpr (STAGED)
+    walk_pairs_staged<VAL>(S, A, rix, pi, s0, ns, col, val, body);
+  else
+    walk_pairs_direct<VAL>(S, A, rix, pi, s0, ns, col, val, body);
+}
+
 // Forming the copy, first kernel (tile t): per-state slice counts, each
 // state's start inside the tile's segment of each slice (rel[b * S + s]), and
 // one atomic add per slice on *fill that places the segment in the copy
@@ -140,6 +209,7 @@ __device__ __forceinline__ void walk_pairs(int64_t S, int A, RowIndex rix, const
 // on the order of the atomic adds; what it holds does not, nor does any sum.
 // Needs rows of at most 255 entries and at most 65535 entries per segment
 // (guaranteed on the host from the longest row of the MDP).
+template <bool STAGED>
 __global__ __launch_bounds__(kBlock) void k_pp_place(int64_t S, int A, RowIndex rix, const int* __restrict__ col,
                                                      const int* __restrict__ pi, int slice, int nblk, int ntiles,
                                                      uint16_t* __restrict__ rel, int2* __restrict__ seg,
@@ -150,7 +220,7 @@ __global__ __launch_bounds__(kBlock) void k_pp_place(int64_t S, int A, RowIndex 
   const int64_t s0 = static_cast<int64_t>(t) * kPPTile;
   const int ns = static_cast<int>(min<int64_t>(kPPTile, S - s0));
   const int hl = threadIdx.x % 32, half = (threadIdx.x % kWave) / 32;
-  walk_pairs<false>(S, A, rix, pi, s0, ns, col, nullptr, [&](int i, int a, int n, int cf, double) {
+  walk_pairs<false, STAGED>(S, A, rix, pi, s0, ns, col, nullptr, [&](int i, int a, int n, int cf, double) {
     const int nmax = max(n, __shfl_xor(n, 32));
     int cnt = 0;  // lane hl < nblk: entries of slice hl
     for (int c0 = 0; c0 < nmax; c0 += 32) {
@@ -182,6 +252,7 @@ __global__ __launch_bounds__(kBlock) void k_pp_place(int64_t S, int A, RowIndex 
 // start there (rel), the entries of its state and slice in earlier chunks of
 // the row, and those before it in its chunk (from the ballot), so each state
 // keeps its CSR order inside every slice.
+template <bool STAGED>
 __global__ __launch_bounds__(kBlock) void k_pp_scatter(int64_t S, int A, RowIndex rix, const int* __restrict__ col,
                                                        const double* __restrict__ val, const int* __restrict__ pi,
                                                        int slice, int nblk, int ntiles, const int2* __restrict__ seg,
@@ -194,7 +265,7 @@ __global__ __launch_bounds__(kBlock) void k_pp_scatter(int64_t S, int A, RowInde
   const int hl = threadIdx.x % 32, half = (threadIdx.x % kWave) / 32;
   if (threadIdx.x < nblk) base[threadIdx.x] = seg[static_cast<int64_t>(threadIdx.x) * ntiles + t].x;
   __syncthreads();
-  walk_pairs<true>(S, A, rix, pi, s0, ns, col, val, [&](int i, int a, int n, int cf, double vf) {
+  walk_pairs<true, STAGED>(S, A, rix, pi, s0, ns, col, val, [&](int i, int a, int n, int cf, double vf) {
     const int nmax = max(n, __shfl_xor(n, 32));
     // lane hl < nblk: the state's next place in slice hl
     int next = (i < ns && hl < nblk) ? base[hl] + rel[static_cast<int64_t>(hl) * S + s0 + i] : 0;
@@ -574,10 +645,20 @@ hipError_t pp_prepare(mdp_handle* h, const int32_t* pi) {
   const RowIndex rix{h->row_ptr, h->kfix};
   hipError_t e = hipMemsetAsync(h->pp_fill, 0, sizeof(int), h->stream);
   if (e != hipSuccess) return e;
-  k_pp_place<<<h->pp_ntiles, kBlock, 0, h->stream>>>(S, h->A, rix, h->col, pi, h->pp_slice, h->pp_blocks,
-                                                     h->pp_ntiles, h->pp_rel, h->pp_seg, h->pp_fill);
-  k_pp_scatter<<<h->pp_ntiles, kBlock, 0, h->stream>>>(S, h->A, rix, h->col, h->val, pi, h->pp_slice, h->pp_blocks,
-                                                       h->pp_ntiles, h->pp_seg, h->pp_rel, h->pp_col, h->pp_val);
+  // rows through row_ptr: bounds staged in LDS; uniform rows: computed per batch
+  if (h->kfix > 0) {
+    k_pp_place<false><<<h->pp_ntiles, kBlock, 0, h->stream>>>(S, h->A, rix, h->col, pi, h->pp_slice, h->pp_blocks,
+                                                              h->pp_ntiles, h->pp_rel, h->pp_seg, h->pp_fill);
+    k_pp_scatter<false><<<h->pp_ntiles, kBlock, 0, h->stream>>>(S, h->A, rix, h->col, h->val, pi, h->pp_slice,
+                                                                h->pp_blocks, h->pp_ntiles, h->pp_seg, h->pp_rel,
+                                                                h->pp_col, h->pp_val);
+  } else {
+    k_pp_place<true><<<h->pp_ntiles, kBlock, 0, h->stream>>>(S, h->A, rix, h->col, pi, h->pp_slice, h->pp_blocks,
+                                                             h->pp_ntiles, h->pp_rel, h->pp_seg, h->pp_fill);
+    k_pp_scatter<true><<<h->pp_ntiles, kBlock, 0, h->stream>>>(S, h->A, rix, h->col, h->val, pi, h->pp_slice,
+                                                               h->pp_blocks, h->pp_ntiles, h->pp_seg, h->pp_rel,
+                                                               h->pp_col, h->pp_val);
+  }
   if ((e = hipGetLastError()) != hipSuccess) return e;
   h->pp_pi = pi;
   h->pp_gen = h->pi_gen;
