@@ -356,10 +356,11 @@ constexpr int64_t kPolicyCopyMaxRowMean = 8;
 hipError_t launch_pp_arnoldi_apply(mdp_handle* h, bool basis_f32, int j, const void* xin, double* partials,
                                    int nb, int* nb_dots);
 // One Horner step y = b + gamma P_pi x of the polynomial preconditioner on
-// the copy (float64 or float32 vectors); ctl may be NULL.
+// the copy (float64 or float32 vectors); ctl may be NULL.  y may be b but not
+// x (on the unsliced copy one launch gathers x while it writes y).
 hipError_t launch_pp_horner(mdp_handle* h, bool f32, const void* x, const void* b, void* y, const Ctl* ctl);
 // The float64 product y = x - gamma P_pi x of BiCGSTAB and TFQMR on the
-// copy; exits at once once ctl->done is set.
+// copy (y must not be x); exits at once once ctl->done is set.
 hipError_t launch_pp_op(mdp_handle* h, const double* x, double* y);
 // The float64 residual g_pi - (x - gamma P_pi x) of a GMRES restart on the
 // copy, into y (float64 or float32) with the per-tile (max, sum of squares)
