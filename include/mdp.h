@@ -99,7 +99,7 @@ typedef struct {
                              otherwise a power of two in [2, 64] */
   int32_t col_blocks;     /* column-blocked copy of P for the float64 sweep: -1 (default)
                              builds one when S >= 2^21 and at least half of the entries lie
-                             outside their row's column slice (slices of 2.75 MB of v); without
+                             outside their row's column slice (slices of 3.25 MB of v); without
                              one, handles of at least 2^17 states with at most 8 entries per row
                              on average stream each tile's rows as one segment in the float64
                              sweep (no copy); 0: never either, every sweep gathers row by row;

@@ -257,12 +257,15 @@ enum ReduceMode { kRedNone = -1, kRedPlain = 0, kRedGmresStart = 1, kRedRichards
 
 // Rows of the Bellman sweep handled by one workgroup (whole states).
 constexpr int kSweepRows = MDP_SWEEP_ROWS;
-// Column-blocked sweep: slices of at most 2.75 MB of the float64 vector, so
+// Column-blocked sweep: slices of at most 3.25 MB of the float64 vector, so
 // that a slice and the streamed entries passing through share one XCD's 4 MB
-// L2 (on the 4M-state workload: 12 passes, 11.6 ms, against 8 passes of 4 MB,
-// 12.0 ms, and 16 of 2 MB, 12.6 ms); built automatically from 2^21 states
+// L2.  On the 4M-state workload (32 MB of v) a sweep takes 10.75 ms in 10
+// slices, against 10.9 ms in 11, 11.2 ms in 9 and in 12, and earlier
+// measurements of 12.0 ms in 8 slices of 4 MB and 12.6 ms in 16 of 2 MB:
+// fewer passes read and write the running sums fewer times, until the slice
+// crowds the streams out of the L2.  Built automatically from 2^21 states
 // (16 MB of v) up.
-constexpr int64_t kColSliceBytes = int64_t{11} << 18;
+constexpr int64_t kColSliceBytes = int64_t{13} << 18;
 // Largest buffer of slice parts (cb_blocks x rows float64) for which the
 // blocked sweep runs all slices in one launch, each XCD on its own slice,
 // instead of one pass per slice.  0: never (on the 4M-state workload the
