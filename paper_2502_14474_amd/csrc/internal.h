@@ -359,8 +359,8 @@ constexpr int64_t kPolicyCopyMaxRowMean = 8;
 hipError_t launch_pp_arnoldi_apply(mdp_handle* h, bool basis_f32, int j, const void* xin, double* partials,
                                    int nb, int* nb_dots);
 // One Horner step y = b + gamma P_pi x of the polynomial preconditioner on
-// the copy (float64 or float32 vectors); ctl may be NULL.  y may be b but not
-// x (on the unsliced copy one launch gathers x while it writes y).
+// the copy (float64 or float32 vectors); ctl may be NULL.  y must be neither
+// x nor b (on the unsliced copy one launch gathers x while it writes y).
 hipError_t launch_pp_horner(mdp_handle* h, bool f32, const void* x, const void* b, void* y, const Ctl* ctl);
 // The float64 product y = x - gamma P_pi x of BiCGSTAB and TFQMR on the
 // copy (y must not be x); exits at once once ctl->done is set.
