@@ -214,8 +214,8 @@ __global__ __launch_bounds__(kBlock) void k_pp_place(int64_t S, int A, RowIndex 
                                                      const int* __restrict__ pi, int slice, int nblk, int ntiles,
                                                      uint16_t* __restrict__ rel, int2* __restrict__ seg,
                                                      int* __restrict__ fill) {
-  __shared__ uint8_t c8[kPPMaxBlocks][kPPTile];
-  __shared__ int pos[kPPTile + 1];
+  __shared__ __align__(16) uint8_t c8[kPPMaxBlocks][kPPTile];
+  __shared__ int wtot[kPPWaves][kPPMaxBlocks];
   const int t = blockIdx.x;
   const int64_t s0 = static_cast<int64_t>(t) * kPPTile;
   const int ns = static_cast<int>(min<int64_t>(kPPTile, S - s0));
@@ -233,17 +233,53 @@ __global__ __launch_bounds__(kBlock) void k_pp_place(int64_t S, int A, RowIndex 
     if (i < ns && hl < nblk) c8[hl][i] = static_cast<uint8_t>(cnt);
   });
   __syncthreads();
+  // The exclusive scans of every slice's counts at once: thread u owns states
+  // 4u .. 4u + 3 (one 32-bit word of c8[b]); a wavefront scan of the thread
+  // sums, then the sums of the earlier wavefronts.  Two barriers in all
+  // (one scan of the 1024 counts per slice took some 18; placing 580 -> 544 us
+  // per policy on the 4M-state, 24-column workload, 266 -> 225 us on the maze).
+  static_assert(kPPTile == 4 * kBlock, "one word of four counts per thread");
+  const int u = threadIdx.x, lane = u % kWave, wv = u / kWave;
+  auto counts = [&](int b, int (&c)[4]) {
+    const uint32_t w = reinterpret_cast<const uint32_t*>(c8[b])[u];
+    int sum = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      c[k] = 4 * u + k < ns ? static_cast<int>((w >> (8 * k)) & 0xffu) : 0;  // past the tile: unwritten
+      sum += c[k];
+    }
+    return sum;
+  };
+  auto wave_incl = [&](int x) {
+#pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) {
+      const int y = __shfl_up(x, off, kWave);
+      x += lane >= off ? y : 0;
+    }
+    return x;
+  };
   for (int b = 0; b < nblk; ++b) {
-    for (int i = threadIdx.x; i < ns; i += kBlock) pos[i] = c8[b][i];
-    __syncthreads();
-    block_exclusive_scan(pos, ns);
-    for (int i = threadIdx.x; i < ns; i += kBlock)
-      rel[static_cast<int64_t>(b) * S + s0 + i] = static_cast<uint16_t>(pos[i]);
-    if (threadIdx.x == 0) {
-      const int len = pos[ns];
+    int c[4];
+    const int incl = wave_incl(counts(b, c));
+    if (lane == kWave - 1) wtot[wv][b] = incl;
+  }
+  __syncthreads();
+  for (int b = 0; b < nblk; ++b) {
+    int c[4];
+    const int own = counts(b, c);
+    int run = wave_incl(own) - own;
+    for (int q = 0; q < wv; ++q) run += wtot[q][b];
+    uint16_t* __restrict__ rb = rel + static_cast<int64_t>(b) * S + s0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      if (4 * u + k < ns) rb[4 * u + k] = static_cast<uint16_t>(run);
+      run += c[k];
+    }
+    if (u == 0) {
+      int len = 0;
+      for (int q = 0; q < kPPWaves; ++q) len += wtot[q][b];
       seg[static_cast<int64_t>(b) * ntiles + t] = make_int2(atomicAdd(fill, len), len);
     }
-    __syncthreads();
   }
 }
 
