@@ -512,6 +512,22 @@ def rows_leg(args, m, h, inst, v, pi, stream):
     log(f"[bench] gmres with CGS2: {1e3 * (t1 - t0):.1f} ms, {st['inner_iters']} steps, "
         f"loss of orthogonality of one pass {st['orth_loss']:.2e}")
 
+    # the inexactness parameter: solve time against alpha (each inner solve
+    # stops at alpha times its initial residual; alpha -> 0 is exact PI)
+    sweep = {}
+    for a in (1e-1, 1e-2, 1e-4, 1e-6):
+        w.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st = m.mdp_solve(h, w, p2, restart=args.restart, alpha=a, atol=args.atol, max_inner=100000)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        sweep[f"{a:g}"] = {"ms": 1e3 * (t1 - t0), "status": st["status"], "sweeps": st["bellman_sweeps"],
+                           "inner": st["inner_iters"], "residual": st["residual"]}
+    rows["gmres_alpha_sweep"] = sweep
+    log("[bench] alpha sweep: " + ", ".join(f"{a}: {d['ms']:.1f} ms ({d['sweeps']} sweeps, {d['inner']} steps)"
+                                             for a, d in sweep.items()))
+
     w = torch.zeros_like(v)
     p2 = torch.zeros_like(pi)
     m.mdp_profile(h, True)
