@@ -241,7 +241,8 @@ __global__ __launch_bounds__(kBlock) void k_pp_place(int64_t S, int A, RowIndex 
   static_assert(kPPTile == 4 * kBlock, "one word of four counts per thread");
   const int u = threadIdx.x, lane = u % kWave, wv = u / kWave;
   auto counts = [&](int b, int (&c)[4]) {
-    const uint32_t w = reinterpret_cast<const uint32_t*>(c8[b])[u];
+    uint32_t w;
+    __builtin_memcpy(&w, &c8[b][4 * u], sizeof(w));  // one aligned 32-bit LDS read
     int sum = 0;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
