@@ -205,6 +205,23 @@ def test_contiguous_policy_copy_in_preconditioned_evaluations():
     assert np.max(np.abs(out[-1] - out[0])) <= 1e-10 * np.max(np.abs(out[0]))
 
 
+def test_contiguous_policy_copy_in_mixed_preconditioned_solves():
+    """Mixed float32 solves with the polynomial preconditioner: the float32
+    Horner steps and Arnoldi products run on the contiguous copy in one launch
+    each; the solve meets the Bellman equation (the oracle's Q values) and its
+    policy is greedy for its values."""
+    import paper_2502_14474_amd as m
+    inst = WHOLE["maze_370"]()
+    with _mdp(inst) as h:
+        v, p, st = h.solve(alpha=1e-2, precision=m.MDP_MIXED_FP32, precond_degree=4, atol=1e-9,
+                           rtol_cert=1e-10)
+    assert st["status"] == 0, st
+    Q = oracle.q_values(inst, v)
+    assert np.max(np.abs(Q.min(axis=1) - v)) <= 2e-9
+    chosen = Q[np.arange(inst.S), p]
+    assert np.all(chosen - Q.min(axis=1) <= 1e-9 * max(1.0, np.max(np.abs(v))))
+
+
 @pytest.mark.parametrize("inner", [2, 3])  # BiCGSTAB, TFQMR
 @pytest.mark.parametrize("name", ["c4twin_b7", "maze_370"])
 def test_policy_copy_in_short_recurrence_solvers(name, inner):
