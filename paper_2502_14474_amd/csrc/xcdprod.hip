@@ -87,52 +87,56 @@ __device__ __forceinline__ uint32_t half_ballot(bool p, int half) {
 // row's first chunk of columns (and, VAL, values) already loaded into cf, vf
 // (lane hl: entry hl, when hl < n).  The wavefronts take pairs in turn, so the
 // workgroup reads neighbouring rows together (giving each wavefront a
-// contiguous quarter of the tile made the scatter 16% slower), kPPWalk pairs
-// at a time, so that the loads of several rows are in flight while one row
-// is worked on.
-#ifndef MDP_PP_WALK
-#define MDP_PP_WALK 4
+// contiguous quarter of the tile made the scatter 16% slower), a batch of
+// pairs at a time, so that the loads of several rows are in flight while one
+// row is worked on.
+#ifndef MDP_PP_WALK_DIRECT
+#define MDP_PP_WALK_DIRECT 8
 #endif
-constexpr int kPPWalk = MDP_PP_WALK;
+#ifndef MDP_PP_WALK_STAGED
+#define MDP_PP_WALK_STAGED 4
+#endif
 
 // Row bounds computed per batch: the batch's first chunks are loaded
 // together and the next batch's bounds before the bodies run.  On the
 // 4M-state, 24-column workload (uniform rows, bounds from the policy entry
-// alone) this took placing 624 -> 578 us and scattering 1127 -> 1041 us per
-// policy against one pair at a time; eight pairs at a time scattered in
-// 972 us there but slowed the maze's scatter from 534 to 743 us.
+// alone) batches of four pairs took placing 624 -> 578 us and scattering
+// 1127 -> 1041 us per policy against one pair at a time, and batches of
+// eight scatter in 972 us (on the maze, whose rows now take the staged walk,
+// eight slowed this walk's scatter from 534 to 743 us).
 template <bool VAL, typename Body>
 __device__ __forceinline__ void walk_pairs_direct(int64_t S, int A, RowIndex rix, const int* __restrict__ pi,
                                                   int64_t s0, int ns, const int* __restrict__ col,
                                                   const double* __restrict__ val, Body body) {
+  constexpr int kWalk = MDP_PP_WALK_DIRECT;
   const int half = (threadIdx.x % kWave) / 32, wave = threadIdx.x / kWave, hl = threadIdx.x % 32;
   constexpr int kStep = 2 * kPPWaves;
   const int lo = 2 * wave;  // the wavefront's first pair (uniform over the wavefront)
-  int a[kPPWalk], e[kPPWalk];
+  int a[kWalk], e[kWalk];
 #pragma unroll
-  for (int d = 0; d < kPPWalk; ++d) {
+  for (int d = 0; d < kWalk; ++d) {
     const int i = lo + half + d * kStep;
     a[d] = e[d] = 0;
     if (i < ns) selected_row(s0 + i, pi, A, S, rix, &a[d], &e[d]);
   }
-  for (int ib = lo; ib < ns; ib += kPPWalk * kStep) {
-    int ia[kPPWalk], na[kPPWalk], cf[kPPWalk];
-    double vf[kPPWalk];
+  for (int ib = lo; ib < ns; ib += kWalk * kStep) {
+    int ia[kWalk], na[kWalk], cf[kWalk];
+    double vf[kWalk];
 #pragma unroll
-    for (int d = 0; d < kPPWalk; ++d) {
+    for (int d = 0; d < kWalk; ++d) {
       ia[d] = a[d];
       na[d] = e[d] - a[d];
       cf[d] = hl < na[d] ? col[a[d] + hl] : 0;
       vf[d] = VAL && hl < na[d] ? val[a[d] + hl] : 0.0;
     }
 #pragma unroll
-    for (int d = 0; d < kPPWalk; ++d) {
-      const int i = ib + half + (kPPWalk + d) * kStep;
+    for (int d = 0; d < kWalk; ++d) {
+      const int i = ib + half + (kWalk + d) * kStep;
       a[d] = e[d] = 0;
       if (i < ns) selected_row(s0 + i, pi, A, S, rix, &a[d], &e[d]);
     }
 #pragma unroll
-    for (int d = 0; d < kPPWalk; ++d) body(ib + half + d * kStep, ia[d], na[d], cf[d], vf[d]);
+    for (int d = 0; d < kWalk; ++d) body(ib + half + d * kStep, ia[d], na[d], cf[d], vf[d]);
   }
 }
 
@@ -148,6 +152,7 @@ template <bool VAL, typename Body>
 __device__ __forceinline__ void walk_pairs_staged(int64_t S, int A, RowIndex rix, const int* __restrict__ pi,
                                                   int64_t s0, int ns, const int* __restrict__ col,
                                                   const double* __restrict__ val, Body body) {
+  constexpr int kWalk = MDP_PP_WALK_STAGED;
   __shared__ int b_lo[kPPTile], b_n[kPPTile];
 #pragma unroll
   for (int k = 0; k < kPPTile / kBlock; ++k) {
@@ -161,11 +166,11 @@ __device__ __forceinline__ void walk_pairs_staged(int64_t S, int A, RowIndex rix
   const int half = (threadIdx.x % kWave) / 32, wave = threadIdx.x / kWave, hl = threadIdx.x % 32;
   constexpr int kStep = 2 * kPPWaves;
   const int lo = 2 * wave;  // the wavefront's first pair (uniform over the wavefront)
-  int cf[kPPWalk];
-  double vf[kPPWalk];
-  auto load = [&](int ib, int (&c)[kPPWalk], double (&v)[kPPWalk]) {
+  int cf[kWalk];
+  double vf[kWalk];
+  auto load = [&](int ib, int (&c)[kWalk], double (&v)[kWalk]) {
 #pragma unroll
-    for (int d = 0; d < kPPWalk; ++d) {
+    for (int d = 0; d < kWalk; ++d) {
       const int i = ib + half + d * kStep;
       const int a = i < ns ? b_lo[i] : 0, n = i < ns ? b_n[i] : 0;
       c[d] = hl < n ? col[a + hl] : 0;
@@ -173,17 +178,17 @@ __device__ __forceinline__ void walk_pairs_staged(int64_t S, int A, RowIndex rix
     }
   };
   load(lo, cf, vf);
-  for (int ib = lo; ib < ns; ib += kPPWalk * kStep) {
-    int cn[kPPWalk];
-    double vn[kPPWalk];
-    load(ib + kPPWalk * kStep, cn, vn);
+  for (int ib = lo; ib < ns; ib += kWalk * kStep) {
+    int cn[kWalk];
+    double vn[kWalk];
+    load(ib + kWalk * kStep, cn, vn);
 #pragma unroll
-    for (int d = 0; d < kPPWalk; ++d) {
+    for (int d = 0; d < kWalk; ++d) {
       const int i = ib + half + d * kStep;
       body(i, i < ns ? b_lo[i] : 0, i < ns ? b_n[i] : 0, cf[d], vf[d]);
     }
 #pragma unroll
-    for (int d = 0; d < kPPWalk; ++d) {
+    for (int d = 0; d < kWalk; ++d) {
       cf[d] = cn[d];
       vf[d] = vn[d];
     }
