@@ -247,6 +247,25 @@ def test_policy_copy_in_short_recurrence_solvers(name, inner):
     assert np.max(np.abs(out[-1] - out[0])) <= 1e-10 * np.max(np.abs(out[0]))
 
 
+@pytest.mark.parametrize("inner", [2, 3])
+def test_short_recurrence_solves_on_the_sliced_copy(inner):
+    """Whole solves with BiCGSTAB / TFQMR on a column-blocked twin: the copy is
+    formed again for every new policy of the outer iteration, and the solve
+    matches the oracle's exact policy iteration (values and policy parity)."""
+    make, blocks = CASES["c4twin_b7"]
+    inst = make()
+    with _mdp(inst, col_blocks=blocks) as h:
+        v, pi, st = h.solve(alpha=1e-2, rtol_cert=1e-10, inner=inner)
+    assert st["status"] == 0, st
+    ref = oracle.policy_iteration(inst, method="certified")
+    err = np.max(np.abs(v - ref["v"])) / np.max(np.abs(ref["v"]))
+    assert err <= 1e-9, err
+    Q = oracle.q_values(inst, ref["v"])
+    tau = max(1e-9, 2 * inst.gamma * (np.max(np.abs(v - ref["v"])) + 1e-11 * np.max(np.abs(ref["v"]))))
+    pp = oracle.policy_parity(inst, Q, pi, ref["pi"], tau)
+    assert pp["mismatch_outside_band"] == 0 and pp["not_tau_optimal"] == 0, pp
+
+
 def test_streamed_sweep_on_short_rows():
     """Handles with short rows (no blocked copy) stream each tile's rows in the
     float64 sweep: against the oracle's Q values within the rounding bound of
