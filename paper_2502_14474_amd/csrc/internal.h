@@ -204,7 +204,8 @@ struct mdp_handle {
   uint16_t* pp_rel = nullptr;   // pp_blocks x S: state start inside its tile's segment
   int2* pp_seg = nullptr;       // pp_blocks x pp_ntiles: (first entry, length) of a segment
   double* pp_part = nullptr;    // pp_blocks x S: slice parts of a product
-  int* pp_fill = nullptr;       // entries placed so far while the copy is formed
+  int* pp_fill = nullptr;       // entries placed so far while the copy is formed, and a changed flag
+  int* pp_snap = nullptr;       // the policy of the last formation (S entries)
   const int32_t* pp_pi = nullptr;
   int64_t pp_gen = -1, pi_gen = 0;
 

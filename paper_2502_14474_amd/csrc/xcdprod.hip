@@ -218,7 +218,8 @@ template <bool STAGED>
 __global__ __launch_bounds__(kBlock) void k_pp_place(int64_t S, int A, RowIndex rix, const int* __restrict__ col,
                                                      const int* __restrict__ pi, int slice, int nblk, int ntiles,
                                                      uint16_t* __restrict__ rel, int2* __restrict__ seg,
-                                                     int* __restrict__ fill) {
+                                                     int* __restrict__ fill, const int* __restrict__ changed) {
+  if (*changed == 0) return;  // the copy already holds this policy (the same for every workgroup)
   __shared__ __align__(16) uint8_t c8[kPPMaxBlocks][kPPTile];
   __shared__ int wtot[kPPWaves][kPPMaxBlocks];
   const int t = blockIdx.x;
@@ -299,7 +300,8 @@ __global__ __launch_bounds__(kBlock) void k_pp_scatter(int64_t S, int A, RowInde
                                                        const double* __restrict__ val, const int* __restrict__ pi,
                                                        int slice, int nblk, int ntiles, const int2* __restrict__ seg,
                                                        const uint16_t* __restrict__ rel, int* __restrict__ pcol,
-                                                       double* __restrict__ pval) {
+                                                       double* __restrict__ pval, const int* __restrict__ changed) {
+  if (*changed == 0) return;  // the copy already holds this policy
   __shared__ int base[kPPMaxBlocks];
   const int t = blockIdx.x;
   const int64_t s0 = static_cast<int64_t>(t) * kPPTile;
@@ -333,6 +335,25 @@ __global__ __launch_bounds__(kBlock) void k_pp_scatter(int64_t S, int A, RowInde
       next += add;
     }
   });
+}
+
+// Has the policy changed since the copy was formed?  snap holds the policy
+// of the last formation: every entry is compared and then overwritten, and
+// *changed is set when any differs (or always, with force).  The formation
+// kernels exit at once when it stays 0, so a policy that the greedy step
+// left as it was costs one pass over 2 x 4 S bytes instead of a formation
+// (on the 4M-state, 24-column workload the last two of a solve's six).
+__global__ __launch_bounds__(kBlock) void k_pp_policy_changed(int64_t S, const int* __restrict__ pi,
+                                                              int* __restrict__ snap, int force,
+                                                              int* __restrict__ changed) {
+  int diff = force;
+  for (int64_t s = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; s < S;
+       s += static_cast<int64_t>(gridDim.x) * kBlock) {
+    const int p = pi[s];
+    diff |= snap[s] != p;
+    snap[s] = p;
+  }
+  if (__syncthreads_or(diff) && threadIdx.x == 0) atomicOr(changed, 1);
 }
 
 // The longest row of the MDP (stored offsets), into *out.
@@ -611,6 +632,7 @@ void pp_release(mdp_handle* h) {
   drop(h->pp_seg);
   drop(h->pp_part);
   drop(h->pp_fill);
+  drop(h->pp_snap);
 }
 
 hipError_t pp_prepare(mdp_handle* h, const int32_t* pi) {
@@ -683,23 +705,51 @@ hipError_t pp_prepare(mdp_handle* h, const int32_t* pi) {
                                             nblk * ntiles * sizeof(int2) + h->pp_cap * 12);
     h->pp_state = 1;
   }
-  // no host round trip: the segments are placed by atomic adds
+  // no host round trip: the segments are placed by atomic adds, and a policy
+  // the copy already holds is found on the device (pp_fill[0]: entries placed,
+  // pp_fill[1]: the policy differs from the last formation's)
   const RowIndex rix{h->row_ptr, h->kfix};
-  hipError_t e = hipMemsetAsync(h->pp_fill, 0, sizeof(int), h->stream);
+  hipError_t e = hipMemsetAsync(h->pp_fill, 0, 2 * sizeof(int), h->stream);
   if (e != hipSuccess) return e;
+  int* changed = h->pp_fill + 1;
+  {
+    const bool first = h->pp_snap == nullptr;
+    if (first) {
+      e = handle_alloc(h, reinterpret_cast<void**>(&h->pp_snap), S * sizeof(int));
+      if (e == hipErrorOutOfMemory) {
+        // no snapshot: form the copy for every policy
+        (void)hipGetLastError();
+        h->pp_snap = nullptr;
+        e = hipMemsetAsync(changed, 0xff, sizeof(int), h->stream);
+        if (e != hipSuccess) return e;
+      } else if (e != hipSuccess) {
+        return e;
+      } else {
+        h->device_bytes += S * static_cast<int64_t>(sizeof(int));
+      }
+    }
+    if (h->pp_snap) {
+      const int64_t g = std::min<int64_t>(4096, (S + kBlock - 1) / kBlock);
+      k_pp_policy_changed<<<static_cast<unsigned>(g), kBlock, 0, h->stream>>>(S, pi, h->pp_snap, first ? 1 : 0,
+                                                                               changed);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+  }
   // rows through row_ptr: bounds staged in LDS; uniform rows: computed per batch
   if (h->kfix > 0) {
     k_pp_place<false><<<h->pp_ntiles, kBlock, 0, h->stream>>>(S, h->A, rix, h->col, pi, h->pp_slice, h->pp_blocks,
-                                                              h->pp_ntiles, h->pp_rel, h->pp_seg, h->pp_fill);
+                                                              h->pp_ntiles, h->pp_rel, h->pp_seg, h->pp_fill,
+                                                              changed);
     k_pp_scatter<false><<<h->pp_ntiles, kBlock, 0, h->stream>>>(S, h->A, rix, h->col, h->val, pi, h->pp_slice,
                                                                 h->pp_blocks, h->pp_ntiles, h->pp_seg, h->pp_rel,
-                                                                h->pp_col, h->pp_val);
+                                                                h->pp_col, h->pp_val, changed);
   } else {
     k_pp_place<true><<<h->pp_ntiles, kBlock, 0, h->stream>>>(S, h->A, rix, h->col, pi, h->pp_slice, h->pp_blocks,
-                                                             h->pp_ntiles, h->pp_rel, h->pp_seg, h->pp_fill);
+                                                             h->pp_ntiles, h->pp_rel, h->pp_seg, h->pp_fill,
+                                                             changed);
     k_pp_scatter<true><<<h->pp_ntiles, kBlock, 0, h->stream>>>(S, h->A, rix, h->col, h->val, pi, h->pp_slice,
                                                                h->pp_blocks, h->pp_ntiles, h->pp_seg, h->pp_rel,
-                                                               h->pp_col, h->pp_val);
+                                                               h->pp_col, h->pp_val, changed);
   }
   if ((e = hipGetLastError()) != hipSuccess) return e;
   h->pp_pi = pi;
